@@ -1,0 +1,107 @@
+"""Each plausible mistake planted in the oracle (on the CPU, in a private copy of
+its source) must make at least one pin fail.  This checks that the pins constrain
+every part of the oracle: a dropped term, a wrong sign, an off-by-one, a
+transposed operand."""
+import contextlib
+import sys
+
+import pytest
+
+import oracle
+from oracle import geometry, composite, sh, loss, grad, adam
+import tests.test_oracle_geometry as TG
+import tests.test_oracle_render as TR
+import tests.test_oracle_grad_loss_adam as TL
+
+_MODS = {"geometry": geometry, "composite": composite, "sh": sh, "loss": loss, "grad": grad, "adam": adam}
+
+
+@contextlib.contextmanager
+def _mutated(modname, old, new):
+    mod = _MODS[modname]
+    src = open(mod.__file__).read()
+    assert src.count(old) >= 1, f"mutation anchor not found: {old!r}"
+    saved = dict(mod.__dict__)
+    exec(compile(src.replace(old, new, 1), mod.__file__, "exec"), mod.__dict__)
+    # rebind names other oracle modules imported from the mutated one
+    patched = []
+    for other in list(_MODS.values()) + [oracle]:
+        for k, v in list(other.__dict__.items()):
+            if k in saved and saved[k] is v and mod.__dict__.get(k) is not v and other is not mod:
+                other.__dict__[k] = mod.__dict__[k]
+                patched.append((other, k, v))
+    try:
+        yield
+    finally:
+        mod.__dict__.clear()
+        mod.__dict__.update(saved)
+        for other, k, v in patched:
+            other.__dict__[k] = v
+
+
+def _fails(tests):
+    for t, args in tests:
+        try:
+            t(*args)
+        except (AssertionError, IndexError, ValueError, RuntimeError):
+            return True
+    return False
+
+
+MUTATIONS = [
+    ("geometry", "J02 = -(fx * txc)", "J02 = (fx * txc)",
+     [(TG.test_ewa_equals_fd_jacobian_route, (False,))]),
+    ("geometry", "T1 = [J11 * R[1][k] + J12 * R[2][k] for k in range(3)]",
+     "T1 = [J11 * R[k][1] + J12 * R[k][2] for k in range(3)]",
+     [(TG.test_ewa_equals_fd_jacobian_route, (False,)), (TG.test_ewa_monte_carlo, ())]),
+    ("geometry", "S11 = ((U1[0] * T1[0] + U1[1] * T1[1]) + U1[2] * T1[2]) + KAPPA",
+     "S11 = ((U1[0] * T1[0] + U1[1] * T1[1]) + U1[2] * T1[2])",
+     [(TG.test_isotropic_on_axis_closed_form, ())]),
+    ("geometry", "b = -S01 / dets", "b = S01 / dets", [(TG.test_conic_and_extent, ())]),
+    ("geometry", "xlo, xhi = np.ceil((un - rn) - 0.5)", "xlo, xhi = np.ceil((un - rn) + 0.5)",
+     [(TG.test_tile_rect_brute_force, (16,))]),
+    ("geometry", "txc = tzs * torch.clamp(tx / tzs, -limx, limx)", "txc = tx",
+     [(TG.test_ewa_equals_fd_jacobian_route, (True,))]),
+    ("geometry", "[2.0 * (x * y + w * z), 1.0", "[2.0 * (x * y - w * z), 1.0",
+     [(TG.test_rotation_matches_scipy_and_is_orthonormal, ())]),
+    ("geometry", "return [-((R[0][k] * t[0] + R[1][k] * t[1]) + R[2][k] * t[2]) for k in range(3)]",
+     "return [-((R[k][0] * t[0] + R[k][1] * t[1]) + R[k][2] * t[2]) for k in range(3)]",
+     [(TG.test_view_dependent_colour_independent_route, ())]),
+    ("geometry", "raw.append(acc)", "raw.append(acc - 0.5 + 0.25)",
+     [(TG.test_view_dependent_colour_independent_route, ())]),
+    ("sh", "coef = norm * ((-1) ** am)", "coef = norm * (1)", [(TR.test_sh_matches_scipy_real_form, ())]),
+    ("sh", "math.factorial(l - am) / math.factorial(l + am)", "math.factorial(l + am) / math.factorial(l - am)",
+     [(TR.test_sh_orthonormal_by_quadrature, ())]),
+    ("composite", "power = -0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy",
+     "power = -0.5 * (a * dx * dx + c * dy * dy) + b * dx * dy",
+     [(TR.test_vectorised_equals_scalar_brute_force, (32, 3, (29, 23)))]),
+    ("composite", "blended = ps & (kidx[None, :] < kstar[:, None])", "blended = ps & (kidx[None, :] <= kstar[:, None])",
+     [(TR.test_blending_invariants, ()), (TR.test_vectorised_equals_scalar_brute_force, (31, 0, (32, 32)))]),
+    ("composite", "Te = torch.cat([ones, Ti[:, :-1]], dim=1) if nc else Ti", "Te = Ti",
+     [(TR.test_two_gaussians_depth_order, ())]),
+    ("composite", "order = np.lexsort((vis, proj[\"depth_bits\"][vis]))", "order = np.lexsort((proj[\"depth_bits\"][vis], vis))",
+     [(TR.test_two_gaussians_depth_order, ())]),
+    ("loss", "C2 = 0.03 ** 2", "C2 = 0.02 ** 2", [(TL.test_ssim_textbook_and_constant_images, ())]),
+    ("loss", "C1 = 0.01 ** 2", "C1 = 0.001 ** 2", [(TL.test_ssim_textbook_and_constant_images, ())]),
+    ("loss", "sxy = blur(x * y) - mx * my", "sxy = blur(x * y)",
+     [(TL.test_ssim_identity_and_l1_value, ())]),
+    ("loss", "return F.conv2d(img[None], w2, padding=WIN // 2, groups=img.shape[0])[0]",
+     "return F.conv2d(F.pad(img[None], (5, 5, 5, 5), mode='replicate'), w2, groups=img.shape[0])[0]",
+     [(TL.test_blur_matches_scipy_gaussian_filter, ())]),
+    ("grad", 'out = r["C"] + r["T_final"][None, :] * bg[:, None]', 'out = r["C"] + r["T_final"].detach()[None, :] * bg[:, None]',
+     [(TL.test_param_grads_finite_differences, (41, 3, (0.3, 0.1, 0.6)))]),
+    ("composite", "alpha2 = torch.clamp(o2[None, :] * torch.exp(power2), max=alpha_max)",
+     "alpha2 = torch.clamp(o2[None, :].detach() * torch.exp(power2), max=alpha_max)",
+     [(TL.test_param_grads_finite_differences, (42, 1, (0.0, 0.0, 0.0)))]),
+    ("adam", "bc2 = 1.0 - b2 ** k", "bc2 = 1.0 - b1 ** k", [(TL.test_adam_matches_torch_fp64, ())]),
+    ("adam", "return np.where(cnt > 0, s / np.maximum(cnt, 1), vs.mean())", "return np.where(cnt > 0, s, vs.mean())",
+     [(TL.test_adam_view_factor_and_first_step_closed_form, ())]),
+]
+
+
+@pytest.mark.parametrize("modname,old,new,tests", MUTATIONS, ids=[f"{m[0]}:{i}" for i, m in enumerate(MUTATIONS)])
+def test_planted_mistake_is_caught(modname, old, new, tests):
+    # the unmutated oracle passes the same pins
+    assert not _fails(tests)
+    with _mutated(modname, old, new):
+        assert _fails(tests), f"planted mistake not caught: {new!r}"
