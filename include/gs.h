@@ -1,0 +1,199 @@
+/*
+ * gs.h - C ABI of the MI355X (gfx950) differentiable tile rasterizer and optimizer
+ * step: the per-iteration hot path of progressive 3D Gaussian Splatting
+ * (Gaussian On-the-Fly Splatting; Sec. III Eq. 1-2, Sec. IV-D Eq. 6-8,
+ * Sec. IV-E, Sec. V-A implementation details).
+ *
+ * Every call is stream-ordered and asynchronous unless stated otherwise, takes
+ * plain pointers and sizes, and returns a gs_status; nothing aborts or throws
+ * across this boundary.  Argument checks happen on the host before any work is
+ * queued; a failed check queues nothing.  The caller owns every parameter,
+ * gradient, optimizer-state, image and target buffer (device memory, fp32 unless
+ * stated).  A context owns only its intermediate buffers (per-view projections,
+ * sort buffers, per-pixel forward state, 2D gradients) and grows them as needed.
+ * One context serves one stream at a time; calls on one context must not
+ * overlap.  A context keeps the views, sizes and buffers of its last
+ * gs_preprocess; gs_bin_sort, gs_render_fwd, gs_loss, gs_render_bwd and
+ * gs_adam_step operate on that state and must follow it in this order.
+ *
+ * Gaussian parameters: one fp32 device array of n_params(D) rows by `stride`
+ * columns (row-major, column g is Gaussian g, stride >= n), D = SH degree 0..3:
+ *   rows 0..2   mean (world)              rows 3..5   log-scale
+ *   rows 6..9   quaternion (w, x, y, z), any norm > 0
+ *   row  10     opacity logit             rows 11..   SH coefficient k, channel c
+ *                                                     at row 11 + 3k + c
+ *   n_params(D) = 11 + 3 (D+1)^2   (14 at D = 0, 59 at D = 3)
+ * Gradients and Adam moments use the same layout.
+ *
+ * Images: fp32, all views concatenated; view v occupies floats
+ * [3 pix_off[v], 3 pix_off[v+1]) laid out [3][height][width] (planar RGB), where
+ * pix_off is the exclusive prefix sum of width*height over views (gs_layout).
+ * Pixel (i, j) has its centre at (i + 1/2, j + 1/2).
+ */
+#ifndef GS_H_
+#define GS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_ABI_VERSION 1
+#define GS_MAX_VIEWS 64
+#define GS_MAX_SH_DEGREE 3
+#define GS_MAX_IMAGE_SIDE 16384
+
+typedef enum gs_status {
+  GS_OK = 0,
+  GS_ERR_INVALID = -1,      /* bad argument (null, out of range, misaligned) */
+  GS_ERR_CAPACITY = -2,     /* a size limit of the library would be exceeded */
+  GS_ERR_HIP = -3,          /* a HIP runtime call failed; see gs_last_error */
+  GS_ERR_UNSUPPORTED = -4,  /* valid but not implemented (e.g. tile size) */
+  GS_ERR_STATE = -5         /* call out of order (e.g. render before preprocess) */
+} gs_status;
+
+typedef struct gs_ctx gs_ctx;
+typedef void* gs_stream; /* a hipStream_t; NULL is the null stream */
+
+/* A pinhole view.  World->camera: x_cam = R x_world + t, R row-major; camera axes
+ * x right, y down, z forward.  Intrinsics in pixels.  bg: background colour. */
+typedef struct gs_camera {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float bg[3];
+} gs_camera;
+
+/* Adam parameter groups (bits of gs_adam_step's group_mask). */
+enum { GS_GROUP_MEAN = 0, GS_GROUP_SCALE = 1, GS_GROUP_ROT = 2, GS_GROUP_OPACITY = 3,
+       GS_GROUP_SH_DC = 4, GS_GROUP_SH_REST = 5, GS_N_GROUPS = 6 };
+
+/* Context buffers readable with gs_copy_buffer (for inspection and tests). */
+enum {
+  GS_BUF_RECORDS = 0,   /* per (view, Gaussian) record, 48 B: double u, double w (pixel-space
+                           centre), float a, b, c (conic), o (opacity), tau (cutoff exponent),
+                           r, g, b (colour); index v*n + g; only visible entries are defined */
+  GS_BUF_DEPTH = 1,     /* uint32 [V*n]: fp32 bit pattern of camera depth (0xffffffff if invisible) */
+  GS_BUF_TOUCHED = 2,   /* uint32 [V*n]: number of tiles of the tile rect (0 = invisible) */
+  GS_BUF_TILE_RECT = 3, /* uint16 [V*n][4]: tx0, tx1, ty0, ty1 (inclusive) */
+  GS_BUF_KEYS = 4,      /* uint64 [K]: sorted keys (global tile << 32) | depth bits */
+  GS_BUF_VALUES = 5,    /* uint32 [K]: Gaussian index of each sorted pair */
+  GS_BUF_RANGES = 6,    /* uint32 [tiles][2]: [start, end) of each tile in the sorted pairs */
+  GS_BUF_T_FINAL = 7,   /* float  [P]: final transmittance per pixel */
+  GS_BUF_N_CONTRIB = 8, /* uint32 [P]: Gaussians blended per pixel */
+  GS_BUF_LAST = 9,      /* uint32 [P]: 1 + position (within its tile's list) of the last
+                           blended Gaussian, 0 if none */
+  GS_BUF_GRAD2D = 10,   /* float  [V*n][9]: dL/d(u, w, a, b, c, o, r, g, b) per (view, Gaussian) */
+  GS_BUF_PAIR_VIEW = 11,/* uint32 [K]: view of each sorted pair */
+  GS_N_BUFS = 12
+};
+
+/* Kernel ids for gs_profile_read. */
+enum {
+  GS_K_PREPROCESS = 0, GS_K_DEPTH_SORT = 1, GS_K_SCAN = 2, GS_K_EMIT = 3, GS_K_TILE_SORT = 4,
+  GS_K_RANGES = 5, GS_K_RENDER_FWD = 6, GS_K_LOSS = 7, GS_K_RENDER_BWD = 8,
+  GS_K_PREPROCESS_BWD = 9, GS_K_ADAM = 10, GS_K_ZERO = 11, GS_N_KERNELS = 12
+};
+
+int32_t gs_abi_version(void);
+
+/* Create a context bound to HIP device `device`.  Allocates nothing large.
+ * Returns GS_ERR_HIP if the device cannot be used.  *out is NULL on failure. */
+gs_status gs_create(gs_ctx** out, int32_t device);
+/* Destroy a context after its stream has drained; NULL is a no-op. */
+void gs_destroy(gs_ctx* ctx);
+/* Message of the last failed call on ctx ("" if none); valid until the next call. */
+const char* gs_last_error(const gs_ctx* ctx);
+
+/* Host-only: pixel and tile offsets of each view.  pix_off and tile_off receive
+ * n_views + 1 entries (exclusive prefix sums of width*height and of
+ * ceil(width/tile)*ceil(height/tile)).  Either may be NULL. */
+gs_status gs_layout(const gs_camera* cams, int32_t n_views, int32_t tile, int64_t* pix_off,
+                    int64_t* tile_off);
+
+/* Sec. III Eq. 1 and the EWA projection of the original 3DGS (Sec. V-A): for each
+ * view of `cams` (host array, 1..GS_MAX_VIEWS views) and each Gaussian: camera
+ * transform, near cull (depth <= 0.2), pinhole projection, 2D covariance
+ * J W Sigma W^T J^T + 0.3 I (Jacobian clamped at 1.3x the half field of view),
+ * conic, extent 3 sqrt(lambda_max), tile rect (tile x tile pixels), cutoff
+ * exponent tau = max(-4.5, -ln(255 o)) and the view-dependent SH colour
+ * max(0, sum_k f_k Y_k(dir) + 1/2).  Depth, screen position, covariance and
+ * extent are evaluated in IEEE FP64 in a fixed order.  params: device, read only.
+ * tile: 16 (other sizes return GS_ERR_UNSUPPORTED).  Errors: GS_ERR_INVALID for
+ * null or misaligned params, n < 1, stride < n, sh_degree outside 0..3, n_views
+ * outside 1..GS_MAX_VIEWS, non-positive or oversized images, non-finite or
+ * non-positive focal lengths; GS_ERR_CAPACITY if n_views * n >= 2^31. */
+gs_status gs_preprocess(gs_ctx* ctx, const float* params, int32_t n, int32_t stride, int32_t sh_degree,
+                        const gs_camera* cams, int32_t n_views, int32_t tile, gs_stream stream);
+
+/* Per-tile depth-ordered lists (tile rasterizer of the original 3DGS): one pair
+ * per (visible Gaussian, tile of its rect), ordered by ascending
+ * (global tile, fp32 depth, Gaussian index), and each tile's [start, end) range.
+ * Synchronises with `stream` once to learn the pair count K, which is written to
+ * *n_pairs_out when it is not NULL.  GS_ERR_CAPACITY if K >= 2^32. */
+gs_status gs_bin_sort(gs_ctx* ctx, int64_t* n_pairs_out, gs_stream stream);
+
+/* Sec. III Eq. 2: front-to-back alpha blending of every pixel of every view.  Per
+ * pixel, in list order: skip Gaussians whose exponent is > 0 or < tau,
+ * alpha = min(0.99, o exp(exponent)), stop before blending once the
+ * transmittance would fall below 1e-4.  Writes the image (layout above) to
+ * `color` (device, 3P floats) and keeps the final transmittance, blend count and
+ * last position per pixel in the context for gs_render_bwd. */
+gs_status gs_render_fwd(gs_ctx* ctx, float* color, gs_stream stream);
+
+/* Eq. 10 image terms: per view, w_l1 * mean|C - T| + w_dssim * (1 - SSIM(C, T))
+ * with SSIM over a normalised 11x11 Gaussian window (sigma 1.5, zero padding),
+ * C1 = 0.01^2, C2 = 0.03^2, averaged over pixels and channels.  color, target:
+ * device images (layout above).  loss_out: device, n_views doubles (per-view
+ * loss), may be NULL.  dL_dcolor: device image receiving dL/dcolor of the sum of
+ * the per-view losses (sign(0) = 0 for the L1 term). */
+gs_status gs_loss(gs_ctx* ctx, const float* color, const float* target, float w_l1, float w_dssim,
+                  double* loss_out, float* dL_dcolor, gs_stream stream);
+
+/* Reverse-order backward of gs_render_fwd and gs_preprocess (Sec. IV-E): per
+ * tile, pixels walk their lists back to front; per-Gaussian partial gradients
+ * are reduced across each wavefront and workgroup before one global atomic per
+ * (tile, Gaussian, component) ("splatting-based" accumulation), then one thread
+ * per Gaussian applies the chain rule through projection, covariance, activations
+ * and SH over all views.  params: the same device array as in gs_preprocess,
+ * unchanged since.  dL_dcolor: device image.  grad: device, parameter layout;
+ * overwritten (accumulate = 0) or added to (accumulate = 1).  A capped alpha and a
+ * colour clamped at 0 have zero derivative. */
+gs_status gs_render_bwd(gs_ctx* ctx, const float* params, const float* dL_dcolor, float* grad,
+                        int32_t accumulate, gs_stream stream);
+
+/* Adam step of the original 3DGS (Sec. V-A) with a learning rate per view
+ * (Sec. IV-D, Eq. 6-8).  Dense over all n Gaussians: per element
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2, k = step[i] + 1,
+ * p -= lr (m / (1 - b1^k)) / (sqrt(v / (1 - b2^k)) + eps); step[i] += 1.
+ * lr = lr_group[group of the row] (host, GS_N_GROUPS floats), multiplied for the
+ * groups in group_mask by the mean of view_lr_scale[v] (host, n_views floats)
+ * over the views of the last gs_preprocess in which Gaussian i is visible (over
+ * all views when none).  n_views = 0 or view_lr_scale = NULL: no view factor.
+ * params, grad, m, v: device, parameter layout; step: device uint32 [n].  When
+ * n_views > 0 the context's last gs_preprocess must have used the same n. */
+gs_status gs_adam_step(gs_ctx* ctx, float* params, const float* grad, float* m, float* v, uint32_t* step,
+                       int32_t n, int32_t stride, int32_t sh_degree, const float* lr_group,
+                       const float* view_lr_scale, int32_t n_views, uint32_t group_mask, float beta1,
+                       float beta2, float eps, gs_stream stream);
+
+/* Size in bytes of a context buffer (GS_BUF_*) for the current state. */
+gs_status gs_buffer_size(const gs_ctx* ctx, int32_t which, size_t* bytes);
+/* Stream-ordered copy of a context buffer into device memory `dst` of `bytes`
+ * bytes (must equal gs_buffer_size).  GS_BUF_KEYS is composed on the fly. */
+gs_status gs_copy_buffer(gs_ctx* ctx, int32_t which, void* dst, size_t bytes, gs_stream stream);
+
+/* Per-kernel timing with HIP events on the launching stream.  enable = 1 starts
+ * recording (and clears earlier records), 0 stops.  gs_profile_read synchronises
+ * the device and returns the launch count and summed duration (ms) of kernel id
+ * `kernel` (GS_K_*) since the last enable. */
+gs_status gs_profile_enable(gs_ctx* ctx, int32_t enable);
+gs_status gs_profile_read(gs_ctx* ctx, int32_t kernel, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GS_H_ */

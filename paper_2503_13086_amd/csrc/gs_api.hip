@@ -1,0 +1,516 @@
+// C ABI of the rasterizer hot path: argument checks, context state, buffer growth,
+// launch sequencing and event timing.  Declarations and contracts: include/gs.h.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "gs_internal.h"
+
+using namespace gsk;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  template <class T>
+  T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+enum Stage { kNone = 0, kProjected = 1, kBinned = 2, kRendered = 3 };
+
+}  // namespace
+
+struct gs_ctx {
+  int device = 0;
+  std::string err;
+  int stage = kNone;
+  int n = 0, stride = 0, D = 0, V = 0;
+  int n_tiles = 0;
+  int64_t P = 0;
+  uint64_t K = 0;
+  std::vector<ViewDev> hviews;
+  int depth_in_b = 0, pairs_in_b = 0;
+  DevBuf views, rec, depth, touched, rect;
+  DevBuf dkey[2], dval[2], offsets, blocksums, total, hist, digit_tot;
+  DevBuf pkey[2], pval[2], ranges;
+  DevBuf tfinal, ncontrib, last, grad2d, lossp, aux;
+  ViewDev* h_views = nullptr;
+  unsigned long long* h_total = nullptr;
+  hipEvent_t views_ev = nullptr;
+  bool views_ev_pending = false;
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[GS_N_KERNELS];
+  std::vector<hipEvent_t> pool;
+  size_t pool_next = 0;
+};
+
+namespace {
+
+gs_status fail(gs_ctx* c, gs_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+gs_status hip_fail(gs_ctx* c, const char* what, hipError_t e) {
+  return fail(c, GS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define GS_HIP(c, expr)                              \
+  do {                                               \
+    hipError_t e_ = (expr);                          \
+    if (e_ != hipSuccess) return hip_fail(c, #expr, e_); \
+  } while (0)
+
+gs_status ensure(gs_ctx* c, DevBuf& b, size_t bytes, hipStream_t s) {
+  if (bytes <= b.cap && b.p) return GS_OK;
+  if (b.p) {
+    GS_HIP(c, hipStreamSynchronize(s));
+    GS_HIP(c, hipFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t want = bytes + bytes / 4 + 256;
+  GS_HIP(c, hipMalloc(&b.p, want));
+  b.cap = want;
+  return GS_OK;
+}
+
+hipEvent_t next_event(gs_ctx* c) {
+  if (c->pool_next == c->pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->pool.push_back(e);
+  }
+  return c->pool[c->pool_next++];
+}
+
+struct Prof {
+  gs_ctx* c;
+  int id;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Prof(gs_ctx* c_, int id_, hipStream_t s_) : c(c_), id(id_), s(s_) {
+    if (c->prof && (a = next_event(c))) (void)hipEventRecord(a, s);
+  }
+  ~Prof() {
+    if (!c->prof || !a) return;
+    hipEvent_t b = next_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    c->ev[id].push_back({a, b});
+  }
+};
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int ceil_log2(uint64_t x) {
+  int b = 0;
+  while ((1ull << b) < x) ++b;
+  return b;
+}
+
+gs_status check_views(gs_ctx* c, const gs_camera* cams, int n_views, int tile) {
+  if (!cams) return fail(c, GS_ERR_INVALID, "cams is NULL");
+  if (n_views < 1 || n_views > GS_MAX_VIEWS) return fail(c, GS_ERR_INVALID, "n_views must be in 1..64");
+  if (tile != kTile) return fail(c, GS_ERR_UNSUPPORTED, "only 16x16 tiles are implemented");
+  for (int v = 0; v < n_views; ++v) {
+    const gs_camera& k = cams[v];
+    if (k.width < 1 || k.height < 1 || k.width > GS_MAX_IMAGE_SIDE || k.height > GS_MAX_IMAGE_SIDE)
+      return fail(c, GS_ERR_INVALID, "image size out of range in view " + std::to_string(v));
+    if (!(std::isfinite(k.fx) && std::isfinite(k.fy) && k.fx > 0.0f && k.fy > 0.0f))
+      return fail(c, GS_ERR_INVALID, "focal lengths must be finite and positive in view " + std::to_string(v));
+    for (int i = 0; i < 9; ++i)
+      if (!std::isfinite(k.R[i])) return fail(c, GS_ERR_INVALID, "non-finite rotation in view " + std::to_string(v));
+    for (int i = 0; i < 3; ++i)
+      if (!std::isfinite(k.t[i]) || !std::isfinite(k.bg[i]))
+        return fail(c, GS_ERR_INVALID, "non-finite translation or background in view " + std::to_string(v));
+    if (!std::isfinite(k.cx) || !std::isfinite(k.cy))
+      return fail(c, GS_ERR_INVALID, "non-finite principal point in view " + std::to_string(v));
+  }
+  return GS_OK;
+}
+
+void build_views(const gs_camera* cams, int n_views, std::vector<ViewDev>& out, int* n_tiles, int64_t* P) {
+  out.resize(n_views);
+  int64_t toff = 0, poff = 0;
+  for (int v = 0; v < n_views; ++v) {
+    ViewDev& d = out[v];
+    const gs_camera& k = cams[v];
+    std::memcpy(d.R, k.R, sizeof(d.R));
+    std::memcpy(d.t, k.t, sizeof(d.t));
+    d.fx = k.fx; d.fy = k.fy; d.cx = k.cx; d.cy = k.cy;
+    d.W = k.width; d.H = k.height;
+    std::memcpy(d.bg, k.bg, sizeof(d.bg));
+    d.tiles_x = (k.width + kTile - 1) / kTile;
+    d.tiles_y = (k.height + kTile - 1) / kTile;
+    d.tile_off = (int32_t)toff;
+    d.pix_off = poff;
+    toff += (int64_t)d.tiles_x * d.tiles_y;
+    poff += (int64_t)k.width * k.height;
+  }
+  *n_tiles = (int)toff;
+  *P = poff;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t gs_abi_version(void) { return GS_ABI_VERSION; }
+
+gs_status gs_create(gs_ctx** out, int32_t device) {
+  if (!out) return GS_ERR_INVALID;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return GS_ERR_HIP;
+  if (hipSetDevice(device) != hipSuccess) return GS_ERR_HIP;
+  gs_ctx* c = new gs_ctx();
+  c->device = device;
+  if (hipHostMalloc((void**)&c->h_views, sizeof(ViewDev) * GS_MAX_VIEWS, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_total, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&c->views_ev, hipEventDisableTiming) != hipSuccess) {
+    gs_destroy(c);
+    return GS_ERR_HIP;
+  }
+  *out = c;
+  return GS_OK;
+}
+
+void gs_destroy(gs_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  DevBuf* bufs[] = {&c->views, &c->rec, &c->depth, &c->touched, &c->rect, &c->dkey[0], &c->dkey[1], &c->dval[0],
+                    &c->dval[1], &c->offsets, &c->blocksums, &c->total, &c->hist, &c->digit_tot, &c->pkey[0],
+                    &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->tfinal, &c->ncontrib, &c->last,
+                    &c->grad2d, &c->lossp, &c->aux};
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  if (c->h_views) (void)hipHostFree(c->h_views);
+  if (c->h_total) (void)hipHostFree(c->h_total);
+  if (c->views_ev) (void)hipEventDestroy(c->views_ev);
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* gs_last_error(const gs_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+gs_status gs_layout(const gs_camera* cams, int32_t n_views, int32_t tile, int64_t* pix_off, int64_t* tile_off) {
+  if (!cams || n_views < 1 || n_views > GS_MAX_VIEWS || tile < 1) return GS_ERR_INVALID;
+  int64_t p = 0, t = 0;
+  for (int v = 0; v <= n_views; ++v) {
+    if (pix_off) pix_off[v] = p;
+    if (tile_off) tile_off[v] = t;
+    if (v == n_views) break;
+    if (cams[v].width < 1 || cams[v].height < 1) return GS_ERR_INVALID;
+    p += (int64_t)cams[v].width * cams[v].height;
+    t += (int64_t)((cams[v].width + tile - 1) / tile) * ((cams[v].height + tile - 1) / tile);
+  }
+  return GS_OK;
+}
+
+gs_status gs_preprocess(gs_ctx* c, const float* params, int32_t n, int32_t stride, int32_t sh_degree,
+                        const gs_camera* cams, int32_t n_views, int32_t tile, gs_stream stream) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (!params || !aligned(params, 4)) return fail(c, GS_ERR_INVALID, "params is NULL or misaligned");
+  if (n < 1 || stride < n) return fail(c, GS_ERR_INVALID, "need n >= 1 and stride >= n");
+  if (sh_degree < 0 || sh_degree > GS_MAX_SH_DEGREE) return fail(c, GS_ERR_INVALID, "sh_degree must be 0..3");
+  gs_status st = check_views(c, cams, n_views, tile);
+  if (st != GS_OK) return st;
+  if ((int64_t)n_views * n >= (1ll << 31)) return fail(c, GS_ERR_CAPACITY, "n_views * n must be < 2^31");
+  hipStream_t s = (hipStream_t)stream;
+  GS_HIP(c, hipSetDevice(c->device));
+  std::vector<ViewDev> hv;
+  int n_tiles = 0;
+  int64_t P = 0;
+  build_views(cams, n_views, hv, &n_tiles, &P);
+  const size_t NV = (size_t)n_views * n;
+  if ((st = ensure(c, c->views, sizeof(ViewDev) * GS_MAX_VIEWS, s)) != GS_OK) return st;
+  if ((st = ensure(c, c->rec, NV * sizeof(Record), s)) != GS_OK) return st;
+  if ((st = ensure(c, c->depth, NV * 4, s)) != GS_OK) return st;
+  if ((st = ensure(c, c->touched, NV * 4, s)) != GS_OK) return st;
+  if ((st = ensure(c, c->rect, NV * 8, s)) != GS_OK) return st;
+  if (c->views_ev_pending) GS_HIP(c, hipEventSynchronize(c->views_ev));
+  std::memcpy(c->h_views, hv.data(), sizeof(ViewDev) * n_views);
+  GS_HIP(c, hipMemcpyAsync(c->views.p, c->h_views, sizeof(ViewDev) * n_views, hipMemcpyHostToDevice, s));
+  GS_HIP(c, hipEventRecord(c->views_ev, s));
+  c->views_ev_pending = true;
+  {
+    Prof pr(c, GS_K_PREPROCESS, s);
+    GS_HIP(c, launch_preprocess(params, n, stride, sh_degree, c->views.as<ViewDev>(), n_views, c->rec.as<Record>(),
+                                c->depth.as<uint32_t>(), c->touched.as<uint32_t>(), c->rect.as<ushort4>(), s));
+  }
+  c->n = n; c->stride = stride; c->D = sh_degree; c->V = n_views;
+  c->hviews = hv; c->n_tiles = n_tiles; c->P = P; c->K = 0;
+  c->stage = kProjected;
+  return GS_OK;
+}
+
+gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (c->stage < kProjected) return fail(c, GS_ERR_STATE, "gs_bin_sort needs a preceding gs_preprocess");
+  hipStream_t s = (hipStream_t)stream;
+  GS_HIP(c, hipSetDevice(c->device));
+  const size_t NV = (size_t)c->V * c->n;
+  gs_status st;
+  for (int i = 0; i < 2; ++i) {
+    if ((st = ensure(c, c->dkey[i], NV * 4, s)) != GS_OK) return st;
+    if ((st = ensure(c, c->dval[i], NV * 4, s)) != GS_OK) return st;
+  }
+  if ((st = ensure(c, c->offsets, NV * 4, s)) != GS_OK) return st;
+  if ((st = ensure(c, c->blocksums, scan_block_words(NV) * 4, s)) != GS_OK) return st;
+  if ((st = ensure(c, c->total, 8, s)) != GS_OK) return st;
+  if ((st = ensure(c, c->hist, sort_hist_words(NV) * 4, s)) != GS_OK) return st;
+  if ((st = ensure(c, c->digit_tot, 256 * 4, s)) != GS_OK) return st;
+  // depth order of all (view, Gaussian) entries (invisible ones carry the largest key)
+  {
+    Prof pr(c, GS_K_DEPTH_SORT, s);
+    GS_HIP(c, hipMemcpyAsync(c->dkey[0].p, c->depth.p, NV * 4, hipMemcpyDeviceToDevice, s));
+    GS_HIP(c, launch_iota(c->dval[0].as<uint32_t>(), NV, s));
+    SortScratch sc{c->hist.as<uint32_t>(), c->digit_tot.as<uint32_t>()};
+    GS_HIP(c, radix_sort_pairs(c->dkey[0].as<uint32_t>(), c->dval[0].as<uint32_t>(), c->dkey[1].as<uint32_t>(),
+                               c->dval[1].as<uint32_t>(), NV, 32, sc, &c->depth_in_b, s));
+  }
+  const uint32_t* order = c->dval[c->depth_in_b].as<uint32_t>();
+  {
+    Prof pr(c, GS_K_SCAN, s);
+    GS_HIP(c, launch_scan_touched(order, c->touched.as<uint32_t>(), NV, c->offsets.as<uint32_t>(),
+                                  c->blocksums.as<uint32_t>(), c->total.as<unsigned long long>(), s));
+  }
+  GS_HIP(c, hipMemcpyAsync(c->h_total, c->total.p, 8, hipMemcpyDeviceToHost, s));
+  GS_HIP(c, hipStreamSynchronize(s));
+  const uint64_t K = *c->h_total;
+  if (K >= (1ull << 32)) return fail(c, GS_ERR_CAPACITY, "more than 2^32 - 1 (tile, Gaussian) pairs");
+  for (int i = 0; i < 2; ++i) {
+    if ((st = ensure(c, c->pkey[i], K * 4 + 4, s)) != GS_OK) return st;
+    if ((st = ensure(c, c->pval[i], K * 4 + 4, s)) != GS_OK) return st;
+  }
+  if ((st = ensure(c, c->hist, sort_hist_words(K > NV ? K : NV) * 4, s)) != GS_OK) return st;
+  if ((st = ensure(c, c->ranges, (size_t)c->n_tiles * 8, s)) != GS_OK) return st;
+  {
+    Prof pr(c, GS_K_EMIT, s);
+    GS_HIP(c, launch_emit_pairs(order, c->touched.as<uint32_t>(), c->offsets.as<uint32_t>(), c->rect.as<ushort4>(), NV,
+                                c->n, c->views.as<ViewDev>(), c->V, (size_t)K, c->pkey[0].as<uint32_t>(),
+                                c->pval[0].as<uint32_t>(), s));
+  }
+  {
+    Prof pr(c, GS_K_TILE_SORT, s);
+    SortScratch sc{c->hist.as<uint32_t>(), c->digit_tot.as<uint32_t>()};
+    const int bits = ceil_log2((uint64_t)c->n_tiles) < 1 ? 1 : ceil_log2((uint64_t)c->n_tiles);
+    GS_HIP(c, radix_sort_pairs(c->pkey[0].as<uint32_t>(), c->pval[0].as<uint32_t>(), c->pkey[1].as<uint32_t>(),
+                               c->pval[1].as<uint32_t>(), K, bits, sc, &c->pairs_in_b, s));
+  }
+  {
+    Prof pr(c, GS_K_RANGES, s);
+    GS_HIP(c, launch_ranges(c->pkey[c->pairs_in_b].as<uint32_t>(), K, c->ranges.as<uint2>(), c->n_tiles, s));
+  }
+  c->K = K;
+  c->stage = kBinned;
+  if (n_pairs_out) *n_pairs_out = (int64_t)K;
+  return GS_OK;
+}
+
+gs_status gs_render_fwd(gs_ctx* c, float* color, gs_stream stream) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (c->stage < kBinned) return fail(c, GS_ERR_STATE, "gs_render_fwd needs a preceding gs_bin_sort");
+  if (!color || !aligned(color, 4)) return fail(c, GS_ERR_INVALID, "color is NULL or misaligned");
+  hipStream_t s = (hipStream_t)stream;
+  GS_HIP(c, hipSetDevice(c->device));
+  gs_status st;
+  if ((st = ensure(c, c->tfinal, (size_t)c->P * 4, s)) != GS_OK) return st;
+  if ((st = ensure(c, c->ncontrib, (size_t)c->P * 4, s)) != GS_OK) return st;
+  if ((st = ensure(c, c->last, (size_t)c->P * 4, s)) != GS_OK) return st;
+  {
+    Prof pr(c, GS_K_RENDER_FWD, s);
+    GS_HIP(c, launch_render_fwd(c->views.as<ViewDev>(), c->V, c->n_tiles, c->ranges.as<uint2>(),
+                                c->pval[c->pairs_in_b].as<uint32_t>(), c->rec.as<Record>(),
+                                (uint32_t)((size_t)c->V * c->n), color, c->tfinal.as<float>(),
+                                c->ncontrib.as<uint32_t>(), c->last.as<uint32_t>(), s));
+  }
+  c->stage = kRendered;
+  return GS_OK;
+}
+
+gs_status gs_loss(gs_ctx* c, const float* color, const float* target, float w_l1, float w_dssim, double* loss_out,
+                  float* dL_dcolor, gs_stream stream) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (c->stage < kProjected) return fail(c, GS_ERR_STATE, "gs_loss needs the views of a preceding gs_preprocess");
+  if (!color || !target || !dL_dcolor || !aligned(color, 4) || !aligned(target, 4) || !aligned(dL_dcolor, 4))
+    return fail(c, GS_ERR_INVALID, "color, target and dL_dcolor must be non-NULL and aligned");
+  if (loss_out && !aligned(loss_out, 8)) return fail(c, GS_ERR_INVALID, "loss_out misaligned");
+  if (!std::isfinite(w_l1) || !std::isfinite(w_dssim)) return fail(c, GS_ERR_INVALID, "non-finite loss weight");
+  hipStream_t s = (hipStream_t)stream;
+  GS_HIP(c, hipSetDevice(c->device));
+  gs_status st;
+  if ((st = ensure(c, c->lossp, (size_t)c->n_tiles * 16, s)) != GS_OK) return st;
+  if (w_dssim != 0.0f && (st = ensure(c, c->aux, (size_t)c->P * 9 * 4, s)) != GS_OK) return st;
+  Prof pr(c, GS_K_LOSS, s);
+  GS_HIP(c, launch_loss_dev(c->views.as<ViewDev>(), c->V, c->n_tiles, color, target, w_l1, w_dssim,
+                            c->lossp.as<double>(), c->aux.as<float>(), loss_out, dL_dcolor, s));
+  return GS_OK;
+}
+
+gs_status gs_render_bwd(gs_ctx* c, const float* params, const float* dL_dcolor, float* grad, int32_t accumulate,
+                        gs_stream stream) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (c->stage < kRendered) return fail(c, GS_ERR_STATE, "gs_render_bwd needs a preceding gs_render_fwd");
+  if (!params || !dL_dcolor || !grad || !aligned(params, 4) || !aligned(dL_dcolor, 4) || !aligned(grad, 4))
+    return fail(c, GS_ERR_INVALID, "params, dL_dcolor and grad must be non-NULL and aligned");
+  hipStream_t s = (hipStream_t)stream;
+  GS_HIP(c, hipSetDevice(c->device));
+  const size_t NV = (size_t)c->V * c->n;
+  gs_status st;
+  if ((st = ensure(c, c->grad2d, NV * kGrad2D * 4, s)) != GS_OK) return st;
+  {
+    Prof pr(c, GS_K_ZERO, s);
+    GS_HIP(c, launch_fill_u32(c->grad2d.as<uint32_t>(), 0u, NV * kGrad2D, s));
+  }
+  {
+    Prof pr(c, GS_K_RENDER_BWD, s);
+    GS_HIP(c, launch_render_bwd(c->views.as<ViewDev>(), c->V, c->n_tiles, c->ranges.as<uint2>(),
+                                c->pval[c->pairs_in_b].as<uint32_t>(), c->rec.as<Record>(), (uint32_t)NV,
+                                c->tfinal.as<float>(), c->last.as<uint32_t>(), dL_dcolor, c->grad2d.as<float>(), s));
+  }
+  {
+    Prof pr(c, GS_K_PREPROCESS_BWD, s);
+    GS_HIP(c, launch_preprocess_bwd(params, c->n, c->stride, c->D, c->views.as<ViewDev>(), c->V,
+                                    c->touched.as<uint32_t>(), c->grad2d.as<float>(), grad, accumulate ? 1 : 0, s));
+  }
+  return GS_OK;
+}
+
+gs_status gs_adam_step(gs_ctx* c, float* params, const float* grad, float* m, float* v, uint32_t* step, int32_t n,
+                       int32_t stride, int32_t sh_degree, const float* lr_group, const float* view_lr_scale,
+                       int32_t n_views, uint32_t group_mask, float beta1, float beta2, float eps, gs_stream stream) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (!params || !grad || !m || !v || !step || !lr_group)
+    return fail(c, GS_ERR_INVALID, "params, grad, m, v, step and lr_group must be non-NULL");
+  if (!aligned(params, 4) || !aligned(grad, 4) || !aligned(m, 4) || !aligned(v, 4) || !aligned(step, 4))
+    return fail(c, GS_ERR_INVALID, "misaligned device pointer");
+  if (n < 1 || stride < n) return fail(c, GS_ERR_INVALID, "need n >= 1 and stride >= n");
+  if (sh_degree < 0 || sh_degree > GS_MAX_SH_DEGREE) return fail(c, GS_ERR_INVALID, "sh_degree must be 0..3");
+  if (n_views < 0 || n_views > GS_MAX_VIEWS) return fail(c, GS_ERR_INVALID, "n_views must be in 0..64");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps >= 0.0f && std::isfinite(eps)))
+    return fail(c, GS_ERR_INVALID, "need 0 <= beta < 1 and finite eps >= 0");
+  AdamArgs a{};
+  for (int i = 0; i < GS_N_GROUPS; ++i) {
+    if (!std::isfinite(lr_group[i])) return fail(c, GS_ERR_INVALID, "non-finite learning rate");
+    a.lr[i] = lr_group[i];
+  }
+  a.n_views = 0;
+  if (n_views > 0 && view_lr_scale) {
+    if (c->stage < kProjected || c->n != n || c->V != n_views)
+      return fail(c, GS_ERR_STATE, "view factors need the last gs_preprocess to match n and n_views");
+    for (int i = 0; i < n_views; ++i) {
+      if (!std::isfinite(view_lr_scale[i])) return fail(c, GS_ERR_INVALID, "non-finite view scale");
+      a.scale[i] = view_lr_scale[i];
+    }
+    a.n_views = n_views;
+  }
+  a.group_mask = group_mask;
+  a.b1 = beta1; a.b2 = beta2; a.eps = eps;
+  hipStream_t s = (hipStream_t)stream;
+  GS_HIP(c, hipSetDevice(c->device));
+  Prof pr(c, GS_K_ADAM, s);
+  GS_HIP(c, launch_adam(params, grad, m, v, step, n, stride, sh_degree, a,
+                        a.n_views ? c->touched.as<uint32_t>() : nullptr, s));
+  return GS_OK;
+}
+
+gs_status gs_buffer_size(const gs_ctx* c, int32_t which, size_t* bytes) {
+  if (!c || !bytes) return GS_ERR_INVALID;
+  const size_t NV = (size_t)c->V * c->n;
+  size_t b = 0;
+  switch (which) {
+    case GS_BUF_RECORDS: b = c->stage >= kProjected ? NV * sizeof(Record) : 0; break;
+    case GS_BUF_DEPTH: case GS_BUF_TOUCHED: b = c->stage >= kProjected ? NV * 4 : 0; break;
+    case GS_BUF_TILE_RECT: b = c->stage >= kProjected ? NV * 8 : 0; break;
+    case GS_BUF_KEYS: b = c->stage >= kBinned ? c->K * 8 : 0; break;
+    case GS_BUF_VALUES: case GS_BUF_PAIR_VIEW: b = c->stage >= kBinned ? c->K * 4 : 0; break;
+    case GS_BUF_RANGES: b = c->stage >= kBinned ? (size_t)c->n_tiles * 8 : 0; break;
+    case GS_BUF_T_FINAL: case GS_BUF_N_CONTRIB: case GS_BUF_LAST: b = c->stage >= kRendered ? (size_t)c->P * 4 : 0; break;
+    case GS_BUF_GRAD2D: b = (c->stage >= kRendered && c->grad2d.p) ? NV * kGrad2D * 4 : 0; break;
+    default: return GS_ERR_INVALID;
+  }
+  *bytes = b;
+  return GS_OK;
+}
+
+gs_status gs_copy_buffer(gs_ctx* c, int32_t which, void* dst, size_t bytes, gs_stream stream) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  size_t need = 0;
+  if (gs_buffer_size(c, which, &need) != GS_OK) return fail(c, GS_ERR_INVALID, "unknown buffer id");
+  if (need == 0) return fail(c, GS_ERR_STATE, "buffer not available in the current state");
+  if (!dst || bytes != need) return fail(c, GS_ERR_INVALID, "dst is NULL or bytes != buffer size");
+  hipStream_t s = (hipStream_t)stream;
+  GS_HIP(c, hipSetDevice(c->device));
+  const void* src = nullptr;
+  switch (which) {
+    case GS_BUF_RECORDS: src = c->rec.p; break;
+    case GS_BUF_DEPTH: src = c->depth.p; break;
+    case GS_BUF_TOUCHED: src = c->touched.p; break;
+    case GS_BUF_TILE_RECT: src = c->rect.p; break;
+    case GS_BUF_RANGES: src = c->ranges.p; break;
+    case GS_BUF_T_FINAL: src = c->tfinal.p; break;
+    case GS_BUF_N_CONTRIB: src = c->ncontrib.p; break;
+    case GS_BUF_LAST: src = c->last.p; break;
+    case GS_BUF_GRAD2D: src = c->grad2d.p; break;
+    case GS_BUF_KEYS:
+      GS_HIP(c, launch_compose_keys(c->pkey[c->pairs_in_b].as<uint32_t>(), c->pval[c->pairs_in_b].as<uint32_t>(),
+                                    c->depth.as<uint32_t>(), c->K, c->n, (size_t)c->V * c->n, (unsigned long long*)dst,
+                                    nullptr, nullptr, 0, s));
+      return GS_OK;
+    case GS_BUF_VALUES:
+      GS_HIP(c, launch_compose_keys(c->pkey[c->pairs_in_b].as<uint32_t>(), c->pval[c->pairs_in_b].as<uint32_t>(),
+                                    c->depth.as<uint32_t>(), c->K, c->n, (size_t)c->V * c->n, nullptr, (uint32_t*)dst,
+                                    nullptr, 0, s));
+      return GS_OK;
+    case GS_BUF_PAIR_VIEW:
+      GS_HIP(c, launch_compose_keys(c->pkey[c->pairs_in_b].as<uint32_t>(), c->pval[c->pairs_in_b].as<uint32_t>(),
+                                    c->depth.as<uint32_t>(), c->K, c->n, (size_t)c->V * c->n, nullptr, nullptr,
+                                    (uint32_t*)dst, 1, s));
+      return GS_OK;
+    default: return fail(c, GS_ERR_INVALID, "unknown buffer id");
+  }
+  GS_HIP(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+  return GS_OK;
+}
+
+gs_status gs_profile_enable(gs_ctx* c, int32_t enable) {
+  if (!c) return GS_ERR_INVALID;
+  c->prof = enable != 0;
+  if (c->prof) {
+    for (auto& v : c->ev) v.clear();
+    c->pool_next = 0;
+  }
+  return GS_OK;
+}
+
+gs_status gs_profile_read(gs_ctx* c, int32_t kernel, int64_t* launches, double* total_ms) {
+  if (!c || kernel < 0 || kernel >= GS_N_KERNELS || !launches || !total_ms) return GS_ERR_INVALID;
+  c->err.clear();
+  GS_HIP(c, hipSetDevice(c->device));
+  GS_HIP(c, hipDeviceSynchronize());
+  double t = 0.0;
+  for (auto& pr : c->ev[kernel]) {
+    float ms = 0.0f;
+    GS_HIP(c, hipEventElapsedTime(&ms, pr.first, pr.second));
+    t += ms;
+  }
+  *launches = (int64_t)c->ev[kernel].size();
+  *total_ms = t;
+  return GS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Library-internal definitions shared by the HIP kernels and the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gs.h"
+
+namespace gsk {
+
+// Rasterizer constants of the original 3DGS configuration (the paper defers to it
+// for everything Sec. III does not state).  FP64 copies are the exact fp32 values.
+constexpr double kKappa = (double)0.3f;        // 2D low-pass dilation (px^2)
+constexpr double kZNear = (double)0.2f;        // near-plane cull depth
+constexpr double kJacClamp = (double)1.3f;     // Jacobian clamp, in half fields of view
+constexpr double kExtentSigmas = 3.0;          // extent = 3 sqrt(lambda_max)
+constexpr double kCutoffFloor = -4.5;          // exponent at the 3-sigma ellipse
+constexpr double kAlphaMinInv = 255.0;         // alpha >= 1/255 to contribute
+constexpr float kAlphaMax = 0.99f;             // alpha cap
+constexpr float kTMin = 1e-4f;                 // stop blending below this transmittance
+constexpr int kTile = 16;                      // tile edge in pixels
+constexpr int kTileThreads = kTile * kTile;    // one thread per pixel of a tile
+constexpr int kGrad2D = 9;                     // dL/d(u, w, a, b, c, o, r, g, b)
+
+// Per-view constants in device memory (one entry per view).
+struct ViewDev {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t W, H;
+  float bg[3];
+  int32_t tiles_x, tiles_y;
+  int32_t tile_off;   // global id of the view's first tile
+  int64_t pix_off;    // index of the view's first pixel in the concatenated image
+};
+
+// Projected splat of one (view, Gaussian), 48 bytes.  The screen centre is kept in
+// FP64 so a tile can take it relative to its own origin without losing the
+// sub-pixel digits an fp32 absolute coordinate would drop at 1000+ px.
+struct alignas(16) Record {
+  double u, w;
+  float a, b, c, o;
+  float tau, r, g, bl;
+};
+static_assert(sizeof(Record) == 48, "record layout");
+
+__host__ __device__ inline int n_sh(int D) { return (D + 1) * (D + 1); }
+__host__ __device__ inline int n_params(int D) { return 11 + 3 * n_sh(D); }
+
+// ---- launchers (each file defines its own) ----
+hipError_t launch_preprocess(const float* P, int n, int stride, int D, const ViewDev* views, int V,
+                             Record* rec, uint32_t* depth, uint32_t* touched, ushort4* rect,
+                             hipStream_t s);
+hipError_t launch_preprocess_bwd(const float* P, int n, int stride, int D, const ViewDev* views, int V,
+                                 const uint32_t* touched, const float* grad2d, float* grad, int accumulate,
+                                 hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
+
+// radix sort of (uint32 key, uint32 value) pairs on bits [0, bits) of the key;
+// returns which buffer (0: *_a, 1: *_b) holds the result
+struct SortScratch {
+  uint32_t* hist;      // 256 * max_blocks
+  uint32_t* digit_tot; // 256
+};
+constexpr int kSortTileItems = 4096;
+size_t sort_hist_words(size_t n);
+hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, size_t n,
+                            int bits, SortScratch scratch, int* result_in_b, hipStream_t s);
+hipError_t launch_iota(uint32_t* p, size_t n, hipStream_t s);
+
+// exclusive scan of touched[order[e]] over e, total written to *total
+size_t scan_block_words(size_t n);
+hipError_t launch_scan_touched(const uint32_t* order, const uint32_t* touched, size_t n, uint32_t* offsets,
+                               uint32_t* block_sums, unsigned long long* total, hipStream_t s);
+hipError_t launch_emit_pairs(const uint32_t* order, const uint32_t* touched, const uint32_t* offsets,
+                             const ushort4* rect, size_t n_entries, int n, const ViewDev* views, int V, size_t K,
+                             uint32_t* pair_tile, uint32_t* pair_rec, hipStream_t s);
+hipError_t launch_ranges(const uint32_t* pair_tile, size_t K, uint2* ranges, int n_tiles, hipStream_t s);
+hipError_t launch_compose_keys(const uint32_t* pair_tile, const uint32_t* pair_rec, const uint32_t* depth,
+                               size_t K, int n, size_t n_rec, unsigned long long* keys, uint32_t* values,
+                               uint32_t* views, int mode, hipStream_t s);
+
+// n_rec: number of records (V * n); record ids at or beyond it are skipped
+hipError_t launch_render_fwd(const ViewDev* views, int V, int n_tiles, const uint2* ranges, const uint32_t* pair_rec,
+                             const Record* rec, uint32_t n_rec, float* color, float* t_final, uint32_t* n_contrib,
+                             uint32_t* last, hipStream_t s);
+hipError_t launch_render_bwd(const ViewDev* views, int V, int n_tiles, const uint2* ranges, const uint32_t* pair_rec,
+                             const Record* rec, uint32_t n_rec, const float* t_final, const uint32_t* last,
+                             const float* dL_dcolor, float* grad2d, hipStream_t s);
+
+// partials: 2 doubles per tile; aux: 9 floats per pixel (SSIM only)
+hipError_t launch_loss_dev(const ViewDev* dviews, int V, int n_tiles, const float* color, const float* target,
+                           float w_l1, float w_dssim, double* partials, float* aux, double* loss_out,
+                           float* dL_dcolor, hipStream_t s);
+
+struct AdamArgs {
+  float lr[GS_N_GROUPS];
+  float scale[GS_MAX_VIEWS];
+  int n_views;          // 0: no per-view factor
+  uint32_t group_mask;  // groups that take the per-view factor
+  float b1, b2, eps;
+};
+hipError_t launch_adam(float* P, const float* G, float* M, float* Vv, uint32_t* step, int n, int stride, int D,
+                       const AdamArgs& a, const uint32_t* touched, hipStream_t s);
+
+}  // namespace gsk

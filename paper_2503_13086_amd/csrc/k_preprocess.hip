@@ -1,0 +1,466 @@
+// Per-Gaussian projection (forward) and its chain rule (backward) for gfx950.
+//
+// Forward: Sec. III Eq. 1 (covariance R S S^T R^T) and the EWA splatting of the
+// original 3DGS configuration (Sec. V-A): camera transform, near cull, pinhole
+// projection, clamped projection Jacobian, 2D covariance J W Sigma W^T J^T + 0.3 I,
+// conic, extent 3 sqrt(lambda_max), tile rect, cutoff exponent and SH colour.
+// One thread per Gaussian reads its parameters once (planar rows, coalesced) and
+// loops over the views, so parameter traffic does not grow with the view count.
+// Everything is evaluated in FP64: CDNA4 issues FP64 FMA at the non-packed FP32
+// rate and this kernel is bound by HBM traffic, so the FP64 arithmetic is hidden,
+// and depth, screen position and extent come out exactly as an IEEE FP64
+// evaluation in the same operation order (contraction is off in this file).
+//
+// Backward: one thread per Gaussian recomputes the same forward quantities per
+// view, applies the chain rule from the per-view 2D gradients
+// (u, w, a, b, c, o, rgb) to mean, log-scale, quaternion, opacity logit and SH
+// coefficients, sums the views in FP64 and writes each gradient once.
+#include "gs_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace gsk {
+namespace {
+
+// Real SH basis of the 3DGS lineage (order k = l^2 + l + m), constants from
+// sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) times the Cartesian polynomial factors.
+constexpr double kPi = 3.14159265358979323846;
+__device__ inline void sh_eval(int D, double x, double y, double z, double* Y) {
+  const double c0 = 0.5 * sqrt(1.0 / kPi);
+  Y[0] = c0;
+  if (D < 1) return;
+  const double c1 = sqrt(3.0 / (4.0 * kPi));
+  Y[1] = -c1 * y;
+  Y[2] = c1 * z;
+  Y[3] = -c1 * x;
+  if (D < 2) return;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  const double c2a = 0.5 * sqrt(15.0 / kPi), c2b = 0.25 * sqrt(5.0 / kPi), c2c = 0.25 * sqrt(15.0 / kPi);
+  Y[4] = c2a * (x * y);
+  Y[5] = -c2a * (y * z);
+  Y[6] = c2b * (2.0 * zz - xx - yy);
+  Y[7] = -c2a * (x * z);
+  Y[8] = c2c * (xx - yy);
+  if (D < 3) return;
+  const double c3a = 0.25 * sqrt(35.0 / (2.0 * kPi)), c3b = 0.5 * sqrt(105.0 / kPi);
+  const double c3c = 0.25 * sqrt(21.0 / (2.0 * kPi)), c3d = 0.25 * sqrt(7.0 / kPi);
+  const double c3e = 0.25 * sqrt(105.0 / kPi);
+  Y[9] = -c3a * y * (3.0 * xx - yy);
+  Y[10] = c3b * (x * y) * z;
+  Y[11] = -c3c * y * (4.0 * zz - xx - yy);
+  Y[12] = c3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+  Y[13] = -c3c * x * (4.0 * zz - xx - yy);
+  Y[14] = c3e * z * (xx - yy);
+  Y[15] = -c3a * x * (xx - 3.0 * yy);
+}
+
+// dL/d(direction) from dL/dY_k (gradient of each basis polynomial)
+__device__ inline void sh_grad_dir(int D, double x, double y, double z, const double* gY, double* gd) {
+  gd[0] = gd[1] = gd[2] = 0.0;
+  if (D < 1) return;
+  const double c1 = sqrt(3.0 / (4.0 * kPi));
+  gd[1] += -c1 * gY[1];
+  gd[2] += c1 * gY[2];
+  gd[0] += -c1 * gY[3];
+  if (D < 2) return;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  const double c2a = 0.5 * sqrt(15.0 / kPi), c2b = 0.25 * sqrt(5.0 / kPi), c2c = 0.25 * sqrt(15.0 / kPi);
+  gd[0] += c2a * y * gY[4];            gd[1] += c2a * x * gY[4];
+  gd[1] += -c2a * z * gY[5];           gd[2] += -c2a * y * gY[5];
+  gd[0] += -2.0 * c2b * x * gY[6];     gd[1] += -2.0 * c2b * y * gY[6];   gd[2] += 4.0 * c2b * z * gY[6];
+  gd[0] += -c2a * z * gY[7];           gd[2] += -c2a * x * gY[7];
+  gd[0] += 2.0 * c2c * x * gY[8];      gd[1] += -2.0 * c2c * y * gY[8];
+  if (D < 3) return;
+  const double c3a = 0.25 * sqrt(35.0 / (2.0 * kPi)), c3b = 0.5 * sqrt(105.0 / kPi);
+  const double c3c = 0.25 * sqrt(21.0 / (2.0 * kPi)), c3d = 0.25 * sqrt(7.0 / kPi);
+  const double c3e = 0.25 * sqrt(105.0 / kPi);
+  gd[0] += -c3a * 6.0 * x * y * gY[9];
+  gd[1] += -c3a * 3.0 * (xx - yy) * gY[9];
+  gd[0] += c3b * y * z * gY[10];
+  gd[1] += c3b * x * z * gY[10];
+  gd[2] += c3b * x * y * gY[10];
+  gd[0] += -c3c * (-2.0 * x * y) * gY[11];
+  gd[1] += -c3c * (4.0 * zz - xx - 3.0 * yy) * gY[11];
+  gd[2] += -c3c * (8.0 * y * z) * gY[11];
+  gd[0] += c3d * (-6.0 * x * z) * gY[12];
+  gd[1] += c3d * (-6.0 * y * z) * gY[12];
+  gd[2] += c3d * (6.0 * zz - 3.0 * xx - 3.0 * yy) * gY[12];
+  gd[0] += -c3c * (4.0 * zz - 3.0 * xx - yy) * gY[13];
+  gd[1] += -c3c * (-2.0 * x * y) * gY[13];
+  gd[2] += -c3c * (8.0 * x * z) * gY[13];
+  gd[0] += c3e * 2.0 * x * z * gY[14];
+  gd[1] += -c3e * 2.0 * y * z * gY[14];
+  gd[2] += c3e * (xx - yy) * gY[14];
+  gd[0] += -c3a * 3.0 * (xx - yy) * gY[15];
+  gd[1] += -c3a * (-6.0 * x * y) * gY[15];
+}
+
+// View-independent quantities of one Gaussian.
+struct Gauss {
+  double m[3];
+  double s[3];
+  double q[4];     // unit quaternion w, x, y, z
+  double qn;       // |q| before normalisation
+  double o;        // opacity
+  double Rq[3][3];
+  double M[3][3];  // Rq diag(s)
+  double Sig[3][3];
+};
+
+__device__ inline void load_gauss(const float* __restrict__ P, int stride, int g, Gauss& G) {
+  for (int i = 0; i < 3; ++i) G.m[i] = (double)P[(size_t)i * stride + g];
+  for (int i = 0; i < 3; ++i) G.s[i] = exp((double)P[(size_t)(3 + i) * stride + g]);
+  const double qw = P[(size_t)6 * stride + g], qx = P[(size_t)7 * stride + g];
+  const double qy = P[(size_t)8 * stride + g], qz = P[(size_t)9 * stride + g];
+  G.qn = sqrt(((qw * qw + qx * qx) + qy * qy) + qz * qz);
+  const double w = qw / G.qn, x = qx / G.qn, y = qy / G.qn, z = qz / G.qn;
+  G.q[0] = w; G.q[1] = x; G.q[2] = y; G.q[3] = z;
+  G.o = 1.0 / (1.0 + exp(-(double)P[(size_t)10 * stride + g]));
+  G.Rq[0][0] = 1.0 - 2.0 * (y * y + z * z);
+  G.Rq[0][1] = 2.0 * (x * y - w * z);
+  G.Rq[0][2] = 2.0 * (x * z + w * y);
+  G.Rq[1][0] = 2.0 * (x * y + w * z);
+  G.Rq[1][1] = 1.0 - 2.0 * (x * x + z * z);
+  G.Rq[1][2] = 2.0 * (y * z - w * x);
+  G.Rq[2][0] = 2.0 * (x * z - w * y);
+  G.Rq[2][1] = 2.0 * (y * z + w * x);
+  G.Rq[2][2] = 1.0 - 2.0 * (x * x + y * y);
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < 3; ++j) G.M[k][j] = G.Rq[k][j] * G.s[j];
+  for (int k = 0; k < 3; ++k)
+    for (int l = 0; l < 3; ++l)
+      G.Sig[k][l] = (G.M[k][0] * G.M[l][0] + G.M[k][1] * G.M[l][1]) + G.M[k][2] * G.M[l][2];
+}
+
+// Per-view quantities of one Gaussian.
+struct Proj {
+  bool visible;
+  bool clx, cly;       // Jacobian clamp active on x / y
+  double tx, ty, tz;   // camera-space mean (tz replaced by 1 when culled)
+  double u, w;
+  double txc, tyc;
+  double J00, J02, J11, J12;
+  double T0[3], T1[3];
+  double S00, S01, S11;
+  double a, b, c;
+  double r;
+  int tx0, tx1, ty0, ty1;
+};
+
+__device__ inline void project(const Gauss& G, const ViewDev& V, Proj& p) {
+  double R[3][3], t[3];
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) R[i][j] = (double)V.R[3 * i + j];
+    t[i] = (double)V.t[i];
+  }
+  const double fx = V.fx, fy = V.fy, cx = V.cx, cy = V.cy;
+  const double tx = ((R[0][0] * G.m[0] + R[0][1] * G.m[1]) + R[0][2] * G.m[2]) + t[0];
+  const double ty = ((R[1][0] * G.m[0] + R[1][1] * G.m[1]) + R[1][2] * G.m[2]) + t[1];
+  const double tz0 = ((R[2][0] * G.m[0] + R[2][1] * G.m[1]) + R[2][2] * G.m[2]) + t[2];
+  const bool in_front = tz0 > kZNear;
+  const double tz = in_front ? tz0 : 1.0;
+  p.tx = tx; p.ty = ty; p.tz = tz;
+  p.u = (fx * tx) / tz + cx;
+  p.w = (fy * ty) / tz + cy;
+  const double limx = (kJacClamp * (0.5 * (double)V.W)) / fx;
+  const double limy = (kJacClamp * (0.5 * (double)V.H)) / fy;
+  const double rx = tx / tz, ry = ty / tz;
+  p.clx = !(rx >= -limx && rx <= limx);
+  p.cly = !(ry >= -limy && ry <= limy);
+  p.txc = tz * fmin(fmax(rx, -limx), limx);
+  p.tyc = tz * fmin(fmax(ry, -limy), limy);
+  p.J00 = fx / tz;
+  p.J02 = -(fx * p.txc) / (tz * tz);
+  p.J11 = fy / tz;
+  p.J12 = -(fy * p.tyc) / (tz * tz);
+  for (int k = 0; k < 3; ++k) {
+    p.T0[k] = p.J00 * R[0][k] + p.J02 * R[2][k];
+    p.T1[k] = p.J11 * R[1][k] + p.J12 * R[2][k];
+  }
+  double U0[3], U1[3];
+  for (int l = 0; l < 3; ++l) {
+    U0[l] = (p.T0[0] * G.Sig[0][l] + p.T0[1] * G.Sig[1][l]) + p.T0[2] * G.Sig[2][l];
+    U1[l] = (p.T1[0] * G.Sig[0][l] + p.T1[1] * G.Sig[1][l]) + p.T1[2] * G.Sig[2][l];
+  }
+  p.S00 = ((U0[0] * p.T0[0] + U0[1] * p.T0[1]) + U0[2] * p.T0[2]) + kKappa;
+  p.S01 = (U0[0] * p.T1[0] + U0[1] * p.T1[1]) + U0[2] * p.T1[2];
+  p.S11 = ((U1[0] * p.T1[0] + U1[1] * p.T1[1]) + U1[2] * p.T1[2]) + kKappa;
+  const double det = p.S00 * p.S11 - p.S01 * p.S01;
+  const bool det_ok = det > 0.0;
+  const double dets = det_ok ? det : 1.0;
+  p.a = p.S11 / dets;
+  p.b = -p.S01 / dets;
+  p.c = p.S00 / dets;
+  const double dd = p.S00 - p.S11;
+  const double lam = 0.5 * (p.S00 + p.S11) + sqrt(0.25 * (dd * dd) + p.S01 * p.S01);
+  p.r = kExtentSigmas * sqrt(lam);
+  // pixel rect: centres within [u - r, u + r] x [w - r, w + r] inside the image
+  const double xlo = ceil((p.u - p.r) - 0.5), xhi = floor((p.u + p.r) - 0.5);
+  const double ylo = ceil((p.w - p.r) - 0.5), yhi = floor((p.w + p.r) - 0.5);
+  const int W = V.W, H = V.H;
+  const int i0 = isnan(xlo) ? W : (int)fmin(fmax(xlo, 0.0), (double)W);
+  const int i1 = isnan(xhi) ? -1 : (int)fmin(fmax(xhi, -1.0), (double)(W - 1));
+  const int j0 = isnan(ylo) ? H : (int)fmin(fmax(ylo, 0.0), (double)H);
+  const int j1 = isnan(yhi) ? -1 : (int)fmin(fmax(yhi, -1.0), (double)(H - 1));
+  p.visible = in_front && det_ok && i0 <= i1 && j0 <= j1;
+  p.tx0 = i0 / kTile; p.tx1 = i1 / kTile;
+  p.ty0 = j0 / kTile; p.ty1 = j1 / kTile;
+}
+
+__device__ inline void camera_dir(const Gauss& G, const ViewDev& V, double dir[3], double& dn) {
+  double oc[3];
+  for (int k = 0; k < 3; ++k)
+    oc[k] = -(((double)V.R[k] * V.t[0] + (double)V.R[3 + k] * V.t[1]) + (double)V.R[6 + k] * V.t[2]);
+  const double d0 = G.m[0] - oc[0], d1 = G.m[1] - oc[1], d2 = G.m[2] - oc[2];
+  dn = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
+  dir[0] = d0 / dn; dir[1] = d1 / dn; dir[2] = d2 / dn;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ P, int n, int stride,
+                                                     const ViewDev* __restrict__ views, int V,
+                                                     Record* __restrict__ rec, uint32_t* __restrict__ depth,
+                                                     uint32_t* __restrict__ touched, ushort4* __restrict__ rect) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  Gauss G;
+  load_gauss(P, stride, g, G);
+  double tau = -log(kAlphaMinInv * G.o);
+  tau = tau < kCutoffFloor ? kCutoffFloor : tau;
+  constexpr int K = (D + 1) * (D + 1);
+  float f[3 * K];
+#pragma unroll
+  for (int i = 0; i < 3 * K; ++i) f[i] = P[(size_t)(11 + i) * stride + g];
+  for (int v = 0; v < V; ++v) {
+    const ViewDev& cv = views[v];
+    Proj p;
+    project(G, cv, p);
+    const size_t idx = (size_t)v * n + g;
+    if (!p.visible) {
+      depth[idx] = 0xffffffffu;
+      touched[idx] = 0u;
+      rect[idx] = make_ushort4(0, 0, 0, 0);
+      continue;
+    }
+    double dir[3], dn;
+    camera_dir(G, cv, dir, dn);
+    double Y[16];
+    sh_eval(D, dir[0], dir[1], dir[2], Y);
+    double col[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      double acc = 0.5;
+#pragma unroll
+      for (int k = 0; k < K; ++k) acc += (double)f[3 * k + ch] * Y[k];
+      col[ch] = acc < 0.0 ? 0.0 : acc;
+    }
+    depth[idx] = __float_as_uint((float)p.tz);
+    touched[idx] = (uint32_t)((p.tx1 - p.tx0 + 1) * (p.ty1 - p.ty0 + 1));
+    rect[idx] = make_ushort4((unsigned short)p.tx0, (unsigned short)p.tx1, (unsigned short)p.ty0,
+                             (unsigned short)p.ty1);
+    double2* r2 = reinterpret_cast<double2*>(rec + idx);
+    r2[0] = make_double2(p.u, p.w);
+    float4* r4 = reinterpret_cast<float4*>(rec + idx);
+    r4[1] = make_float4((float)p.a, (float)p.b, (float)p.c, (float)G.o);
+    r4[2] = make_float4((float)tau, (float)col[0], (float)col[1], (float)col[2]);
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_preprocess_bwd(const float* __restrict__ P, int n, int stride,
+                                                         const ViewDev* __restrict__ views, int V,
+                                                         const uint32_t* __restrict__ touched,
+                                                         const float* __restrict__ grad2d, float* __restrict__ out,
+                                                         int accumulate) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  Gauss G;
+  load_gauss(P, stride, g, G);
+  constexpr int K = (D + 1) * (D + 1);
+  float f[3 * K];
+#pragma unroll
+  for (int i = 0; i < 3 * K; ++i) f[i] = P[(size_t)(11 + i) * stride + g];
+
+  double gm[3] = {0, 0, 0};         // dL/dmean
+  double gSig[3][3] = {{0}};        // symmetric dL/dSigma accumulated over views
+  double go = 0.0;                  // dL/dopacity
+  double gf[3 * K];                 // dL/dSH
+#pragma unroll
+  for (int i = 0; i < 3 * K; ++i) gf[i] = 0.0;
+
+  for (int v = 0; v < V; ++v) {
+    const size_t idx = (size_t)v * n + g;
+    if (touched[idx] == 0u) continue;
+    const ViewDev& cv = views[v];
+    Proj p;
+    project(G, cv, p);
+    const float* g2 = grad2d + idx * kGrad2D;
+    const double gu = g2[0], gw = g2[1], ga = g2[2], gb = g2[3], gc = g2[4];
+    go += (double)g2[5];
+    const double grgb[3] = {g2[6], g2[7], g2[8]};
+
+    // colour: raw = 1/2 + sum_k f_k Y_k(dir), clamped at 0 (zero derivative when clamped)
+    double dir[3], dn;
+    camera_dir(G, cv, dir, dn);
+    double Y[16];
+    sh_eval(D, dir[0], dir[1], dir[2], Y);
+    double graw[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      double acc = 0.5;
+#pragma unroll
+      for (int k = 0; k < K; ++k) acc += (double)f[3 * k + ch] * Y[k];
+      graw[ch] = acc < 0.0 ? 0.0 : grgb[ch];
+    }
+    double gY[16];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      gY[k] = 0.0;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        gf[3 * k + ch] += graw[ch] * Y[k];
+        gY[k] += graw[ch] * (double)f[3 * k + ch];
+      }
+    }
+    double gdir[3];
+    sh_grad_dir(D, dir[0], dir[1], dir[2], gY, gdir);
+    const double dd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
+    for (int k = 0; k < 3; ++k) gm[k] += (gdir[k] - dir[k] * dd) / dn;
+
+    // conic (a, b, c) = inverse of S -> dL/dS = -A Gc A, Gc = [[ga, gb/2], [gb/2, gc]]
+    const double A00 = p.a, A01 = p.b, A11 = p.c;
+    const double H00 = ga * A00 + 0.5 * gb * A01, H01 = ga * A01 + 0.5 * gb * A11;
+    const double H10 = 0.5 * gb * A00 + gc * A01, H11 = 0.5 * gb * A01 + gc * A11;  // Gc A
+    const double gS00 = -(A00 * H00 + A01 * H10);
+    const double gS11 = -(A01 * H01 + A11 * H11);
+    const double gS01 = -2.0 * (A00 * H01 + A01 * H11);   // S01 appears in both off-diagonal slots
+
+    // S = T Sigma T^T (+ kappa I): dL/dSigma (symmetric part) and dL/dT
+    for (int k = 0; k < 3; ++k)
+      for (int l = 0; l < 3; ++l)
+        gSig[k][l] += gS00 * p.T0[k] * p.T0[l] + 0.5 * gS01 * (p.T0[k] * p.T1[l] + p.T1[k] * p.T0[l]) +
+                      gS11 * p.T1[k] * p.T1[l];
+    double ST0[3], ST1[3];
+    for (int k = 0; k < 3; ++k) {
+      ST0[k] = G.Sig[k][0] * p.T0[0] + G.Sig[k][1] * p.T0[1] + G.Sig[k][2] * p.T0[2];
+      ST1[k] = G.Sig[k][0] * p.T1[0] + G.Sig[k][1] * p.T1[1] + G.Sig[k][2] * p.T1[2];
+    }
+    double gT0[3], gT1[3];
+    for (int k = 0; k < 3; ++k) {
+      gT0[k] = 2.0 * gS00 * ST0[k] + gS01 * ST1[k];
+      gT1[k] = gS01 * ST0[k] + 2.0 * gS11 * ST1[k];
+    }
+    // T0 = J00 W0 + J02 W2, T1 = J11 W1 + J12 W2 (W = view rotation rows)
+    double Wr[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Wr[i][j] = cv.R[3 * i + j];
+    double gJ00 = 0, gJ02 = 0, gJ11 = 0, gJ12 = 0;
+    for (int k = 0; k < 3; ++k) {
+      gJ00 += gT0[k] * Wr[0][k];
+      gJ02 += gT0[k] * Wr[2][k];
+      gJ11 += gT1[k] * Wr[1][k];
+      gJ12 += gT1[k] * Wr[2][k];
+    }
+    const double tz = p.tz, tz2 = tz * tz, tz3 = tz2 * tz;
+    const double fx = cv.fx, fy = cv.fy;
+    double gt[3] = {0, 0, 0};
+    // u = fx tx / tz + cx, w = fy ty / tz + cy
+    gt[0] += gu * fx / tz;
+    gt[1] += gw * fy / tz;
+    gt[2] += -(gu * fx * p.tx + gw * fy * p.ty) / tz2;
+    // J00 = fx / tz, J11 = fy / tz
+    gt[2] += -(gJ00 * fx + gJ11 * fy) / tz2;
+    // J02 = -fx txc / tz^2 with txc = tx (free) or tz * (+-lim) (clamped)
+    if (!p.clx) {
+      gt[0] += -gJ02 * fx / tz2;
+      gt[2] += gJ02 * 2.0 * fx * p.txc / tz3;
+    } else {
+      gt[2] += gJ02 * fx * p.txc / tz3;
+    }
+    if (!p.cly) {
+      gt[1] += -gJ12 * fy / tz2;
+      gt[2] += gJ12 * 2.0 * fy * p.tyc / tz3;
+    } else {
+      gt[2] += gJ12 * fy * p.tyc / tz3;
+    }
+    // t = W mean + t_v
+    for (int k = 0; k < 3; ++k) gm[k] += Wr[0][k] * gt[0] + Wr[1][k] * gt[1] + Wr[2][k] * gt[2];
+  }
+
+  // Sigma = M M^T -> dL/dM = 2 sym(dL/dSigma) M; M = Rq diag(s)
+  double gs[3] = {0, 0, 0};
+  double gR[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < 3; ++j) {
+      const double gM = 2.0 * (gSig[k][0] * G.M[0][j] + gSig[k][1] * G.M[1][j] + gSig[k][2] * G.M[2][j]);
+      gs[j] += gM * G.Rq[k][j];
+      gR[k][j] = gM * G.s[j];
+    }
+  const double w = G.q[0], x = G.q[1], y = G.q[2], z = G.q[3];
+  double gq[4];
+  gq[0] = 2.0 * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] - y * gR[2][0] + x * gR[2][1]);
+  gq[1] = 2.0 * (y * gR[0][1] + z * gR[0][2] + y * gR[1][0] - 2.0 * x * gR[1][1] - w * gR[1][2] + z * gR[2][0] +
+                 w * gR[2][1] - 2.0 * x * gR[2][2]);
+  gq[2] = 2.0 * (-2.0 * y * gR[0][0] + x * gR[0][1] + w * gR[0][2] + x * gR[1][0] + z * gR[1][2] - w * gR[2][0] +
+                 z * gR[2][1] - 2.0 * y * gR[2][2]);
+  gq[3] = 2.0 * (-2.0 * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] - 2.0 * z * gR[1][1] +
+                 y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
+  const double qd = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * z;
+
+  double outv[11];
+  for (int k = 0; k < 3; ++k) outv[k] = gm[k];
+  for (int k = 0; k < 3; ++k) outv[3 + k] = gs[k] * G.s[k];
+  for (int k = 0; k < 4; ++k) outv[6 + k] = (gq[k] - G.q[k] * qd) / G.qn;
+  outv[10] = go * G.o * (1.0 - G.o);
+  for (int r = 0; r < 11; ++r) {
+    float* dst = out + (size_t)r * stride + g;
+    *dst = accumulate ? *dst + (float)outv[r] : (float)outv[r];
+  }
+#pragma unroll
+  for (int i = 0; i < 3 * K; ++i) {
+    float* dst = out + (size_t)(11 + i) * stride + g;
+    *dst = accumulate ? *dst + (float)gf[i] : (float)gf[i];
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+}  // namespace
+
+hipError_t launch_preprocess(const float* P, int n, int stride, int D, const ViewDev* views, int V, Record* rec,
+                             uint32_t* depth, uint32_t* touched, ushort4* rect, hipStream_t s) {
+  const int blocks = (n + 255) / 256;
+  switch (D) {
+    case 0: hipLaunchKernelGGL(k_preprocess<0>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, rec, depth, touched, rect); break;
+    case 1: hipLaunchKernelGGL(k_preprocess<1>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, rec, depth, touched, rect); break;
+    case 2: hipLaunchKernelGGL(k_preprocess<2>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, rec, depth, touched, rect); break;
+    default: hipLaunchKernelGGL(k_preprocess<3>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, rec, depth, touched, rect); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_bwd(const float* P, int n, int stride, int D, const ViewDev* views, int V,
+                                 const uint32_t* touched, const float* grad2d, float* grad, int accumulate,
+                                 hipStream_t s) {
+  const int blocks = (n + 255) / 256;
+  switch (D) {
+    case 0: hipLaunchKernelGGL(k_preprocess_bwd<0>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, touched, grad2d, grad, accumulate); break;
+    case 1: hipLaunchKernelGGL(k_preprocess_bwd<1>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, touched, grad2d, grad, accumulate); break;
+    case 2: hipLaunchKernelGGL(k_preprocess_bwd<2>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, touched, grad2d, grad, accumulate); break;
+    default: hipLaunchKernelGGL(k_preprocess_bwd<3>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, touched, grad2d, grad, accumulate); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  size_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, value, count);
+  return hipGetLastError();
+}
+
+}  // namespace gsk

@@ -1,0 +1,120 @@
+"""Helpers for the GPU parity tests: run the HIP path through the C ABI and the
+oracle on the same seeded inputs, and decide which pixels are ambiguous."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle
+from oracle import composite
+
+# A pixel is set aside when one of its discrete decisions lies closer to its
+# threshold (relative to the magnitudes involved) than fp32 evaluation can resolve:
+# exponent vs cutoff, exponent sign, alpha cap, and the transmittance stop (the
+# latter accumulates rounding over the whole list, hence the looser bound).
+MARGIN_CUT = 1e-5
+MARGIN_SIGN = 1e-5
+MARGIN_CAP = 1e-5
+MARGIN_T = 2e-3
+
+
+def ambiguous(r) -> np.ndarray:
+    return ((r["m_cut"] < MARGIN_CUT) | (r["m_sign"] < MARGIN_SIGN) | (r["m_cap"] < MARGIN_CAP) |
+            (r["m_T"] < MARGIN_T))
+
+
+def run_gpu(scene, upstream=None, loss=False, keep=None):
+    """Forward (and optionally backward) of the HIP path; returns numpy outputs."""
+    from paper_2503_13086_amd.pipeline import Rasterizer, params_to_device
+    from paper_2503_13086_amd import (GS_BUF_RECORDS, GS_BUF_DEPTH, GS_BUF_TOUCHED, GS_BUF_TILE_RECT,
+                                      GS_BUF_KEYS, GS_BUF_VALUES, GS_BUF_RANGES, GS_BUF_T_FINAL,
+                                      GS_BUF_N_CONTRIB, GS_BUF_LAST, GS_BUF_PAIR_VIEW)
+    rz = Rasterizer(0)
+    try:
+        P = params_to_device(scene.params)
+        rz.preprocess(P, scene.n, scene.sh_degree, scene.cams)
+        K = rz.bin_sort()
+        color = rz.render_fwd()
+        out = dict(K=K, color=[x.cpu().numpy() for x in rz.image_views(color)])
+        V, n = len(scene.cams), scene.n
+        rec = rz.buffer(GS_BUF_RECORDS).cpu().numpy().view(np.uint8).reshape(V, n, 48)
+        out["u"] = rec[:, :, 0:8].copy().view(np.float64)[..., 0]
+        out["w"] = rec[:, :, 8:16].copy().view(np.float64)[..., 0]
+        f = rec[:, :, 16:48].copy().view(np.float32)
+        for k, name in enumerate(["a", "b", "c", "o", "tau", "r", "g", "bl"]):
+            out[name] = f[..., k]
+        out["depth"] = rz.buffer(GS_BUF_DEPTH).cpu().numpy().view(np.uint32).reshape(V, n)
+        out["touched"] = rz.buffer(GS_BUF_TOUCHED).cpu().numpy().reshape(V, n)
+        out["rect"] = rz.buffer(GS_BUF_TILE_RECT).cpu().numpy().view(np.uint16).reshape(V, n, 4)
+        out["keys"] = rz.buffer(GS_BUF_KEYS).cpu().numpy().view(np.uint64)
+        out["values"] = rz.buffer(GS_BUF_VALUES).cpu().numpy().view(np.uint32)
+        out["pair_view"] = rz.buffer(GS_BUF_PAIR_VIEW).cpu().numpy().view(np.uint32)
+        out["ranges"] = rz.buffer(GS_BUF_RANGES).cpu().numpy().view(np.uint32).reshape(-1, 2)
+        P_ = rz.P
+        out["T_final"] = rz.buffer(GS_BUF_T_FINAL).cpu().numpy()
+        out["n_contrib"] = rz.buffer(GS_BUF_N_CONTRIB).cpu().numpy()
+        out["last"] = rz.buffer(GS_BUF_LAST).cpu().numpy()
+        assert out["T_final"].size == P_
+        if loss:
+            tgt = rz.pack_images(scene.targets)
+            lo, dl = rz.loss(color, tgt, scene.w_l1, scene.w_dssim)
+            out["loss"] = lo.cpu().numpy()
+            out["dL_dcolor"] = [x.cpu().numpy() for x in rz.image_views(dl)]
+            if upstream is None:
+                upstream_t = dl
+        if upstream is not None:
+            upstream_t = rz.pack_images(upstream)
+        if upstream is not None or loss:
+            grad = rz.render_bwd(upstream_t)
+            out["grad"] = grad[:, :scene.n].cpu().numpy()
+        torch.cuda.synchronize()
+        return out
+    finally:
+        rz.close()
+
+
+def split_pixels(scene, flat):
+    """Per-view [H, W] views of a concatenated per-pixel buffer."""
+    out, off = [], 0
+    for c in scene.cams:
+        hw = c["width"] * c["height"]
+        out.append(flat[off:off + hw].reshape(c["height"], c["width"]))
+        off += hw
+    return out
+
+
+def touching_mask(projs, amb_maps, n):
+    """Gaussians whose pixel rect contains an ambiguous pixel in some view."""
+    bad = np.zeros(n, bool)
+    for p, amb in zip(projs, amb_maps):
+        jj, ii = np.nonzero(amb)
+        if len(ii) == 0:
+            continue
+        vis = p["visible"]
+        for i, j in zip(ii, jj):
+            bad |= vis & (p["i0"] <= i) & (i <= p["i1"]) & (p["j0"] <= j) & (j <= p["j1"])
+    return bad
+
+
+def grad_errors(g_gpu, g_ref, keep, groups):
+    """Per parameter group: relative L2 error and worst per-element excess over
+    |d| <= 1e-3 (|ref| + 1e-2 rms(ref))."""
+    res = {}
+    for name, rows in groups.items():
+        a = g_gpu[rows][:, keep]
+        b = g_ref[rows][:, keep]
+        if b.size == 0:
+            continue
+        rms = np.sqrt(np.mean(b * b)) + 1e-30
+        rel = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-30)
+        elem = np.abs(a - b) / (1e-3 * (np.abs(b) + 1e-2 * rms))
+        res[name] = (rel, float(elem.max()))
+    return res
+
+
+def param_groups(sh_degree):
+    g = {"mean": slice(0, 3), "scale": slice(3, 6), "rot": slice(6, 10), "opacity": slice(10, 11),
+         "sh_dc": slice(11, 14)}
+    if sh_degree > 0:
+        g["sh_rest"] = slice(14, 11 + 3 * (sh_degree + 1) ** 2)
+    return g

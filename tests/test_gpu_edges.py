@@ -1,0 +1,163 @@
+"""Edge and degenerate cases of the HIP path (through the C ABI) against the oracle,
+and the argument checks of every entry point."""
+import numpy as np
+import pytest
+import torch
+
+import scenegen
+import oracle
+from oracle import composite
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+
+def _one_gaussian(z=3.0, ls=-2.0, rho=2.0, size=(1, 1), bg=(0.25, 0.5, 0.75)):
+    P = np.zeros((14, 1), np.float32)
+    P[2, 0] = z
+    P[3:6, 0] = ls
+    P[6, 0] = 1.0
+    P[10, 0] = rho
+    P[11:14, 0] = [1.0, -0.5, 0.3]
+    W, H = size
+    cam = scenegen.camera(np.eye(3), np.zeros(3), 50.0, 50.0, W / 2, H / 2, W, H, bg)
+    return scenegen.Scene(P, 1, 0, [cam], [np.zeros((3, H, W), np.float32)])
+
+
+@pytest.mark.parametrize("size", [(1, 1), (17, 1), (1, 33), (16, 16), (31, 17)])
+def test_single_gaussian_tiny_images(size):
+    sc = _one_gaussian(size=size)
+    p = oracle.project_views(sc.params, 1, 0, sc.cams)
+    g = gu.run_gpu(sc, upstream=[np.ones((3, size[1], size[0]), np.float32)])
+    r = composite.render_view(p[0])
+    assert np.abs(g["color"][0] - r["color"]).max() <= 1e-5
+    ref = oracle.param_grads(sc.params, 1, 0, sc.cams, [np.ones((3, size[1], size[0]))])
+    assert np.abs(g["grad"] - ref).max() <= 1e-4 * max(1e-6, np.abs(ref).max())
+
+
+def test_nothing_visible():
+    """Every Gaussian behind the camera: no pairs, image = background, zero grads."""
+    sc = scenegen.small_scene(3, 200, 1, [(40, 30), (20, 20)], bg=(0.3, 0.6, 0.9))
+    sc.params[2, :] = -50.0       # far behind both cameras (cameras sit at z ~ -3 looking at +z)
+    sc.params[0:2, :] = 0.0
+    g = gu.run_gpu(sc, upstream=scenegen.upstream_grads(1, sc.cams))
+    assert g["K"] == 0
+    for v, c in enumerate(sc.cams):
+        assert np.allclose(g["color"][v], np.asarray(c["bg"], np.float32)[:, None, None])
+    assert (g["T_final"] == 1.0).all() and (g["n_contrib"] == 0).all()
+    assert (g["grad"] == 0).all()
+
+
+def test_near_plane_and_offscreen():
+    """Gaussians straddling the near plane and far off-screen are culled exactly as
+    the oracle culls them; large ones overlapping the border are kept."""
+    rng = np.random.default_rng(4)
+    n = 600
+    P = scenegen.make_field(rng, n, 0, center=(0, 0, 0.5), half_extent=2.0, log_scale_mean=-1.5)
+    P[2, :200] = rng.uniform(0.15, 0.25, 200)          # around the near plane (0.2)
+    cam = scenegen.camera(np.eye(3), np.zeros(3), 60.0, 60.0, 32.0, 24.0, 64, 48)
+    sc = scenegen.Scene(P, n, 0, [cam], [np.zeros((3, 48, 64), np.float32)])
+    projs = oracle.project_views(P, n, 0, [cam])
+    g = gu.run_gpu(sc)
+    assert np.array_equal(g["touched"][0], projs[0]["touched"])
+    b = oracle.bin_pairs(projs, [cam], 16)
+    assert np.array_equal(g["keys"], b["keys"]) and np.array_equal(g["values"], b["values"])
+    r = composite.render_view(projs[0])
+    ok = ~gu.ambiguous(r)
+    assert np.abs(g["color"][0] - r["color"]).max(axis=0)[ok].max() <= 1e-4
+
+
+def test_stride_larger_than_n_and_accumulate():
+    """Columns beyond n are never read or written; accumulate adds to grad."""
+    from paper_2503_13086_amd.pipeline import Rasterizer
+    sc = scenegen.small_scene(8, 300, 2, [(48, 40)])
+    stride = 512
+    P = np.full((sc.params.shape[0], stride), np.nan, np.float32)
+    P[:, :sc.n] = sc.params[:, :sc.n]
+    up = scenegen.upstream_grads(2, sc.cams)
+    rz = Rasterizer(0)
+    try:
+        tP = torch.as_tensor(P).cuda()
+        rz.preprocess(tP, sc.n, 2, sc.cams)
+        rz.bin_sort()
+        rz.render_fwd()
+        grad = torch.full_like(tP, 7.0)
+        rz.render_bwd(rz.pack_images(up), grad, accumulate=True)
+        g = grad.cpu().numpy()
+    finally:
+        rz.close()
+    assert (g[:, sc.n:] == 7.0).all()
+    ref = oracle.param_grads(sc.params, sc.n, 2, sc.cams, up)
+    assert np.abs((g[:, :sc.n] - 7.0) - ref).max() <= 1e-3 * np.abs(ref).max() + 1e-6
+
+
+def test_batched_equals_plain_loop():
+    """Rendering three views in one batch equals three single-view calls (images
+    bit for bit, gradients summed over views within fp32 atomics)."""
+    from paper_2503_13086_amd.pipeline import Rasterizer, params_to_device
+    sc = scenegen.small_scene(12, 1500, 3, [(70, 50), (33, 64), (90, 20)], log_scale_mean=-2.6)
+    up = scenegen.upstream_grads(5, sc.cams, 1e-2)
+    rz = Rasterizer(0)
+    try:
+        P = params_to_device(sc.params)
+        rz.preprocess(P, sc.n, 3, sc.cams)
+        rz.bin_sort()
+        col = rz.render_fwd()
+        imgs = [x.clone() for x in rz.image_views(col)]
+        gb = rz.render_bwd(rz.pack_images(up))
+        gl = torch.zeros_like(P)
+        singles = []
+        for v, c in enumerate(sc.cams):
+            rz.preprocess(P, sc.n, 3, [c])
+            rz.bin_sort()
+            singles.append(rz.render_fwd().view(3, c["height"], c["width"]).clone())
+            rz.render_bwd(rz.pack_images([up[v]]), gl, accumulate=True)
+        for a, b in zip(imgs, singles):
+            assert torch.equal(a, b)
+        gb, gl = gb.cpu().numpy(), gl.cpu().numpy()
+    finally:
+        rz.close()
+    assert np.abs(gb - gl).max() <= 1e-5 * np.abs(gb).max()
+
+
+def test_argument_checks():
+    import paper_2503_13086_amd as gs
+    from paper_2503_13086_amd.pipeline import Rasterizer
+    sc = scenegen.small_scene(1, 10, 0, [(16, 16)])
+    rz = Rasterizer(0)
+    try:
+        P = torch.as_tensor(sc.params).cuda()
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_bin_sort(rz.ctx)
+        assert e.value.status == gs.GS_ERR_STATE
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_preprocess(rz.ctx, P, 10, 5, 0, sc.cams)            # stride < n
+        assert e.value.status == gs.GS_ERR_INVALID
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_preprocess(rz.ctx, P, 10, 10, 4, sc.cams)           # SH degree 4
+        assert e.value.status == gs.GS_ERR_INVALID
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_preprocess(rz.ctx, P, 10, 10, 0, sc.cams, tile=8)
+        assert e.value.status == gs.GS_ERR_UNSUPPORTED
+        bad = dict(sc.cams[0])
+        bad["fx"] = 0.0
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_preprocess(rz.ctx, P, 10, 10, 0, [bad])
+        assert e.value.status == gs.GS_ERR_INVALID
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_preprocess(rz.ctx, P, 10, 10, 0, sc.cams * 65)      # too many views
+        assert e.value.status == gs.GS_ERR_INVALID
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_preprocess(rz.ctx, P.data_ptr() + 2, 10, 10, 0, sc.cams)   # misaligned
+        assert e.value.status == gs.GS_ERR_INVALID
+        gs.gs_preprocess(rz.ctx, P, 10, 10, 0, sc.cams)
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_render_fwd(rz.ctx, rz.new_image())                   # before bin_sort
+        assert e.value.status == gs.GS_ERR_STATE
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_adam_step(rz.ctx, P, P, P, P, torch.zeros(10, dtype=torch.int32).cuda(), 10, 10, 0,
+                            [1e-3] * 6, [1.0, 1.0], beta1=0.9)             # 2 view scales, 1 view
+        assert e.value.status == gs.GS_ERR_STATE
+        assert "n_views" in gs.gs_last_error(rz.ctx)
+    finally:
+        rz.close()
