@@ -1,0 +1,253 @@
+"""Benchmark of the rasterizer training step on one MI355X.
+
+One step = the whole hot path over one batch of views, inputs resident in HBM:
+gs_preprocess -> gs_bin_sort -> gs_render_fwd -> gs_loss -> gs_render_bwd ->
+gs_adam_step.  Default workload: 1M Gaussians (SH degree 3) and 9 views (the
+newest pose of a seeded random-walk camera path plus its 8 neighbours by frustum
+overlap) at 3x 1600x1067, 3x 1296x864, 3x 979x546, loss 0.8 L1 + 0.2 D-SSIM,
+per-view learning rates from Eq. 6-7.  Prints one JSON line (rank 0).
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--workload c3|c2|c1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X fp32 vector (packed); non-packed issue is half of it
+
+
+def eq6_lr(iters, eta0=1.6e-4, etaf=1.6e-6, t_a=30000.0):
+    """Per-image learning rate of Eq. 6-7 (log-linear in trained iterations)."""
+    t = min(iters / t_a, 1.0)
+    return math.exp(math.log(eta0) * (1.0 - t) + math.log(etaf) * t)
+
+
+def make_workload(name):
+    import scenegen
+    if name == "c3":
+        return scenegen.config3()
+    if name == "c2":
+        return scenegen.config2()
+    if name == "c1":
+        return scenegen.config1()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def algorithmic_bytes(n, n_p, V, K, P, tiles, ssim):
+    """Compulsory HBM bytes per stage: each input read once, each output written once."""
+    return {
+        "preprocess": 4 * n_p * n + 64 * V * n,
+        "scan_emit": 8 * V * n + 12 * K,
+        "tile_sort": 24 * K,
+        "ranges": 8 * K + 8 * tiles,
+        "render_fwd": 52 * K + 20 * P,
+        "loss": (72 if ssim else 36) * P,
+        "render_bwd": 52 * K + 24 * P,
+        "preprocess_bwd": 36 * V * n + 8 * n_p * n,
+        "adam": 28 * n_p * n + 8 * n,
+    }
+
+
+def cpu_baseline(scene, budget_s=20.0):
+    """The FP64 oracle, as it is, on a bounded sample of the workload: forward and
+    backward of a few pixels of the first view (every Gaussian evaluated per pixel),
+    timed on the host's cores."""
+    import torch
+    import oracle
+    from oracle import composite
+    from oracle.geometry import params_f64, project_view
+    cam = scene.cams[0]
+    rng = np.random.default_rng(0)
+    t0 = time.perf_counter()
+    P = params_f64(scene.params, scene.n, requires_grad=True)
+    proj = project_view(P, cam, scene.sh_degree, 16)
+    t_proj = time.perf_counter() - t0
+    ids = composite.ordered_visible(proj)
+    sel = composite.select(proj, ids, requires_grad=True)
+    leaves = {k: sel[k].detach().clone().requires_grad_(True) for k in ("u", "w", "a", "b", "c", "o", "rgb")}
+    q = {k: v.detach() for k, v in sel.items()}
+    gq = dict(leaves)
+    gq["tau"] = q["tau"]
+    n_pix = 0
+    t1 = time.perf_counter()
+    chunk = 4
+    while time.perf_counter() - t1 < budget_s and n_pix < 4096:
+        px = rng.integers(0, cam["width"], chunk)
+        py = rng.integers(0, cam["height"], chunk)
+        r = composite.blend(q, px, py, margins=False, grad_q=gq)
+        (r["C"].sum() + r["T_final"].sum()).backward()
+        n_pix += chunk
+    outs = [sel[k] for k in leaves if leaves[k].grad is not None]
+    grads = [leaves[k].grad for k in leaves if leaves[k].grad is not None]
+    torch.autograd.backward(outs, grads)
+    t_total = time.perf_counter() - t1 + t_proj
+    return {"value": n_pix / t_total / 1e6, "unit": "Mpix/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"{n_pix} random pixels of view 0 ({cam['width']}x{cam['height']}), FP64 forward + "
+                      f"autograd backward over all {len(ids)} visible Gaussians, including one projection of "
+                      f"all {scene.n} Gaussians; {t_total:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain-loop", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU split of this path "
+              "is a design note, not a measured configuration.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2503_13086_amd.pipeline import Rasterizer, params_to_device, DEFAULT_LR, n_params
+
+    t_gen = time.perf_counter()
+    sc = make_workload(args.workload)
+    print(f"[bench] workload {sc.name}: n={sc.n}, views={len(sc.cams)}, generated in "
+          f"{time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
+    V = len(sc.cams)
+    iters = sc.iters if sc.iters is not None else np.zeros(V, np.int64)
+    lrs = [eq6_lr(float(it)) for it in iters]
+    scales = [lr / DEFAULT_LR[0] for lr in lrs]
+
+    rz = Rasterizer(0)
+    dev = rz.device
+    params = params_to_device(sc.params)
+    n, D = sc.n, sc.sh_degree
+    rz.set_views(sc.cams)
+    P = rz.P
+    target = rz.pack_images(sc.targets)
+    color = rz.new_image()
+    dl = rz.new_image()
+    loss = torch.zeros(V, dtype=torch.float64, device=dev)
+    grad = torch.zeros_like(params)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    step = torch.zeros(n, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def one_step(batched=True):
+        rz.preprocess(params, n, D, sc.cams)
+        rz.bin_sort()
+        rz.render_fwd(color)
+        rz.loss(color, target, sc.w_l1, sc.w_dssim, loss, dl)
+        rz.render_bwd(dl, grad)
+        rz.adam_step(grad, m, v, step, DEFAULT_LR, scales, group_mask=1)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    K = rz.K
+    rz.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step()
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / args.steps
+    prof = rz.profile_read()
+    rz.profile(False)
+    kern_ms = {k: (ms / cnt if cnt else 0.0) for k, (cnt, ms) in prof.items()}
+    kern_launches = {k: cnt for k, (cnt, ms) in prof.items()}
+    fwd_bwd_ms = sum(kern_ms[k] * kern_launches[k] / args.steps for k in
+                     ["preprocess", "depth_sort", "scan", "emit", "tile_sort", "ranges", "render_fwd", "loss", "zero",
+                      "render_bwd", "preprocess_bwd"])
+
+    # per-pixel work actually needed: list positions up to each pixel's last blended Gaussian
+    from paper_2503_13086_amd import GS_BUF_LAST
+    last = rz.buffer(GS_BUF_LAST).to(torch.int64)
+    evals_bwd = int(last.sum().item())
+
+    # plain loop: each view on its own call sequence, gradients summed, one Adam step
+    plain_ms = None
+    if not args.no_plain_loop and V > 1:
+        def plain_step():
+            for vi, c in enumerate(sc.cams):
+                rz.preprocess(params, n, D, [c])
+                rz.bin_sort()
+                col = rz.render_fwd(color[: 3 * c["width"] * c["height"]])
+                rz.loss(col, target[3 * rz_off[vi]: 3 * rz_off[vi + 1]], sc.w_l1, sc.w_dssim, loss[:1],
+                        dl[: 3 * c["width"] * c["height"]])
+                rz.render_bwd(dl[: 3 * c["width"] * c["height"]], grad, accumulate=vi > 0)
+            rz.adam_step(grad, m, v, step, DEFAULT_LR, None, group_mask=1)
+        from paper_2503_13086_amd import gs_layout
+        rz_off, _ = gs_layout(sc.cams, 16)
+        for _ in range(2):
+            plain_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = max(2, args.steps // 4)
+        for _ in range(reps):
+            plain_step()
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - t0) / reps * 1e3
+
+    n_p = n_params(D)
+    n_tiles = rz.tile_off[-1]
+    algo = algorithmic_bytes(n, n_p, V, K, P, n_tiles, sc.w_dssim != 0)
+    # dominant kernel and its roofline
+    dom = max(["render_fwd", "render_bwd", "preprocess", "tile_sort", "depth_sort", "preprocess_bwd", "adam", "loss"],
+              key=lambda k: kern_ms[k] * kern_launches[k])
+    flops_per_eval_bwd = 60.0   # VALU flops per (pixel, Gaussian) visit of the backward incl. reductions
+    if dom in ("render_bwd", "render_fwd"):
+        if dom == "render_bwd":
+            achieved = evals_bwd * flops_per_eval_bwd / (kern_ms[dom] * 1e-3) / 1e12
+        else:
+            achieved = evals_bwd * 25.0 / (kern_ms[dom] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": dom,
+                "kernel_ms": kern_ms[dom]}
+    else:
+        key = {"tile_sort": "tile_sort", "depth_sort": "tile_sort"}.get(dom, dom)
+        achieved = algo[key] / (kern_ms[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom, "kernel_ms": kern_ms[dom]}
+
+    mpix = P / (t_step) / 1e6
+    line = {
+        "metric": "fwd+bwd Mpix/s at 1M Gaussians vs plain loop; p50/p99 per-new-image latency",
+        "value": round(mpix, 3),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_step * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": sc.name, "gaussians": n, "sh_degree": D, "views": V,
+                   "resolutions": [f"{c['width']}x{c['height']}" for c in sc.cams], "pixels": P,
+                   "loss": f"{sc.w_l1} L1 + {sc.w_dssim} D-SSIM", "tile": 16, "pairs": K},
+        "fwd_bwd_mpix_s": round(P / (fwd_bwd_ms * 1e-3) / 1e6, 3),
+        "plain_loop_mpix_s": round(P / (plain_ms * 1e-3) / 1e6, 3) if plain_ms else None,
+        "plain_loop_ms_per_step": round(plain_ms, 3) if plain_ms else None,
+        "kernel_ms_per_step": {k: round(kern_ms[k] * kern_launches[k] / args.steps, 4) for k in kern_ms},
+        "algorithmic_gb_per_step": {k: round(b / 1e9, 4) for k, b in algo.items()},
+        "evals_bwd": evals_bwd,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle on a bounded sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(sc)
+    rz.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

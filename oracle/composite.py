@@ -21,7 +21,8 @@ factor of exactly 1, so they are dropped before the products; this changes no bi
 of the result.
 
 The oracle also reports, per pixel, how close each discrete decision came to its
-threshold (relative margins), so a test can set aside pixels where an fp32
+threshold (relative margins; the stop test's margin is divided by the running
+product's accumulated sensitivity), so a test can set aside pixels where an fp32
 evaluation may legitimately decide the other way.
 """
 from __future__ import annotations
@@ -99,7 +100,10 @@ def blend(q, px: np.ndarray, py: np.ndarray, *, cutoffs=True, alpha_max=ALPHA_MA
         out["n_contrib"] = blended.sum(1).numpy().astype(np.int64)
         lastk = torch.where(blended.any(1), nc - 1 - _first_true(blended.flip(1)),
                             torch.full((n,), -1, dtype=torch.long))
-        out["last"] = torch.where(lastk >= 0, cols[lastk.clamp(min=0)], torch.full((n,), -1, dtype=torch.long)).numpy()
+        if nc:
+            out["last"] = torch.where(lastk >= 0, cols[lastk.clamp(min=0)], torch.full((n,), -1, dtype=torch.long)).numpy()
+        else:
+            out["last"] = np.full(n, -1, np.int64)
         if margins:
             inf = torch.tensor(float("inf"), dtype=F64)
             # decisions that matter: every pair up to and including the stopping one
@@ -113,7 +117,13 @@ def blend(q, px: np.ndarray, py: np.ndarray, *, cutoffs=True, alpha_max=ALPHA_MA
             out["m_sign"] = torch.where(upto, m_sign, inf).amin(1).numpy() if G else np.full(n, np.inf)
             upto_c = ps & (kidx[None, :] <= kstar[:, None])
             m_cap = (og - alpha_max).abs() / alpha_max
-            m_T = (T_incl - t_min).abs() / t_min if t_min > 0 else torch.full_like(T_incl, float("inf"))
+            # the stop test compares a running product: its distance to the threshold is
+            # measured in units of the product's accumulated relative sensitivity
+            # sum_k (1 + alpha_k / (1 - alpha_k)) (one unit per factor, amplified where
+            # 1 - alpha is small)
+            sens = torch.cumsum(torch.where(ps, 1.0 + alpha / (1.0 - alpha), torch.zeros_like(alpha)), dim=1)
+            m_T = ((T_incl - t_min).abs() / (t_min * sens.clamp(min=1.0)) if t_min > 0
+                   else torch.full_like(T_incl, float("inf")))
             out["m_cap"] = torch.where(upto_c, m_cap, inf).amin(1).numpy() if nc else np.full(n, np.inf)
             out["m_T"] = torch.where(upto_c, m_T, inf).amin(1).numpy() if nc else np.full(n, np.inf)
 

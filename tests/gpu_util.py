@@ -9,13 +9,15 @@ import oracle
 from oracle import composite
 
 # A pixel is set aside when one of its discrete decisions lies closer to its
-# threshold (relative to the magnitudes involved) than fp32 evaluation can resolve:
-# exponent vs cutoff, exponent sign, alpha cap, and the transmittance stop (the
-# latter accumulates rounding over the whole list, hence the looser bound).
-MARGIN_CUT = 1e-5
-MARGIN_SIGN = 1e-5
-MARGIN_CAP = 1e-5
-MARGIN_T = 2e-3
+# threshold than fp32 evaluation can resolve: exponent vs cutoff and exponent sign
+# (relative to the magnitude of the exponent's terms; fp32 error ~4 ulp), alpha cap
+# (relative; exp and opacity rounding ~8 ulp), and the transmittance stop (in units
+# of the running product's accumulated sensitivity; ~8 ulp per unit).  Each bound
+# is several times the fp32 error it covers.
+MARGIN_CUT = 2e-6
+MARGIN_SIGN = 2e-6
+MARGIN_CAP = 2e-6
+MARGIN_T = 3e-6
 
 
 def ambiguous(r) -> np.ndarray:
@@ -71,6 +73,12 @@ def run_gpu(scene, upstream=None, loss=False, keep=None):
         return out
     finally:
         rz.close()
+
+
+def masked_upstream(up, amb_maps):
+    """Upstream images with the ambiguous pixels zeroed: such pixels then add
+    exactly nothing to any gradient, on either side."""
+    return [np.where(a[None], 0.0, u).astype(np.float32) for u, a in zip(up, amb_maps)]
 
 
 def split_pixels(scene, flat):

@@ -127,6 +127,7 @@ def test_argument_checks():
     rz = Rasterizer(0)
     try:
         P = torch.as_tensor(sc.params).cuda()
+        rz.set_views(sc.cams)
         with pytest.raises(gs.GsError) as e:
             gs.gs_bin_sort(rz.ctx)
         assert e.value.status == gs.GS_ERR_STATE
