@@ -180,6 +180,17 @@ gs_status gs_adam_step(gs_ctx* ctx, float* params, const float* grad, float* m, 
                        const float* view_lr_scale, int32_t n_views, uint32_t group_mask, float beta1,
                        float beta2, float eps, gs_stream stream);
 
+/* Pair culling of gs_bin_sort.  GS_CULL_RECT lists every tile of a Gaussian's tile
+ * rect.  GS_CULL_ELLIPSE (the default) lists a tile only if the Gaussian's cutoff
+ * region {a dx^2 + 2 b dx dy + c dy^2 <= -2 tau} meets the box spanned by the
+ * tile's pixel centres (tested in FP64 on the stored conic, cutoff and centre);
+ * the other pairs of the rect can blend into no pixel of their tile, so images
+ * and gradients are the same in both modes.  Culled pairs keep their slot in the
+ * sorted arrays with tile id = number of tiles (they sort after every real tile
+ * and belong to no range).  Takes effect at the next gs_bin_sort. */
+enum { GS_CULL_RECT = 0, GS_CULL_ELLIPSE = 1 };
+gs_status gs_set_cull(gs_ctx* ctx, int32_t mode);
+
 /* Size in bytes of a context buffer (GS_BUF_*) for the current state. */
 gs_status gs_buffer_size(const gs_ctx* ctx, int32_t which, size_t* bytes);
 /* Stream-ordered copy of a context buffer into device memory `dst` of `bytes`

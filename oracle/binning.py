@@ -8,6 +8,15 @@ emits one pair per tile of its tile rect (geometry.py); the key is
 ascending (key, g).  Depths are above the near plane (> 0), so the fp32 bit
 patterns order like the depth values.  Tile t's range is the half-open interval of
 sorted positions whose key has tile t ([0, 0) for an empty tile).
+
+With cull="ellipse" a pair is listed only if the Gaussian's cutoff region
+{d : a dx^2 + 2 b dx dy + c dy^2 <= -2 tau} (exactly the pixels where the cutoff
+rule can pass) meets the box spanned by the tile's pixel centres; the other pairs
+of the rect contribute nothing to any pixel of their tile.  The test is evaluated
+in FP64 on the per-splat values as stored for rasterization (conic and cutoff
+rounded to fp32, centre in FP64), so it is reproducible.  The minimum of the
+quadratic over the box is 0 when the centre lies inside, else the smallest of its
+minima along the four edges (each a clamped 1-D minimiser).
 """
 from __future__ import annotations
 
@@ -16,9 +25,50 @@ import numpy as np
 from .geometry import tile_layout
 
 
-def bin_pairs(projs, cams, tile: int = 16):
+def _f32(x):
+    return np.asarray(x, np.float64).astype(np.float32).astype(np.float64)
+
+
+def box_min_q(a, b, c, dx0, dx1, dy0, dy1):
+    """Minimum of q(dx, dy) = a dx^2 + 2 b dx dy + c dy^2 (positive definite) over
+    the box [dx0, dx1] x [dy0, dy1]: 0 if the box holds the origin, else the
+    smallest of the minima along the four edges."""
+    nbc = -b / c
+    nba = -b / a
+
+    def q(dx, dy):
+        return ((a * dx) * dx + ((2.0 * b) * dx) * dy) + (c * dy) * dy
+
+    best = np.full(np.shape(dx0), np.inf)
+    for dxe in (dx0, dx1):
+        best = np.minimum(best, q(dxe, np.clip(nbc * dxe, dy0, dy1)))
+    for dye in (dy0, dy1):
+        best = np.minimum(best, q(np.clip(nba * dye, dx0, dx1), dye))
+    inside = (dx0 <= 0) & (dx1 >= 0) & (dy0 <= 0) & (dy1 >= 0)
+    return np.where(inside, 0.0, best)
+
+
+def ellipse_meets_tile(p, g, tx, ty, W, H, tile):
+    """Vectorised cutoff-region / tile-box test for Gaussians g of projection p
+    and tiles (tx, ty) (arrays of equal length)."""
+    u = p["u"].detach().numpy()[g]
+    w = p["w"].detach().numpy()[g]
+    a = _f32(p["a"].detach().numpy()[g])
+    b = _f32(p["b"].detach().numpy()[g])
+    c = _f32(p["c"].detach().numpy()[g])
+    L = -2.0 * _f32(p["tau"].detach().numpy()[g])
+    x0 = tx * tile + 0.5
+    x1 = np.minimum(tx * tile + (tile - 0.5), W - 0.5)
+    y0 = ty * tile + 0.5
+    y1 = np.minimum(ty * tile + (tile - 0.5), H - 0.5)
+    return box_min_q(a, b, c, x0 - u, x1 - u, y0 - w, y1 - w) <= L
+
+
+def bin_pairs(projs, cams, tile: int = 16, cull: str = "ellipse"):
     """Returns dict with keys (uint64 [K]), values (uint32 [K], Gaussian index),
-    views (int32 [K]), ranges (int64 [n_tiles, 2]) and counts (int64 [n_tiles])."""
+    views (int32 [K]), ranges (int64 [n_tiles, 2]) and counts (int64 [n_tiles]).
+    cull: "rect" lists every tile of the rect, "ellipse" only the tiles the
+    cutoff region meets."""
     tiles_x, tiles_y, off = tile_layout(cams, tile)
     tiles_all, depth_all, g_all, v_all = [], [], [], []
     for v, p in enumerate(projs):
@@ -34,6 +84,14 @@ def bin_pairs(projs, cams, tile: int = 16):
         nx = (p["tx1"] - p["tx0"] + 1)[rep]
         tx = p["tx0"][rep] + local % nx
         ty = p["ty0"][rep] + local // nx
+        if cull == "ellipse":
+            keep = ellipse_meets_tile(p, rep, tx, ty, p["width"], p["height"], tile)
+            rep, tx, ty = rep[keep], tx[keep], ty[keep]
+            k = int(keep.sum())
+            if k == 0:
+                continue
+        elif cull != "rect":
+            raise ValueError(cull)
         tiles_all.append(off[v] + ty * tiles_x[v] + tx)
         depth_all.append(p["depth_bits"][rep].astype(np.uint64))
         g_all.append(rep.astype(np.int64))

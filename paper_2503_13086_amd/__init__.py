@@ -33,8 +33,9 @@ _STATUS = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_CAPACITY", -3: "GS_ERR_
 
 # Exported symbols (must match include/gs.h).
 EXPORTS = ["gs_abi_version", "gs_create", "gs_destroy", "gs_last_error", "gs_layout", "gs_preprocess", "gs_bin_sort",
-           "gs_render_fwd", "gs_loss", "gs_render_bwd", "gs_adam_step", "gs_buffer_size", "gs_copy_buffer",
-           "gs_profile_enable", "gs_profile_read"]
+           "gs_render_fwd", "gs_loss", "gs_render_bwd", "gs_adam_step", "gs_set_cull", "gs_buffer_size",
+           "gs_copy_buffer", "gs_profile_enable", "gs_profile_read"]
+GS_CULL_RECT, GS_CULL_ELLIPSE = 0, 1
 
 
 class GsError(RuntimeError):
@@ -77,6 +78,7 @@ def _load():
         "gs_adam_step": (_I32, [_P, _P, _P, _P, _P, _P, _I32, _I32, _I32, ctypes.POINTER(ctypes.c_float),
                                 ctypes.POINTER(ctypes.c_float), _I32, ctypes.c_uint32, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float, _P]),
+        "gs_set_cull": (_I32, [_P, _I32]),
         "gs_buffer_size": (_I32, [_P, _I32, ctypes.POINTER(ctypes.c_size_t)]),
         "gs_copy_buffer": (_I32, [_P, _I32, _P, ctypes.c_size_t, _P]),
         "gs_profile_enable": (_I32, [_P, _I32]),
@@ -199,6 +201,10 @@ def gs_adam_step(ctx, params, grad, m, v, step, n: int, stride: int, sh_degree: 
     _check(ctx, _load().gs_adam_step(ctx, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), _ptr(step), n, stride,
                                      sh_degree, lg, vs, nv, group_mask, beta1, beta2, eps, _stream(stream)),
            "gs_adam_step")
+
+
+def gs_set_cull(ctx, mode: int) -> None:
+    _check(ctx, _load().gs_set_cull(ctx, mode), "gs_set_cull")
 
 
 def gs_buffer_size(ctx, which: int) -> int:

@@ -34,8 +34,9 @@ struct gs_ctx {
   uint64_t K = 0;
   std::vector<ViewDev> hviews;
   int depth_in_b = 0, pairs_in_b = 0;
+  int cull = GS_CULL_ELLIPSE;
   DevBuf views, rec, depth, touched, rect;
-  DevBuf dkey[2], dval[2], offsets, blocksums, total, hist, digit_tot;
+  DevBuf dkey[2], dval[2], counts, offsets, blocksums, total, hist, digit_tot;
   DevBuf pkey[2], pval[2], ranges;
   DevBuf tfinal, ncontrib, last, grad2d, lossp, aux;
   ViewDev* h_views = nullptr;
@@ -185,7 +186,7 @@ void gs_destroy(gs_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   DevBuf* bufs[] = {&c->views, &c->rec, &c->depth, &c->touched, &c->rect, &c->dkey[0], &c->dkey[1], &c->dval[0],
-                    &c->dval[1], &c->offsets, &c->blocksums, &c->total, &c->hist, &c->digit_tot, &c->pkey[0],
+                    &c->dval[1], &c->counts, &c->offsets, &c->blocksums, &c->total, &c->hist, &c->digit_tot, &c->pkey[0],
                     &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->tfinal, &c->ncontrib, &c->last,
                     &c->grad2d, &c->lossp, &c->aux};
   for (DevBuf* b : bufs)
@@ -264,6 +265,7 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
     if ((st = ensure(c, c->dval[i], NV * 4, s)) != GS_OK) return st;
   }
   if ((st = ensure(c, c->offsets, NV * 4, s)) != GS_OK) return st;
+  if ((st = ensure(c, c->counts, NV * 4, s)) != GS_OK) return st;
   if ((st = ensure(c, c->blocksums, scan_block_words(NV) * 4, s)) != GS_OK) return st;
   if ((st = ensure(c, c->total, 8, s)) != GS_OK) return st;
   if ((st = ensure(c, c->hist, sort_hist_words(NV) * 4, s)) != GS_OK) return st;
@@ -280,8 +282,9 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
   const uint32_t* order = c->dval[c->depth_in_b].as<uint32_t>();
   {
     Prof pr(c, GS_K_SCAN, s);
-    GS_HIP(c, launch_scan_touched(order, c->touched.as<uint32_t>(), NV, c->offsets.as<uint32_t>(),
-                                  c->blocksums.as<uint32_t>(), c->total.as<unsigned long long>(), s));
+    GS_HIP(c, launch_scan_touched(order, c->touched.as<uint32_t>(), NV, c->counts.as<uint32_t>(),
+                                  c->offsets.as<uint32_t>(), c->blocksums.as<uint32_t>(),
+                                  c->total.as<unsigned long long>(), s));
   }
   GS_HIP(c, hipMemcpyAsync(c->h_total, c->total.p, 8, hipMemcpyDeviceToHost, s));
   GS_HIP(c, hipStreamSynchronize(s));
@@ -295,14 +298,16 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
   if ((st = ensure(c, c->ranges, (size_t)c->n_tiles * 8, s)) != GS_OK) return st;
   {
     Prof pr(c, GS_K_EMIT, s);
-    GS_HIP(c, launch_emit_pairs(order, c->touched.as<uint32_t>(), c->offsets.as<uint32_t>(), c->rect.as<ushort4>(), NV,
-                                c->n, c->views.as<ViewDev>(), c->V, (size_t)K, c->pkey[0].as<uint32_t>(),
+    GS_HIP(c, launch_emit_pairs(order, c->counts.as<uint32_t>(), c->offsets.as<uint32_t>(), c->rect.as<ushort4>(),
+                                c->rec.as<Record>(), NV, c->n, c->views.as<ViewDev>(), c->V, (size_t)K,
+                                (uint32_t)c->n_tiles, c->cull == GS_CULL_ELLIPSE ? 1 : 0, c->pkey[0].as<uint32_t>(),
                                 c->pval[0].as<uint32_t>(), s));
   }
   {
     Prof pr(c, GS_K_TILE_SORT, s);
     SortScratch sc{c->hist.as<uint32_t>(), c->digit_tot.as<uint32_t>()};
-    const int bits = ceil_log2((uint64_t)c->n_tiles) < 1 ? 1 : ceil_log2((uint64_t)c->n_tiles);
+    // tile ids run to n_tiles inclusive (culled pairs)
+    const int bits = ceil_log2((uint64_t)c->n_tiles + 1) < 1 ? 1 : ceil_log2((uint64_t)c->n_tiles + 1);
     GS_HIP(c, radix_sort_pairs(c->pkey[0].as<uint32_t>(), c->pval[0].as<uint32_t>(), c->pkey[1].as<uint32_t>(),
                                c->pval[1].as<uint32_t>(), K, bits, sc, &c->pairs_in_b, s));
   }
@@ -350,10 +355,10 @@ gs_status gs_loss(gs_ctx* c, const float* color, const float* target, float w_l1
   hipStream_t s = (hipStream_t)stream;
   GS_HIP(c, hipSetDevice(c->device));
   gs_status st;
-  if ((st = ensure(c, c->lossp, (size_t)c->n_tiles * 16, s)) != GS_OK) return st;
+  if ((st = ensure(c, c->lossp, (size_t)loss_tiles(c->hviews.data(), c->V) * 16, s)) != GS_OK) return st;
   if (w_dssim != 0.0f && (st = ensure(c, c->aux, (size_t)c->P * 9 * 4, s)) != GS_OK) return st;
   Prof pr(c, GS_K_LOSS, s);
-  GS_HIP(c, launch_loss_dev(c->views.as<ViewDev>(), c->V, c->n_tiles, color, target, w_l1, w_dssim,
+  GS_HIP(c, launch_loss_dev(c->views.as<ViewDev>(), c->hviews.data(), c->V, color, target, w_l1, w_dssim,
                             c->lossp.as<double>(), c->aux.as<float>(), loss_out, dL_dcolor, s));
   return GS_OK;
 }
@@ -424,6 +429,15 @@ gs_status gs_adam_step(gs_ctx* c, float* params, const float* grad, float* m, fl
   Prof pr(c, GS_K_ADAM, s);
   GS_HIP(c, launch_adam(params, grad, m, v, step, n, stride, sh_degree, a,
                         a.n_views ? c->touched.as<uint32_t>() : nullptr, s));
+  return GS_OK;
+}
+
+gs_status gs_set_cull(gs_ctx* c, int32_t mode) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (mode != GS_CULL_RECT && mode != GS_CULL_ELLIPSE) return fail(c, GS_ERR_INVALID, "unknown cull mode");
+  c->cull = mode;
+  if (c->stage > kProjected) c->stage = kProjected;   // pair lists must be rebuilt
   return GS_OK;
 }
 

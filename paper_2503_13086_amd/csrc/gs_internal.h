@@ -68,13 +68,15 @@ hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b
                             int bits, SortScratch scratch, int* result_in_b, hipStream_t s);
 hipError_t launch_iota(uint32_t* p, size_t n, hipStream_t s);
 
-// exclusive scan of touched[order[e]] over e, total written to *total
+// counts[e] = touched[order[e]] and its exclusive scan over e; total written to *total
 size_t scan_block_words(size_t n);
-hipError_t launch_scan_touched(const uint32_t* order, const uint32_t* touched, size_t n, uint32_t* offsets,
-                               uint32_t* block_sums, unsigned long long* total, hipStream_t s);
-hipError_t launch_emit_pairs(const uint32_t* order, const uint32_t* touched, const uint32_t* offsets,
-                             const ushort4* rect, size_t n_entries, int n, const ViewDev* views, int V, size_t K,
-                             uint32_t* pair_tile, uint32_t* pair_rec, hipStream_t s);
+hipError_t launch_scan_touched(const uint32_t* order, const uint32_t* touched, size_t n, uint32_t* counts,
+                               uint32_t* offsets, uint32_t* block_sums, unsigned long long* total, hipStream_t s);
+// cull != 0: pairs whose tile box the cutoff region misses get tile id n_tiles
+hipError_t launch_emit_pairs(const uint32_t* order, const uint32_t* counts, const uint32_t* offsets,
+                             const ushort4* rect, const Record* rec, size_t n_entries, int n, const ViewDev* views,
+                             int V, size_t K, uint32_t n_tiles, int cull, uint32_t* pair_tile, uint32_t* pair_rec,
+                             hipStream_t s);
 hipError_t launch_ranges(const uint32_t* pair_tile, size_t K, uint2* ranges, int n_tiles, hipStream_t s);
 hipError_t launch_compose_keys(const uint32_t* pair_tile, const uint32_t* pair_rec, const uint32_t* depth,
                                size_t K, int n, size_t n_rec, unsigned long long* keys, uint32_t* values,
@@ -88,10 +90,12 @@ hipError_t launch_render_bwd(const ViewDev* views, int V, int n_tiles, const uin
                              const Record* rec, uint32_t n_rec, const float* t_final, const uint32_t* last,
                              const float* dL_dcolor, float* grad2d, hipStream_t s);
 
-// partials: 2 doubles per tile; aux: 9 floats per pixel (SSIM only)
-hipError_t launch_loss_dev(const ViewDev* dviews, int V, int n_tiles, const float* color, const float* target,
-                           float w_l1, float w_dssim, double* partials, float* aux, double* loss_out,
-                           float* dL_dcolor, hipStream_t s);
+// Loss over all views in 32x32-pixel tiles: loss_tiles() tiles, partials 2 doubles
+// per tile, aux 9 floats per pixel (SSIM only).
+int loss_tiles(const ViewDev* hviews, int V);
+hipError_t launch_loss_dev(const ViewDev* dviews, const ViewDev* hviews, int V, const float* color,
+                           const float* target, float w_l1, float w_dssim, double* partials, float* aux,
+                           double* loss_out, float* dL_dcolor, hipStream_t s);
 
 struct AdamArgs {
   float lr[GS_N_GROUPS];

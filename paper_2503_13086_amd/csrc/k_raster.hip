@@ -9,13 +9,17 @@
 // offsets are accurate fp32 numbers at any image size.
 //
 // Backward (Sec. IV-E): the same tiling, walking each list back to front from the
-// last position any pixel of the tile blended.  Each pixel recovers its
-// transmittance by division and keeps the colour accumulated behind the current
-// Gaussian.  The nine per-Gaussian partials (u, w, a, b, c, o, r, g, b) are summed
-// across the wavefront with DPP row shifts and row broadcasts, across the four
-// wavefronts with LDS atomics, and leave the workgroup as one global atomic per
-// (tile, Gaussian, component) instead of one per (pixel, Gaussian, component).
-// Wavefronts in which no pixel touches a Gaussian skip its reduction.
+// last position any pixel of the tile blended (each wavefront starts at the last
+// position its own pixels blended).  Each pixel recovers its transmittance with
+// one reciprocal per Gaussian and keeps the colour accumulated behind it.  Per
+// Gaussian, nine per-pixel values (the moments of dL/d(exponent) over dx, dy,
+// dx^2, dx dy, dy^2, then opacity and colour partials) are summed across the
+// wavefront by a reduce-scatter (CDNA4 permlane swaps across halves and row
+// pairs, then DPP row sums) and across the four wavefronts with LDS atomics; the
+// moments become centre and conic partials once per tile, and each workgroup
+// issues one global atomic per (tile, Gaussian, component) instead of one per
+// (pixel, Gaussian, component).  Wavefronts in which no pixel blended a Gaussian
+// skip it.
 #include "gs_internal.h"
 
 #pragma clang fp contract(off)
@@ -32,8 +36,12 @@ __device__ inline int view_of_tile(const ViewDev* __restrict__ views, int V, int
   return v;
 }
 
-// exponent of the 2D Gaussian at offset (dx, dy); A = -a/2, B = -b, C = -c/2
-__device__ inline float gauss_power(float A, float B, float C, float dx, float dy) {
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+// Base-2 exponent of the 2D Gaussian at offset (dx, dy): with A = -a/2, B = -b,
+// C = -c/2 pre-scaled by log2(e), e^power = 2^result.
+__device__ inline float gauss_power2(float A, float B, float C, float dx, float dy) {
   return __fmaf_rn(A * dx, dx, __fmaf_rn(C * dy, dy, (B * dx) * dy));
 }
 
@@ -60,15 +68,17 @@ __device__ inline TileGeom tile_geom(const ViewDev* __restrict__ views, int V, i
   return t;
 }
 
-// stage record `rid` for a tile with origin (ox, oy)
+// Stage record `rid` for a tile with origin (ox, oy): centre relative to the tile,
+// exponent coefficients and cutoff in base-2 units (the exponent's sign and the
+// cutoff test are unchanged by the positive factor), opacity, colour.
 __device__ inline void stage(const Record* __restrict__ rec, uint32_t rid, double ox, double oy, float4& q0,
                              float4& q1, float4& q2) {
   const Record* r = rec + rid;
   const double2 uw = *reinterpret_cast<const double2*>(r);
   const float4 c = reinterpret_cast<const float4*>(r)[1];
   const float4 d = reinterpret_cast<const float4*>(r)[2];
-  q0 = make_float4((float)(uw.x - ox), (float)(uw.y - oy), -0.5f * c.x, -c.y);
-  q1 = make_float4(-0.5f * c.z, c.w, d.x, 0.0f);
+  q0 = make_float4((float)(uw.x - ox), (float)(uw.y - oy), (-0.5f * c.x) * kLog2e, (-c.y) * kLog2e);
+  q1 = make_float4((-0.5f * c.z) * kLog2e, c.w, d.x * kLog2e, 0.0f);
   q2 = make_float4(d.y, d.z, d.w, 0.0f);
 }
 
@@ -101,28 +111,30 @@ __global__ __launch_bounds__(NT) void k_render_fwd(const ViewDev* __restrict__ v
       }
     }
     __syncthreads();
-    if (!done) {
+    if (__ballot(!done) != 0ull) {
+      // straight-line per-Gaussian update; lanes that skip or have stopped keep their state
+      const uint32_t pos0 = base - rg.x + 1;
       for (uint32_t j = 0; j < m; ++j) {
+        if ((j & 7u) == 0u && j != 0u && __ballot(!done) == 0ull) break;
         const float4 a0 = s0[j];
         const float4 a1 = s1[j];
         const float dx = a0.x - fx, dy = a0.y - fy;
-        const float power = gauss_power(a0.z, a0.w, a1.x, dx, dy);
-        if (power > 0.0f || power < a1.z) continue;
-        const float og = a1.y * __expf(power);
-        const float alpha = fminf(kAlphaMax, og);
-        const float Tn = Tr * (1.0f - alpha);
-        if (Tn < kTMin) {
-          done = true;
-          break;
-        }
+        const float p2 = gauss_power2(a0.z, a0.w, a1.x, dx, dy);
+        const bool pass = !done && p2 <= 0.0f && p2 >= a1.z;
+        if (__ballot(pass) == 0ull) continue;   // no pixel of this wave takes it
         const float4 a2 = s2[j];
-        const float wgt = alpha * Tr;
-        C0 += a2.x * wgt;
-        C1 += a2.y * wgt;
-        C2 += a2.z * wgt;
-        Tr = Tn;
-        ++cnt;
-        lastp = base - rg.x + j + 1;
+        const float alpha = fminf(kAlphaMax, a1.y * __builtin_amdgcn_exp2f(p2));
+        const float Tn = Tr * (1.0f - alpha);
+        const bool stop = pass && Tn < kTMin;
+        const bool blend = pass && !stop;
+        done = done || stop;
+        const float wgt = blend ? alpha * Tr : 0.0f;
+        C0 = __fmaf_rn(a2.x, wgt, C0);
+        C1 = __fmaf_rn(a2.y, wgt, C1);
+        C2 = __fmaf_rn(a2.z, wgt, C2);
+        Tr = blend ? Tn : Tr;
+        cnt += blend ? 1u : 0u;
+        lastp = blend ? pos0 + j : lastp;
       }
     }
     if (__syncthreads_and(done)) break;
@@ -142,15 +154,52 @@ __global__ __launch_bounds__(NT) void k_render_fwd(const ViewDev* __restrict__ v
   }
 }
 
-// Sum of v over the wavefront, valid in lane 63 (GFX9 DPP: row shifts, then row broadcasts).
-__device__ inline float wave_sum_lane63(float v) {
+// a + b across the two halves of the wave: lanes 0-31 receive the sum of a over
+// lanes l and l + 32, lanes 32-63 the sum of b (v_permlane32_swap, CDNA4).
+__device__ inline float fold32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// The same across row pairs: rows (0, 1) and (2, 3) of 16 lanes; row 0 and row 2
+// keep a, rows 1 and 3 keep b (v_permlane16_swap, CDNA4).
+__device__ inline float fold16(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Sum over the 16 lanes of each row, valid in the row's lane 15 (DPP row shifts).
+__device__ inline float row_sum(float v) {
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));  // row_shr:1
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, true));  // row_shr:2
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xf, 0xf, true));  // row_shr:4
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, true));  // row_shr:8
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xa, 0xf, false)); // row_bcast:15
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xc, 0xf, false)); // row_bcast:31
   return v;
+}
+
+// Reduce-scatter of nine per-lane values over the wave, added into acc[0..8].
+// Halving folds across wave halves and row pairs leave each row holding the
+// partial sums of distinct values (3 registers instead of 9), a row sum finishes
+// them in lane 15 of each row, and four lanes add their sums into LDS with three
+// instructions: row r of the first register holds value {0, 2, 1, 3}[r], of the
+// second that value + 4, and row 0 of the third holds value 8.
+__device__ inline void wave_reduce9_to_lds(const float (&v)[kGrad2D], float* acc) {
+  const float b0 = fold32(v[0], v[1]);
+  const float b1 = fold32(v[2], v[3]);
+  const float b2 = fold32(v[4], v[5]);
+  const float b3 = fold32(v[6], v[7]);
+  const float b4 = fold32(v[8], 0.0f);
+  const float c0 = row_sum(fold16(b0, b1));
+  const float c1 = row_sum(fold16(b2, b3));
+  const float c2 = row_sum(fold16(b4, 0.0f));
+  const unsigned lane = __lane_id();
+  if ((lane & 15u) == 15u) {
+    const unsigned row = lane >> 4;
+    const unsigned k0 = ((row & 1u) << 1) | (row >> 1);
+    atomicAdd(acc + k0, c0);
+    atomicAdd(acc + k0 + 4, c1);
+    if (row == 0) atomicAdd(acc + 8, c2);
+  }
 }
 
 __global__ __launch_bounds__(NT) void k_render_bwd(const ViewDev* __restrict__ views, int V,
@@ -188,6 +237,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(const ViewDev* __restrict__ v
   }
   uint32_t mx = lp;
   for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
+  const int wave_last = (int)mx;           // this wave never needs list positions >= wave_last
   if (__lane_id() == 0) smax[threadIdx.x / 64] = mx;
   for (int k = 0; k < kGrad2D; ++k) acc[threadIdx.x][k] = 0.0f;
   __syncthreads();
@@ -210,70 +260,61 @@ __global__ __launch_bounds__(NT) void k_render_bwd(const ViewDev* __restrict__ v
       }
     }
     __syncthreads();
-    for (int j = m - 1; j >= 0; --j) {
-      bool on = tg.inside && (uint32_t)(beg + j) < lp;
-      float pu = 0.f, pw = 0.f, pa = 0.f, pb = 0.f, pc = 0.f, po = 0.f, pr = 0.f, pg = 0.f, pbl = 0.f;
-      if (on) {
-        const float4 a0 = s0[j];
-        const float4 a1 = s1[j];
-        const float dx = a0.x - fx, dy = a0.y - fy;
-        const float power = gauss_power(a0.z, a0.w, a1.x, dx, dy);
-        if (power > 0.0f || power < a1.z) {
-          on = false;
-        } else {
-          const float4 a2 = s2[j];
-          const float G = __expf(power);
-          const float og = a1.y * G;
-          const bool capped = og > kAlphaMax;
-          const float alpha = capped ? kAlphaMax : og;
-          const float oma = 1.0f - alpha;
-          Tr = Tr / oma;                    // transmittance in front of this Gaussian
-          const float wgt = alpha * Tr;
-          pr = g0 * wgt;
-          pg = g1 * wgt;
-          pbl = g2 * wgt;
-          const float dLda = g0 * (a2.x * Tr - S0 / oma) + g1 * (a2.y * Tr - S1 / oma) + g2 * (a2.z * Tr - S2 / oma);
-          S0 += a2.x * wgt;
-          S1 += a2.y * wgt;
-          S2 += a2.z * wgt;
-          if (!capped) {
-            const float dpow = dLda * og;
-            po = dLda * G;
-            pu = dpow * (2.0f * a0.z * dx + a0.w * dy);
-            pw = dpow * (a0.w * dx + 2.0f * a1.x * dy);
-            pa = dpow * (-0.5f * dx * dx);
-            pb = dpow * (-(dx * dy));
-            pc = dpow * (-0.5f * dy * dy);
-          }
-        }
-      }
-      if (__ballot(on) != 0ull) {
-        pu = wave_sum_lane63(pu);
-        pw = wave_sum_lane63(pw);
-        pa = wave_sum_lane63(pa);
-        pb = wave_sum_lane63(pb);
-        pc = wave_sum_lane63(pc);
-        po = wave_sum_lane63(po);
-        pr = wave_sum_lane63(pr);
-        pg = wave_sum_lane63(pg);
-        pbl = wave_sum_lane63(pbl);
-        if (__lane_id() == 63) {
-          float* a = acc[j];
-          atomicAdd(a + 0, pu);
-          atomicAdd(a + 1, pw);
-          atomicAdd(a + 2, pa);
-          atomicAdd(a + 3, pb);
-          atomicAdd(a + 4, pc);
-          atomicAdd(a + 5, po);
-          atomicAdd(a + 6, pr);
-          atomicAdd(a + 7, pg);
-          atomicAdd(a + 8, pbl);
-        }
-      }
+    const int jtop = min(m, wave_last - beg) - 1;
+    for (int j = jtop; j >= 0; --j) {
+      const float4 a0 = s0[j];
+      const float4 a1 = s1[j];
+      const float dx = a0.x - fx, dy = a0.y - fy;
+      const float p2 = gauss_power2(a0.z, a0.w, a1.x, dx, dy);
+      const bool on = tg.inside && (uint32_t)(beg + j) < lp && p2 <= 0.0f && p2 >= a1.z;
+      if (__ballot(on) == 0ull) continue;    // no pixel of this wave blended it
+      // straight-line update; lanes that did not blend this Gaussian keep their state
+      // and contribute zeros
+      const float4 a2 = s2[j];
+      const float G = __builtin_amdgcn_exp2f(p2);
+      const float og = a1.y * G;
+      const bool capped = og > kAlphaMax;
+      const float alpha = capped ? kAlphaMax : og;
+      const float ri = __builtin_amdgcn_rcpf(1.0f - alpha);
+      Tr = on ? Tr * ri : Tr;                // transmittance in front of this Gaussian
+      const float wgt = on ? alpha * Tr : 0.0f;
+      // Per pixel: colour partials, opacity partial and the moments of the exponent's
+      // derivative dpow over (dx, dy, dx^2, dx dy, dy^2); the centre and conic
+      // partials are fixed linear maps of these moments (applied once per tile).
+      float p[kGrad2D];
+      p[6] = g0 * wgt;
+      p[7] = g1 * wgt;
+      p[8] = g2 * wgt;
+      float dLda = g0 * __fmaf_rn(-S0, ri, a2.x * Tr);
+      dLda = __fmaf_rn(g1, __fmaf_rn(-S1, ri, a2.y * Tr), dLda);
+      dLda = __fmaf_rn(g2, __fmaf_rn(-S2, ri, a2.z * Tr), dLda);
+      dLda = (on && !capped) ? dLda : 0.0f;  // a capped alpha has zero derivative
+      S0 = __fmaf_rn(a2.x, wgt, S0);
+      S1 = __fmaf_rn(a2.y, wgt, S1);
+      S2 = __fmaf_rn(a2.z, wgt, S2);
+      const float dpow = dLda * og;           // dL/d(exponent)
+      p[5] = dLda * G;
+      p[0] = dpow * dx;
+      p[1] = dpow * dy;
+      p[2] = p[0] * dx;
+      p[3] = p[0] * dy;
+      p[4] = p[1] * dy;
+      wave_reduce9_to_lds(p, acc[j]);
     }
     __syncthreads();
     if ((int)threadIdx.x < m) {
       float* a = acc[threadIdx.x];
+      // moments -> partials: with exponent p = -(a dx^2 + 2 b dx dy + c dy^2)/2 and the
+      // staged coefficients A, B, C = (-a/2, -b, -c/2) log2(e):
+      // dp/du = ln2 (2A dx + B dy), dp/dw = ln2 (B dx + 2C dy),
+      // dp/da = -dx^2/2, dp/db = -dx dy, dp/dc = -dy^2/2
+      const float A = s0[threadIdx.x].z, B = s0[threadIdx.x].w, C = s1[threadIdx.x].x;
+      const float m1 = a[0], m2 = a[1], m3 = a[2], m4 = a[3], m5 = a[4];
+      a[0] = kLn2 * (2.0f * A * m1 + B * m2);
+      a[1] = kLn2 * (B * m1 + 2.0f * C * m2);
+      a[2] = -0.5f * m3;
+      a[3] = -m4;
+      a[4] = -0.5f * m5;
       const uint32_t rid = srid[threadIdx.x];
       float* dst = grad2d + (size_t)rid * kGrad2D;
       for (int k = 0; k < kGrad2D; ++k) {

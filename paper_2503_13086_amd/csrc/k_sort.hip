@@ -16,6 +16,8 @@
 // LDS in digit order and writes each digit's run contiguously to global memory.
 #include "gs_internal.h"
 
+#pragma clang fp contract(off)
+
 namespace gsk {
 namespace {
 
@@ -41,22 +43,36 @@ __device__ inline uint64_t match_digit(uint32_t d, bool valid) {
   return peers;
 }
 
+// Per-workgroup digit histogram.  Wave w of a workgroup owns items
+// [base + 1024 w, base + 1024 (w + 1)); per 64-item round the leader lane of each
+// digit group adds the group's size to the wave's own counter (distinct
+// addresses, no atomics).
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys, size_t n, int shift,
                                                           uint32_t* __restrict__ hist, int n_blocks) {
-  __shared__ uint32_t h[kRadix];
-  h[threadIdx.x] = 0;
+  __shared__ uint32_t hw[kWaves][kRadix];
+  const int w = threadIdx.x / 64;
+  for (int i = 0; i < kWaves; ++i) hw[i][threadIdx.x] = 0;
   __syncthreads();
-  const size_t base = (size_t)blockIdx.x * kSortTileItems;
+  const size_t base = (size_t)blockIdx.x * kSortTileItems + (size_t)w * (kItems * 64) + __lane_id();
+  uint32_t kk[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {   // all loads in flight before any ranking
+    const size_t i = base + (size_t)r * 64;
+    kk[r] = i < n ? keys[i] : 0u;
+  }
+  const uint64_t lt = lanemask_lt();
+#pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    const size_t i = base + (size_t)r * kThreads + threadIdx.x;
-    const bool valid = i < n;
-    const uint32_t d = valid ? (keys[i] >> shift) & 0xffu : 0u;
+    const bool valid = base + (size_t)r * 64 < n;
+    const uint32_t d = (kk[r] >> shift) & 0xffu;
     const uint64_t peers = match_digit(d, valid);
-    // the lowest lane of each digit group adds the group's size
-    if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    if (valid && (peers & lt) == 0) hw[w][d] += (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();   // the leaders' updates precede the next round's reads
   }
   __syncthreads();
-  hist[(size_t)threadIdx.x * n_blocks + blockIdx.x] = h[threadIdx.x];
+  uint32_t t = 0;
+  for (int i = 0; i < kWaves; ++i) t += hw[i][threadIdx.x];
+  hist[(size_t)threadIdx.x * n_blocks + blockIdx.x] = t;
 }
 
 // digit_tot[d] = sum over blocks of hist[d][*]
@@ -116,6 +132,11 @@ __global__ __launch_bounds__(kThreads) void k_radix_scan_rows(uint32_t* __restri
   }
 }
 
+// Stable scatter of one digit pass.  Items are ranked in workgroup order (wave w
+// owns items [base + 1024 w, base + 1024 (w + 1)), then round, then lane): within a
+// wave from ballot peer masks and the wave's running digit counters (no barrier per
+// round), across waves from the counters' prefix.  The workgroup then places its
+// items in LDS in digit order and writes each digit's run contiguously.
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __restrict__ keys_in,
                                                              const uint32_t* __restrict__ vals_in, size_t n, int shift,
                                                              const uint32_t* __restrict__ offsets, int n_blocks,
@@ -123,65 +144,63 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
                                                              uint32_t* __restrict__ vals_out) {
   __shared__ uint32_t s_keys[kSortTileItems];
   __shared__ uint32_t s_vals[kSortTileItems];
-  __shared__ uint32_t wc[kWaves][kRadix];   // per-wave digit counts of the current round
-  __shared__ uint32_t run[kRadix];          // items of each digit in earlier rounds
+  __shared__ uint32_t wc[kWaves][kRadix];   // per-wave running digit counts
   __shared__ uint32_t lstart[kRadix];       // workgroup-local start of each digit
   __shared__ uint32_t goff[kRadix];         // global start of this workgroup's run of each digit
+  __shared__ uint32_t wsum[kWaves];
   const int tid = threadIdx.x;
   const int wave = tid / 64;
-  run[tid] = 0;
   for (int w = 0; w < kWaves; ++w) wc[w][tid] = 0;
   goff[tid] = offsets[(size_t)tid * n_blocks + blockIdx.x];
   __syncthreads();
 
-  const size_t base = (size_t)blockIdx.x * kSortTileItems;
+  const size_t base = (size_t)blockIdx.x * kSortTileItems + (size_t)wave * (kItems * 64) + __lane_id();
   uint32_t k[kItems], v[kItems], rank[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {   // all loads in flight before any ranking
+    const size_t i = base + (size_t)r * 64;
+    k[r] = i < n ? keys_in[i] : 0xffffffffu;
+    v[r] = i < n ? vals_in[i] : 0u;
+  }
   const uint64_t lt = lanemask_lt();
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    const size_t i = base + (size_t)r * kThreads + tid;
-    const bool valid = i < n;
-    k[r] = valid ? keys_in[i] : 0xffffffffu;
-    v[r] = valid ? vals_in[i] : 0u;
+    const bool valid = base + (size_t)r * 64 < n;
     const uint32_t d = (k[r] >> shift) & 0xffu;
     const uint64_t peers = match_digit(d, valid);
-    const bool leader = valid && (peers & lt) == 0;
-    if (leader) wc[wave][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    uint32_t before = run[d];
-    for (int w = 0; w < wave; ++w) before += wc[w][d];
-    rank[r] = before + (uint32_t)__popcll(peers & lt);
-    __syncthreads();
+    rank[r] = wc[wave][d] + (uint32_t)__popcll(peers & lt);
+    if (valid && (peers & lt) == 0) wc[wave][d] += (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();   // the leaders' updates precede the next round's reads
+  }
+  __syncthreads();
+  // per digit: totals over waves (into wc[.][d] as exclusive wave prefixes) and the
+  // exclusive scan over digits of the totals
+  {
     uint32_t tot = 0;
     for (int w = 0; w < kWaves; ++w) {
-      tot += wc[w][tid];
-      wc[w][tid] = 0;
+      const uint32_t c = wc[w][tid];
+      wc[w][tid] = tot;
+      tot += c;
     }
-    run[tid] += tot;
-    __syncthreads();
-  }
-  // exclusive scan of run[] over digits -> local digit starts
-  {
-    const uint32_t x = run[tid];
-    uint32_t incl = x;
+    uint32_t incl = tot;
     for (int off = 1; off < 64; off <<= 1) {
       const uint32_t y = __shfl_up(incl, off);
       if ((int)__lane_id() >= off) incl += y;
     }
-    if (__lane_id() == 63) wc[0][wave] = incl;
+    if (__lane_id() == 63) wsum[wave] = incl;
     __syncthreads();
     uint32_t wpre = 0;
-    for (int w = 0; w < wave; ++w) wpre += wc[0][w];
-    lstart[tid] = wpre + incl - x;
+    for (int w = 0; w < wave; ++w) wpre += wsum[w];
+    lstart[tid] = wpre + incl - tot;
     __syncthreads();
   }
-  const size_t valid_items = n > base ? (n - base < (size_t)kSortTileItems ? n - base : (size_t)kSortTileItems) : 0;
+  const size_t blk0 = (size_t)blockIdx.x * kSortTileItems;
+  const size_t valid_items = n > blk0 ? (n - blk0 < (size_t)kSortTileItems ? n - blk0 : (size_t)kSortTileItems) : 0;
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    const size_t i = base + (size_t)r * kThreads + tid;
-    if (i < n) {
+    if (base + (size_t)r * 64 < n) {
       const uint32_t d = (k[r] >> shift) & 0xffu;
-      const uint32_t pos = lstart[d] + rank[r];
+      const uint32_t pos = lstart[d] + wc[wave][d] + rank[r];
       s_keys[pos] = k[r];
       s_vals[pos] = v[r];
     }
@@ -216,15 +235,22 @@ __device__ inline uint32_t block_sum_u32(uint32_t x, uint32_t* sh) {
   return t;
 }
 
+// Block sums of touched[order[e]]; the gathered counts are stored in depth order
+// (counts[e]) so the later passes read them contiguously.
 __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t* __restrict__ order,
                                                            const uint32_t* __restrict__ touched, size_t n,
+                                                           uint32_t* __restrict__ counts,
                                                            uint32_t* __restrict__ block_sums) {
   __shared__ uint32_t sh[kWaves];
   const size_t base = (size_t)blockIdx.x * kScanItems;
   uint32_t s = 0;
   for (int r = 0; r < kScanItems / kThreads; ++r) {
     const size_t i = base + (size_t)r * kThreads + threadIdx.x;
-    if (i < n) s += touched[order[i]];
+    if (i < n) {
+      const uint32_t c = touched[order[i]];
+      counts[i] = c;
+      s += c;
+    }
   }
   const uint32_t t = block_sum_u32(s, sh);
   if (threadIdx.x == 0) block_sums[blockIdx.x] = t;
@@ -258,8 +284,7 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t* __restrict__ blo
   if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t* __restrict__ order,
-                                                          const uint32_t* __restrict__ touched, size_t n,
+__global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t* __restrict__ counts, size_t n,
                                                           const uint32_t* __restrict__ block_off,
                                                           uint32_t* __restrict__ offsets) {
   __shared__ uint32_t wsum[kWaves];
@@ -269,7 +294,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t* __restr
   const size_t base = (size_t)blockIdx.x * kScanItems;
   for (int r = 0; r < kScanItems / kThreads; ++r) {
     const size_t i = base + (size_t)r * kThreads + threadIdx.x;
-    const uint32_t x = i < n ? touched[order[i]] : 0u;
+    const uint32_t x = i < n ? counts[i] : 0u;
     uint32_t incl = x;
     for (int off = 1; off < 64; off <<= 1) {
       const uint32_t y = __shfl_up(incl, off);
@@ -287,39 +312,134 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t* __restr
   }
 }
 
-// One thread per depth-ordered entry writes the (tile, record) pairs of its tile rect.
-__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ order,
-                                                    const uint32_t* __restrict__ touched,
-                                                    const uint32_t* __restrict__ offsets,
-                                                    const ushort4* __restrict__ rect, size_t n_entries, int n,
-                                                    const ViewDev* __restrict__ views, size_t K,
-                                                    uint32_t* __restrict__ pair_tile, uint32_t* __restrict__ pair_rec) {
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n_entries) return;
-  const uint32_t rid = order[e];
-  const uint32_t cnt = touched[rid];
-  if (cnt == 0) return;
-  const int v = (int)(rid / (uint32_t)n);
-  const ushort4 rc = rect[rid];
-  const uint32_t tiles_x = (uint32_t)views[v].tiles_x;
-  const uint32_t toff = (uint32_t)views[v].tile_off;
-  size_t o = offsets[e];
-  if (o + cnt > K) return;   // never for a consistent scan; guards the writes
-  for (uint32_t ty = rc.z; ty <= rc.w; ++ty)
-    for (uint32_t tx = rc.x; tx <= rc.y; ++tx) {
-      pair_tile[o] = toff + ty * tiles_x + tx;
-      pair_rec[o] = rid;
-      ++o;
-    }
+// Minimum of q(dx, dy) = a dx^2 + 2 b dx dy + c dy^2 (positive definite) over the
+// box [dx0, dx1] x [dy0, dy1]: 0 when the box holds the origin, else the smallest
+// of the minima along the four edges (clamped 1-D minimisers).  FP64, no
+// contraction, fixed operation order, so the decision is reproducible.
+__device__ inline double qform(double a, double b, double c, double dx, double dy) {
+  return ((a * dx) * dx + ((2.0 * b) * dx) * dy) + (c * dy) * dy;
+}
+__device__ inline double box_min_q(double a, double b, double c, double nbc, double nba, double dx0, double dx1,
+                                   double dy0, double dy1) {
+  double best = qform(a, b, c, dx0, fmin(fmax(nbc * dx0, dy0), dy1));
+  best = fmin(best, qform(a, b, c, dx1, fmin(fmax(nbc * dx1, dy0), dy1)));
+  best = fmin(best, qform(a, b, c, fmin(fmax(nba * dy0, dx0), dx1), dy0));
+  best = fmin(best, qform(a, b, c, fmin(fmax(nba * dy1, dx0), dx1), dy1));
+  if (dx0 <= 0.0 && dx1 >= 0.0 && dy0 <= 0.0 && dy1 >= 0.0) best = 0.0;
+  return best;
 }
 
-__global__ void k_ranges(const uint32_t* __restrict__ tile, size_t K, uint2* __restrict__ ranges, uint32_t n_tiles) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (size_t)gridDim.x * blockDim.x) {
-    const uint32_t t = tile[i];
-    if (t >= n_tiles) continue;
-    if (i == 0 || tile[i - 1] != t) ranges[t].x = (uint32_t)i;
-    if (i == K - 1 || tile[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+// Pair emission, one wave per 64 consecutive depth-ordered entries.  The wave's
+// pairs occupy one contiguous output range; each lane writes every 64th output
+// position of it, finding its entry by binary search over the wave's entry
+// offsets in LDS, so writes are coalesced and large tile rects are shared by the
+// whole wave.  With culling on, a pair whose tile box (spanned by the tile's
+// pixel centres) the Gaussian's cutoff region a dx^2 + 2 b dx dy + c dy^2 <= -2 tau
+// does not meet is given the tile id n_tiles, which sorts after every real tile
+// and belongs to no range: no pixel of that tile could blend it.
+__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ order,
+                                                    const uint32_t* __restrict__ counts,
+                                                    const uint32_t* __restrict__ offsets,
+                                                    const ushort4* __restrict__ rect,
+                                                    const Record* __restrict__ rec, size_t n_entries, int n,
+                                                    const ViewDev* __restrict__ views, size_t K, uint32_t n_tiles,
+                                                    int cull, uint32_t* __restrict__ pair_tile,
+                                                    uint32_t* __restrict__ pair_rec) {
+  __shared__ uint32_t s_off[kWaves][65];
+  __shared__ uint32_t s_rid[kWaves][64];
+  __shared__ uint32_t s_base[kWaves][64];   // global tile id of the rect's first tile
+  __shared__ uint32_t s_nx[kWaves][64];     // rect width in tiles
+  __shared__ uint32_t s_tx[kWaves][64];     // tiles per row of the entry's view
+  __shared__ uint32_t s_org[kWaves][64];    // rect origin (tx0 | ty0 << 16)
+  __shared__ uint32_t s_wh[kWaves][64];     // view size (W | H << 16)
+  __shared__ double s_geo[kWaves][64][7];   // u, w, a, b, c, -b/c, -b/a
+  __shared__ double s_lim[kWaves][64];      // -2 tau
+  const int w = threadIdx.x / 64;
+  const unsigned lane = __lane_id();
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = e < n_entries;
+  uint32_t cnt = 0, off = 0, rid = 0;
+  if (valid) {
+    rid = order[e];
+    cnt = counts[e];
+    off = offsets[e];
   }
+  // lanes past the last entry take the wave's end offset
+  uint32_t end = valid ? off + cnt : 0u;
+  for (int o = 32; o > 0; o >>= 1) end = max(end, (uint32_t)__shfl_xor((int)end, o));
+  if (!valid) off = end;
+  s_off[w][lane] = off;
+  s_rid[w][lane] = rid;
+  if (lane == 0) s_off[w][64] = end;
+  if (cnt) {
+    const ushort4 rc = rect[rid];
+    const ViewDev& cv = views[rid / (uint32_t)n];
+    s_base[w][lane] = (uint32_t)cv.tile_off + (uint32_t)rc.z * (uint32_t)cv.tiles_x + rc.x;
+    s_nx[w][lane] = (uint32_t)(rc.y - rc.x + 1);
+    s_tx[w][lane] = (uint32_t)cv.tiles_x;
+    if (cull) {
+      const Record& r = rec[rid];
+      const double a = r.a, b = r.b, c = r.c;
+      s_org[w][lane] = (uint32_t)rc.x | ((uint32_t)rc.z << 16);
+      s_wh[w][lane] = (uint32_t)cv.W | ((uint32_t)cv.H << 16);
+      s_geo[w][lane][0] = r.u;
+      s_geo[w][lane][1] = r.w;
+      s_geo[w][lane][2] = a;
+      s_geo[w][lane][3] = b;
+      s_geo[w][lane][4] = c;
+      s_geo[w][lane][5] = -b / c;
+      s_geo[w][lane][6] = -b / a;
+      s_lim[w][lane] = -2.0 * (double)r.tau;
+    }
+  }
+  __syncthreads();
+  const uint32_t start = s_off[w][0];
+  if (end > K) return;                     // never for a consistent scan; guards the writes
+  for (uint32_t q = start + lane; q < end; q += 64) {
+    // largest l with s_off[l] <= q (entries without pairs share their successor's offset)
+    int lo = 0, hi = 63;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_off[w][mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t local = q - s_off[w][lo];
+    const uint32_t nx = s_nx[w][lo];
+    uint32_t ty = (uint32_t)((float)local / (float)nx);
+    if (ty * nx > local) --ty;
+    else if ((ty + 1) * nx <= local) ++ty;
+    const uint32_t tx = local - ty * nx;
+    uint32_t tile = s_base[w][lo] + ty * s_tx[w][lo] + tx;
+    if (cull) {
+      const double* gp = s_geo[w][lo];
+      const uint32_t org = s_org[w][lo], wh = s_wh[w][lo];
+      const int gx = (int)((org & 0xffffu) + tx), gy = (int)((org >> 16) + ty);
+      const double x0 = (double)(gx * kTile) + 0.5;
+      const double x1 = fmin((double)(gx * kTile) + (kTile - 0.5), (double)(wh & 0xffffu) - 0.5);
+      const double y0 = (double)(gy * kTile) + 0.5;
+      const double y1 = fmin((double)(gy * kTile) + (kTile - 0.5), (double)(wh >> 16) - 0.5);
+      const double qm = box_min_q(gp[2], gp[3], gp[4], gp[5], gp[6], x0 - gp[0], x1 - gp[0], y0 - gp[1], y1 - gp[1]);
+      if (!(qm <= s_lim[w][lo])) tile = n_tiles;
+    }
+    pair_tile[q] = tile;
+    pair_rec[q] = s_rid[w][lo];
+  }
+}
+
+// Tile boundaries in the sorted tile ids; each thread scans 8 consecutive ids.
+__global__ void k_ranges(const uint32_t* __restrict__ tile, size_t K, uint2* __restrict__ ranges, uint32_t n_tiles) {
+  const size_t i0 = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
+  if (i0 >= K) return;
+  uint32_t prev = i0 == 0 ? 0xffffffffu : tile[i0 - 1];
+  const size_t i1 = i0 + 8 < K ? i0 + 8 : K;
+  for (size_t i = i0; i < i1; ++i) {
+    const uint32_t t = tile[i];
+    if (t != prev) {
+      if (t < n_tiles) ranges[t].x = (uint32_t)i;
+      if (prev < n_tiles) ranges[prev].y = (uint32_t)i;
+    }
+    prev = t;
+  }
+  if (i1 == K && prev < n_tiles) ranges[prev].y = (uint32_t)K;
 }
 
 // mode 0: keys + values, mode 1: views of the pairs
@@ -379,29 +499,32 @@ hipError_t launch_iota(uint32_t* p, size_t n, hipStream_t s) {
 
 size_t scan_block_words(size_t n) { return (n + kScanItems - 1) / kScanItems + 1; }
 
-hipError_t launch_scan_touched(const uint32_t* order, const uint32_t* touched, size_t n, uint32_t* offsets,
-                               uint32_t* block_sums, unsigned long long* total, hipStream_t s) {
+hipError_t launch_scan_touched(const uint32_t* order, const uint32_t* touched, size_t n, uint32_t* counts,
+                               uint32_t* offsets, uint32_t* block_sums, unsigned long long* total, hipStream_t s) {
   const int nb = (int)((n + kScanItems - 1) / kScanItems);
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, s, order, touched, n, block_sums);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, s, order, touched, n, counts, block_sums);
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, block_sums, nb, total);
-  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kThreads), 0, s, order, touched, n, block_sums, offsets);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kThreads), 0, s, counts, n, block_sums, offsets);
   return hipGetLastError();
 }
 
-hipError_t launch_emit_pairs(const uint32_t* order, const uint32_t* touched, const uint32_t* offsets,
-                             const ushort4* rect, size_t n_entries, int n, const ViewDev* views, int V, size_t K,
-                             uint32_t* pair_tile, uint32_t* pair_rec, hipStream_t s) {
+hipError_t launch_emit_pairs(const uint32_t* order, const uint32_t* counts, const uint32_t* offsets,
+                             const ushort4* rect, const Record* rec, size_t n_entries, int n, const ViewDev* views,
+                             int V, size_t K, uint32_t n_tiles, int cull, uint32_t* pair_tile, uint32_t* pair_rec,
+                             hipStream_t s) {
   (void)V;
-  hipLaunchKernelGGL(k_emit, dim3(grid_for(n_entries, kThreads)), dim3(kThreads), 0, s, order, touched, offsets, rect,
-                     n_entries, n, views, K, pair_tile, pair_rec);
+  if (n_entries == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((n_entries + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, order, counts, offsets, rect, rec, n_entries, n,
+                     views, K, n_tiles, cull, pair_tile, pair_rec);
   return hipGetLastError();
 }
 
 hipError_t launch_ranges(const uint32_t* pair_tile, size_t K, uint2* ranges, int n_tiles, hipStream_t s) {
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, (size_t)n_tiles * 2, s);
   if (e != hipSuccess || K == 0) return e;
-  hipLaunchKernelGGL(k_ranges, dim3(grid_for(K, 256, 65536)), dim3(256), 0, s, pair_tile, K, ranges,
-                     (uint32_t)n_tiles);
+  const unsigned blocks = (unsigned)((K + 8 * 256 - 1) / (8 * 256));
+  hipLaunchKernelGGL(k_ranges, dim3(blocks), dim3(256), 0, s, pair_tile, K, ranges, (uint32_t)n_tiles);
   return hipGetLastError();
 }
 

@@ -25,19 +25,23 @@ def ambiguous(r) -> np.ndarray:
             (r["m_T"] < MARGIN_T))
 
 
-def run_gpu(scene, upstream=None, loss=False, keep=None):
-    """Forward (and optionally backward) of the HIP path; returns numpy outputs."""
+def run_gpu(scene, upstream=None, loss=False, cull=None):
+    """Forward (and optionally backward) of the HIP path; returns numpy outputs.
+    cull: None (library default), "rect" or "ellipse"."""
     from paper_2503_13086_amd.pipeline import Rasterizer, params_to_device
     from paper_2503_13086_amd import (GS_BUF_RECORDS, GS_BUF_DEPTH, GS_BUF_TOUCHED, GS_BUF_TILE_RECT,
                                       GS_BUF_KEYS, GS_BUF_VALUES, GS_BUF_RANGES, GS_BUF_T_FINAL,
                                       GS_BUF_N_CONTRIB, GS_BUF_LAST, GS_BUF_PAIR_VIEW)
+    import paper_2503_13086_amd as gs
     rz = Rasterizer(0)
     try:
+        if cull is not None:
+            gs.gs_set_cull(rz.ctx, gs.GS_CULL_RECT if cull == "rect" else gs.GS_CULL_ELLIPSE)
         P = params_to_device(scene.params)
         rz.preprocess(P, scene.n, scene.sh_degree, scene.cams)
         K = rz.bin_sort()
         color = rz.render_fwd()
-        out = dict(K=K, color=[x.cpu().numpy() for x in rz.image_views(color)])
+        out = dict(K=K, n_tiles=rz.tile_off[-1], color=[x.cpu().numpy() for x in rz.image_views(color)])
         V, n = len(scene.cams), scene.n
         rec = rz.buffer(GS_BUF_RECORDS).cpu().numpy().view(np.uint8).reshape(V, n, 48)
         out["u"] = rec[:, :, 0:8].copy().view(np.float64)[..., 0]
@@ -73,6 +77,16 @@ def run_gpu(scene, upstream=None, loss=False, keep=None):
         return out
     finally:
         rz.close()
+
+
+def valid_pairs(g):
+    """Sorted pairs that belong to a tile (culled pairs carry tile id n_tiles)."""
+    tiles = (g["keys"] >> np.uint64(32)).astype(np.int64)
+    ok = tiles < g["n_tiles"]
+    n_ok = int(ok.sum())
+    assert ok[:n_ok].all(), "culled pairs must sort after every real tile"
+    assert (tiles[n_ok:] == g["n_tiles"]).all()
+    return g["keys"][:n_ok], g["values"][:n_ok], g["pair_view"][:n_ok]
 
 
 def masked_upstream(up, amb_maps):

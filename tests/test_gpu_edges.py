@@ -61,7 +61,8 @@ def test_near_plane_and_offscreen():
     g = gu.run_gpu(sc)
     assert np.array_equal(g["touched"][0], projs[0]["touched"])
     b = oracle.bin_pairs(projs, [cam], 16)
-    assert np.array_equal(g["keys"], b["keys"]) and np.array_equal(g["values"], b["values"])
+    keys, values, _ = gu.valid_pairs(g)
+    assert np.array_equal(keys, b["keys"]) and np.array_equal(values, b["values"])
     r = composite.render_view(projs[0])
     ok = ~gu.ambiguous(r)
     assert np.abs(g["color"][0] - r["color"]).max(axis=0)[ok].max() <= 1e-4

@@ -66,14 +66,36 @@ def test_preprocess_parity(name):
 
 @pytest.mark.parametrize("name", list(SCENES))
 def test_bin_sort_bit_exact(name):
+    """Default (cutoff-region) culling: the pairs that belong to tiles, their order
+    and the ranges equal the oracle's; every rect pair keeps a slot."""
     sc, projs, g, _, renders = _get(name)
-    b = oracle.bin_pairs(projs, sc.cams, 16)
+    b = oracle.bin_pairs(projs, sc.cams, 16, cull="ellipse")
+    full = oracle.bin_pairs(projs, sc.cams, 16, cull="rect")
+    assert g["K"] == len(full["keys"])
+    keys, values, views = gu.valid_pairs(g)
+    assert np.array_equal(keys, b["keys"])
+    assert np.array_equal(values, b["values"])
+    assert np.array_equal(views, b["views"].astype(np.uint32))
+    assert np.array_equal(g["ranges"].astype(np.int64), b["ranges"])
+    assert np.array_equal((g["ranges"][:, 1] - g["ranges"][:, 0]).astype(np.int64), b["counts"])
+    assert len(keys) < len(full["keys"])
+
+
+@pytest.mark.parametrize("name", ["ragged2v_sh3", "c1_10k_sh0"])
+def test_bin_sort_rect_mode_bit_exact_and_same_image(name):
+    """Rect mode: every pair of every tile rect, bit-exact; the image matches the
+    oracle just as in the culled mode."""
+    sc, projs, g_cull, _, renders = _get(name)
+    g = gu.run_gpu(sc, cull="rect")
+    b = oracle.bin_pairs(projs, sc.cams, 16, cull="rect")
     assert g["K"] == len(b["keys"])
     assert np.array_equal(g["keys"], b["keys"])
     assert np.array_equal(g["values"], b["values"])
-    assert np.array_equal(g["pair_view"], b["views"].astype(np.uint32))
     assert np.array_equal(g["ranges"].astype(np.int64), b["ranges"])
-    assert np.array_equal((g["ranges"][:, 1] - g["ranges"][:, 0]).astype(np.int64), b["counts"])
+    for v, r in enumerate(renders):
+        ok = ~gu.ambiguous(r)
+        assert np.abs(g["color"][v] - r["color"]).max(axis=0)[ok].max() <= 1e-4
+        assert np.abs(g["color"][v] - g_cull["color"][v]).max(axis=0)[ok].max() <= 1e-6
 
 
 @pytest.mark.parametrize("name", list(SCENES))

@@ -244,7 +244,7 @@ def test_tile_rect_brute_force(tile):
 def test_binning_sorted_and_ranges():
     sc = scenegen.small_scene(12, 120, 1, [(40, 29), (33, 50)], log_scale_mean=-2.4)
     projs = geometry.project_views(sc.params, sc.n, 1, sc.cams, 16)
-    b = binning.bin_pairs(projs, sc.cams, 16)
+    b = binning.bin_pairs(projs, sc.cams, 16, cull="rect")
     tiles_x, tiles_y, off = geometry.tile_layout(sc.cams, 16)
     tup = []
     for v, pr in enumerate(projs):
@@ -292,3 +292,53 @@ def test_view_dependent_colour_independent_route():
     # solved centre differ at that level
     assert np.abs(pr["rgb"].numpy() - ref).max() < 1e-5
     assert (ref == 0).any() and (ref > 0).any()
+
+
+def test_box_min_matches_dense_sampling():
+    """Closed-form minimum of a positive-definite quadratic over a box against a
+    dense grid over the box (the grid can only be above it, and not by much)."""
+    rng = np.random.default_rng(13)
+    for _ in range(300):
+        Lm = rng.normal(size=(2, 2))
+        A = Lm @ Lm.T + 0.05 * np.eye(2)
+        a, b, c = A[0, 0], A[0, 1], A[1, 1]
+        dx0, dy0 = rng.uniform(-6, 4, 2)
+        dx1, dy1 = dx0 + rng.uniform(0.1, 5), dy0 + rng.uniform(0.1, 5)
+        qm = float(binning.box_min_q(np.float64(a), np.float64(b), np.float64(c), np.float64(dx0),
+                                     np.float64(dx1), np.float64(dy0), np.float64(dy1)))
+        X, Y = np.meshgrid(np.linspace(dx0, dx1, 201), np.linspace(dy0, dy1, 201))
+        grid = a * X * X + 2 * b * X * Y + c * Y * Y
+        assert grid.min() >= qm - 1e-12 * max(1.0, abs(qm))
+        step = max(dx1 - dx0, dy1 - dy0) / 200
+        gmax = 2 * max(abs(a) + abs(b), abs(b) + abs(c)) * (max(abs(dx0), abs(dx1), abs(dy0), abs(dy1)) + 1)
+        assert grid.min() - qm <= gmax * step
+
+
+@pytest.mark.parametrize("tile", [16, 8])
+def test_ellipse_culling_keeps_every_contributing_tile(tile):
+    """Every (Gaussian, tile) pair with a pixel centre that passes the cutoff is
+    kept; the culled pairs hold none; culling removes a real share of the rect."""
+    sc = scenegen.small_scene(14, 300, 0, [(90, 70)], log_scale_mean=-2.0, half_extent=1.2, depth=2.5)
+    p = geometry.project_views(sc.params, sc.n, 0, sc.cams, tile)[0]
+    full = binning.bin_pairs([p], sc.cams, tile, cull="rect")
+    kept = binning.bin_pairs([p], sc.cams, tile, cull="ellipse")
+    tiles_x = (90 + tile - 1) // tile
+    kset = set(zip((kept["keys"] >> np.uint64(32)).astype(np.int64).tolist(), kept["values"].tolist()))
+    u, w = p["u"].numpy(), p["w"].numpy()
+    a, b, c, tau = (p[k].numpy() for k in ("a", "b", "c", "tau"))
+    n_contrib_pairs = 0
+    for key, g in zip(full["keys"], full["values"]):
+        t = int(key >> np.uint64(32))
+        tx, ty = t % tiles_x, t // tiles_x
+        xs = np.arange(tx * tile, min((tx + 1) * tile, 90)) + 0.5
+        ys = np.arange(ty * tile, min((ty + 1) * tile, 70)) + 0.5
+        X, Y = np.meshgrid(xs - u[g], ys - w[g])
+        power = -0.5 * (a[g] * X * X + c[g] * Y * Y) - b[g] * X * Y
+        margin = (power - tau[g]) / (abs(tau[g]) + np.abs(power) + 1e-12)
+        if (margin > 1e-6).any():
+            n_contrib_pairs += 1
+            assert (t, int(g)) in kset
+        if (t, int(g)) not in kset:
+            assert (margin < 1e-6).all()
+    assert len(kept["keys"]) < 0.9 * len(full["keys"])
+    assert n_contrib_pairs > 0.5 * len(kept["keys"])

@@ -8,12 +8,13 @@ import sys
 import pytest
 
 import oracle
-from oracle import geometry, composite, sh, loss, grad, adam
+from oracle import geometry, composite, sh, loss, grad, adam, binning
 import tests.test_oracle_geometry as TG
 import tests.test_oracle_render as TR
 import tests.test_oracle_grad_loss_adam as TL
 
-_MODS = {"geometry": geometry, "composite": composite, "sh": sh, "loss": loss, "grad": grad, "adam": adam}
+_MODS = {"geometry": geometry, "composite": composite, "sh": sh, "loss": loss, "grad": grad, "adam": adam,
+         "binning": binning}
 
 
 @contextlib.contextmanager
@@ -94,6 +95,12 @@ MUTATIONS = [
      "alpha2 = torch.clamp(o2[None, :].detach() * torch.exp(power2), max=alpha_max)",
      [(TL.test_param_grads_finite_differences, (42, 1, (0.0, 0.0, 0.0)))]),
     ("adam", "bc2 = 1.0 - b2 ** k", "bc2 = 1.0 - b1 ** k", [(TL.test_adam_matches_torch_fp64, ())]),
+    ("binning", "    nbc = -b / c\n", "    nbc = b / c\n", [(TG.test_box_min_matches_dense_sampling, ())]),
+    ("binning", "    return np.where(inside, 0.0, best)", "    return best",
+     [(TG.test_box_min_matches_dense_sampling, ())]),
+    ("binning", "L = -2.0 * _f32(", "L = -1.0 * _f32(", [(TG.test_ellipse_culling_keeps_every_contributing_tile, (16,))]),
+    ("binning", "order = np.lexsort((gg, dp, tl))", "order = np.lexsort((dp, gg, tl))",
+     [(TG.test_binning_sorted_and_ranges, ())]),
     ("adam", "return np.where(cnt > 0, s / np.maximum(cnt, 1), vs.mean())", "return np.where(cnt > 0, s, vs.mean())",
      [(TL.test_adam_view_factor_and_first_step_closed_form, ())]),
 ]
