@@ -59,6 +59,49 @@ def algorithmic_bytes(n, n_p, V, K, P, tiles, ssim):
     }
 
 
+# Flops per pixel-Gaussian evaluation (add, mul, compare, min, exp2, reciprocal = 1;
+# fma = 2).  Every list position up to a pixel's last blended Gaussian takes the
+# cutoff test: centre offset (2), base-2 exponent (3 mul + 2 fma = 7), two
+# comparisons (2) = 11.  A blended Gaussian adds, in the forward, exp2, opacity
+# product, clamp, 1 - alpha, transmittance product, stop test, weight and three
+# colour fmas = 13; in the backward, exp2, opacity product, clamp, 1 - alpha,
+# reciprocal, transmittance recovery, weight, the alpha derivative over three
+# channels (15), cap select, exponent derivative, six moment/opacity products,
+# three colour products, three suffix-colour fmas (6) and the nine sums over
+# pixels = 48.
+TEST_FLOPS = 11
+FWD_BLEND_FLOPS = 13
+BWD_BLEND_FLOPS = 48
+
+
+def raster_flops(visits, blends):
+    """Algorithmic flops of one forward and one backward raster launch."""
+    return {"render_fwd": TEST_FLOPS * visits + FWD_BLEND_FLOPS * blends,
+            "render_bwd": TEST_FLOPS * visits + BWD_BLEND_FLOPS * blends}
+
+
+KERNEL_SOURCE = {"render_fwd": "k_raster.hip", "render_bwd": "k_raster.hip", "preprocess": "k_preprocess.hip",
+                 "preprocess_bwd": "k_preprocess.hip", "tile_sort": "k_sort.hip", "depth_sort": "k_sort.hip",
+                 "emit": "k_sort.hip", "loss": "k_loss.hip", "adam": "k_adam.hip"}
+
+
+def traffic_for(kernel, workload):
+    """HBM bytes per launch of `kernel` measured with the FETCH_SIZE and WRITE_SIZE
+    counters (profiles/<kernel>_traffic_<workload>.json), or None when there is no
+    such record or the kernel's source has changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic_{workload}.json")
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCE:
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, "paper_2503_13086_amd", "csrc", KERNEL_SOURCE[kernel])
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec.get("source_sha256"):
+            return None
+    return rec.get("bytes_per_launch")
+
+
 def cpu_baseline(scene, budget_s=20.0):
     """The FP64 oracle, as it is, on a bounded sample of the workload: forward and
     backward of a few pixels of the first view (every Gaussian evaluated per pixel),
@@ -98,6 +141,39 @@ def cpu_baseline(scene, budget_s=20.0):
                       f"all {scene.n} Gaussians; {t_total:.1f} s"}
 
 
+def serving_leg(n_arrivals, time_scale, slots):
+    """The on-the-fly stream served twice on fresh fields: the plain loop (one job
+    at a time, one view per step) and continuous batching (up to `slots` jobs per
+    step).  Targets and new Gaussians are resident on the device before timing."""
+    import torch
+    import scenegen
+    from paper_2503_13086_amd.serving import Engine, Field
+    t = time.perf_counter()
+    st = scenegen.serving_stream(n_arrivals=n_arrivals)
+    dev = torch.device("cuda", 0)
+    targets = [torch.as_tensor(a.target()).reshape(-1).to(dev) for a in st.arrivals]
+    for a in st.arrivals:
+        a.block = torch.as_tensor(a.block).to(dev)
+    print(f"[bench] serving stream {st.name}: {n_arrivals} arrivals, prepared in {time.perf_counter() - t:.1f}s",
+          file=sys.stderr, flush=True)
+    out = {"workload": st.name, "arrivals": n_arrivals, "iterations_per_arrival": 200,
+           "time_scale": time_scale, "mean_interarrival_s": 2.0 * time_scale,
+           "initial_gaussians": int(st.initial.shape[1]),
+           "loss": "0.8 L1 + 0.2 D-SSIM", "lr": "Eq. 6-8, T_a = 200"}
+    for name, s in (("plain_loop", 1), ("continuous_batching", slots)):
+        fld = Field(st.initial, st.sh_degree, capacity=st.initial.shape[1])
+        eng = Engine(fld, max_slots=s, t_i=200, seed=5)
+        t = time.perf_counter()
+        stats = eng.run(st.arrivals, targets, time_scale=time_scale)
+        eng.close()
+        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in stats.summary().items()}
+        print(f"[bench] serving {name}: {json.dumps(out[name])} ({time.perf_counter() - t:.1f}s)", file=sys.stderr,
+              flush=True)
+        del fld, eng
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +182,14 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain-loop", action="store_true")
+    ap.add_argument("--serve-arrivals", type=int, default=200,
+                    help="arrivals of the serving stream (0 skips the serving leg)")
+    ap.add_argument("--serve-time-scale", type=float, default=0.1,
+                    help="arrival times (Poisson, mean gap 2 s) are multiplied by this factor")
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (a known-size kernel that calibrates "
+                         "HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU split of this path "
@@ -138,9 +222,8 @@ def main():
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
     step = torch.zeros(n, dtype=torch.int32, device=dev)
-    stream = torch.cuda.current_stream()
 
-    def one_step(batched=True):
+    def one_step():
         rz.preprocess(params, n, D, sc.cams)
         rz.bin_sort()
         rz.render_fwd(color)
@@ -151,6 +234,12 @@ def main():
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     K = rz.K
     rz.profile(True)
     torch.cuda.synchronize()
@@ -167,10 +256,11 @@ def main():
                      ["preprocess", "depth_sort", "scan", "emit", "tile_sort", "ranges", "render_fwd", "loss", "zero",
                       "render_bwd", "preprocess_bwd"])
 
-    # per-pixel work actually needed: list positions up to each pixel's last blended Gaussian
-    from paper_2503_13086_amd import GS_BUF_LAST
-    last = rz.buffer(GS_BUF_LAST).to(torch.int64)
-    evals_bwd = int(last.sum().item())
+    # per-pixel work the method needs: list positions up to each pixel's last blended
+    # Gaussian (each takes the cutoff test) and the Gaussians it blended
+    from paper_2503_13086_amd import GS_BUF_LAST, GS_BUF_N_CONTRIB
+    visits = int(rz.buffer(GS_BUF_LAST).to(torch.int64).sum().item())
+    blends = int(rz.buffer(GS_BUF_N_CONTRIB).to(torch.int64).sum().item())
 
     # plain loop: each view on its own call sequence, gradients summed, one Adam step
     plain_ms = None
@@ -200,22 +290,20 @@ def main():
     n_tiles = rz.tile_off[-1]
     algo = algorithmic_bytes(n, n_p, V, K, P, n_tiles, sc.w_dssim != 0)
     # dominant kernel and its roofline
-    dom = max(["render_fwd", "render_bwd", "preprocess", "tile_sort", "depth_sort", "preprocess_bwd", "adam", "loss"],
-              key=lambda k: kern_ms[k] * kern_launches[k])
-    flops_per_eval_bwd = 60.0   # VALU flops per (pixel, Gaussian) visit of the backward incl. reductions
+    dom = max(["render_fwd", "render_bwd", "preprocess", "tile_sort", "depth_sort", "preprocess_bwd", "adam", "loss",
+               "emit"], key=lambda k: kern_ms[k] * kern_launches[k])
     if dom in ("render_bwd", "render_fwd"):
-        if dom == "render_bwd":
-            achieved = evals_bwd * flops_per_eval_bwd / (kern_ms[dom] * 1e-3) / 1e12
-        else:
-            achieved = evals_bwd * 25.0 / (kern_ms[dom] * 1e-3) / 1e12
+        flops = raster_flops(visits, blends)[dom]
+        achieved = flops / (kern_ms[dom] * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": dom,
-                "kernel_ms": kern_ms[dom]}
+                "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic_for(dom, args.workload), "kernel": dom,
+                "kernel_ms": kern_ms[dom], "algorithmic_flops": flops}
     else:
-        key = {"tile_sort": "tile_sort", "depth_sort": "tile_sort"}.get(dom, dom)
+        key = {"tile_sort": "tile_sort", "depth_sort": "tile_sort", "emit": "scan_emit"}.get(dom, dom)
         achieved = algo[key] / (kern_ms[dom] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom, "kernel_ms": kern_ms[dom]}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom, args.workload), "kernel": dom,
+                "kernel_ms": kern_ms[dom]}
 
     mpix = P / (t_step) / 1e6
     line = {
@@ -239,9 +327,13 @@ def main():
         "plain_loop_ms_per_step": round(plain_ms, 3) if plain_ms else None,
         "kernel_ms_per_step": {k: round(kern_ms[k] * kern_launches[k] / args.steps, 4) for k in kern_ms},
         "algorithmic_gb_per_step": {k: round(b / 1e9, 4) for k, b in algo.items()},
-        "evals_bwd": evals_bwd,
+        "visits": visits,
+        "blends": blends,
         "roofline": roof,
     }
+    if args.serve_arrivals > 0:
+        rz.close()
+        line["serving"] = serving_leg(args.serve_arrivals, args.serve_time_scale, args.serve_slots)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(sc)

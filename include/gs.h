@@ -204,6 +204,45 @@ gs_status gs_copy_buffer(gs_ctx* ctx, int32_t which, void* dst, size_t bytes, gs
 gs_status gs_profile_enable(gs_ctx* ctx, int32_t enable);
 gs_status gs_profile_read(gs_ctx* ctx, int32_t kernel, int64_t* launches, double* total_ms);
 
+/* Device memory (bytes) held by the context's own buffers right now. */
+gs_status gs_memory_bytes(const gs_ctx* ctx, size_t* bytes);
+
+/* ---- Host-only schedule of progressive training (no device work, no context) ----
+ * Images are numbered 0..n-1.  overlap: host FP64 [n][n] row-major, entry (i, j)
+ * the overlap degree of images i and j normalised to [0, 1] (0 = no overlap; the
+ * diagonal is ignored).  Negative or non-finite entries give GS_ERR_INVALID. */
+
+/* Sec. IV-C, Eq. 3-4: hierarchical weights for the newly added image new_image.
+ * The new image has weight 1 (layer 1).  Layer k >= 2 holds the images not in an
+ * earlier layer that overlap some image of layer k-1; each gets the mean over
+ * layer k-1 of (that image's weight x overlap), which for layer 2 is Eq. 3's
+ * overlap with the new image.  weights: host FP64 [n] out, -1 for images no layer
+ * reaches.  layer: host int32 [n] out (1 = new image, 0 = unreached), may be NULL. */
+gs_status gs_sched_weights(const double* overlap, int32_t n, int32_t new_image, double* weights,
+                           int32_t* layer);
+
+/* Sec. IV-C: which image each of the t_i iterations after an arrival trains.
+ * Local half (t_i / 2 iterations): the n_m reached images (weight >= 0) of largest
+ * weight (ties: smaller index) share it by Eq. 5 in proportion to 1 - exp(-w),
+ * rounded by largest remainder (ties: smaller index) to sum exactly to t_i / 2, and
+ * are visited round robin in weight order while their share lasts.  Semi-global
+ * half (the remaining t_i - t_i / 2): the other images (every image when all are
+ * key images) ordered by the caller's uniform draws u (host FP64 [n]; ties by
+ * index) and taken cyclically, so counts differ by at most one and more images
+ * than iterations means a draw without replacement.  plan: host int32 [t_i] out.
+ * local_iters: host int32 [n] out (Eq. 5 share, 0 off the key set), may be NULL. */
+gs_status gs_sched_plan(const double* weights, int32_t n, int32_t n_m, int32_t t_i, const double* u,
+                        int32_t* plan, int32_t* local_iters);
+
+/* Sec. IV-D, Eq. 6-8: per-image learning rate.  trained: host int64 [n],
+ * iterations image j has been trained so far.  Eq. 7 progress t = min(1, T_j/t_a);
+ * Eq. 6 current rate exp(ln(eta0)(1 - t) + ln(etaf) t) -> lr_current (host FP64
+ * [n], may be NULL); Eq. 8 rate (own rate + sum over overlapping images i of
+ * overlap(i, j) x their rate) / (their count + 1) -> lr (host FP64 [n]).
+ * GS_ERR_INVALID for non-positive rates or t_a, or negative counts. */
+gs_status gs_sched_lr(const int64_t* trained, const double* overlap, int32_t n, double eta0, double etaf,
+                      double t_a, double* lr_current, double* lr);
+
 #ifdef __cplusplus
 }
 #endif

@@ -64,3 +64,29 @@ def local_budget(weights: Dict[int, float], n_m: int, t_i: int) -> Dict[int, int
     for i in sorted(top, key=lambda i: (-(share[i] - base[i]), i))[:rem]:
         base[i] += 1
     return base
+
+
+def iteration_plan(weights: Dict[int, float], n: int, n_m: int, t_i: int, u: Sequence[float]) -> List[int]:
+    """Sec. IV-C: the image trained by each of the T_I iterations after an arrival.
+
+    Local half: the Eq. 5 shares of the key images (local_budget), spent round
+    robin over the key images in weight order (ties by index) while a share lasts.
+    Semi-global half (T_I minus the local count): the remaining images are spread
+    evenly -- ordered by the uniform draws u (ties by index) and taken cyclically,
+    so counts differ by at most one and, with more images than iterations, the
+    ones trained are a draw without replacement.  With no remaining image the
+    semi-global half covers every image.  (The paper fixes neither the visiting
+    order nor the rounding; these are readings.)"""
+    share = local_budget(weights, n_m, t_i) if weights else {}
+    keys = sorted(share, key=lambda i: (-weights[i], i))
+    left = dict(share)
+    local: List[int] = []
+    while any(left[i] > 0 for i in keys):
+        for i in keys:
+            if left[i] > 0:
+                local.append(i)
+                left[i] -= 1
+    rest = [i for i in range(n) if i not in share] or list(range(n))
+    rest.sort(key=lambda i: (u[i], i))
+    semi = [rest[k % len(rest)] for k in range(t_i - len(local))]
+    return local + semi

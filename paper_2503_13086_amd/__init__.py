@@ -34,7 +34,8 @@ _STATUS = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_CAPACITY", -3: "GS_ERR_
 # Exported symbols (must match include/gs.h).
 EXPORTS = ["gs_abi_version", "gs_create", "gs_destroy", "gs_last_error", "gs_layout", "gs_preprocess", "gs_bin_sort",
            "gs_render_fwd", "gs_loss", "gs_render_bwd", "gs_adam_step", "gs_set_cull", "gs_buffer_size",
-           "gs_copy_buffer", "gs_profile_enable", "gs_profile_read"]
+           "gs_copy_buffer", "gs_profile_enable", "gs_profile_read", "gs_memory_bytes", "gs_sched_weights",
+           "gs_sched_plan", "gs_sched_lr"]
 GS_CULL_RECT, GS_CULL_ELLIPSE = 0, 1
 
 
@@ -53,6 +54,9 @@ class GsCamera(ctypes.Structure):
 _lib = None
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
+_D = ctypes.POINTER(ctypes.c_double)
+_IP = ctypes.POINTER(ctypes.c_int32)
+_LP = ctypes.POINTER(ctypes.c_int64)
 
 
 def _load():
@@ -83,6 +87,10 @@ def _load():
         "gs_copy_buffer": (_I32, [_P, _I32, _P, ctypes.c_size_t, _P]),
         "gs_profile_enable": (_I32, [_P, _I32]),
         "gs_profile_read": (_I32, [_P, _I32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
+        "gs_memory_bytes": (_I32, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+        "gs_sched_weights": (_I32, [_D, _I32, _I32, _D, _IP]),
+        "gs_sched_plan": (_I32, [_D, _I32, _I32, _I32, _D, _IP, _IP]),
+        "gs_sched_lr": (_I32, [_LP, _D, _I32, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D, _D]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -226,3 +234,58 @@ def gs_profile_read(ctx, kernel: int):
     t = ctypes.c_double(0.0)
     _check(ctx, _load().gs_profile_read(ctx, kernel, ctypes.byref(n), ctypes.byref(t)), "gs_profile_read")
     return n.value, t.value
+
+
+def gs_memory_bytes(ctx) -> int:
+    b = ctypes.c_size_t(0)
+    _check(ctx, _load().gs_memory_bytes(ctx, ctypes.byref(b)), "gs_memory_bytes")
+    return b.value
+
+
+def _f64_array(x, n=None):
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a, a.ctypes.data_as(_D)
+
+
+def gs_sched_weights(overlap, new_image: int):
+    """Eq. 3-4 weights (-1 = unreached) and layers of every image; host only."""
+    import numpy as np
+    M, pM = _f64_array(overlap)
+    n = int(round(M.size ** 0.5))
+    if M.shape != (n, n):
+        raise ValueError("overlap must be a square matrix")
+    w = np.empty(n, np.float64)
+    lay = np.empty(n, np.int32)
+    _check(None, _load().gs_sched_weights(pM, n, new_image, w.ctypes.data_as(_D), lay.ctypes.data_as(_IP)),
+           "gs_sched_weights")
+    return w, lay
+
+
+def gs_sched_plan(weights, n_m: int, t_i: int, u):
+    """Image trained by each of the t_i iterations of an arrival, and the Eq. 5
+    local shares; host only."""
+    import numpy as np
+    w, pw = _f64_array(weights)
+    n = w.size
+    uu, pu = _f64_array(u, n)
+    plan = np.empty(max(t_i, 1), np.int32)
+    share = np.empty(n, np.int32)
+    _check(None, _load().gs_sched_plan(pw, n, n_m, t_i, pu, plan.ctypes.data_as(_IP), share.ctypes.data_as(_IP)),
+           "gs_sched_plan")
+    return plan[:t_i], share
+
+
+def gs_sched_lr(trained, overlap, eta0: float, etaf: float, t_a: float):
+    """Eq. 6-7 current rates and Eq. 8 rates of every image; host only."""
+    import numpy as np
+    T = np.ascontiguousarray(np.asarray(trained, dtype=np.int64))
+    n = T.size
+    M, pM = _f64_array(overlap, n * n)
+    cur = np.empty(n, np.float64)
+    lr = np.empty(n, np.float64)
+    _check(None, _load().gs_sched_lr(T.ctypes.data_as(_LP), pM, n, eta0, etaf, t_a, cur.ctypes.data_as(_D),
+                                     lr.ctypes.data_as(_D)), "gs_sched_lr")
+    return cur, lr

@@ -17,6 +17,7 @@ library context between the two calls:
 """
 from __future__ import annotations
 
+import weakref
 from typing import Optional, Sequence
 
 import torch
@@ -24,6 +25,14 @@ import torch
 from .pipeline import Rasterizer
 
 _shared: dict = {}
+_live: "weakref.WeakSet[Rasterizer]" = weakref.WeakSet()
+
+
+def context_bytes() -> int:
+    """Device memory held right now by the library contexts of this module (the
+    per-call contexts of mode "store" that await their backward, and the shared
+    contexts of mode "recompute")."""
+    return sum(rz.memory_bytes() for rz in list(_live) if rz.ctx)
 
 
 def _shared_rasterizer(device: int) -> Rasterizer:
@@ -32,6 +41,7 @@ def _shared_rasterizer(device: int) -> Rasterizer:
         rz = Rasterizer(device)
         rz.generation = 0
         _shared[device] = rz
+        _live.add(rz)
     return rz
 
 
@@ -51,6 +61,7 @@ class GSRasterize(torch.autograd.Function):
         p = params.detach()
         if mode == "store":
             rz = Rasterizer(device)
+            _live.add(rz)
         elif mode == "recompute":
             rz = _shared_rasterizer(device)
         else:

@@ -80,6 +80,13 @@ gs_status ensure(gs_ctx* c, DevBuf& b, size_t bytes, hipStream_t s) {
   return GS_OK;
 }
 
+std::vector<DevBuf*> all_bufs(gs_ctx* c) {
+  return {&c->views, &c->rec, &c->depth, &c->touched, &c->rect, &c->dkey[0], &c->dkey[1], &c->dval[0],
+          &c->dval[1], &c->counts, &c->offsets, &c->blocksums, &c->total, &c->hist, &c->digit_tot, &c->pkey[0],
+          &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->tfinal, &c->ncontrib, &c->last,
+          &c->grad2d, &c->lossp, &c->aux};
+}
+
 hipEvent_t next_event(gs_ctx* c) {
   if (c->pool_next == c->pool.size()) {
     hipEvent_t e;
@@ -185,11 +192,7 @@ void gs_destroy(gs_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&c->views, &c->rec, &c->depth, &c->touched, &c->rect, &c->dkey[0], &c->dkey[1], &c->dval[0],
-                    &c->dval[1], &c->counts, &c->offsets, &c->blocksums, &c->total, &c->hist, &c->digit_tot, &c->pkey[0],
-                    &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->tfinal, &c->ncontrib, &c->last,
-                    &c->grad2d, &c->lossp, &c->aux};
-  for (DevBuf* b : bufs)
+  for (DevBuf* b : all_bufs(c))
     if (b->p) (void)hipFree(b->p);
   if (c->h_views) (void)hipHostFree(c->h_views);
   if (c->h_total) (void)hipHostFree(c->h_total);
@@ -508,6 +511,14 @@ gs_status gs_profile_enable(gs_ctx* c, int32_t enable) {
     for (auto& v : c->ev) v.clear();
     c->pool_next = 0;
   }
+  return GS_OK;
+}
+
+gs_status gs_memory_bytes(const gs_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return GS_ERR_INVALID;
+  size_t t = 0;
+  for (DevBuf* b : all_bufs(const_cast<gs_ctx*>(c))) t += b->p ? b->cap : 0;
+  *bytes = t;
   return GS_OK;
 }
 

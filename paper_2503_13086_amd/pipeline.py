@@ -11,7 +11,7 @@ from typing import Optional, Sequence
 import numpy as np
 import torch
 
-from . import (gs_create, gs_destroy, gs_layout, gs_preprocess, gs_bin_sort, gs_render_fwd, gs_loss,
+from . import (gs_memory_bytes, gs_create, gs_destroy, gs_layout, gs_preprocess, gs_bin_sort, gs_render_fwd, gs_loss,
                gs_render_bwd, gs_adam_step, gs_buffer_size, gs_copy_buffer, gs_profile_enable, gs_profile_read,
                KERNEL_NAMES, GS_BUF_RECORDS, GS_BUF_DEPTH, GS_BUF_TOUCHED, GS_BUF_TILE_RECT, GS_BUF_KEYS,
                GS_BUF_VALUES, GS_BUF_RANGES, GS_BUF_T_FINAL, GS_BUF_N_CONTRIB, GS_BUF_LAST, GS_BUF_GRAD2D,
@@ -122,6 +122,10 @@ class Rasterizer:
         if nbytes:
             gs_copy_buffer(self.ctx, which, out, nbytes, stream)
         return out
+
+    def memory_bytes(self) -> int:
+        """Device memory held by the library context's own buffers."""
+        return gs_memory_bytes(self.ctx)
 
     def profile(self, enable=True):
         gs_profile_enable(self.ctx, enable)

@@ -230,3 +230,67 @@ def upstream_grads(seed: int, cams, scale=1e-3) -> List[np.ndarray]:
     """Seeded synthetic dL/dcolor images (fp32 [3, H, W] per view)."""
     rng = np.random.default_rng(seed)
     return [(rng.normal(0.0, scale, size=(3, c["height"], c["width"]))).astype(np.float32) for c in cams]
+
+
+def _axis_angle(a, b) -> float:
+    ca = float(np.clip(np.dot(np.asarray(a[0], np.float64)[2], np.asarray(b[0], np.float64)[2]), -1.0, 1.0))
+    return math.degrees(math.acos(ca))
+
+
+@dataclass
+class Arrival:
+    """One image of an on-the-fly stream: when it arrives, its camera, the Gaussians
+    appended to the field for it, and its overlap degree with each earlier image."""
+    time: float
+    cam: dict
+    block: np.ndarray
+    overlap: np.ndarray
+    target_seed: int
+
+    def target(self) -> np.ndarray:
+        rng = np.random.default_rng(self.target_seed)
+        return rng.uniform(0.0, 1.0, size=(3, self.cam["height"], self.cam["width"])).astype(np.float32)
+
+
+@dataclass
+class Stream:
+    initial: np.ndarray
+    sh_degree: int
+    arrivals: List[Arrival]
+    name: str = "stream"
+
+
+def serving_stream(seed=5, n_arrivals=200, n0=50_000, add=(5_000, 20_000), size=(1296, 864), sh_degree=3,
+                   mean_interarrival=2.0, n_landmarks=20_000, block_half_extent=3.0, match_deg=20.0) -> Stream:
+    """Images arriving along a random-walk camera path at Poisson times
+    (exponential gaps of mean `mean_interarrival` seconds, the first at 0).  The
+    field starts with n0 Gaussians in the 20 m box (scale law at n0); each arrival
+    appends U{add} Gaussians in a cube around a point on its optical axis 0.9 of
+    the way to the look-at point (scale law at 2.5M).  The overlap degree of two
+    images (the stand-in for the matched feature points an online SfM reports) is
+    the fraction of the new image's visible landmarks (uniform points in the box)
+    that the earlier image also sees, tapered linearly to 0 as the angle between
+    the two optical axes grows to match_deg (feature matching fails across large
+    viewpoint changes)."""
+    rng = np.random.default_rng(seed)
+    W, H = size
+    initial = make_field(rng, n0, sh_degree, half_extent=10.0, log_scale_mean=scale_law(n0))
+    poses = random_walk(rng, n_arrivals)
+    gaps = rng.exponential(mean_interarrival, size=n_arrivals)
+    gaps[0] = 0.0
+    times = np.cumsum(gaps)
+    marks = rng.uniform(-10.0, 10.0, size=(3, n_landmarks))
+    vis = [in_frustum(marks, R, t, W, H) for (R, t) in poses]
+    arrivals = []
+    for i, (R, t) in enumerate(poses):
+        R64 = np.asarray(R, np.float64)
+        eye = -R64.T @ np.asarray(t, np.float64)
+        centre = eye + 0.9 * np.linalg.norm(eye) * R64[2]
+        k = int(rng.integers(add[0], add[1] + 1))
+        block = make_field(rng, k, sh_degree, center=centre, half_extent=block_half_extent,
+                           log_scale_mean=scale_law(2_500_000))
+        nv = max(1, int(vis[i].sum()))
+        ov = np.array([(vis[i] & vis[j]).sum() / nv * max(0.0, 1.0 - _axis_angle(poses[i], poses[j]) / match_deg)
+                       for j in range(i)], np.float64)
+        arrivals.append(Arrival(float(times[i]), pinhole(R, t, W, H), block, ov, int(rng.integers(0, 2**63 - 1))))
+    return Stream(initial, sh_degree, arrivals, name=f"stream_{n_arrivals}x{W}x{H}_n0_{n0}")

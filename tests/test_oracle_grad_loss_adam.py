@@ -225,3 +225,34 @@ def test_schedule_eq3_to_eq5():
     raw = {i: 1 - math.exp(-w[i]) for i in b}
     for i in b:
         assert abs(b[i] - raw[i] / (2 * sum(raw.values())) * 200) < 1.0
+
+
+def test_schedule_iteration_plan():
+    """Plan pins: local counts are Eq. 5's shares, the semi-global half is spread
+    evenly (counts differ by <= 1) over the non-key images, draws without
+    replacement when they outnumber the iterations, and hand-worked small case."""
+    M = np.array([[0, .5, 0, 0], [.5, 0, .2, 0], [0, .2, 0, 0], [0, 0, 0, 0]], float)
+    w = schedule.hierarchical_weights(M, 0)
+    # shares of Eq. 5 at T_I = 10 over the top 2 (images 0, 1): 3.08 -> 3, 1.92 -> 2
+    assert schedule.iteration_plan(w, 4, 2, 10, [.3, .1, .2, .05]) == [0, 1, 0, 1, 0, 3, 2, 3, 2, 3]
+    rng = np.random.default_rng(7)
+    n = 60
+    A = (rng.random((n, n)) < 0.08) * rng.random((n, n))
+    A = np.maximum(A, A.T)
+    np.fill_diagonal(A, 0)
+    w = schedule.hierarchical_weights(A, 5)
+    u = rng.random(n)
+    plan = schedule.iteration_plan(w, n, 10, 200, u)
+    assert len(plan) == 200
+    share = schedule.local_budget(w, 10, 200)
+    local = plan[:100]
+    assert {i: local.count(i) for i in share} == share
+    semi = plan[100:]
+    others = [i for i in range(n) if i not in share]
+    cnt = np.array([semi.count(i) for i in others])
+    assert cnt.sum() == 100 and cnt.max() - cnt.min() <= 1 and not set(semi) & set(share)
+    # more remaining images than iterations: no repeats
+    plan = schedule.iteration_plan(w, n, 10, 20, u)
+    assert len(set(plan[10:])) == 10
+    # a lone image takes every iteration
+    assert schedule.iteration_plan({0: 1.0}, 1, 10, 7, [0.5]) == [0] * 7
