@@ -159,10 +159,10 @@ def serving_leg(n_arrivals, time_scale, slots):
     out = {"workload": st.name, "arrivals": n_arrivals, "iterations_per_arrival": 200,
            "time_scale": time_scale, "mean_interarrival_s": 2.0 * time_scale,
            "initial_gaussians": int(st.initial.shape[1]),
-           "loss": "0.8 L1 + 0.2 D-SSIM", "lr": "Eq. 6-8, T_a = 200"}
+           "loss": "Eq. 10: 0.47 L1 + 0.12 D-SSIM + 0.41 load balance (Eq. 9)", "lr": "Eq. 6-8, T_a = 200"}
     for name, s in (("plain_loop", 1), ("continuous_batching", slots)):
         fld = Field(st.initial, st.sh_degree, capacity=st.initial.shape[1])
-        eng = Engine(fld, max_slots=s, t_i=200, seed=5)
+        eng = Engine(fld, max_slots=s, t_i=200, seed=5, w_l1=0.47, w_dssim=0.12, w_load=0.41)
         t = time.perf_counter()
         stats = eng.run(st.arrivals, targets, time_scale=time_scale)
         eng.close()
@@ -182,7 +182,7 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain-loop", action="store_true")
-    ap.add_argument("--serve-arrivals", type=int, default=200,
+    ap.add_argument("--serve-arrivals", type=int, default=60,
                     help="arrivals of the serving stream (0 skips the serving leg)")
     ap.add_argument("--serve-time-scale", type=float, default=0.1,
                     help="arrival times (Poisson, mean gap 2 s) are multiplied by this factor")
@@ -213,15 +213,22 @@ def main():
     params = params_to_device(sc.params)
     n, D = sc.n, sc.sh_degree
     rz.set_views(sc.cams)
-    P = rz.P
     target = rz.pack_images(sc.targets)
-    color = rz.new_image()
-    dl = rz.new_image()
     loss = torch.zeros(V, dtype=torch.float64, device=dev)
     grad = torch.zeros_like(params)
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
     step = torch.zeros(n, dtype=torch.int32, device=dev)
+
+    from paper_2503_13086_amd.autotune import Autotuner
+    tuner = Autotuner()
+    tile = tuner.choose(rz, params, n, D, sc.cams, target, sc.w_l1, sc.w_dssim)
+    tune_ms = tuner.last_timings(n, D, sc.cams)
+    print(f"[bench] autotuned tile {tile}: " + ", ".join(f"{t}: {ms:.3f} ms" for t, ms in tune_ms.items()),
+          file=sys.stderr, flush=True)
+    P = rz.P
+    color = rz.new_image()
+    dl = rz.new_image()
 
     def one_step():
         rz.preprocess(params, n, D, sc.cams)
@@ -275,7 +282,7 @@ def main():
                 rz.render_bwd(dl[: 3 * c["width"] * c["height"]], grad, accumulate=vi > 0)
             rz.adam_step(grad, m, v, step, DEFAULT_LR, None, group_mask=1)
         from paper_2503_13086_amd import gs_layout
-        rz_off, _ = gs_layout(sc.cams, 16)
+        rz_off, _ = gs_layout(sc.cams, tile)
         for _ in range(2):
             plain_step()
         torch.cuda.synchronize()
@@ -287,6 +294,7 @@ def main():
         plain_ms = (time.perf_counter() - t0) / reps * 1e3
 
     n_p = n_params(D)
+    rz.set_views(sc.cams)
     n_tiles = rz.tile_off[-1]
     algo = algorithmic_bytes(n, n_p, V, K, P, n_tiles, sc.w_dssim != 0)
     # dominant kernel and its roofline
@@ -321,7 +329,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": sc.name, "gaussians": n, "sh_degree": D, "views": V,
                    "resolutions": [f"{c['width']}x{c['height']}" for c in sc.cams], "pixels": P,
-                   "loss": f"{sc.w_l1} L1 + {sc.w_dssim} D-SSIM", "tile": 16, "pairs": K},
+                   "loss": f"{sc.w_l1} L1 + {sc.w_dssim} D-SSIM", "tile": tile, "pairs": K,
+                   "autotune_fwd_bwd_ms": {str(t): round(ms, 4) for t, ms in tune_ms.items()}},
         "fwd_bwd_mpix_s": round(P / (fwd_bwd_ms * 1e-3) / 1e6, 3),
         "plain_loop_mpix_s": round(P / (plain_ms * 1e-3) / 1e6, 3) if plain_ms else None,
         "plain_loop_ms_per_step": round(plain_ms, 3) if plain_ms else None,

@@ -88,14 +88,15 @@ enum {
                            blended Gaussian, 0 if none */
   GS_BUF_GRAD2D = 10,   /* float  [V*n][9]: dL/d(u, w, a, b, c, o, r, g, b) per (view, Gaussian) */
   GS_BUF_PAIR_VIEW = 11,/* uint32 [K]: view of each sorted pair */
-  GS_N_BUFS = 12
+  GS_BUF_ALPHA_SUM = 12,/* float  [P]: sum of the alphas each pixel blended (soft Gaussian count) */
+  GS_N_BUFS = 13
 };
 
 /* Kernel ids for gs_profile_read. */
 enum {
   GS_K_PREPROCESS = 0, GS_K_DEPTH_SORT = 1, GS_K_SCAN = 2, GS_K_EMIT = 3, GS_K_TILE_SORT = 4,
   GS_K_RANGES = 5, GS_K_RENDER_FWD = 6, GS_K_LOSS = 7, GS_K_RENDER_BWD = 8,
-  GS_K_PREPROCESS_BWD = 9, GS_K_ADAM = 10, GS_K_ZERO = 11, GS_N_KERNELS = 12
+  GS_K_PREPROCESS_BWD = 9, GS_K_ADAM = 10, GS_K_ZERO = 11, GS_K_LOAD = 12, GS_N_KERNELS = 13
 };
 
 int32_t gs_abi_version(void);
@@ -122,7 +123,7 @@ gs_status gs_layout(const gs_camera* cams, int32_t n_views, int32_t tile, int64_
  * exponent tau = max(-4.5, -ln(255 o)) and the view-dependent SH colour
  * max(0, sum_k f_k Y_k(dir) + 1/2).  Depth, screen position, covariance and
  * extent are evaluated in IEEE FP64 in a fixed order.  params: device, read only.
- * tile: 16 (other sizes return GS_ERR_UNSUPPORTED).  Errors: GS_ERR_INVALID for
+ * tile: 8, 16 or 32 (others return GS_ERR_UNSUPPORTED).  Errors: GS_ERR_INVALID for
  * null or misaligned params, n < 1, stride < n, sh_degree outside 0..3, n_views
  * outside 1..GS_MAX_VIEWS, non-positive or oversized images, non-finite or
  * non-positive focal lengths; GS_ERR_CAPACITY if n_views * n >= 2^31. */
@@ -152,6 +153,17 @@ gs_status gs_render_fwd(gs_ctx* ctx, float* color, gs_stream stream);
  * the per-view losses (sign(0) = 0 for the L1 term). */
 gs_status gs_loss(gs_ctx* ctx, const float* color, const float* target, float w_l1, float w_dssim,
                   double* loss_out, float* dL_dcolor, gs_stream stream);
+
+/* Eq. 9 load-balancing term: per view, w_load * std over the view's pixels of G_p,
+ * the number of Gaussians associated with pixel p, read as the soft count
+ * G_p = sum of the alphas p blended (written by gs_render_fwd; a count has no
+ * derivative), std the population standard deviation.  loss_out: device, n_views
+ * doubles (per-view term), may be NULL.  Also stores dL/dG_p =
+ * w_load (G_p - mean) / (P_v std) (0 when std = 0) in the context: the next
+ * gs_render_bwd of the same forward adds it to the derivative of every blended
+ * alpha (on top of dL_dcolor's terms).  w_load = 0 clears it.  A gs_render_fwd
+ * discards it. */
+gs_status gs_load_balance(gs_ctx* ctx, float w_load, double* loss_out, gs_stream stream);
 
 /* Reverse-order backward of gs_render_fwd and gs_preprocess (Sec. IV-E): per
  * tile, pixels walk their lists back to front; per-Gaussian partial gradients

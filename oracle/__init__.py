@@ -20,8 +20,8 @@ remaining conventions follow the original 3DGS configuration, as Sec. V-A states
                 per-image learning rate)
   brute.py      scalar pure-Python compositing for tiny scenes (a pin for composite)
 
-Every function states the passage it follows; the design doc lists the readings taken
-where the paper is silent.
+Every function states the passage it follows and the reading it takes where the
+paper is silent.
 """
 from . import constants  # noqa: F401
 from .geometry import project_view, project_views, tile_layout  # noqa: F401

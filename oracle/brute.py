@@ -15,7 +15,9 @@ from .constants import ALPHA_MAX, T_MIN
 
 
 def render_pixel(proj, i: int, j: int):
-    """Returns (colour [3] with background, T_final, n_blended, last_g)."""
+    """Returns (colour [3] with background, T_final, n_blended, last_g, alpha_sum):
+    alpha_sum is the sum of the alphas of the blended Gaussians (the soft
+    per-pixel Gaussian count of the load-balancing term, see loss.py)."""
     vis = [g for g in range(len(proj["visible"])) if proj["visible"][g]]
     vis.sort(key=lambda g: (int(proj["depth_bits"][g]), g))
     u, w = proj["u"].detach().numpy(), proj["w"].detach().numpy()
@@ -25,6 +27,7 @@ def render_pixel(proj, i: int, j: int):
     T = 1.0
     C = [0.0, 0.0, 0.0]
     nb, last = 0, -1
+    asum = 0.0
     for g in vis:
         dx = float(u[g]) - (i + 0.5)
         dy = float(w[g]) - (j + 0.5)
@@ -40,8 +43,9 @@ def render_pixel(proj, i: int, j: int):
         T = Tn
         nb += 1
         last = g
+        asum += alpha
     bg = proj["bg"]
-    return [C[ch] + T * bg[ch] for ch in range(3)], T, nb, last
+    return [C[ch] + T * bg[ch] for ch in range(3)], T, nb, last, asum
 
 
 def render_image(proj):
@@ -50,11 +54,13 @@ def render_image(proj):
     Tf = np.zeros((H, W))
     nc = np.zeros((H, W), np.int64)
     lg = np.zeros((H, W), np.int64)
+    asum = np.zeros((H, W))
     for j in range(H):
         for i in range(W):
-            cc, t, n, l = render_pixel(proj, i, j)
+            cc, t, n, l, a = render_pixel(proj, i, j)
             col[:, j, i] = cc
             Tf[j, i] = t
             nc[j, i] = n
             lg[j, i] = l
-    return dict(color=col, T_final=Tf, n_contrib=nc, last_g=lg)
+            asum[j, i] = a
+    return dict(color=col, T_final=Tf, n_contrib=nc, last_g=lg, alpha_sum=asum)

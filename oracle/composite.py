@@ -70,7 +70,8 @@ def blend(q, px: np.ndarray, py: np.ndarray, *, cutoffs=True, alpha_max=ALPHA_MA
 
     Returns dict with C [3, n] (differentiable through grad_q when given), T_final
     [n], n_contrib [n], last (position in the ordered list of the last blended
-    Gaussian, -1 if none) and, if margins, m_cut / m_sign / m_cap / m_T [n]."""
+    Gaussian, -1 if none), alpha_sum [n] (sum of the blended alphas, differentiable
+    like C) and, if margins, m_cut / m_sign / m_cap / m_T [n]."""
     n = len(px)
     G = q["u"].shape[0]
     pxc = torch.as_tensor(np.asarray(px, np.float64) + 0.5)
@@ -145,6 +146,9 @@ def blend(q, px: np.ndarray, py: np.ndarray, *, cutoffs=True, alpha_max=ALPHA_MA
     T_final = Tall.gather(1, kstar[:, None]).squeeze(1)
     out["C"] = C
     out["T_final"] = T_final
+    # soft per-pixel Gaussian count of the load-balancing term (loss.py): the sum of
+    # the alphas of the blended Gaussians
+    out["alpha_sum"] = torch.where(blended, alpha2, torch.zeros_like(alpha2)).sum(1)
     return out
 
 
@@ -152,7 +156,7 @@ def composite_pixels(proj, px, py, *, cutoffs=True, alpha_max=ALPHA_MAX, t_min=T
                      max_elems=4_000_000):
     """Blend arbitrary pixels (int arrays px, py) of one view; no autograd.
     Returns color [3, n] (background added), T_final, n_contrib, last_g (index of
-    the last blended Gaussian, -1 if none) and margins."""
+    the last blended Gaussian, -1 if none), alpha_sum and margins."""
     ids = ordered_visible(proj)
     q = select(proj, ids)
     px = np.asarray(px, np.int64)
@@ -160,7 +164,7 @@ def composite_pixels(proj, px, py, *, cutoffs=True, alpha_max=ALPHA_MAX, t_min=T
     n = len(px)
     chunk = max(1, min(1024, max_elems // max(1, len(ids))))
     keys = ["m_cut", "m_sign", "m_cap", "m_T"] if margins else []
-    acc = {k: [] for k in ["C", "T_final", "n_contrib", "last"] + keys}
+    acc = {k: [] for k in ["C", "T_final", "n_contrib", "last", "alpha_sum"] + keys}
     for s in range(0, n, chunk):
         r = blend(q, px[s:s + chunk], py[s:s + chunk], cutoffs=cutoffs, alpha_max=alpha_max,
                   t_min=t_min, margins=margins)

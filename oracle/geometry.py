@@ -3,8 +3,10 @@
 Follows Eq. 1 (Sec. III): a Gaussian centred at X0 with covariance
 Sigma = R S S^T R^T.  The projection to the image (EWA splatting), the extent,
 the cutoff and the tile rect are not written out in the paper; they follow the
-original 3DGS configuration (Sec. V-A, implementation details) with the readings
-listed in DESIGN.md.
+original 3DGS configuration (Sec. V-A, implementation details); each reading is
+stated at the function that takes it (pixel centres at half-integers, near plane
+0.2, Jacobian clamp 1.3x the half field of view, dilation 0.3 px^2, extent
+3 sqrt(lambda_max), cutoff tau = max(-4.5, -ln(255 o))).
 
 Every decision quantity (camera depth, screen position, 2D covariance and its
 largest eigenvalue) is evaluated in FP64 from the fp32 inputs in a fixed operation

@@ -28,10 +28,13 @@ _LEAF_KEYS = ("u", "w", "a", "b", "c", "o", "rgb")
 
 
 def param_grads(params32: np.ndarray, n: int, sh_degree: int, cams: List[dict], dL_dcolor: List[np.ndarray],
-                tile: int = 16, max_elems: int = 4_000_000, pixel_masks: Optional[List[np.ndarray]] = None):
+                tile: int = 16, max_elems: int = 4_000_000, pixel_masks: Optional[List[np.ndarray]] = None,
+                dL_dalpha_sum: Optional[List[np.ndarray]] = None):
     """dL/dparams as FP64 numpy [n_params, n] for upstream images dL_dcolor[v]
-    ([3, H, W], any float type).  pixel_masks[v] ([H, W] bool) optionally limits
-    the pixels evaluated (pixels outside it must have zero upstream gradient)."""
+    ([3, H, W], any float type) and, optionally, upstream gradients of the soft
+    per-pixel count dL_dalpha_sum[v] ([H, W]; the load-balancing term).
+    pixel_masks[v] ([H, W] bool) optionally limits the pixels evaluated (pixels
+    outside it must have zero upstream gradient)."""
     P = params_f64(params32, n, requires_grad=True)
     for v, cam in enumerate(cams):
         proj = project_view(P, cam, sh_degree, tile)
@@ -40,7 +43,10 @@ def param_grads(params32: np.ndarray, n: int, sh_degree: int, cams: List[dict], 
         leaves = {k: sel[k].detach().clone().requires_grad_(True) for k in _LEAF_KEYS}
         q = {k: sel[k].detach() for k in sel}
         g = np.asarray(dL_dcolor[v], np.float64)
+        gA = None if dL_dalpha_sum is None else np.asarray(dL_dalpha_sum[v], np.float64)
         active = np.any(g != 0, axis=0)
+        if gA is not None:
+            active |= gA != 0
         if pixel_masks is not None:
             active &= pixel_masks[v]
         py, px = np.nonzero(active)
@@ -53,7 +59,10 @@ def param_grads(params32: np.ndarray, n: int, sh_degree: int, cams: List[dict], 
                 r = blend(q, px[s:s + chunk], py[s:s + chunk], margins=False, grad_q=gq)
                 out = r["C"] + r["T_final"][None, :] * bg[:, None]
                 up = torch.as_tensor(g[:, py[s:s + chunk], px[s:s + chunk]])
-                (out * up).sum().backward()
+                obj = (out * up).sum()
+                if gA is not None:
+                    obj = obj + (r["alpha_sum"] * torch.as_tensor(gA[py[s:s + chunk], px[s:s + chunk]])).sum()
+                obj.backward()
             outs, grads = [], []
             for k in _LEAF_KEYS:
                 if leaves[k].grad is not None:

@@ -1,8 +1,7 @@
 """Image losses and their gradient w.r.t. the rendered image (oracle; test
 infrastructure only).
 
-Eq. 10 combines an L1 term and an SSIM term (and the load-balancing term of Eq. 9,
-which is not part of this path).  The SSIM term follows the original 3DGS
+Eq. 10 combines an L1 term, an SSIM term and the load-balancing term of Eq. 9.  The SSIM term follows the original 3DGS
 configuration (Sec. V-A): per channel, windowed statistics under a normalised
 11x11 Gaussian window with sigma 1.5 and zero padding outside the image, constants
 C1 = 0.01^2 and C2 = 0.03^2, averaged over pixels and channels; D-SSIM = 1 - SSIM.
@@ -62,3 +61,19 @@ def image_loss_and_grad(x32, y32, w_l1: float, w_dssim: float):
     val = image_loss(x, y, w_l1, w_dssim)
     val.backward()
     return float(val.detach()), x.grad.numpy()
+
+
+def load_balance_loss_and_grad(G):
+    """Eq. 9: L_load = std over the pixels of one image of G_p, the number of
+    Gaussians associated with pixel p.  Readings: a count has no derivative, so
+    G_p is the soft count sum_k alpha_k over the Gaussians blended at p (it grows
+    by up to 0.99 per blended Gaussian and moves every blended Gaussian's alpha);
+    std is the population standard deviation over all pixels of the image; its
+    derivative at std = 0 is taken as 0.  Returns (value, dL/dG) for G [H, W]."""
+    g = torch.as_tensor(np.asarray(G, np.float64)).clone().requires_grad_(True)
+    var = ((g - g.mean()) ** 2).mean()
+    if float(var.detach()) == 0.0:
+        return 0.0, np.zeros(g.shape)
+    val = torch.sqrt(var)
+    val.backward()
+    return float(val.detach()), g.grad.numpy()

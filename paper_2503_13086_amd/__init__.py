@@ -22,18 +22,18 @@ GS_MAX_VIEWS = 64
 (GS_GROUP_MEAN, GS_GROUP_SCALE, GS_GROUP_ROT, GS_GROUP_OPACITY, GS_GROUP_SH_DC, GS_GROUP_SH_REST) = range(6)
 GS_N_GROUPS = 6
 (GS_BUF_RECORDS, GS_BUF_DEPTH, GS_BUF_TOUCHED, GS_BUF_TILE_RECT, GS_BUF_KEYS, GS_BUF_VALUES, GS_BUF_RANGES,
- GS_BUF_T_FINAL, GS_BUF_N_CONTRIB, GS_BUF_LAST, GS_BUF_GRAD2D, GS_BUF_PAIR_VIEW) = range(12)
+ GS_BUF_T_FINAL, GS_BUF_N_CONTRIB, GS_BUF_LAST, GS_BUF_GRAD2D, GS_BUF_PAIR_VIEW, GS_BUF_ALPHA_SUM) = range(13)
 (GS_K_PREPROCESS, GS_K_DEPTH_SORT, GS_K_SCAN, GS_K_EMIT, GS_K_TILE_SORT, GS_K_RANGES, GS_K_RENDER_FWD, GS_K_LOSS,
- GS_K_RENDER_BWD, GS_K_PREPROCESS_BWD, GS_K_ADAM, GS_K_ZERO) = range(12)
+ GS_K_RENDER_BWD, GS_K_PREPROCESS_BWD, GS_K_ADAM, GS_K_ZERO, GS_K_LOAD) = range(13)
 KERNEL_NAMES = ["preprocess", "depth_sort", "scan", "emit", "tile_sort", "ranges", "render_fwd", "loss",
-                "render_bwd", "preprocess_bwd", "adam", "zero"]
+                "render_bwd", "preprocess_bwd", "adam", "zero", "load"]
 
 _STATUS = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_CAPACITY", -3: "GS_ERR_HIP", -4: "GS_ERR_UNSUPPORTED",
            -5: "GS_ERR_STATE"}
 
 # Exported symbols (must match include/gs.h).
 EXPORTS = ["gs_abi_version", "gs_create", "gs_destroy", "gs_last_error", "gs_layout", "gs_preprocess", "gs_bin_sort",
-           "gs_render_fwd", "gs_loss", "gs_render_bwd", "gs_adam_step", "gs_set_cull", "gs_buffer_size",
+           "gs_render_fwd", "gs_loss", "gs_load_balance", "gs_render_bwd", "gs_adam_step", "gs_set_cull", "gs_buffer_size",
            "gs_copy_buffer", "gs_profile_enable", "gs_profile_read", "gs_memory_bytes", "gs_sched_weights",
            "gs_sched_plan", "gs_sched_lr"]
 GS_CULL_RECT, GS_CULL_ELLIPSE = 0, 1
@@ -79,6 +79,7 @@ def _load():
         "gs_render_fwd": (_I32, [_P, _P, _P]),
         "gs_loss": (_I32, [_P, _P, _P, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
         "gs_render_bwd": (_I32, [_P, _P, _P, _P, _I32, _P]),
+        "gs_load_balance": (_I32, [_P, ctypes.c_float, _P, _P]),
         "gs_adam_step": (_I32, [_P, _P, _P, _P, _P, _P, _I32, _I32, _I32, ctypes.POINTER(ctypes.c_float),
                                 ctypes.POINTER(ctypes.c_float), _I32, ctypes.c_uint32, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float, _P]),
@@ -190,6 +191,10 @@ def gs_render_fwd(ctx, color, stream=None) -> None:
 def gs_loss(ctx, color, target, w_l1: float, w_dssim: float, loss_out, dL_dcolor, stream=None) -> None:
     _check(ctx, _load().gs_loss(ctx, _ptr(color), _ptr(target), w_l1, w_dssim, _ptr(loss_out), _ptr(dL_dcolor),
                                 _stream(stream)), "gs_loss")
+
+
+def gs_load_balance(ctx, w_load: float, loss_out=None, stream=None) -> None:
+    _check(ctx, _load().gs_load_balance(ctx, w_load, _ptr(loss_out), _stream(stream)), "gs_load_balance")
 
 
 def gs_render_bwd(ctx, params, dL_dcolor, grad, accumulate: bool = False, stream=None) -> None:

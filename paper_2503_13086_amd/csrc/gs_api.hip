@@ -30,6 +30,7 @@ struct gs_ctx {
   int stage = kNone;
   int n = 0, stride = 0, D = 0, V = 0;
   int n_tiles = 0;
+  int tile = kTile;
   int64_t P = 0;
   uint64_t K = 0;
   std::vector<ViewDev> hviews;
@@ -39,6 +40,8 @@ struct gs_ctx {
   DevBuf dkey[2], dval[2], counts, offsets, blocksums, total, hist, digit_tot;
   DevBuf pkey[2], pval[2], ranges;
   DevBuf tfinal, ncontrib, last, grad2d, lossp, aux;
+  DevBuf asum, dG, loadp, loadst;
+  bool load_pending = false;   // dG holds a load-balancing gradient for the current forward
   ViewDev* h_views = nullptr;
   unsigned long long* h_total = nullptr;
   hipEvent_t views_ev = nullptr;
@@ -84,7 +87,7 @@ std::vector<DevBuf*> all_bufs(gs_ctx* c) {
   return {&c->views, &c->rec, &c->depth, &c->touched, &c->rect, &c->dkey[0], &c->dkey[1], &c->dval[0],
           &c->dval[1], &c->counts, &c->offsets, &c->blocksums, &c->total, &c->hist, &c->digit_tot, &c->pkey[0],
           &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->tfinal, &c->ncontrib, &c->last,
-          &c->grad2d, &c->lossp, &c->aux};
+          &c->grad2d, &c->lossp, &c->aux, &c->asum, &c->dG, &c->loadp, &c->loadst};
 }
 
 hipEvent_t next_event(gs_ctx* c) {
@@ -124,7 +127,7 @@ int ceil_log2(uint64_t x) {
 gs_status check_views(gs_ctx* c, const gs_camera* cams, int n_views, int tile) {
   if (!cams) return fail(c, GS_ERR_INVALID, "cams is NULL");
   if (n_views < 1 || n_views > GS_MAX_VIEWS) return fail(c, GS_ERR_INVALID, "n_views must be in 1..64");
-  if (tile != kTile) return fail(c, GS_ERR_UNSUPPORTED, "only 16x16 tiles are implemented");
+  if (!tile_supported(tile)) return fail(c, GS_ERR_UNSUPPORTED, "tile must be 8, 16 or 32");
   for (int v = 0; v < n_views; ++v) {
     const gs_camera& k = cams[v];
     if (k.width < 1 || k.height < 1 || k.width > GS_MAX_IMAGE_SIDE || k.height > GS_MAX_IMAGE_SIDE)
@@ -142,7 +145,7 @@ gs_status check_views(gs_ctx* c, const gs_camera* cams, int n_views, int tile) {
   return GS_OK;
 }
 
-void build_views(const gs_camera* cams, int n_views, std::vector<ViewDev>& out, int* n_tiles, int64_t* P) {
+void build_views(const gs_camera* cams, int n_views, int tile, std::vector<ViewDev>& out, int* n_tiles, int64_t* P) {
   out.resize(n_views);
   int64_t toff = 0, poff = 0;
   for (int v = 0; v < n_views; ++v) {
@@ -153,8 +156,9 @@ void build_views(const gs_camera* cams, int n_views, std::vector<ViewDev>& out, 
     d.fx = k.fx; d.fy = k.fy; d.cx = k.cx; d.cy = k.cy;
     d.W = k.width; d.H = k.height;
     std::memcpy(d.bg, k.bg, sizeof(d.bg));
-    d.tiles_x = (k.width + kTile - 1) / kTile;
-    d.tiles_y = (k.height + kTile - 1) / kTile;
+    d.tile = tile;
+    d.tiles_x = (k.width + tile - 1) / tile;
+    d.tiles_y = (k.height + tile - 1) / tile;
     d.tile_off = (int32_t)toff;
     d.pix_off = poff;
     toff += (int64_t)d.tiles_x * d.tiles_y;
@@ -232,7 +236,7 @@ gs_status gs_preprocess(gs_ctx* c, const float* params, int32_t n, int32_t strid
   std::vector<ViewDev> hv;
   int n_tiles = 0;
   int64_t P = 0;
-  build_views(cams, n_views, hv, &n_tiles, &P);
+  build_views(cams, n_views, tile, hv, &n_tiles, &P);
   const size_t NV = (size_t)n_views * n;
   if ((st = ensure(c, c->views, sizeof(ViewDev) * GS_MAX_VIEWS, s)) != GS_OK) return st;
   if ((st = ensure(c, c->rec, NV * sizeof(Record), s)) != GS_OK) return st;
@@ -250,7 +254,7 @@ gs_status gs_preprocess(gs_ctx* c, const float* params, int32_t n, int32_t strid
                                 c->depth.as<uint32_t>(), c->touched.as<uint32_t>(), c->rect.as<ushort4>(), s));
   }
   c->n = n; c->stride = stride; c->D = sh_degree; c->V = n_views;
-  c->hviews = hv; c->n_tiles = n_tiles; c->P = P; c->K = 0;
+  c->hviews = hv; c->n_tiles = n_tiles; c->tile = tile; c->P = P; c->K = 0;
   c->stage = kProjected;
   return GS_OK;
 }
@@ -303,7 +307,7 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
     Prof pr(c, GS_K_EMIT, s);
     GS_HIP(c, launch_emit_pairs(order, c->counts.as<uint32_t>(), c->offsets.as<uint32_t>(), c->rect.as<ushort4>(),
                                 c->rec.as<Record>(), NV, c->n, c->views.as<ViewDev>(), c->V, (size_t)K,
-                                (uint32_t)c->n_tiles, c->cull == GS_CULL_ELLIPSE ? 1 : 0, c->pkey[0].as<uint32_t>(),
+                                (uint32_t)c->n_tiles, c->cull == GS_CULL_ELLIPSE ? 1 : 0, c->tile, c->pkey[0].as<uint32_t>(),
                                 c->pval[0].as<uint32_t>(), s));
   }
   {
@@ -335,14 +339,17 @@ gs_status gs_render_fwd(gs_ctx* c, float* color, gs_stream stream) {
   if ((st = ensure(c, c->tfinal, (size_t)c->P * 4, s)) != GS_OK) return st;
   if ((st = ensure(c, c->ncontrib, (size_t)c->P * 4, s)) != GS_OK) return st;
   if ((st = ensure(c, c->last, (size_t)c->P * 4, s)) != GS_OK) return st;
+  if ((st = ensure(c, c->asum, (size_t)c->P * 4, s)) != GS_OK) return st;
   {
     Prof pr(c, GS_K_RENDER_FWD, s);
     GS_HIP(c, launch_render_fwd(c->views.as<ViewDev>(), c->V, c->n_tiles, c->ranges.as<uint2>(),
                                 c->pval[c->pairs_in_b].as<uint32_t>(), c->rec.as<Record>(),
                                 (uint32_t)((size_t)c->V * c->n), color, c->tfinal.as<float>(),
-                                c->ncontrib.as<uint32_t>(), c->last.as<uint32_t>(), s));
+                                c->ncontrib.as<uint32_t>(), c->last.as<uint32_t>(), c->asum.as<float>(), c->tile,
+                                s));
   }
   c->stage = kRendered;
+  c->load_pending = false;
   return GS_OK;
 }
 
@@ -366,6 +373,28 @@ gs_status gs_loss(gs_ctx* c, const float* color, const float* target, float w_l1
   return GS_OK;
 }
 
+gs_status gs_load_balance(gs_ctx* c, float w_load, double* loss_out, gs_stream stream) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (c->stage < kRendered) return fail(c, GS_ERR_STATE, "gs_load_balance needs a preceding gs_render_fwd");
+  if (loss_out && !aligned(loss_out, 8)) return fail(c, GS_ERR_INVALID, "loss_out misaligned");
+  if (!std::isfinite(w_load)) return fail(c, GS_ERR_INVALID, "non-finite loss weight");
+  hipStream_t s = (hipStream_t)stream;
+  GS_HIP(c, hipSetDevice(c->device));
+  gs_status st;
+  const size_t chunks = (size_t)load_chunks(c->hviews.data(), c->V);
+  if ((st = ensure(c, c->dG, (size_t)c->P * 4, s)) != GS_OK) return st;
+  if ((st = ensure(c, c->loadp, chunks * c->V * 16, s)) != GS_OK) return st;
+  if ((st = ensure(c, c->loadst, (size_t)c->V * 16, s)) != GS_OK) return st;
+  {
+    Prof pr(c, GS_K_LOAD, s);
+    GS_HIP(c, launch_load_balance(c->views.as<ViewDev>(), c->hviews.data(), c->V, c->asum.as<float>(), w_load,
+                                  c->loadp.as<double>(), c->loadst.as<double>(), loss_out, c->dG.as<float>(), s));
+  }
+  c->load_pending = w_load != 0.0f;
+  return GS_OK;
+}
+
 gs_status gs_render_bwd(gs_ctx* c, const float* params, const float* dL_dcolor, float* grad, int32_t accumulate,
                         gs_stream stream) {
   if (!c) return GS_ERR_INVALID;
@@ -386,7 +415,8 @@ gs_status gs_render_bwd(gs_ctx* c, const float* params, const float* dL_dcolor, 
     Prof pr(c, GS_K_RENDER_BWD, s);
     GS_HIP(c, launch_render_bwd(c->views.as<ViewDev>(), c->V, c->n_tiles, c->ranges.as<uint2>(),
                                 c->pval[c->pairs_in_b].as<uint32_t>(), c->rec.as<Record>(), (uint32_t)NV,
-                                c->tfinal.as<float>(), c->last.as<uint32_t>(), dL_dcolor, c->grad2d.as<float>(), s));
+                                c->tfinal.as<float>(), c->last.as<uint32_t>(), dL_dcolor,
+                                c->load_pending ? c->dG.as<float>() : nullptr, c->grad2d.as<float>(), c->tile, s));
   }
   {
     Prof pr(c, GS_K_PREPROCESS_BWD, s);
@@ -455,7 +485,9 @@ gs_status gs_buffer_size(const gs_ctx* c, int32_t which, size_t* bytes) {
     case GS_BUF_KEYS: b = c->stage >= kBinned ? c->K * 8 : 0; break;
     case GS_BUF_VALUES: case GS_BUF_PAIR_VIEW: b = c->stage >= kBinned ? c->K * 4 : 0; break;
     case GS_BUF_RANGES: b = c->stage >= kBinned ? (size_t)c->n_tiles * 8 : 0; break;
-    case GS_BUF_T_FINAL: case GS_BUF_N_CONTRIB: case GS_BUF_LAST: b = c->stage >= kRendered ? (size_t)c->P * 4 : 0; break;
+    case GS_BUF_T_FINAL: case GS_BUF_N_CONTRIB: case GS_BUF_LAST: case GS_BUF_ALPHA_SUM:
+      b = c->stage >= kRendered ? (size_t)c->P * 4 : 0;
+      break;
     case GS_BUF_GRAD2D: b = (c->stage >= kRendered && c->grad2d.p) ? NV * kGrad2D * 4 : 0; break;
     default: return GS_ERR_INVALID;
   }
@@ -482,6 +514,7 @@ gs_status gs_copy_buffer(gs_ctx* c, int32_t which, void* dst, size_t bytes, gs_s
     case GS_BUF_T_FINAL: src = c->tfinal.p; break;
     case GS_BUF_N_CONTRIB: src = c->ncontrib.p; break;
     case GS_BUF_LAST: src = c->last.p; break;
+    case GS_BUF_ALPHA_SUM: src = c->asum.p; break;
     case GS_BUF_GRAD2D: src = c->grad2d.p; break;
     case GS_BUF_KEYS:
       GS_HIP(c, launch_compose_keys(c->pkey[c->pairs_in_b].as<uint32_t>(), c->pval[c->pairs_in_b].as<uint32_t>(),

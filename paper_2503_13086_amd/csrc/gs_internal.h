@@ -18,8 +18,8 @@ constexpr double kCutoffFloor = -4.5;          // exponent at the 3-sigma ellips
 constexpr double kAlphaMinInv = 255.0;         // alpha >= 1/255 to contribute
 constexpr float kAlphaMax = 0.99f;             // alpha cap
 constexpr float kTMin = 1e-4f;                 // stop blending below this transmittance
-constexpr int kTile = 16;                      // tile edge in pixels
-constexpr int kTileThreads = kTile * kTile;    // one thread per pixel of a tile
+constexpr int kTile = 16;                      // default tile edge in pixels
+__host__ __device__ inline bool tile_supported(int t) { return t == 8 || t == 16 || t == 32; }
 constexpr int kGrad2D = 9;                     // dL/d(u, w, a, b, c, o, r, g, b)
 
 // Per-view constants in device memory (one entry per view).
@@ -29,6 +29,7 @@ struct ViewDev {
   float fx, fy, cx, cy;
   int32_t W, H;
   float bg[3];
+  int32_t tile;       // tile edge in pixels (8, 16 or 32; the same for every view of a batch)
   int32_t tiles_x, tiles_y;
   int32_t tile_off;   // global id of the view's first tile
   int64_t pix_off;    // index of the view's first pixel in the concatenated image
@@ -75,24 +76,31 @@ hipError_t launch_scan_touched(const uint32_t* order, const uint32_t* touched, s
 // cull != 0: pairs whose tile box the cutoff region misses get tile id n_tiles
 hipError_t launch_emit_pairs(const uint32_t* order, const uint32_t* counts, const uint32_t* offsets,
                              const ushort4* rect, const Record* rec, size_t n_entries, int n, const ViewDev* views,
-                             int V, size_t K, uint32_t n_tiles, int cull, uint32_t* pair_tile, uint32_t* pair_rec,
-                             hipStream_t s);
+                             int V, size_t K, uint32_t n_tiles, int cull, int tile, uint32_t* pair_tile,
+                             uint32_t* pair_rec, hipStream_t s);
 hipError_t launch_ranges(const uint32_t* pair_tile, size_t K, uint2* ranges, int n_tiles, hipStream_t s);
 hipError_t launch_compose_keys(const uint32_t* pair_tile, const uint32_t* pair_rec, const uint32_t* depth,
                                size_t K, int n, size_t n_rec, unsigned long long* keys, uint32_t* values,
                                uint32_t* views, int mode, hipStream_t s);
 
 // n_rec: number of records (V * n); record ids at or beyond it are skipped
+// forward also writes the soft count asum [P] (sum of blended alphas); the
+// backward adds dL/dG [P] (may be NULL) to every blended alpha's derivative
 hipError_t launch_render_fwd(const ViewDev* views, int V, int n_tiles, const uint2* ranges, const uint32_t* pair_rec,
                              const Record* rec, uint32_t n_rec, float* color, float* t_final, uint32_t* n_contrib,
-                             uint32_t* last, hipStream_t s);
+                             uint32_t* last, float* asum, int tile, hipStream_t s);
 hipError_t launch_render_bwd(const ViewDev* views, int V, int n_tiles, const uint2* ranges, const uint32_t* pair_rec,
                              const Record* rec, uint32_t n_rec, const float* t_final, const uint32_t* last,
-                             const float* dL_dcolor, float* grad2d, hipStream_t s);
+                             const float* dL_dcolor, const float* dL_dG, float* grad2d, int tile, hipStream_t s);
 
 // Loss over all views in 32x32-pixel tiles: loss_tiles() tiles, partials 2 doubles
 // per tile, aux 9 floats per pixel (SSIM only).
 int loss_tiles(const ViewDev* hviews, int V);
+// Eq. 9 on the soft count asum [P]: per-view loss w std (loss_out, may be NULL)
+// and dL/dG [P]; partials: V x load_chunks doubles2, stats: V doubles2
+int load_chunks(const ViewDev* hviews, int V);
+hipError_t launch_load_balance(const ViewDev* dviews, const ViewDev* hviews, int V, const float* asum, float w,
+                               double* partials, double* stats, double* loss_out, float* dG, hipStream_t s);
 hipError_t launch_loss_dev(const ViewDev* dviews, const ViewDev* hviews, int V, const float* color,
                            const float* target, float w_l1, float w_dssim, double* partials, float* aux,
                            double* loss_out, float* dL_dcolor, hipStream_t s);

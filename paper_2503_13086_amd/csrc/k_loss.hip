@@ -16,6 +16,9 @@
 // and dS_mean/dx = (window * A + 2 x (window * B) + y (window * Cc)) / N.  The first
 // kernel stores A, B, Cc; the second filters them the same way (the window is
 // symmetric) and adds the L1 term.  Loss sums are reduced per tile in FP64.
+//
+// The load-balancing term of Eq. 9 (kernels at the end) works on the soft
+// per-pixel Gaussian count the forward writes.
 #include "gs_internal.h"
 
 namespace gsk {
@@ -271,7 +274,91 @@ __global__ void k_loss_final(const ViewDev* __restrict__ views, int V, LossTiles
   }
 }
 
+// ---- Eq. 9 load-balancing term on the soft per-pixel count G_p (sum of the
+// alphas a pixel blended, written by the forward): per view, L = w std_p(G_p)
+// (population std) and dL/dG_p = w (G_p - mean) / (P std) (0 when std = 0).
+// Sums of G and G^2 are taken in FP64 per 2048-pixel chunk, then per view.
+constexpr int kLoadChunk = 2048;
+
+__global__ __launch_bounds__(256) void k_load_partial(const ViewDev* __restrict__ views,
+                                                      const float* __restrict__ asum, int chunks,
+                                                      double2* __restrict__ part) {
+  __shared__ double sh[4];
+  const ViewDev& cv = views[blockIdx.y];
+  const int64_t P = (int64_t)cv.W * cv.H;
+  const int64_t base = (int64_t)blockIdx.x * kLoadChunk;
+  double a = 0.0, b = 0.0;
+  for (int k = 0; k < kLoadChunk / 256; ++k) {
+    const int64_t i = base + k * 256 + threadIdx.x;
+    if (i < P) {
+      const double g = (double)asum[cv.pix_off + i];
+      a += g;
+      b += g * g;
+    }
+  }
+  a = block_sum_d(a, sh);
+  b = block_sum_d(b, sh);
+  if (threadIdx.x == 0) part[(size_t)blockIdx.y * chunks + blockIdx.x] = make_double2(a, b);
+}
+
+__global__ __launch_bounds__(256) void k_load_final(const ViewDev* __restrict__ views, int chunks,
+                                                    const double2* __restrict__ part, float w,
+                                                    double2* __restrict__ stats, double* __restrict__ loss_out) {
+  __shared__ double sh[4];
+  const int v = blockIdx.x;
+  const ViewDev& cv = views[v];
+  const int64_t P = (int64_t)cv.W * cv.H;
+  const int nc = (int)((P + kLoadChunk - 1) / kLoadChunk);
+  double a = 0.0, b = 0.0;
+  for (int t = threadIdx.x; t < nc; t += blockDim.x) {
+    a += part[(size_t)v * chunks + t].x;
+    b += part[(size_t)v * chunks + t].y;
+  }
+  a = block_sum_d(a, sh);
+  b = block_sum_d(b, sh);
+  if (threadIdx.x == 0) {
+    const double m = a / (double)P;
+    const double var = fmax(b / (double)P - m * m, 0.0);
+    const double sd = sqrt(var);
+    stats[v] = make_double2(m, sd > 0.0 ? (double)w / ((double)P * sd) : 0.0);
+    if (loss_out) loss_out[v] = (double)w * sd;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_load_grad(const ViewDev* __restrict__ views,
+                                                   const double2* __restrict__ stats,
+                                                   const float* __restrict__ asum, float* __restrict__ dG) {
+  const ViewDev& cv = views[blockIdx.y];
+  const int64_t P = (int64_t)cv.W * cv.H;
+  const double2 st = stats[blockIdx.y];
+  const int64_t base = (int64_t)blockIdx.x * kLoadChunk;
+  for (int k = 0; k < kLoadChunk / 256; ++k) {
+    const int64_t i = base + k * 256 + threadIdx.x;
+    if (i < P) dG[cv.pix_off + i] = (float)(((double)asum[cv.pix_off + i] - st.x) * st.y);
+  }
+}
+
 }  // namespace
+
+int load_chunks(const ViewDev* hviews, int V) {
+  int64_t mx = 1;
+  for (int v = 0; v < V; ++v) {
+    const int64_t c = ((int64_t)hviews[v].W * hviews[v].H + kLoadChunk - 1) / kLoadChunk;
+    mx = c > mx ? c : mx;
+  }
+  return (int)mx;
+}
+
+hipError_t launch_load_balance(const ViewDev* dviews, const ViewDev* hviews, int V, const float* asum, float w,
+                               double* partials, double* stats, double* loss_out, float* dG, hipStream_t s) {
+  const int chunks = load_chunks(hviews, V);
+  double2* part = reinterpret_cast<double2*>(partials);
+  double2* st = reinterpret_cast<double2*>(stats);
+  hipLaunchKernelGGL(k_load_partial, dim3(chunks, V), dim3(256), 0, s, dviews, asum, chunks, part);
+  hipLaunchKernelGGL(k_load_final, dim3(V), dim3(256), 0, s, dviews, chunks, part, w, st, loss_out);
+  hipLaunchKernelGGL(k_load_grad, dim3(chunks, V), dim3(256), 0, s, dviews, st, asum, dG);
+  return hipGetLastError();
+}
 
 int loss_tiles(const ViewDev* hviews, int V) {
   int t = 0;

@@ -203,8 +203,8 @@ __device__ inline void project(const Gauss& G, const ViewDev& V, Proj& p) {
   const int j0 = isnan(ylo) ? H : (int)fmin(fmax(ylo, 0.0), (double)H);
   const int j1 = isnan(yhi) ? -1 : (int)fmin(fmax(yhi, -1.0), (double)(H - 1));
   p.visible = in_front && det_ok && i0 <= i1 && j0 <= j1;
-  p.tx0 = i0 / kTile; p.tx1 = i1 / kTile;
-  p.ty0 = j0 / kTile; p.ty1 = j1 / kTile;
+  p.tx0 = i0 / V.tile; p.tx1 = i1 / V.tile;
+  p.ty0 = j0 / V.tile; p.ty1 = j1 / V.tile;
 }
 
 __device__ inline void camera_dir(const Gauss& G, const ViewDev& V, double dir[3], double& dn) {

@@ -1,16 +1,20 @@
 // Tile rasterizer forward and backward for gfx950.
 //
 // Forward (Sec. III Eq. 2): one 256-thread workgroup (four wave64s) per 16x16
-// tile, one thread per pixel.  The tile's depth-ordered list is walked in batches
-// of 256 records staged in LDS; every pixel reads each staged record by LDS
-// broadcast, so a record fetched from HBM once serves all 256 pixels.  The
-// workgroup stops when every pixel has stopped blending.  Screen centres arrive
-// in FP64 and are made relative to the tile origin while staging, so per-pixel
-// offsets are accurate fp32 numbers at any image size.
+// tile, one thread per pixel, each wavefront owning an 8x8 quadrant.  The tile's
+// depth-ordered list is walked in batches of 256 records staged in LDS; every
+// pixel reads each staged record by LDS broadcast, so a record fetched from HBM
+// once serves all 256 pixels.  While staging, each record also gets the bounding
+// box of its cutoff ellipse; each wavefront then tests the batch against its
+// quadrant (one record per lane, four ballots) and walks only the records whose
+// box meets it.  A wavefront stops when all its pixels have stopped blending,
+// the workgroup when all four have.  Screen centres arrive in FP64 and are made
+// relative to the tile origin while staging, so per-pixel offsets are accurate
+// fp32 numbers at any image size.
 //
-// Backward (Sec. IV-E): the same tiling, walking each list back to front from the
-// last position any pixel of the tile blended (each wavefront starts at the last
-// position its own pixels blended).  Each pixel recovers its transmittance with
+// Backward (Sec. IV-E): the same tiling and per-quadrant candidate sets, walking
+// each list back to front from the last position any pixel of the tile blended
+// (each wavefront starts at the last position its own pixels blended).  Each pixel recovers its transmittance with
 // one reciprocal per Gaussian and keeps the colour accumulated behind it.  Per
 // Gaussian, nine per-pixel values (the moments of dL/d(exponent) over dx, dy,
 // dx^2, dx dy, dy^2, then opacity and colour partials) are summed across the
@@ -26,9 +30,6 @@
 
 namespace gsk {
 namespace {
-
-constexpr int T = kTile;
-constexpr int NT = kTileThreads;
 
 __device__ inline int view_of_tile(const ViewDev* __restrict__ views, int V, int tile) {
   int v = 0;
@@ -51,6 +52,7 @@ struct TileGeom {
   double ox, oy;
 };
 
+template <int T>
 __device__ inline TileGeom tile_geom(const ViewDev* __restrict__ views, int V, int tile) {
   TileGeom t;
   t.v = view_of_tile(views, V, tile);
@@ -58,8 +60,12 @@ __device__ inline TileGeom tile_geom(const ViewDev* __restrict__ views, int V, i
   const int lt = tile - cv.tile_off;
   t.tx = lt % cv.tiles_x;
   t.ty = lt / cv.tiles_x;
-  t.lx = threadIdx.x % T;
-  t.ly = threadIdx.x / T;
+  // wavefront w covers the 8x8 block (w mod T/8, w div T/8) of the tile; lane l
+  // its pixel (l & 7, l >> 3)
+  constexpr int QW = T / 8;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  t.lx = ((w % QW) << 3) | (l & 7);
+  t.ly = ((w / QW) << 3) | (l >> 3);
   t.px = t.tx * T + t.lx;
   t.py = t.ty * T + t.ly;
   t.inside = t.px < cv.W && t.py < cv.H;
@@ -70,31 +76,74 @@ __device__ inline TileGeom tile_geom(const ViewDev* __restrict__ views, int V, i
 
 // Stage record `rid` for a tile with origin (ox, oy): centre relative to the tile,
 // exponent coefficients and cutoff in base-2 units (the exponent's sign and the
-// cutoff test are unchanged by the positive factor), opacity, colour.
+// cutoff test are unchanged by the positive factor), opacity, colour, and the
+// half-widths (ex, ey) of the bounding box of the cutoff region
+// {a dx^2 + 2 b dx dy + c dy^2 <= -2 tau}: sqrt(-2 tau c / det) and
+// sqrt(-2 tau a / det), det = ac - b^2 taken in FP64 (the fp32 entries multiply
+// exactly there), widened by 1e-4 relative + 0.01 px so that the per-pixel fp32
+// test never passes a pixel outside the box.
+//   q0 = (u', w', A, B)   q1 = (C, o, tau', ex)   q2 = (r, g, b, ey)
 __device__ inline void stage(const Record* __restrict__ rec, uint32_t rid, double ox, double oy, float4& q0,
                              float4& q1, float4& q2) {
   const Record* r = rec + rid;
   const double2 uw = *reinterpret_cast<const double2*>(r);
   const float4 c = reinterpret_cast<const float4*>(r)[1];
   const float4 d = reinterpret_cast<const float4*>(r)[2];
+  const double det = (double)c.x * (double)c.z - (double)c.y * (double)c.y;
+  float ex = 3.0e38f, ey = 3.0e38f;
+  if (det > 0.0) {
+    const double L = -2.0 * (double)d.x / det;
+    ex = (float)(sqrt(L * (double)c.z) * (1.0 + 1e-4) + 0.01);
+    ey = (float)(sqrt(L * (double)c.x) * (1.0 + 1e-4) + 0.01);
+  }
   q0 = make_float4((float)(uw.x - ox), (float)(uw.y - oy), (-0.5f * c.x) * kLog2e, (-c.y) * kLog2e);
-  q1 = make_float4((-0.5f * c.z) * kLog2e, c.w, d.x * kLog2e, 0.0f);
-  q2 = make_float4(d.y, d.z, d.w, 0.0f);
+  q1 = make_float4((-0.5f * c.z) * kLog2e, c.w, d.x * kLog2e, ex);
+  q2 = make_float4(d.y, d.z, d.w, ey);
 }
 
-__global__ __launch_bounds__(NT) void k_render_fwd(const ViewDev* __restrict__ views, int V,
+// Placeholder for an entry that belongs to no Gaussian (never for a consistent
+// sort): no pixel accepts it and no quadrant lists it.
+__device__ inline void stage_empty(float4& q0, float4& q1, float4& q2) {
+  q0 = make_float4(0.f, 0.f, 0.f, 0.f);
+  q1 = make_float4(0.f, 0.f, 1.f, -1.f);
+  q2 = make_float4(0.f, 0.f, 0.f, -1.f);
+}
+
+// Ballots of the staged records [0, m) whose cutoff box meets this wavefront's
+// 8x8 block of pixel centres [qx, qx + 7] x [qy, qy + 7] (tile-relative); bit b
+// of mask[k] is record 64 k + b.
+template <int NM>
+__device__ inline void quadrant_masks(const float4* s0, const float4* s1, const float4* s2, int m, float qx,
+                                      float qy, uint64_t (&mask)[NM]) {
+  const int lane = (int)__lane_id();
+#pragma unroll
+  for (int k = 0; k < NM; ++k) {
+    const int j = lane + 64 * k;
+    bool hit = false;
+    if (j < m) {
+      const float u = s0[j].x, w = s0[j].y, ex = s1[j].w, ey = s2[j].w;
+      hit = u + ex >= qx && u - ex <= qx + 7.0f && w + ey >= qy && w - ey <= qy + 7.0f;
+    }
+    mask[k] = __ballot(hit);
+  }
+}
+
+template <int T>
+__global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict__ views, int V,
                                                     const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ pair_rec,
                                                     const Record* __restrict__ rec, uint32_t n_rec,
                                                     float* __restrict__ color,
                                                     float* __restrict__ t_final, uint32_t* __restrict__ n_contrib,
-                                                    uint32_t* __restrict__ last) {
+                                                    uint32_t* __restrict__ last, float* __restrict__ asum) {
+  constexpr int NT = T * T, NM = NT / 64;
   __shared__ float4 s0[NT], s1[NT], s2[NT];
   const int tile = blockIdx.x;
-  const TileGeom tg = tile_geom(views, V, tile);
+  const TileGeom tg = tile_geom<T>(views, V, tile);
   const uint2 rg = ranges[tile];
   const float fx = (float)tg.lx, fy = (float)tg.ly;
-  float Tr = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+  const float qx = (float)(tg.lx & ~7), qy = (float)(tg.ly & ~7);
+  float Tr = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, A = 0.0f;
   uint32_t cnt = 0, lastp = 0;
   bool done = !tg.inside;
   for (uint32_t base = rg.x; base < rg.y; base += NT) {
@@ -104,37 +153,47 @@ __global__ __launch_bounds__(NT) void k_render_fwd(const ViewDev* __restrict__ v
       const uint32_t rid = pair_rec[base + threadIdx.x];
       if (rid < n_rec) {
         stage(rec, rid, tg.ox, tg.oy, s0[threadIdx.x], s1[threadIdx.x], s2[threadIdx.x]);
-      } else {   // never for a consistent sort: an entry that no pixel accepts
-        s0[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
-        s1[threadIdx.x] = make_float4(0.f, 0.f, 1.f, 0.f);
-        s2[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+      } else {
+        stage_empty(s0[threadIdx.x], s1[threadIdx.x], s2[threadIdx.x]);
       }
     }
     __syncthreads();
     if (__ballot(!done) != 0ull) {
+      uint64_t mask[NM];
+      quadrant_masks<NM>(s0, s1, s2, (int)m, qx, qy, mask);
       // straight-line per-Gaussian update; lanes that skip or have stopped keep their state
       const uint32_t pos0 = base - rg.x + 1;
-      for (uint32_t j = 0; j < m; ++j) {
-        if ((j & 7u) == 0u && j != 0u && __ballot(!done) == 0ull) break;
-        const float4 a0 = s0[j];
-        const float4 a1 = s1[j];
-        const float dx = a0.x - fx, dy = a0.y - fy;
-        const float p2 = gauss_power2(a0.z, a0.w, a1.x, dx, dy);
-        const bool pass = !done && p2 <= 0.0f && p2 >= a1.z;
-        if (__ballot(pass) == 0ull) continue;   // no pixel of this wave takes it
-        const float4 a2 = s2[j];
-        const float alpha = fminf(kAlphaMax, a1.y * __builtin_amdgcn_exp2f(p2));
-        const float Tn = Tr * (1.0f - alpha);
-        const bool stop = pass && Tn < kTMin;
-        const bool blend = pass && !stop;
-        done = done || stop;
-        const float wgt = blend ? alpha * Tr : 0.0f;
-        C0 = __fmaf_rn(a2.x, wgt, C0);
-        C1 = __fmaf_rn(a2.y, wgt, C1);
-        C2 = __fmaf_rn(a2.z, wgt, C2);
-        Tr = blend ? Tn : Tr;
-        cnt += blend ? 1u : 0u;
-        lastp = blend ? pos0 + j : lastp;
+      bool live = true;
+      for (int k = 0; k < NM && live; ++k) {
+        uint64_t mk = mask[k];
+        while (mk) {
+          const uint32_t j = 64u * k + (uint32_t)__builtin_ctzll(mk);
+          mk &= mk - 1ull;
+          const float4 a0 = s0[j];
+          const float4 a1 = s1[j];
+          const float dx = a0.x - fx, dy = a0.y - fy;
+          const float p2 = gauss_power2(a0.z, a0.w, a1.x, dx, dy);
+          const bool pass = !done && p2 <= 0.0f && p2 >= a1.z;
+          if (__ballot(pass) == 0ull) continue;   // no pixel of this wave takes it
+          const float4 a2 = s2[j];
+          const float alpha = fminf(kAlphaMax, a1.y * __builtin_amdgcn_exp2f(p2));
+          const float Tn = Tr * (1.0f - alpha);
+          const bool stop = pass && Tn < kTMin;
+          const bool blend = pass && !stop;
+          done = done || stop;
+          const float wgt = blend ? alpha * Tr : 0.0f;
+          C0 = __fmaf_rn(a2.x, wgt, C0);
+          C1 = __fmaf_rn(a2.y, wgt, C1);
+          C2 = __fmaf_rn(a2.z, wgt, C2);
+          Tr = blend ? Tn : Tr;
+          A += blend ? alpha : 0.0f;
+          cnt += blend ? 1u : 0u;
+          lastp = blend ? pos0 + j : lastp;
+          if (__ballot(stop) != 0ull && __ballot(!done) == 0ull) {   // every pixel of this wavefront stopped
+            live = false;
+            break;
+          }
+        }
       }
     }
     if (__syncthreads_and(done)) break;
@@ -151,6 +210,7 @@ __global__ __launch_bounds__(NT) void k_render_fwd(const ViewDev* __restrict__ v
     t_final[gp] = Tr;
     n_contrib[gp] = cnt;
     last[gp] = lastp;
+    asum[gp] = A;
   }
 }
 
@@ -202,24 +262,28 @@ __device__ inline void wave_reduce9_to_lds(const float (&v)[kGrad2D], float* acc
   }
 }
 
-__global__ __launch_bounds__(NT) void k_render_bwd(const ViewDev* __restrict__ views, int V,
+template <int T>
+__global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict__ views, int V,
                                                     const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ pair_rec,
                                                     const Record* __restrict__ rec, uint32_t n_rec,
                                                     const float* __restrict__ t_final,
                                                     const uint32_t* __restrict__ last,
-                                                    const float* __restrict__ dL_dcolor, float* __restrict__ grad2d) {
+                                                    const float* __restrict__ dL_dcolor,
+                                                    const float* __restrict__ dL_dG, float* __restrict__ grad2d) {
+  constexpr int NT = T * T, NM = NT / 64;
   __shared__ float4 s0[NT], s1[NT], s2[NT];
   __shared__ uint32_t srid[NT];
   __shared__ float acc[NT][kGrad2D];
-  __shared__ uint32_t smax[NT / 64];
+  __shared__ uint32_t smax[NM];
   const int tile = blockIdx.x;
-  const TileGeom tg = tile_geom(views, V, tile);
+  const TileGeom tg = tile_geom<T>(views, V, tile);
   const ViewDev& cv = views[tg.v];
   const uint2 rg = ranges[tile];
   const float fx = (float)tg.lx, fy = (float)tg.ly;
+  const float qx = (float)(tg.lx & ~7), qy = (float)(tg.ly & ~7);
 
-  float Tr = 0.0f, S0 = 0.0f, S1 = 0.0f, S2 = 0.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+  float Tr = 0.0f, S0 = 0.0f, S1 = 0.0f, S2 = 0.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, gG = 0.0f;
   uint32_t lp = 0;
   if (tg.inside) {
     const size_t hw = (size_t)cv.W * cv.H;
@@ -231,6 +295,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(const ViewDev* __restrict__ v
     g0 = gimg[pix];
     g1 = gimg[hw + pix];
     g2 = gimg[2 * hw + pix];
+    if (dL_dG) gG = dL_dG[gp];
     S0 = Tr * cv.bg[0];
     S1 = Tr * cv.bg[1];
     S2 = Tr * cv.bg[2];
@@ -242,7 +307,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(const ViewDev* __restrict__ v
   for (int k = 0; k < kGrad2D; ++k) acc[threadIdx.x][k] = 0.0f;
   __syncthreads();
   int jmax = 0;
-  for (int w = 0; w < NT / 64; ++w) jmax = max(jmax, (int)smax[w]);
+  for (int w = 0; w < NM; ++w) jmax = max(jmax, (int)smax[w]);
 
   for (int end = jmax; end > 0; end -= NT) {
     const int beg = end > NT ? end - NT : 0;
@@ -253,53 +318,62 @@ __global__ __launch_bounds__(NT) void k_render_bwd(const ViewDev* __restrict__ v
       srid[threadIdx.x] = rid;
       if (rid < n_rec) {
         stage(rec, rid, tg.ox, tg.oy, s0[threadIdx.x], s1[threadIdx.x], s2[threadIdx.x]);
-      } else {   // never for a consistent sort: an entry that no pixel accepts
-        s0[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
-        s1[threadIdx.x] = make_float4(0.f, 0.f, 1.f, 0.f);
-        s2[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+      } else {
+        stage_empty(s0[threadIdx.x], s1[threadIdx.x], s2[threadIdx.x]);
       }
     }
     __syncthreads();
-    const int jtop = min(m, wave_last - beg) - 1;
-    for (int j = jtop; j >= 0; --j) {
-      const float4 a0 = s0[j];
-      const float4 a1 = s1[j];
-      const float dx = a0.x - fx, dy = a0.y - fy;
-      const float p2 = gauss_power2(a0.z, a0.w, a1.x, dx, dy);
-      const bool on = tg.inside && (uint32_t)(beg + j) < lp && p2 <= 0.0f && p2 >= a1.z;
-      if (__ballot(on) == 0ull) continue;    // no pixel of this wave blended it
-      // straight-line update; lanes that did not blend this Gaussian keep their state
-      // and contribute zeros
-      const float4 a2 = s2[j];
-      const float G = __builtin_amdgcn_exp2f(p2);
-      const float og = a1.y * G;
-      const bool capped = og > kAlphaMax;
-      const float alpha = capped ? kAlphaMax : og;
-      const float ri = __builtin_amdgcn_rcpf(1.0f - alpha);
-      Tr = on ? Tr * ri : Tr;                // transmittance in front of this Gaussian
-      const float wgt = on ? alpha * Tr : 0.0f;
-      // Per pixel: colour partials, opacity partial and the moments of the exponent's
-      // derivative dpow over (dx, dy, dx^2, dx dy, dy^2); the centre and conic
-      // partials are fixed linear maps of these moments (applied once per tile).
-      float p[kGrad2D];
-      p[6] = g0 * wgt;
-      p[7] = g1 * wgt;
-      p[8] = g2 * wgt;
-      float dLda = g0 * __fmaf_rn(-S0, ri, a2.x * Tr);
-      dLda = __fmaf_rn(g1, __fmaf_rn(-S1, ri, a2.y * Tr), dLda);
-      dLda = __fmaf_rn(g2, __fmaf_rn(-S2, ri, a2.z * Tr), dLda);
-      dLda = (on && !capped) ? dLda : 0.0f;  // a capped alpha has zero derivative
-      S0 = __fmaf_rn(a2.x, wgt, S0);
-      S1 = __fmaf_rn(a2.y, wgt, S1);
-      S2 = __fmaf_rn(a2.z, wgt, S2);
-      const float dpow = dLda * og;           // dL/d(exponent)
-      p[5] = dLda * G;
-      p[0] = dpow * dx;
-      p[1] = dpow * dy;
-      p[2] = p[0] * dx;
-      p[3] = p[0] * dy;
-      p[4] = p[1] * dy;
-      wave_reduce9_to_lds(p, acc[j]);
+    // records this wavefront may need: positions below its own last blended one
+    // whose cutoff box meets its quadrant, walked back to front
+    uint64_t mask[NM];
+    quadrant_masks<NM>(s0, s1, s2, min(m, wave_last - beg), qx, qy, mask);
+    for (int k = NM - 1; k >= 0; --k) {
+      uint64_t mk = mask[k];
+      while (mk) {
+        const int b = 63 - __builtin_clzll(mk);
+        mk &= ~(1ull << b);
+        const int j = 64 * k + b;
+        const float4 a0 = s0[j];
+        const float4 a1 = s1[j];
+        const float dx = a0.x - fx, dy = a0.y - fy;
+        const float p2 = gauss_power2(a0.z, a0.w, a1.x, dx, dy);
+        const bool on = tg.inside && (uint32_t)(beg + j) < lp && p2 <= 0.0f && p2 >= a1.z;
+        if (__ballot(on) == 0ull) continue;    // no pixel of this wave blended it
+        // straight-line update; lanes that did not blend this Gaussian keep their state
+        // and contribute zeros
+        const float4 a2 = s2[j];
+        const float G = __builtin_amdgcn_exp2f(p2);
+        const float og = a1.y * G;
+        const bool capped = og > kAlphaMax;
+        const float alpha = capped ? kAlphaMax : og;
+        const float ri = __builtin_amdgcn_rcpf(1.0f - alpha);
+        Tr = on ? Tr * ri : Tr;                // transmittance in front of this Gaussian
+        const float wgt = on ? alpha * Tr : 0.0f;
+        // Per pixel: colour partials, opacity partial and the moments of the exponent's
+        // derivative dpow over (dx, dy, dx^2, dx dy, dy^2); the centre and conic
+        // partials are fixed linear maps of these moments (applied once per tile).
+        // dL/dalpha collects the colour terms and gG, the load-balancing gradient of
+        // the pixel's soft count (each blended alpha enters it with weight 1).
+        float p[kGrad2D];
+        p[6] = g0 * wgt;
+        p[7] = g1 * wgt;
+        p[8] = g2 * wgt;
+        float dLda = __fmaf_rn(g0, __fmaf_rn(-S0, ri, a2.x * Tr), gG);
+        dLda = __fmaf_rn(g1, __fmaf_rn(-S1, ri, a2.y * Tr), dLda);
+        dLda = __fmaf_rn(g2, __fmaf_rn(-S2, ri, a2.z * Tr), dLda);
+        dLda = (on && !capped) ? dLda : 0.0f;  // a capped alpha has zero derivative
+        S0 = __fmaf_rn(a2.x, wgt, S0);
+        S1 = __fmaf_rn(a2.y, wgt, S1);
+        S2 = __fmaf_rn(a2.z, wgt, S2);
+        const float dpow = dLda * og;           // dL/d(exponent)
+        p[5] = dLda * G;
+        p[0] = dpow * dx;
+        p[1] = dpow * dy;
+        p[2] = p[0] * dx;
+        p[3] = p[0] * dy;
+        p[4] = p[1] * dy;
+        wave_reduce9_to_lds(p, acc[j]);
+      }
     }
     __syncthreads();
     if ((int)threadIdx.x < m) {
@@ -330,19 +404,47 @@ __global__ __launch_bounds__(NT) void k_render_bwd(const ViewDev* __restrict__ v
 
 hipError_t launch_render_fwd(const ViewDev* views, int V, int n_tiles, const uint2* ranges, const uint32_t* pair_rec,
                              const Record* rec, uint32_t n_rec, float* color, float* t_final, uint32_t* n_contrib,
-                             uint32_t* last, hipStream_t s) {
+                             uint32_t* last, float* asum, int tile, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_render_fwd, dim3(n_tiles), dim3(NT), 0, s, views, V, ranges, pair_rec, rec, n_rec, color,
-                     t_final, n_contrib, last);
+  const dim3 grid(n_tiles);
+  switch (tile) {
+    case 8:
+      hipLaunchKernelGGL(k_render_fwd<8>, grid, dim3(64), 0, s, views, V, ranges, pair_rec, rec, n_rec, color, t_final,
+                         n_contrib, last, asum);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_render_fwd<16>, grid, dim3(256), 0, s, views, V, ranges, pair_rec, rec, n_rec, color,
+                         t_final, n_contrib, last, asum);
+      break;
+    case 32:
+      hipLaunchKernelGGL(k_render_fwd<32>, grid, dim3(1024), 0, s, views, V, ranges, pair_rec, rec, n_rec, color,
+                         t_final, n_contrib, last, asum);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_render_bwd(const ViewDev* views, int V, int n_tiles, const uint2* ranges, const uint32_t* pair_rec,
                              const Record* rec, uint32_t n_rec, const float* t_final, const uint32_t* last,
-                             const float* dL_dcolor, float* grad2d, hipStream_t s) {
+                             const float* dL_dcolor, const float* dL_dG, float* grad2d, int tile, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_render_bwd, dim3(n_tiles), dim3(NT), 0, s, views, V, ranges, pair_rec, rec, n_rec, t_final,
-                     last, dL_dcolor, grad2d);
+  const dim3 grid(n_tiles);
+  switch (tile) {
+    case 8:
+      hipLaunchKernelGGL(k_render_bwd<8>, grid, dim3(64), 0, s, views, V, ranges, pair_rec, rec, n_rec, t_final, last,
+                         dL_dcolor, dL_dG, grad2d);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_render_bwd<16>, grid, dim3(256), 0, s, views, V, ranges, pair_rec, rec, n_rec, t_final,
+                         last, dL_dcolor, dL_dG, grad2d);
+      break;
+    case 32:
+      hipLaunchKernelGGL(k_render_bwd<32>, grid, dim3(1024), 0, s, views, V, ranges, pair_rec, rec, n_rec, t_final,
+                         last, dL_dcolor, dL_dG, grad2d);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -343,7 +343,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
                                                     const ushort4* __restrict__ rect,
                                                     const Record* __restrict__ rec, size_t n_entries, int n,
                                                     const ViewDev* __restrict__ views, size_t K, uint32_t n_tiles,
-                                                    int cull, uint32_t* __restrict__ pair_tile,
+                                                    int cull, int T, uint32_t* __restrict__ pair_tile,
                                                     uint32_t* __restrict__ pair_rec) {
   __shared__ uint32_t s_off[kWaves][65];
   __shared__ uint32_t s_rid[kWaves][64];
@@ -413,10 +413,10 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
       const double* gp = s_geo[w][lo];
       const uint32_t org = s_org[w][lo], wh = s_wh[w][lo];
       const int gx = (int)((org & 0xffffu) + tx), gy = (int)((org >> 16) + ty);
-      const double x0 = (double)(gx * kTile) + 0.5;
-      const double x1 = fmin((double)(gx * kTile) + (kTile - 0.5), (double)(wh & 0xffffu) - 0.5);
-      const double y0 = (double)(gy * kTile) + 0.5;
-      const double y1 = fmin((double)(gy * kTile) + (kTile - 0.5), (double)(wh >> 16) - 0.5);
+      const double x0 = (double)(gx * T) + 0.5;
+      const double x1 = fmin((double)(gx * T) + ((double)T - 0.5), (double)(wh & 0xffffu) - 0.5);
+      const double y0 = (double)(gy * T) + 0.5;
+      const double y1 = fmin((double)(gy * T) + ((double)T - 0.5), (double)(wh >> 16) - 0.5);
       const double qm = box_min_q(gp[2], gp[3], gp[4], gp[5], gp[6], x0 - gp[0], x1 - gp[0], y0 - gp[1], y1 - gp[1]);
       if (!(qm <= s_lim[w][lo])) tile = n_tiles;
     }
@@ -510,13 +510,13 @@ hipError_t launch_scan_touched(const uint32_t* order, const uint32_t* touched, s
 
 hipError_t launch_emit_pairs(const uint32_t* order, const uint32_t* counts, const uint32_t* offsets,
                              const ushort4* rect, const Record* rec, size_t n_entries, int n, const ViewDev* views,
-                             int V, size_t K, uint32_t n_tiles, int cull, uint32_t* pair_tile, uint32_t* pair_rec,
-                             hipStream_t s) {
+                             int V, size_t K, uint32_t n_tiles, int cull, int tile, uint32_t* pair_tile,
+                             uint32_t* pair_rec, hipStream_t s) {
   (void)V;
   if (n_entries == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n_entries + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, order, counts, offsets, rect, rec, n_entries, n,
-                     views, K, n_tiles, cull, pair_tile, pair_rec);
+                     views, K, n_tiles, cull, tile, pair_tile, pair_rec);
   return hipGetLastError();
 }
 

@@ -11,16 +11,17 @@ from typing import Optional, Sequence
 import numpy as np
 import torch
 
-from . import (gs_memory_bytes, gs_create, gs_destroy, gs_layout, gs_preprocess, gs_bin_sort, gs_render_fwd, gs_loss,
+from . import (gs_memory_bytes, gs_load_balance, gs_create, gs_destroy, gs_layout, gs_preprocess, gs_bin_sort, gs_render_fwd, gs_loss,
                gs_render_bwd, gs_adam_step, gs_buffer_size, gs_copy_buffer, gs_profile_enable, gs_profile_read,
                KERNEL_NAMES, GS_BUF_RECORDS, GS_BUF_DEPTH, GS_BUF_TOUCHED, GS_BUF_TILE_RECT, GS_BUF_KEYS,
                GS_BUF_VALUES, GS_BUF_RANGES, GS_BUF_T_FINAL, GS_BUF_N_CONTRIB, GS_BUF_LAST, GS_BUF_GRAD2D,
-               GS_BUF_PAIR_VIEW)
+               GS_BUF_PAIR_VIEW, GS_BUF_ALPHA_SUM)
 
 _BUF_DTYPES = {GS_BUF_RECORDS: torch.uint8, GS_BUF_DEPTH: torch.int32, GS_BUF_TOUCHED: torch.int32,
                GS_BUF_TILE_RECT: torch.int16, GS_BUF_KEYS: torch.int64, GS_BUF_VALUES: torch.int32,
                GS_BUF_RANGES: torch.int32, GS_BUF_T_FINAL: torch.float32, GS_BUF_N_CONTRIB: torch.int32,
-               GS_BUF_LAST: torch.int32, GS_BUF_GRAD2D: torch.float32, GS_BUF_PAIR_VIEW: torch.int32}
+               GS_BUF_LAST: torch.int32, GS_BUF_GRAD2D: torch.float32, GS_BUF_PAIR_VIEW: torch.int32,
+               GS_BUF_ALPHA_SUM: torch.float32}
 
 # 3DGS-lineage per-group learning rates (position is the per-view Eq. 6-8 rate's eta^0):
 # mean, log-scale, rotation, opacity, SH DC, SH rest
@@ -38,6 +39,7 @@ class Rasterizer:
         self.cams = None
         self.pix_off = None
         self.K = None
+        self.tile = 16
 
     def close(self):
         if self.ctx:
@@ -52,10 +54,12 @@ class Rasterizer:
             pass
 
     # ---- geometry of the batch of views ----
-    def set_views(self, cams: Sequence[dict], tile: int = 16):
+    def set_views(self, cams: Sequence[dict], tile: Optional[int] = None):
+        """Views of the next steps; tile: 8, 16 or 32 (default: keep the current edge)."""
         self.cams = list(cams)
-        self.tile = tile
-        self.pix_off, self.tile_off = gs_layout(self.cams, tile)
+        if tile is not None:
+            self.tile = tile
+        self.pix_off, self.tile_off = gs_layout(self.cams, self.tile)
         self.P = self.pix_off[-1]
 
     def image_views(self, flat: torch.Tensor):
@@ -101,6 +105,11 @@ class Rasterizer:
             loss_out = torch.zeros(len(self.cams), dtype=torch.float64, device=self.device)
         gs_loss(self.ctx, color, target, w_l1, w_dssim, loss_out, dL_dcolor, stream)
         return loss_out, dL_dcolor
+
+    def load_balance(self, w_load: float, loss_out=None, stream=None):
+        """Eq. 9 term on the last forward; its gradient joins the next render_bwd."""
+        gs_load_balance(self.ctx, w_load, loss_out, stream)
+        return loss_out
 
     def render_bwd(self, dL_dcolor, grad: Optional[torch.Tensor] = None, accumulate=False, stream=None):
         if grad is None:

@@ -9,6 +9,9 @@ semi-global half (gs_sched_weights, gs_sched_plan).  Every iteration trains one
 image with its Eq. 6-8 learning rate (gs_sched_lr, trained-iteration counts kept
 per image).
 
+The loss of an iteration is Eq. 10: w_l1 L1 + w_dssim (1 - SSIM) + w_load L_load
+(Eq. 9 on the soft per-pixel count; the paper's weights are 0.47, 0.12, 0.41).
+
 Continuous batching: the engine keeps up to `max_slots` jobs in flight.  Each
 engine step takes the next iteration of every active job and runs them as one
 batched multi-view step (one gs_preprocess / gs_bin_sort / gs_render_fwd /
@@ -144,8 +147,8 @@ class Engine:
 
     def __init__(self, fld: Field, *, max_slots: int = 8, hbm_budget: Optional[int] = None, t_i: int = 200,
                  n_m: int = 10, eta0: float = 1.6e-4, etaf: float = 1.6e-6, t_a: float = 200.0, w_l1: float = 0.8,
-                 w_dssim: float = 0.2, lr_group: Sequence[float] = DEFAULT_LR, group_mask: int = 1, seed: int = 0,
-                 rasterizer=None):
+                 w_dssim: float = 0.2, w_load: float = 0.0, lr_group: Sequence[float] = DEFAULT_LR,
+                 group_mask: int = 1, seed: int = 0, rasterizer=None):
         if not 1 <= max_slots <= 64:
             raise ValueError("max_slots must be in 1..64 (views per batched launch)")
         self.field = fld
@@ -153,7 +156,7 @@ class Engine:
         self.budget = hbm_budget
         self.t_i, self.n_m = t_i, n_m
         self.eta0, self.etaf, self.t_a = eta0, etaf, t_a
-        self.w_l1, self.w_dssim = w_l1, w_dssim
+        self.w_l1, self.w_dssim, self.w_load = w_l1, w_dssim, w_load
         self.lr_group = tuple(float(x) for x in lr_group)
         self.group_mask = group_mask
         self.rng = np.random.default_rng(seed)
@@ -165,6 +168,7 @@ class Engine:
         self.pairs_per_view = None
         self._img = self._dl = None
         self._loss = torch.zeros(64, dtype=torch.float64, device=fld.device)
+        self._load = torch.zeros(64, dtype=torch.float64, device=fld.device)
         self.stats = ServeStats()
         self.jobs: List[Job] = []
 
@@ -200,14 +204,15 @@ class Engine:
         return job
 
     def _view_bytes(self, n: int, pixels: int) -> int:
-        """Context and image memory of one view of a step: 124 B per Gaussian
+        """Context and image memory of one view of a step: 125 B per Gaussian
         (record, depth, tiles touched, rect, sort keys and values, scan, 2D
-        gradient), 16 B per pair (tile ids and record ids, ping-pong), the buffers'
-        25 % over-allocation and small fixed buffers; 84 B per pixel (per-pixel
-        forward state, SSIM statistics, image and dL/dimage)."""
+        gradient, histograms), 16 B per pair (tile ids and record ids, ping-pong),
+        the buffers' 25 % over-allocation and small fixed buffers; 100 B per pixel
+        (per-pixel forward state, soft count and its gradient, SSIM statistics,
+        image and dL/dimage)."""
         pairs = self.pairs_per_view if self.pairs_per_view is not None else 16 * n
-        ctx = int((124 * n + 16 * pairs) * 5 // 4) + 65536
-        return ctx + 84 * pixels
+        ctx = int((125 * n + 16 * pairs) * 5 // 4) + 65536
+        return ctx + 100 * pixels
 
     def _resident_bytes(self, n_total: int, extra_targets: int) -> int:
         tgt = sum(t.numel() * 4 for t in self.targets) + extra_targets
@@ -251,6 +256,10 @@ class Engine:
         rz.render_fwd(color)
         loss = self._loss[: len(views)]
         rz.loss(color, target, self.w_l1, self.w_dssim, loss, dl)
+        if self.w_load != 0.0:
+            load = self._load[: len(views)]
+            rz.load_balance(self.w_load, load)
+            loss = loss + load
         rz.render_bwd(dl, fld.grad)
         out = None
         if record:

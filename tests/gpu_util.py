@@ -25,9 +25,9 @@ def ambiguous(r) -> np.ndarray:
             (r["m_T"] < MARGIN_T))
 
 
-def run_gpu(scene, upstream=None, loss=False, cull=None):
+def run_gpu(scene, upstream=None, loss=False, cull=None, tile=16):
     """Forward (and optionally backward) of the HIP path; returns numpy outputs.
-    cull: None (library default), "rect" or "ellipse"."""
+    cull: None (library default), "rect" or "ellipse"; tile: 8, 16 or 32."""
     from paper_2503_13086_amd.pipeline import Rasterizer, params_to_device
     from paper_2503_13086_amd import (GS_BUF_RECORDS, GS_BUF_DEPTH, GS_BUF_TOUCHED, GS_BUF_TILE_RECT,
                                       GS_BUF_KEYS, GS_BUF_VALUES, GS_BUF_RANGES, GS_BUF_T_FINAL,
@@ -38,7 +38,8 @@ def run_gpu(scene, upstream=None, loss=False, cull=None):
         if cull is not None:
             gs.gs_set_cull(rz.ctx, gs.GS_CULL_RECT if cull == "rect" else gs.GS_CULL_ELLIPSE)
         P = params_to_device(scene.params)
-        rz.preprocess(P, scene.n, scene.sh_degree, scene.cams)
+        rz.set_views(scene.cams, tile)
+        rz.preprocess(P, scene.n, scene.sh_degree)
         K = rz.bin_sort()
         color = rz.render_fwd()
         out = dict(K=K, n_tiles=rz.tile_off[-1], color=[x.cpu().numpy() for x in rz.image_views(color)])
@@ -115,6 +116,23 @@ def touching_mask(projs, amb_maps, n):
         vis = p["visible"]
         for i, j in zip(ii, jj):
             bad |= vis & (p["i0"] <= i) & (i <= p["i1"]) & (p["j0"] <= j) & (j <= p["j1"])
+    return bad
+
+
+def cutoff_touching_mask(projs, amb_maps, n, slack=1e-3):
+    """Gaussians whose cutoff region a dx^2 + 2b dx dy + c dy^2 <= -2 tau (widened
+    by a relative slack) contains an ambiguous pixel centre in some view: the only
+    Gaussians such a pixel can blend."""
+    bad = np.zeros(n, bool)
+    for p, amb in zip(projs, amb_maps):
+        jj, ii = np.nonzero(amb)
+        vis = p["visible"]
+        u, w = p["u"].numpy(), p["w"].numpy()
+        a, b, c = p["a"].numpy(), p["b"].numpy(), p["c"].numpy()
+        lim = -2.0 * p["tau"].numpy() * (1.0 + slack)
+        for i, j in zip(ii, jj):
+            dx, dy = (i + 0.5) - u, (j + 0.5) - w
+            bad |= vis & ((a * dx * dx + 2.0 * b * dx * dy + c * dy * dy) <= lim)
     return bad
 
 

@@ -139,7 +139,7 @@ def test_argument_checks():
             gs.gs_preprocess(rz.ctx, P, 10, 10, 4, sc.cams)           # SH degree 4
         assert e.value.status == gs.GS_ERR_INVALID
         with pytest.raises(gs.GsError) as e:
-            gs.gs_preprocess(rz.ctx, P, 10, 10, 0, sc.cams, tile=8)
+            gs.gs_preprocess(rz.ctx, P, 10, 10, 0, sc.cams, tile=12)
         assert e.value.status == gs.GS_ERR_UNSUPPORTED
         bad = dict(sc.cams[0])
         bad["fx"] = 0.0

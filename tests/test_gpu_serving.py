@@ -49,7 +49,7 @@ def test_alone_equals_mix():
     the same field snapshot: images and losses bit for bit, gradient = sum of the
     single-view gradients within fp32 atomics."""
     st = _stream(3)
-    eng = _engine(st, max_slots=4, t_i=8)
+    eng = _engine(st, max_slots=4, t_i=8, w_l1=0.47, w_dssim=0.12, w_load=0.41)    # Eq. 10 weights
     tg = _targets(st)
     try:
         jobs = [eng.register(a.cam, tg[i], a.overlap, a.block) for i, a in enumerate(st.arrivals)]

@@ -256,3 +256,72 @@ def test_schedule_iteration_plan():
     assert len(set(plan[10:])) == 10
     # a lone image takes every iteration
     assert schedule.iteration_plan({0: 1.0}, 1, 10, 7, [0.5]) == [0] * 7
+
+
+
+def test_load_balance_loss_eq9():
+    """Eq. 9 pins: population std (numpy), two-valued closed form, zero for a
+    constant map with zero gradient, and central differences of the gradient."""
+    rng = np.random.default_rng(3)
+    G = rng.random((7, 9)) * 3.0
+    val, g = loss.load_balance_loss_and_grad(G)
+    assert val == pytest.approx(float(np.std(G)), rel=1e-14)
+    half = np.zeros((4, 6))
+    half[:, :3] = 1.0
+    v2, g2 = loss.load_balance_loss_and_grad(half)
+    assert v2 == pytest.approx(0.5, rel=1e-15)
+    assert np.allclose(g2, (half - 0.5) / (half.size * 0.5), rtol=1e-14)
+    v0, g0 = loss.load_balance_loss_and_grad(np.full((3, 3), 2.5))
+    assert v0 == 0.0 and not g0.any()
+    h = 1e-6
+    for (j, i) in [(0, 0), (3, 4), (6, 8)]:
+        Gp, Gm = G.copy(), G.copy()
+        Gp[j, i] += h
+        Gm[j, i] -= h
+        fd = (np.std(Gp) - np.std(Gm)) / (2 * h)
+        assert abs(fd - g[j, i]) <= 1e-8
+
+
+def test_param_grads_with_load_term_finite_differences():
+    """The gradient of L = <dL/dC, C> + <dL/dA, alpha_sum> (load-balancing upstream
+    on the soft count) agrees with central differences of the oracle forward."""
+    sc = scenegen.small_scene(47, 24, 1, [(22, 18)], log_scale_mean=-1.9)
+    up = scenegen.upstream_grads(147, sc.cams, scale=1.0)
+    rng = np.random.default_rng(47)
+    upA = [rng.normal(0, 1, size=(c["height"], c["width"])) for c in sc.cams]
+    G = grad.param_grads(sc.params, sc.n, 1, sc.cams, up, dL_dalpha_sum=upA)
+    G0 = grad.param_grads(sc.params, sc.n, 1, sc.cams, up)
+    assert np.abs(G - G0).max() > 1e-3 * np.abs(G0).max()      # the load term moves the gradient
+
+    def obj(Q):
+        tot = 0.0
+        for c, g, gA in zip(sc.cams, up, upA):
+            p = geometry.project_view(torch.as_tensor(Q), c, 1)
+            r = composite.render_view(p, margins=False)
+            tot += float((r["color"] * g).sum()) + float((r["alpha_sum"] * gA).sum())
+        return tot
+
+    base_sig, _ = _structure(sc.params, sc.n, 1, sc.cams)
+    checked = 0
+    for _ in range(300):
+        if checked >= 30:
+            break
+        r_, g_ = int(rng.integers(sc.params.shape[0])), int(rng.integers(sc.n))
+        x0 = float(sc.params[r_, g_])
+        h = 1e-6 * max(1.0, abs(x0))
+        vals = []
+        for sgn in (+1, -1):
+            Q = sc.params.astype(np.float64).copy()
+            Q[r_, g_] = x0 + sgn * h
+            sig, _ = _structure(Q, sc.n, 1, sc.cams)
+            if not _same(sig, base_sig):
+                vals = None
+                break
+            vals.append(obj(Q[:, :sc.n]))
+        if vals is None:
+            continue
+        fd = (vals[0] - vals[1]) / (2 * h)
+        noise = 64 * np.finfo(np.float64).eps * (abs(vals[0]) + abs(vals[1])) / (2 * h)
+        assert abs(fd - G[r_, g_]) <= 1e-6 * abs(fd) + noise, (r_, g_, fd, G[r_, g_])
+        checked += 1
+    assert checked >= 20

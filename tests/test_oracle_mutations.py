@@ -8,13 +8,13 @@ import sys
 import pytest
 
 import oracle
-from oracle import geometry, composite, sh, loss, grad, adam, binning
+from oracle import geometry, composite, sh, loss, grad, adam, binning, schedule
 import tests.test_oracle_geometry as TG
 import tests.test_oracle_render as TR
 import tests.test_oracle_grad_loss_adam as TL
 
 _MODS = {"geometry": geometry, "composite": composite, "sh": sh, "loss": loss, "grad": grad, "adam": adam,
-         "binning": binning}
+         "binning": binning, "schedule": schedule}
 
 
 @contextlib.contextmanager
@@ -103,6 +103,23 @@ MUTATIONS = [
      [(TG.test_binning_sorted_and_ranges, ())]),
     ("adam", "return np.where(cnt > 0, s / np.maximum(cnt, 1), vs.mean())", "return np.where(cnt > 0, s, vs.mean())",
      [(TL.test_adam_view_factor_and_first_step_closed_form, ())]),
+    ("schedule", "w[i] = sum(w[j] * M[j, i] for j in prev) / len(prev)", "w[i] = sum(w[j] * M[j, i] for j in prev)",
+     [(TL.test_schedule_eq3_to_eq5, ())]),
+    ("schedule", "t = 1.0 if trained_iters > t_a else trained_iters / t_a", "t = trained_iters / t_a",
+     [(TL.test_schedule_eq6_to_eq8, ())]),
+    ("schedule", "/ (len(nb) + 1)", "/ len(nb)", [(TL.test_schedule_eq6_to_eq8, ())]),
+    ("schedule", "share = {i: raw[i] / (2.0 * tot) * t_i for i in top}", "share = {i: raw[i] / tot * t_i for i in top}",
+     [(TL.test_schedule_eq3_to_eq5, ()), (TL.test_schedule_iteration_plan, ())]),
+    ("schedule", "rest.sort(key=lambda i: (u[i], i))", "rest.sort(key=lambda i: (-u[i], i))",
+     [(TL.test_schedule_iteration_plan, ())]),
+    ("composite", 'out["alpha_sum"] = torch.where(blended, alpha2', 'out["alpha_sum"] = torch.where(ps, alpha2',
+     [(TR.test_vectorised_equals_scalar_brute_force, (31, 0, (32, 32))),
+      (TR.test_soft_count_stops_with_the_walk, ())]),
+    ("loss", "var = ((g - g.mean()) ** 2).mean()", "var = (g ** 2).mean()", [(TL.test_load_balance_loss_eq9, ())]),
+    ("grad", "obj = obj + (r[\"alpha_sum\"]", "obj = obj + 0.0 * (r[\"alpha_sum\"]",
+     [(TL.test_param_grads_with_load_term_finite_differences, ())]),
+    ("schedule", "rest = [i for i in range(n) if i not in share] or list(range(n))",
+     "rest = list(range(n))", [(TL.test_schedule_iteration_plan, ())]),
 ]
 
 

@@ -85,6 +85,7 @@ def test_single_isotropic_gaussian_closed_form(o_logit, ls):
             a = min(ALPHA_MAX, g) if inside else 0.0
             assert np.allclose(r["color"][:, j, i], col * a, rtol=1e-12, atol=1e-14)
             assert abs(r["T_final"][j, i] - (1 - a)) < 1e-14
+            assert abs(r["alpha_sum"][j, i] - a) < 1e-14
 
 
 def test_two_gaussians_depth_order():
@@ -126,6 +127,9 @@ def test_blending_invariants():
     pr1["rgb"] = torch.ones_like(pr["rgb"])
     r1 = composite.render_view(pr1)
     assert np.abs(r1["color"] - (1 - r["T_final"])[None]).max() < 1e-13
+    # soft count: sum alpha >= 1 - prod(1 - alpha) = 1 - T_final, each blended alpha <= 0.99
+    assert (r["alpha_sum"] >= 1 - r["T_final"] - 1e-13).all()
+    assert (r["alpha_sum"] <= ALPHA_MAX * r["n_contrib"] + 1e-13).all()
     # 0 <= C <= max colour * (1 - T_final) with a black background
     cmax = pr["rgb"].numpy()[:, pr["visible"]].max()
     assert r["color"].min() >= 0 and (r["color"] <= cmax * (1 - r["T_final"])[None] + 1e-13).all()
@@ -172,4 +176,27 @@ def test_vectorised_equals_scalar_brute_force(seed, deg, size):
     assert np.abs(rv["T_final"] - rb["T_final"]).max() < 1e-15
     assert (rv["n_contrib"] == rb["n_contrib"]).all()
     assert (rv["last_g"] == rb["last_g"]).all()
+    assert np.abs(rv["alpha_sum"] - rb["alpha_sum"]).max() < 1e-13
     assert rv["n_contrib"].max() >= 4
+
+
+
+def test_soft_count_stops_with_the_walk():
+    """Four opaque Gaussians stacked on the axis: at the centre pixel the first
+    blends (alpha capped at fl32(0.99), T = 1 - fl32(0.99) after it) and the second
+    stops the walk ((1 - fl32(0.99))^2 < fl32(1e-4)), so the soft count is one
+    capped alpha although all four pass the cutoff; the scalar walk agrees
+    everywhere."""
+    cam = scenegen.camera(np.eye(3), np.zeros(3), 64.0, 64.0, 8.0, 8.0, 16, 16)
+    P = np.zeros((14, 4), np.float32)
+    P[2] = [2.0, 2.5, 3.0, 3.5]
+    P[3:6] = -1.0
+    P[6] = 1.0
+    P[10] = 8.0
+    pr = geometry.project_view(geometry.params_f64(P, 4), cam, 0)
+    r = composite.render_view(pr)
+    assert (1 - ALPHA_MAX) ** 2 < T_MIN
+    assert r["n_contrib"][8, 8] == 1
+    assert abs(r["alpha_sum"][8, 8] - ALPHA_MAX) < 1e-15
+    rb = brute.render_image(pr)
+    assert np.abs(r["alpha_sum"] - rb["alpha_sum"]).max() < 1e-13
