@@ -34,6 +34,12 @@ def _run(cmd):
     return r.stdout + r.stderr
 
 
+# Per-source flags.  The raster kernels' LDS and global atomics take per-lane
+# addresses by design; the compiler's wave-level atomic combining would turn the
+# one uniform-address LDS add of the backward's reduction into a read-lane loop.
+EXTRA = {"k_raster.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+
+
 def build(verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
@@ -41,7 +47,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for src in SOURCES:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmds.append([HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        cmds.append([HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj])
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         outs = list(ex.map(_run, cmds))
     tmp = LIB + ".tmp"

@@ -389,13 +389,17 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
       a[2] = -0.5f * m3;
       a[3] = -m4;
       a[4] = -0.5f * m5;
-      const uint32_t rid = srid[threadIdx.x];
-      float* dst = grad2d + (size_t)rid * kGrad2D;
-      for (int k = 0; k < kGrad2D; ++k) {
-        const float x = a[k];
-        if (x != 0.0f && rid < n_rec) unsafeAtomicAdd(dst + k, x);
-        a[k] = 0.0f;
-      }
+    }
+    __syncthreads();
+    // one global atomic per (tile, Gaussian, component); consecutive lanes take
+    // consecutive components, so a wavefront's atomics fall on a few cache lines
+    float* af = &acc[0][0];
+    for (int i = threadIdx.x; i < m * kGrad2D; i += NT) {
+      const int j = i / kGrad2D;
+      const uint32_t rid = srid[j];
+      const float x = af[i];
+      if (x != 0.0f && rid < n_rec) unsafeAtomicAdd(grad2d + (size_t)rid * kGrad2D + (i - j * kGrad2D), x);
+      af[i] = 0.0f;
     }
   }
 }
