@@ -11,10 +11,12 @@
 // and depth, screen position and extent come out exactly as an IEEE FP64
 // evaluation in the same operation order (contraction is off in this file).
 //
-// Backward: one thread per Gaussian recomputes the same forward quantities per
-// view, applies the chain rule from the per-view 2D gradients
-// (u, w, a, b, c, o, rgb) to mean, log-scale, quaternion, opacity logit and SH
-// coefficients, sums the views in FP64 and writes each gradient once.
+// Backward: one thread per Gaussian recomputes the forward quantities per view in
+// fp32 (gradients carry no discrete decision; visibility is the forward's
+// tiles-touched count), applies the chain rule from the per-view 2D gradients
+// (u, w, a, b, c, o, rgb) to mean, covariance, opacity and SH coefficients, sums
+// the views, takes covariance to log-scale and quaternion in FP64 once, and
+// writes each gradient once.
 #include "gs_internal.h"
 
 #pragma clang fp contract(off)
@@ -25,74 +27,77 @@ namespace {
 // Real SH basis of the 3DGS lineage (order k = l^2 + l + m), constants from
 // sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) times the Cartesian polynomial factors.
 constexpr double kPi = 3.14159265358979323846;
-__device__ inline void sh_eval(int D, double x, double y, double z, double* Y) {
-  const double c0 = 0.5 * sqrt(1.0 / kPi);
+template <typename F>
+__device__ inline void sh_eval(int D, F x, F y, F z, F* Y) {
+  const F c0 = (F)(0.5 * sqrt(1.0 / kPi));
   Y[0] = c0;
   if (D < 1) return;
-  const double c1 = sqrt(3.0 / (4.0 * kPi));
+  const F c1 = (F)sqrt(3.0 / (4.0 * kPi));
   Y[1] = -c1 * y;
   Y[2] = c1 * z;
   Y[3] = -c1 * x;
   if (D < 2) return;
-  const double xx = x * x, yy = y * y, zz = z * z;
-  const double c2a = 0.5 * sqrt(15.0 / kPi), c2b = 0.25 * sqrt(5.0 / kPi), c2c = 0.25 * sqrt(15.0 / kPi);
+  const F xx = x * x, yy = y * y, zz = z * z;
+  const F c2a = (F)(0.5 * sqrt(15.0 / kPi)), c2b = (F)(0.25 * sqrt(5.0 / kPi)), c2c = (F)(0.25 * sqrt(15.0 / kPi));
   Y[4] = c2a * (x * y);
   Y[5] = -c2a * (y * z);
-  Y[6] = c2b * (2.0 * zz - xx - yy);
+  Y[6] = c2b * ((F)2 * zz - xx - yy);
   Y[7] = -c2a * (x * z);
   Y[8] = c2c * (xx - yy);
   if (D < 3) return;
-  const double c3a = 0.25 * sqrt(35.0 / (2.0 * kPi)), c3b = 0.5 * sqrt(105.0 / kPi);
-  const double c3c = 0.25 * sqrt(21.0 / (2.0 * kPi)), c3d = 0.25 * sqrt(7.0 / kPi);
-  const double c3e = 0.25 * sqrt(105.0 / kPi);
-  Y[9] = -c3a * y * (3.0 * xx - yy);
+  const F c3a = (F)(0.25 * sqrt(35.0 / (2.0 * kPi))), c3b = (F)(0.5 * sqrt(105.0 / kPi));
+  const F c3c = (F)(0.25 * sqrt(21.0 / (2.0 * kPi))), c3d = (F)(0.25 * sqrt(7.0 / kPi));
+  const F c3e = (F)(0.25 * sqrt(105.0 / kPi));
+  Y[9] = -c3a * y * ((F)3 * xx - yy);
   Y[10] = c3b * (x * y) * z;
-  Y[11] = -c3c * y * (4.0 * zz - xx - yy);
-  Y[12] = c3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
-  Y[13] = -c3c * x * (4.0 * zz - xx - yy);
+  Y[11] = -c3c * y * ((F)4 * zz - xx - yy);
+  Y[12] = c3d * z * ((F)2 * zz - (F)3 * xx - (F)3 * yy);
+  Y[13] = -c3c * x * ((F)4 * zz - xx - yy);
   Y[14] = c3e * z * (xx - yy);
-  Y[15] = -c3a * x * (xx - 3.0 * yy);
+  Y[15] = -c3a * x * (xx - (F)3 * yy);
 }
 
-// dL/d(direction) from dL/dY_k (gradient of each basis polynomial)
-__device__ inline void sh_grad_dir(int D, double x, double y, double z, const double* gY, double* gd) {
-  gd[0] = gd[1] = gd[2] = 0.0;
+// dL/d(direction) from dL/dY_k (gradient of each basis polynomial); evaluated in
+// fp32 by the backward
+__device__ inline void sh_grad_dir(int D, float x, float y, float z, const float* gY, float* gd) {
+  gd[0] = gd[1] = gd[2] = 0.0f;
   if (D < 1) return;
-  const double c1 = sqrt(3.0 / (4.0 * kPi));
+  const float c1 = (float)sqrt(3.0 / (4.0 * kPi));
   gd[1] += -c1 * gY[1];
   gd[2] += c1 * gY[2];
   gd[0] += -c1 * gY[3];
   if (D < 2) return;
-  const double xx = x * x, yy = y * y, zz = z * z;
-  const double c2a = 0.5 * sqrt(15.0 / kPi), c2b = 0.25 * sqrt(5.0 / kPi), c2c = 0.25 * sqrt(15.0 / kPi);
+  const float xx = x * x, yy = y * y, zz = z * z;
+  const float c2a = (float)(0.5 * sqrt(15.0 / kPi)), c2b = (float)(0.25 * sqrt(5.0 / kPi));
+  const float c2c = (float)(0.25 * sqrt(15.0 / kPi));
   gd[0] += c2a * y * gY[4];            gd[1] += c2a * x * gY[4];
   gd[1] += -c2a * z * gY[5];           gd[2] += -c2a * y * gY[5];
-  gd[0] += -2.0 * c2b * x * gY[6];     gd[1] += -2.0 * c2b * y * gY[6];   gd[2] += 4.0 * c2b * z * gY[6];
+  gd[0] += -2.0f * c2b * x * gY[6];    gd[1] += -2.0f * c2b * y * gY[6];  gd[2] += 4.0f * c2b * z * gY[6];
   gd[0] += -c2a * z * gY[7];           gd[2] += -c2a * x * gY[7];
-  gd[0] += 2.0 * c2c * x * gY[8];      gd[1] += -2.0 * c2c * y * gY[8];
+  gd[0] += 2.0f * c2c * x * gY[8];     gd[1] += -2.0f * c2c * y * gY[8];
   if (D < 3) return;
-  const double c3a = 0.25 * sqrt(35.0 / (2.0 * kPi)), c3b = 0.5 * sqrt(105.0 / kPi);
-  const double c3c = 0.25 * sqrt(21.0 / (2.0 * kPi)), c3d = 0.25 * sqrt(7.0 / kPi);
-  const double c3e = 0.25 * sqrt(105.0 / kPi);
-  gd[0] += -c3a * 6.0 * x * y * gY[9];
-  gd[1] += -c3a * 3.0 * (xx - yy) * gY[9];
+  const float c3a = (float)(0.25 * sqrt(35.0 / (2.0 * kPi))), c3b = (float)(0.5 * sqrt(105.0 / kPi));
+  const float c3c = (float)(0.25 * sqrt(21.0 / (2.0 * kPi))), c3d = (float)(0.25 * sqrt(7.0 / kPi));
+  const float c3e = (float)(0.25 * sqrt(105.0 / kPi));
+  gd[0] += -c3a * 6.0f * x * y * gY[9];
+  gd[1] += -c3a * 3.0f * (xx - yy) * gY[9];
   gd[0] += c3b * y * z * gY[10];
   gd[1] += c3b * x * z * gY[10];
   gd[2] += c3b * x * y * gY[10];
-  gd[0] += -c3c * (-2.0 * x * y) * gY[11];
-  gd[1] += -c3c * (4.0 * zz - xx - 3.0 * yy) * gY[11];
-  gd[2] += -c3c * (8.0 * y * z) * gY[11];
-  gd[0] += c3d * (-6.0 * x * z) * gY[12];
-  gd[1] += c3d * (-6.0 * y * z) * gY[12];
-  gd[2] += c3d * (6.0 * zz - 3.0 * xx - 3.0 * yy) * gY[12];
-  gd[0] += -c3c * (4.0 * zz - 3.0 * xx - yy) * gY[13];
-  gd[1] += -c3c * (-2.0 * x * y) * gY[13];
-  gd[2] += -c3c * (8.0 * x * z) * gY[13];
-  gd[0] += c3e * 2.0 * x * z * gY[14];
-  gd[1] += -c3e * 2.0 * y * z * gY[14];
+  gd[0] += -c3c * (-2.0f * x * y) * gY[11];
+  gd[1] += -c3c * (4.0f * zz - xx - 3.0f * yy) * gY[11];
+  gd[2] += -c3c * (8.0f * y * z) * gY[11];
+  gd[0] += c3d * (-6.0f * x * z) * gY[12];
+  gd[1] += c3d * (-6.0f * y * z) * gY[12];
+  gd[2] += c3d * (6.0f * zz - 3.0f * xx - 3.0f * yy) * gY[12];
+  gd[0] += -c3c * (4.0f * zz - 3.0f * xx - yy) * gY[13];
+  gd[1] += -c3c * (-2.0f * x * y) * gY[13];
+  gd[2] += -c3c * (8.0f * x * z) * gY[13];
+  gd[0] += c3e * 2.0f * x * z * gY[14];
+  gd[1] += -c3e * 2.0f * y * z * gY[14];
   gd[2] += c3e * (xx - yy) * gY[14];
-  gd[0] += -c3a * 3.0 * (xx - yy) * gY[15];
-  gd[1] += -c3a * (-6.0 * x * y) * gY[15];
+  gd[0] += -c3a * 3.0f * (xx - yy) * gY[15];
+  gd[1] += -c3a * (-6.0f * x * y) * gY[15];
 }
 
 // View-independent quantities of one Gaussian.
@@ -266,137 +271,192 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ P,
   }
 }
 
+// ---- backward, in fp32 (gradients carry no discrete decision; visibility comes
+// from the forward's tiles-touched count) ----
+struct GaussF {
+  float m[3];
+  float Sig[3][3];
+};
+
+__device__ inline void gauss_geom_f(const float* __restrict__ P, int stride, int g, GaussF& G) {
+#pragma clang fp contract(fast)
+  for (int i = 0; i < 3; ++i) G.m[i] = P[(size_t)i * stride + g];
+  float sc[3];
+  for (int i = 0; i < 3; ++i) sc[i] = expf(P[(size_t)(3 + i) * stride + g]);
+  const float qw = P[(size_t)6 * stride + g], qx = P[(size_t)7 * stride + g];
+  const float qy = P[(size_t)8 * stride + g], qz = P[(size_t)9 * stride + g];
+  const float inv = 1.0f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+  const float w = qw * inv, x = qx * inv, y = qy * inv, z = qz * inv;
+  const float Rq[3][3] = {{1.0f - 2.0f * (y * y + z * z), 2.0f * (x * y - w * z), 2.0f * (x * z + w * y)},
+                          {2.0f * (x * y + w * z), 1.0f - 2.0f * (x * x + z * z), 2.0f * (y * z - w * x)},
+                          {2.0f * (x * z - w * y), 2.0f * (y * z + w * x), 1.0f - 2.0f * (x * x + y * y)}};
+  float M[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int l = 0; l < 3; ++l) M[k][l] = Rq[k][l] * sc[l];
+  for (int k = 0; k < 3; ++k)
+    for (int l = 0; l < 3; ++l) G.Sig[k][l] = M[k][0] * M[l][0] + M[k][1] * M[l][1] + M[k][2] * M[l][2];
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(const float* __restrict__ P, int n, int stride,
                                                          const ViewDev* __restrict__ views, int V,
                                                          const uint32_t* __restrict__ touched,
                                                          const float* __restrict__ grad2d, float* __restrict__ out,
                                                          int accumulate) {
+#pragma clang fp contract(fast)
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
-  Gauss G;
-  load_gauss(P, stride, g, G);
   constexpr int K = (D + 1) * (D + 1);
-  float f[3 * K];
-#pragma unroll
-  for (int i = 0; i < 3 * K; ++i) f[i] = P[(size_t)(11 + i) * stride + g];
+  GaussF G;
+  gauss_geom_f(P, stride, g, G);
 
-  double gm[3] = {0, 0, 0};         // dL/dmean
-  double gSig[3][3] = {{0}};        // symmetric dL/dSigma accumulated over views
-  double go = 0.0;                  // dL/dopacity
-  double gf[3 * K];                 // dL/dSH
+  float gm[3] = {0.f, 0.f, 0.f};       // dL/dmean
+  float gSig[3][3] = {{0.f}};          // symmetric dL/dSigma accumulated over views
+  float go = 0.f;                      // dL/dopacity
+  float gf[3 * K];                     // dL/dSH
 #pragma unroll
-  for (int i = 0; i < 3 * K; ++i) gf[i] = 0.0;
+  for (int i = 0; i < 3 * K; ++i) gf[i] = 0.f;
 
   for (int v = 0; v < V; ++v) {
     const size_t idx = (size_t)v * n + g;
     if (touched[idx] == 0u) continue;
     const ViewDev& cv = views[v];
-    Proj p;
-    project(G, cv, p);
     const float* g2 = grad2d + idx * kGrad2D;
-    const double gu = g2[0], gw = g2[1], ga = g2[2], gb = g2[3], gc = g2[4];
-    go += (double)g2[5];
-    const double grgb[3] = {g2[6], g2[7], g2[8]};
+    const float gu = g2[0], gw = g2[1], ga = g2[2], gb = g2[3], gc = g2[4];
+    go += g2[5];
+    const float grgb[3] = {g2[6], g2[7], g2[8]};
+    float Wr[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Wr[i][j] = cv.R[3 * i + j];
 
-    // colour: raw = 1/2 + sum_k f_k Y_k(dir), clamped at 0 (zero derivative when clamped)
-    double dir[3], dn;
-    camera_dir(G, cv, dir, dn);
-    double Y[16];
-    sh_eval(D, dir[0], dir[1], dir[2], Y);
-    double graw[3];
+    // colour: raw = 1/2 + sum_k f_k Y_k(dir), clamped at 0 (zero derivative when
+    // clamped); dir from the camera centre -W^T t to the mean
+    float oc[3];
+    for (int k = 0; k < 3; ++k) oc[k] = -(Wr[0][k] * cv.t[0] + Wr[1][k] * cv.t[1] + Wr[2][k] * cv.t[2]);
+    const float d0 = G.m[0] - oc[0], d1 = G.m[1] - oc[1], d2 = G.m[2] - oc[2];
+    const float dn = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+    const float dir[3] = {d0 / dn, d1 / dn, d2 / dn};
+    // SH coefficients are re-read per view (cache hits) instead of being held in
+    // registers across the loop; the empty asm keeps the compiler from hoisting
+    // the loads out of it
+    const float* fp = P + (size_t)11 * stride + g;
+    asm volatile("" : "+v"(fp));
+    float Y[16];
+    sh_eval<float>(D, dir[0], dir[1], dir[2], Y);
+    float graw[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-      double acc = 0.5;
+      float acc = 0.5f;
 #pragma unroll
-      for (int k = 0; k < K; ++k) acc += (double)f[3 * k + ch] * Y[k];
-      graw[ch] = acc < 0.0 ? 0.0 : grgb[ch];
+      for (int k = 0; k < K; ++k) acc += fp[(size_t)(3 * k + ch) * stride] * Y[k];
+      graw[ch] = acc < 0.0f ? 0.0f : grgb[ch];
     }
-    double gY[16];
+    float gY[16];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      gY[k] = 0.0;
+      gY[k] = 0.0f;
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
         gf[3 * k + ch] += graw[ch] * Y[k];
-        gY[k] += graw[ch] * (double)f[3 * k + ch];
+        gY[k] += graw[ch] * fp[(size_t)(3 * k + ch) * stride];
       }
     }
-    double gdir[3];
+    float gdir[3];
     sh_grad_dir(D, dir[0], dir[1], dir[2], gY, gdir);
-    const double dd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
+    const float dd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
     for (int k = 0; k < 3; ++k) gm[k] += (gdir[k] - dir[k] * dd) / dn;
 
+    // projection (the forward's formulas; the clamp state is re-derived)
+    const float tx = Wr[0][0] * G.m[0] + Wr[0][1] * G.m[1] + Wr[0][2] * G.m[2] + cv.t[0];
+    const float ty = Wr[1][0] * G.m[0] + Wr[1][1] * G.m[1] + Wr[1][2] * G.m[2] + cv.t[1];
+    const float tz = Wr[2][0] * G.m[0] + Wr[2][1] * G.m[1] + Wr[2][2] * G.m[2] + cv.t[2];
+    const float fx = cv.fx, fy = cv.fy;
+    const float limx = ((float)kJacClamp * (0.5f * (float)cv.W)) / fx;
+    const float limy = ((float)kJacClamp * (0.5f * (float)cv.H)) / fy;
+    const float rx = tx / tz, ry = ty / tz;
+    const bool clx = !(rx >= -limx && rx <= limx), cly = !(ry >= -limy && ry <= limy);
+    const float txc = tz * fminf(fmaxf(rx, -limx), limx), tyc = tz * fminf(fmaxf(ry, -limy), limy);
+    const float J00 = fx / tz, J02 = -(fx * txc) / (tz * tz);
+    const float J11 = fy / tz, J12 = -(fy * tyc) / (tz * tz);
+    float T0[3], T1[3];
+    for (int k = 0; k < 3; ++k) {
+      T0[k] = J00 * Wr[0][k] + J02 * Wr[2][k];
+      T1[k] = J11 * Wr[1][k] + J12 * Wr[2][k];
+    }
+    float ST0[3], ST1[3];
+    for (int k = 0; k < 3; ++k) {
+      ST0[k] = G.Sig[k][0] * T0[0] + G.Sig[k][1] * T0[1] + G.Sig[k][2] * T0[2];
+      ST1[k] = G.Sig[k][0] * T1[0] + G.Sig[k][1] * T1[1] + G.Sig[k][2] * T1[2];
+    }
+    const float S00 = ST0[0] * T0[0] + ST0[1] * T0[1] + ST0[2] * T0[2] + (float)kKappa;
+    const float S01 = ST0[0] * T1[0] + ST0[1] * T1[1] + ST0[2] * T1[2];
+    const float S11 = ST1[0] * T1[0] + ST1[1] * T1[1] + ST1[2] * T1[2] + (float)kKappa;
+    const float idet = 1.0f / (S00 * S11 - S01 * S01);
+    const float A00 = S11 * idet, A01 = -S01 * idet, A11 = S00 * idet;
+
     // conic (a, b, c) = inverse of S -> dL/dS = -A Gc A, Gc = [[ga, gb/2], [gb/2, gc]]
-    const double A00 = p.a, A01 = p.b, A11 = p.c;
-    const double H00 = ga * A00 + 0.5 * gb * A01, H01 = ga * A01 + 0.5 * gb * A11;
-    const double H10 = 0.5 * gb * A00 + gc * A01, H11 = 0.5 * gb * A01 + gc * A11;  // Gc A
-    const double gS00 = -(A00 * H00 + A01 * H10);
-    const double gS11 = -(A01 * H01 + A11 * H11);
-    const double gS01 = -2.0 * (A00 * H01 + A01 * H11);   // S01 appears in both off-diagonal slots
+    const float H00 = ga * A00 + 0.5f * gb * A01, H01 = ga * A01 + 0.5f * gb * A11;
+    const float H10 = 0.5f * gb * A00 + gc * A01, H11 = 0.5f * gb * A01 + gc * A11;  // Gc A
+    const float gS00 = -(A00 * H00 + A01 * H10);
+    const float gS11 = -(A01 * H01 + A11 * H11);
+    const float gS01 = -2.0f * (A00 * H01 + A01 * H11);   // S01 appears in both off-diagonal slots
 
     // S = T Sigma T^T (+ kappa I): dL/dSigma (symmetric part) and dL/dT
     for (int k = 0; k < 3; ++k)
       for (int l = 0; l < 3; ++l)
-        gSig[k][l] += gS00 * p.T0[k] * p.T0[l] + 0.5 * gS01 * (p.T0[k] * p.T1[l] + p.T1[k] * p.T0[l]) +
-                      gS11 * p.T1[k] * p.T1[l];
-    double ST0[3], ST1[3];
+        gSig[k][l] += gS00 * T0[k] * T0[l] + 0.5f * gS01 * (T0[k] * T1[l] + T1[k] * T0[l]) + gS11 * T1[k] * T1[l];
+    float gT0[3], gT1[3];
     for (int k = 0; k < 3; ++k) {
-      ST0[k] = G.Sig[k][0] * p.T0[0] + G.Sig[k][1] * p.T0[1] + G.Sig[k][2] * p.T0[2];
-      ST1[k] = G.Sig[k][0] * p.T1[0] + G.Sig[k][1] * p.T1[1] + G.Sig[k][2] * p.T1[2];
-    }
-    double gT0[3], gT1[3];
-    for (int k = 0; k < 3; ++k) {
-      gT0[k] = 2.0 * gS00 * ST0[k] + gS01 * ST1[k];
-      gT1[k] = gS01 * ST0[k] + 2.0 * gS11 * ST1[k];
+      gT0[k] = 2.0f * gS00 * ST0[k] + gS01 * ST1[k];
+      gT1[k] = gS01 * ST0[k] + 2.0f * gS11 * ST1[k];
     }
     // T0 = J00 W0 + J02 W2, T1 = J11 W1 + J12 W2 (W = view rotation rows)
-    double Wr[3][3];
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) Wr[i][j] = cv.R[3 * i + j];
-    double gJ00 = 0, gJ02 = 0, gJ11 = 0, gJ12 = 0;
+    float gJ00 = 0.f, gJ02 = 0.f, gJ11 = 0.f, gJ12 = 0.f;
     for (int k = 0; k < 3; ++k) {
       gJ00 += gT0[k] * Wr[0][k];
       gJ02 += gT0[k] * Wr[2][k];
       gJ11 += gT1[k] * Wr[1][k];
       gJ12 += gT1[k] * Wr[2][k];
     }
-    const double tz = p.tz, tz2 = tz * tz, tz3 = tz2 * tz;
-    const double fx = cv.fx, fy = cv.fy;
-    double gt[3] = {0, 0, 0};
+    const float tz2 = tz * tz, tz3 = tz2 * tz;
+    float gt[3] = {0.f, 0.f, 0.f};
     // u = fx tx / tz + cx, w = fy ty / tz + cy
     gt[0] += gu * fx / tz;
     gt[1] += gw * fy / tz;
-    gt[2] += -(gu * fx * p.tx + gw * fy * p.ty) / tz2;
+    gt[2] += -(gu * fx * tx + gw * fy * ty) / tz2;
     // J00 = fx / tz, J11 = fy / tz
     gt[2] += -(gJ00 * fx + gJ11 * fy) / tz2;
     // J02 = -fx txc / tz^2 with txc = tx (free) or tz * (+-lim) (clamped)
-    if (!p.clx) {
+    if (!clx) {
       gt[0] += -gJ02 * fx / tz2;
-      gt[2] += gJ02 * 2.0 * fx * p.txc / tz3;
+      gt[2] += gJ02 * 2.0f * fx * txc / tz3;
     } else {
-      gt[2] += gJ02 * fx * p.txc / tz3;
+      gt[2] += gJ02 * fx * txc / tz3;
     }
-    if (!p.cly) {
+    if (!cly) {
       gt[1] += -gJ12 * fy / tz2;
-      gt[2] += gJ12 * 2.0 * fy * p.tyc / tz3;
+      gt[2] += gJ12 * 2.0f * fy * tyc / tz3;
     } else {
-      gt[2] += gJ12 * fy * p.tyc / tz3;
+      gt[2] += gJ12 * fy * tyc / tz3;
     }
     // t = W mean + t_v
     for (int k = 0; k < 3; ++k) gm[k] += Wr[0][k] * gt[0] + Wr[1][k] * gt[1] + Wr[2][k] * gt[2];
   }
 
-  // Sigma = M M^T -> dL/dM = 2 sym(dL/dSigma) M; M = Rq diag(s)
+  // Sigma = M M^T -> dL/dM = 2 sym(dL/dSigma) M; M = Rq diag(s); then the
+  // activations (FP64, once per Gaussian)
+  Gauss H;
+  load_gauss(P, stride, g, H);
   double gs[3] = {0, 0, 0};
   double gR[3][3];
   for (int k = 0; k < 3; ++k)
     for (int j = 0; j < 3; ++j) {
-      const double gM = 2.0 * (gSig[k][0] * G.M[0][j] + gSig[k][1] * G.M[1][j] + gSig[k][2] * G.M[2][j]);
-      gs[j] += gM * G.Rq[k][j];
-      gR[k][j] = gM * G.s[j];
+      const double gM = 2.0 * ((double)gSig[k][0] * H.M[0][j] + (double)gSig[k][1] * H.M[1][j] +
+                               (double)gSig[k][2] * H.M[2][j]);
+      gs[j] += gM * H.Rq[k][j];
+      gR[k][j] = gM * H.s[j];
     }
-  const double w = G.q[0], x = G.q[1], y = G.q[2], z = G.q[3];
+  const double w = H.q[0], x = H.q[1], y = H.q[2], z = H.q[3];
   double gq[4];
   gq[0] = 2.0 * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] - y * gR[2][0] + x * gR[2][1]);
   gq[1] = 2.0 * (y * gR[0][1] + z * gR[0][2] + y * gR[1][0] - 2.0 * x * gR[1][1] - w * gR[1][2] + z * gR[2][0] +
@@ -409,9 +469,9 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(const float* __restrict_
 
   double outv[11];
   for (int k = 0; k < 3; ++k) outv[k] = gm[k];
-  for (int k = 0; k < 3; ++k) outv[3 + k] = gs[k] * G.s[k];
-  for (int k = 0; k < 4; ++k) outv[6 + k] = (gq[k] - G.q[k] * qd) / G.qn;
-  outv[10] = go * G.o * (1.0 - G.o);
+  for (int k = 0; k < 3; ++k) outv[3 + k] = gs[k] * H.s[k];
+  for (int k = 0; k < 4; ++k) outv[6 + k] = (gq[k] - H.q[k] * qd) / H.qn;
+  outv[10] = (double)go * H.o * (1.0 - H.o);
   for (int r = 0; r < 11; ++r) {
     float* dst = out + (size_t)r * stride + g;
     *dst = accumulate ? *dst + (float)outv[r] : (float)outv[r];
@@ -419,7 +479,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(const float* __restrict_
 #pragma unroll
   for (int i = 0; i < 3 * K; ++i) {
     float* dst = out + (size_t)(11 + i) * stride + g;
-    *dst = accumulate ? *dst + (float)gf[i] : (float)gf[i];
+    *dst = accumulate ? *dst + gf[i] : gf[i];
   }
 }
 
