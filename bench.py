@@ -24,7 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
-FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X fp32 vector (packed); non-packed issue is half of it
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X fp32 vector, packed FMA: 256 CUs x 4 SIMDs x 16 lanes x 2 x 2 x 2.4 GHz
+FP32_NONPACKED_PEAK_TFLOPS = 78.6  # the same without packed issue (the build disables packed fp32)
 
 
 def eq6_lr(iters, eta0=1.6e-4, etaf=1.6e-6, t_a=30000.0):
@@ -45,7 +46,8 @@ def make_workload(name):
 
 
 def algorithmic_bytes(n, n_p, V, K, P, tiles, ssim):
-    """Compulsory HBM bytes per stage: each input read once, each output written once."""
+    """Compulsory HBM bytes per stage: each input read once, each output written
+    once; K = the (tile, Gaussian) pairs that belong to a tile's list."""
     return {
         "preprocess": 4 * n_p * n + 64 * V * n,
         "scan_emit": 8 * V * n + 12 * K,
@@ -265,9 +267,11 @@ def main():
 
     # per-pixel work the method needs: list positions up to each pixel's last blended
     # Gaussian (each takes the cutoff test) and the Gaussians it blended
-    from paper_2503_13086_amd import GS_BUF_LAST, GS_BUF_N_CONTRIB
+    from paper_2503_13086_amd import GS_BUF_LAST, GS_BUF_N_CONTRIB, GS_BUF_RANGES
     visits = int(rz.buffer(GS_BUF_LAST).to(torch.int64).sum().item())
     blends = int(rz.buffer(GS_BUF_N_CONTRIB).to(torch.int64).sum().item())
+    rg = rz.buffer(GS_BUF_RANGES).view(-1, 2).to(torch.int64)
+    K_valid = int((rg[:, 1] - rg[:, 0]).sum().item())      # pairs in some tile's list
 
     # plain loop: each view on its own call sequence, gradients summed, one Adam step
     plain_ms = None
@@ -296,7 +300,7 @@ def main():
     n_p = n_params(D)
     rz.set_views(sc.cams)
     n_tiles = rz.tile_off[-1]
-    algo = algorithmic_bytes(n, n_p, V, K, P, n_tiles, sc.w_dssim != 0)
+    algo = algorithmic_bytes(n, n_p, V, K_valid, P, n_tiles, sc.w_dssim != 0)
     # dominant kernel and its roofline
     dom = max(["render_fwd", "render_bwd", "preprocess", "tile_sort", "depth_sort", "preprocess_bwd", "adam", "loss",
                "emit"], key=lambda k: kern_ms[k] * kern_launches[k])
@@ -305,13 +309,30 @@ def main():
         achieved = flops / (kern_ms[dom] * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic_for(dom, args.workload), "kernel": dom,
-                "kernel_ms": kern_ms[dom], "algorithmic_flops": flops}
+                "kernel_ms": kern_ms[dom], "algorithmic_flops": flops,
+                "peak_nonpacked": FP32_NONPACKED_PEAK_TFLOPS, "frac_nonpacked": achieved / FP32_NONPACKED_PEAK_TFLOPS}
     else:
         key = {"tile_sort": "tile_sort", "depth_sort": "tile_sort", "emit": "scan_emit"}.get(dom, dom)
         achieved = algo[key] / (kern_ms[dom] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom, args.workload), "kernel": dom,
                 "kernel_ms": kern_ms[dom]}
+
+    # achievable HBM bandwidth: a plain device copy of 1 GiB (read + write), best of 3
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    best = float("inf")
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    copy_gbs = 2 * src.numel() * 4 / (best * 1e-3) / 1e9
+    del src, dst
+    fb_stages = ["preprocess", "scan_emit", "tile_sort", "ranges", "render_fwd", "loss", "render_bwd", "preprocess_bwd"]
+    fb_gbs = sum(algo[k] for k in fb_stages) / (fwd_bwd_ms * 1e-3) / 1e9
 
     mpix = P / (t_step) / 1e6
     line = {
@@ -330,12 +351,16 @@ def main():
         "config": {"workload": sc.name, "gaussians": n, "sh_degree": D, "views": V,
                    "resolutions": [f"{c['width']}x{c['height']}" for c in sc.cams], "pixels": P,
                    "loss": f"{sc.w_l1} L1 + {sc.w_dssim} D-SSIM", "tile": tile, "pairs": K,
+                   "pairs_in_tiles": K_valid,
                    "autotune_fwd_bwd_ms": {str(t): round(ms, 4) for t, ms in tune_ms.items()}},
         "fwd_bwd_mpix_s": round(P / (fwd_bwd_ms * 1e-3) / 1e6, 3),
         "plain_loop_mpix_s": round(P / (plain_ms * 1e-3) / 1e6, 3) if plain_ms else None,
         "plain_loop_ms_per_step": round(plain_ms, 3) if plain_ms else None,
         "kernel_ms_per_step": {k: round(kern_ms[k] * kern_launches[k] / args.steps, 4) for k in kern_ms},
         "algorithmic_gb_per_step": {k: round(b / 1e9, 4) for k, b in algo.items()},
+        "fwd_bwd_algorithmic_gbs": round(fb_gbs, 1),
+        "achievable_hbm_gbs": round(copy_gbs, 1),
+        "fwd_bwd_frac_of_achievable_hbm": round(fb_gbs / copy_gbs, 4),
         "visits": visits,
         "blends": blends,
         "roofline": roof,
