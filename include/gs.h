@@ -131,7 +131,7 @@ gs_status gs_preprocess(gs_ctx* ctx, const float* params, int32_t n, int32_t str
                         const gs_camera* cams, int32_t n_views, int32_t tile, gs_stream stream);
 
 /* Per-tile depth-ordered lists (tile rasterizer of the original 3DGS): one pair
- * per (visible Gaussian, tile of its rect), ordered by ascending
+ * per (visible Gaussian, tile of its rect; see gs_set_cull), ordered by ascending
  * (global tile, fp32 depth, Gaussian index), and each tile's [start, end) range.
  * Synchronises with `stream` once to learn the pair count K, which is written to
  * *n_pairs_out when it is not NULL.  GS_ERR_CAPACITY if K >= 2^32. */
@@ -197,9 +197,8 @@ gs_status gs_adam_step(gs_ctx* ctx, float* params, const float* grad, float* m, 
  * region {a dx^2 + 2 b dx dy + c dy^2 <= -2 tau} meets the box spanned by the
  * tile's pixel centres (tested in FP64 on the stored conic, cutoff and centre);
  * the other pairs of the rect can blend into no pixel of their tile, so images
- * and gradients are the same in both modes.  Culled pairs keep their slot in the
- * sorted arrays with tile id = number of tiles (they sort after every real tile
- * and belong to no range).  Takes effect at the next gs_bin_sort. */
+ * and gradients are the same in both modes.  K (and every pair buffer) then
+ * counts only the listed pairs.  Takes effect at the next gs_bin_sort. */
 enum { GS_CULL_RECT = 0, GS_CULL_ELLIPSE = 1 };
 gs_status gs_set_cull(gs_ctx* ctx, int32_t mode);
 

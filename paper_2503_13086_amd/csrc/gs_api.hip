@@ -40,7 +40,7 @@ struct gs_ctx {
   DevBuf dkey[2], dval[2], counts, offsets, blocksums, total, hist, digit_tot;
   DevBuf pkey[2], pval[2], ranges;
   DevBuf tfinal, ncontrib, last, grad2d, lossp, aux;
-  DevBuf asum, dG, loadp, loadst;
+  DevBuf asum, dG, loadp, loadst, kept;
   bool load_pending = false;   // dG holds a load-balancing gradient for the current forward
   ViewDev* h_views = nullptr;
   unsigned long long* h_total = nullptr;
@@ -87,7 +87,7 @@ std::vector<DevBuf*> all_bufs(gs_ctx* c) {
   return {&c->views, &c->rec, &c->depth, &c->touched, &c->rect, &c->dkey[0], &c->dkey[1], &c->dval[0],
           &c->dval[1], &c->counts, &c->offsets, &c->blocksums, &c->total, &c->hist, &c->digit_tot, &c->pkey[0],
           &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->tfinal, &c->ncontrib, &c->last,
-          &c->grad2d, &c->lossp, &c->aux, &c->asum, &c->dG, &c->loadp, &c->loadst};
+          &c->grad2d, &c->lossp, &c->aux, &c->asum, &c->dG, &c->loadp, &c->loadst, &c->kept};
 }
 
 hipEvent_t next_event(gs_ctx* c) {
@@ -287,11 +287,20 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
                                c->dval[1].as<uint32_t>(), NV, 32, sc, &c->depth_in_b, s));
   }
   const uint32_t* order = c->dval[c->depth_in_b].as<uint32_t>();
+  const bool cull = c->cull == GS_CULL_ELLIPSE;
   {
     Prof pr(c, GS_K_SCAN, s);
-    GS_HIP(c, launch_scan_touched(order, c->touched.as<uint32_t>(), NV, c->counts.as<uint32_t>(),
-                                  c->offsets.as<uint32_t>(), c->blocksums.as<uint32_t>(),
-                                  c->total.as<unsigned long long>(), s));
+    // pairs per entry: the rect's tiles, or with culling the tiles whose pixel-centre
+    // box meets the cutoff region (counted in index order, coalesced)
+    const uint32_t* per_entry = c->touched.as<uint32_t>();
+    if (cull) {
+      if ((st = ensure(c, c->kept, NV * 4, s)) != GS_OK) return st;
+      GS_HIP(c, launch_count_kept(c->touched.as<uint32_t>(), c->rect.as<ushort4>(), c->rec.as<Record>(), NV, c->n,
+                                  c->views.as<ViewDev>(), c->tile, c->kept.as<uint32_t>(), s));
+      per_entry = c->kept.as<uint32_t>();
+    }
+    GS_HIP(c, launch_scan_touched(order, per_entry, NV, c->counts.as<uint32_t>(), c->offsets.as<uint32_t>(),
+                                  c->blocksums.as<uint32_t>(), c->total.as<unsigned long long>(), s));
   }
   GS_HIP(c, hipMemcpyAsync(c->h_total, c->total.p, 8, hipMemcpyDeviceToHost, s));
   GS_HIP(c, hipStreamSynchronize(s));
@@ -306,15 +315,13 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
   {
     Prof pr(c, GS_K_EMIT, s);
     GS_HIP(c, launch_emit_pairs(order, c->counts.as<uint32_t>(), c->offsets.as<uint32_t>(), c->rect.as<ushort4>(),
-                                c->rec.as<Record>(), NV, c->n, c->views.as<ViewDev>(), c->V, (size_t)K,
-                                (uint32_t)c->n_tiles, c->cull == GS_CULL_ELLIPSE ? 1 : 0, c->tile, c->pkey[0].as<uint32_t>(),
-                                c->pval[0].as<uint32_t>(), s));
+                                c->rec.as<Record>(), NV, c->n, c->views.as<ViewDev>(), (size_t)K, cull ? 1 : 0,
+                                c->tile, c->pkey[0].as<uint32_t>(), c->pval[0].as<uint32_t>(), s));
   }
   {
     Prof pr(c, GS_K_TILE_SORT, s);
     SortScratch sc{c->hist.as<uint32_t>(), c->digit_tot.as<uint32_t>()};
-    // tile ids run to n_tiles inclusive (culled pairs)
-    const int bits = ceil_log2((uint64_t)c->n_tiles + 1) < 1 ? 1 : ceil_log2((uint64_t)c->n_tiles + 1);
+    const int bits = ceil_log2((uint64_t)c->n_tiles) < 1 ? 1 : ceil_log2((uint64_t)c->n_tiles);
     GS_HIP(c, radix_sort_pairs(c->pkey[0].as<uint32_t>(), c->pval[0].as<uint32_t>(), c->pkey[1].as<uint32_t>(),
                                c->pval[1].as<uint32_t>(), K, bits, sc, &c->pairs_in_b, s));
   }

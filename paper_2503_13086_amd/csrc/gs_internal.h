@@ -46,6 +46,49 @@ struct alignas(16) Record {
 static_assert(sizeof(Record) == 48, "record layout");
 
 __host__ __device__ inline int n_sh(int D) { return (D + 1) * (D + 1); }
+
+// Does the cutoff region {q(dx, dy) = a dx^2 + 2 b dx dy + c dy^2 <= lim} of a
+// splat centred at (u, w) meet the box spanned by the pixel centres of tile
+// (gx, gy) (edge T, image W x H)?  The minimum of q over the box is 0 when the box
+// holds the centre, else the smallest of the minima along the four edges (clamped
+// 1-D minimisers, nbc = -b/c, nba = -b/a).  FP64, no contraction, fixed operation
+// order: every kernel that asks gets the same answer.
+struct CutoffGeo {
+  double u, w, a, b, c, nbc, nba, lim;
+};
+
+__device__ inline CutoffGeo cutoff_geo(const Record& r) {
+#pragma clang fp contract(off)
+  CutoffGeo g;
+  g.u = r.u;
+  g.w = r.w;
+  g.a = r.a;
+  g.b = r.b;
+  g.c = r.c;
+  g.nbc = -g.b / g.c;
+  g.nba = -g.b / g.a;
+  g.lim = -2.0 * (double)r.tau;
+  return g;
+}
+
+__device__ inline double cutoff_qform(double a, double b, double c, double dx, double dy) {
+#pragma clang fp contract(off)
+  return ((a * dx) * dx + ((2.0 * b) * dx) * dy) + (c * dy) * dy;
+}
+
+__device__ inline bool tile_meets_cutoff(const CutoffGeo& g, int gx, int gy, int T, int W, int H) {
+#pragma clang fp contract(off)
+  const double dx0 = ((double)(gx * T) + 0.5) - g.u;
+  const double dx1 = fmin((double)(gx * T) + ((double)T - 0.5), (double)W - 0.5) - g.u;
+  const double dy0 = ((double)(gy * T) + 0.5) - g.w;
+  const double dy1 = fmin((double)(gy * T) + ((double)T - 0.5), (double)H - 0.5) - g.w;
+  double best = cutoff_qform(g.a, g.b, g.c, dx0, fmin(fmax(g.nbc * dx0, dy0), dy1));
+  best = fmin(best, cutoff_qform(g.a, g.b, g.c, dx1, fmin(fmax(g.nbc * dx1, dy0), dy1)));
+  best = fmin(best, cutoff_qform(g.a, g.b, g.c, fmin(fmax(g.nba * dy0, dx0), dx1), dy0));
+  best = fmin(best, cutoff_qform(g.a, g.b, g.c, fmin(fmax(g.nba * dy1, dx0), dx1), dy1));
+  if (dx0 <= 0.0 && dx1 >= 0.0 && dy0 <= 0.0 && dy1 >= 0.0) best = 0.0;
+  return best <= g.lim;
+}
 __host__ __device__ inline int n_params(int D) { return 11 + 3 * n_sh(D); }
 
 // ---- launchers (each file defines its own) ----
@@ -71,13 +114,19 @@ hipError_t launch_iota(uint32_t* p, size_t n, hipStream_t s);
 
 // counts[e] = touched[order[e]] and its exclusive scan over e; total written to *total
 size_t scan_block_words(size_t n);
+// counts[i] = touched[order[i]]; offsets = exclusive prefix of counts; *total = sum
 hipError_t launch_scan_touched(const uint32_t* order, const uint32_t* touched, size_t n, uint32_t* counts,
                                uint32_t* offsets, uint32_t* block_sums, unsigned long long* total, hipStream_t s);
-// cull != 0: pairs whose tile box the cutoff region misses get tile id n_tiles
+// kept[e] = tiles of entry e's rect whose pixel-centre box meets its cutoff region
+// (entries in index order; rect tile count in touched)
+hipError_t launch_count_kept(const uint32_t* touched, const ushort4* rect, const Record* rec, size_t n_entries, int n,
+                             const ViewDev* views, int tile, uint32_t* kept, hipStream_t s);
+// pairs of the depth-ordered entries order[0..n_entries): counts/offsets are the
+// scanned per-entry pair counts; cull != 0 keeps only the rect tiles that meet the
+// cutoff region (counts must then be the kept counts)
 hipError_t launch_emit_pairs(const uint32_t* order, const uint32_t* counts, const uint32_t* offsets,
                              const ushort4* rect, const Record* rec, size_t n_entries, int n, const ViewDev* views,
-                             int V, size_t K, uint32_t n_tiles, int cull, int tile, uint32_t* pair_tile,
-                             uint32_t* pair_rec, hipStream_t s);
+                             size_t K, int cull, int tile, uint32_t* pair_tile, uint32_t* pair_rec, hipStream_t s);
 hipError_t launch_ranges(const uint32_t* pair_tile, size_t K, uint2* ranges, int n_tiles, hipStream_t s);
 hipError_t launch_compose_keys(const uint32_t* pair_tile, const uint32_t* pair_rec, const uint32_t* depth,
                                size_t K, int n, size_t n_rec, unsigned long long* keys, uint32_t* values,

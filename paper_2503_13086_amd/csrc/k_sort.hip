@@ -312,116 +312,187 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t* __restr
   }
 }
 
-// Minimum of q(dx, dy) = a dx^2 + 2 b dx dy + c dy^2 (positive definite) over the
-// box [dx0, dx1] x [dy0, dy1]: 0 when the box holds the origin, else the smallest
-// of the minima along the four edges (clamped 1-D minimisers).  FP64, no
-// contraction, fixed operation order, so the decision is reproducible.
-__device__ inline double qform(double a, double b, double c, double dx, double dy) {
-  return ((a * dx) * dx + ((2.0 * b) * dx) * dy) + (c * dy) * dy;
+// Cooperative walk over the candidate pairs of 64 consecutive entries, one wave:
+// entry l of the wave has cand[l] candidates (the tiles of its rect, row-major);
+// s_cp holds the inclusive prefix of the candidate counts with s_cp[0] = 0 at
+// index 0 (s_cp[l + 1] = candidates of entries 0..l).  Returns the entry of
+// candidate q (largest l with s_cp[l] <= q).
+__device__ inline int entry_of(const uint32_t* s_cp, uint32_t q) {
+  int lo = 0, hi = 63;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_cp[mid] <= q) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }
-__device__ inline double box_min_q(double a, double b, double c, double nbc, double nba, double dx0, double dx1,
-                                   double dy0, double dy1) {
-  double best = qform(a, b, c, dx0, fmin(fmax(nbc * dx0, dy0), dy1));
-  best = fmin(best, qform(a, b, c, dx1, fmin(fmax(nbc * dx1, dy0), dy1)));
-  best = fmin(best, qform(a, b, c, fmin(fmax(nba * dy0, dx0), dx1), dy0));
-  best = fmin(best, qform(a, b, c, fmin(fmax(nba * dy1, dx0), dx1), dy1));
-  if (dx0 <= 0.0 && dx1 >= 0.0 && dy0 <= 0.0 && dy1 >= 0.0) best = 0.0;
-  return best;
+
+// (tile column, row) offsets of candidate `local` in a rect nx tiles wide
+__device__ inline void rect_cell(uint32_t local, uint32_t nx, uint32_t& tx, uint32_t& ty) {
+  ty = (uint32_t)((float)local / (float)nx);
+  if (ty * nx > local) --ty;
+  else if ((ty + 1) * nx <= local) ++ty;
+  tx = local - ty * nx;
+}
+
+// Wave-inclusive prefix of x over lanes.
+__device__ inline uint32_t wave_incl_scan(uint32_t x) {
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off);
+    if ((int)__lane_id() >= off) x += y;
+  }
+  return x;
+}
+
+// Kept pairs per entry (index order, coalesced reads): the tiles of the entry's
+// rect whose pixel-centre box meets its cutoff region.  The wave's candidates are
+// spread over its lanes; runs of one entry within 64 candidates are counted with
+// ballots by the run's first lane.
+__global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restrict__ touched,
+                                                          const ushort4* __restrict__ rect,
+                                                          const Record* __restrict__ rec, size_t n_entries, int n,
+                                                          const ViewDev* __restrict__ views, int T,
+                                                          uint32_t* __restrict__ kept) {
+  __shared__ uint32_t s_cp[kWaves][65];
+  __shared__ uint32_t s_nx[kWaves][64];
+  __shared__ uint32_t s_org[kWaves][64];    // rect origin (tx0 | ty0 << 16)
+  __shared__ uint32_t s_wh[kWaves][64];     // view size (W | H << 16)
+  __shared__ uint32_t s_k[kWaves][64];
+  __shared__ CutoffGeo s_geo[kWaves][64];
+  const int w = threadIdx.x / 64;
+  const unsigned lane = __lane_id();
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t cand = e < n_entries ? touched[e] : 0u;
+  const uint32_t incl = wave_incl_scan(cand);
+  s_cp[w][lane + 1] = incl;
+  if (lane == 0) s_cp[w][0] = 0u;
+  s_k[w][lane] = 0u;
+  if (cand) {
+    const ushort4 rc = rect[e];
+    const ViewDev& cv = views[e / (size_t)n];
+    s_nx[w][lane] = (uint32_t)(rc.y - rc.x + 1);
+    s_org[w][lane] = (uint32_t)rc.x | ((uint32_t)rc.z << 16);
+    s_wh[w][lane] = (uint32_t)cv.W | ((uint32_t)cv.H << 16);
+    s_geo[w][lane] = cutoff_geo(rec[e]);
+  }
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t C = s_cp[w][64];
+  for (uint32_t cb = 0; cb < C; cb += 64) {
+    const uint32_t q = cb + lane;
+    const bool valid = q < C;
+    int lo = 0;
+    bool pass = false;
+    if (valid) {
+      lo = entry_of(s_cp[w], q);
+      uint32_t tx, ty;
+      rect_cell(q - s_cp[w][lo], s_nx[w][lo], tx, ty);
+      const uint32_t org = s_org[w][lo], wh = s_wh[w][lo];
+      pass = tile_meets_cutoff(s_geo[w][lo], (int)((org & 0xffffu) + tx), (int)((org >> 16) + ty), T,
+                               (int)(wh & 0xffffu), (int)(wh >> 16));
+    }
+    const int prev = __shfl_up(lo, 1);
+    const bool first = valid && (lane == 0 || prev != lo);
+    const uint64_t fmask = __ballot(first);
+    const uint64_t pmask = __ballot(pass);
+    if (first) {
+      const uint64_t above = lane == 63 ? 0ull : (fmask & (~0ull << (lane + 1)));
+      const unsigned next = above ? (unsigned)__builtin_ctzll(above) : 64u;
+      const uint64_t run = (next == 64u ? ~0ull : ((1ull << next) - 1ull)) & (~0ull << lane);
+      s_k[w][lo] += (uint32_t)__popcll(pmask & run);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (e < n_entries) kept[e] = s_k[w][lane];
 }
 
 // Pair emission, one wave per 64 consecutive depth-ordered entries.  The wave's
-// pairs occupy one contiguous output range; each lane writes every 64th output
-// position of it, finding its entry by binary search over the wave's entry
-// offsets in LDS, so writes are coalesced and large tile rects are shared by the
-// whole wave.  With culling on, a pair whose tile box (spanned by the tile's
-// pixel centres) the Gaussian's cutoff region a dx^2 + 2 b dx dy + c dy^2 <= -2 tau
-// does not meet is given the tile id n_tiles, which sorts after every real tile
-// and belongs to no range: no pixel of that tile could blend it.
+// pairs occupy one contiguous output range.  Its candidates (rect tiles of its
+// entries, entry by entry, row-major) are spread over the lanes in rounds of 64;
+// with culling on, a candidate is kept only if its tile's pixel-centre box meets
+// the cutoff region (the test k_count_kept made, so the kept counts and offsets
+// agree), and kept candidates are written in order at running positions taken
+// from a ballot: writes are coalesced and large rects are shared by the wave.
 __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ order,
                                                     const uint32_t* __restrict__ counts,
                                                     const uint32_t* __restrict__ offsets,
                                                     const ushort4* __restrict__ rect,
                                                     const Record* __restrict__ rec, size_t n_entries, int n,
-                                                    const ViewDev* __restrict__ views, size_t K, uint32_t n_tiles,
-                                                    int cull, int T, uint32_t* __restrict__ pair_tile,
+                                                    const ViewDev* __restrict__ views, size_t K, int cull, int T,
+                                                    uint32_t* __restrict__ pair_tile,
                                                     uint32_t* __restrict__ pair_rec) {
-  __shared__ uint32_t s_off[kWaves][65];
+  __shared__ uint32_t s_cp[kWaves][65];
   __shared__ uint32_t s_rid[kWaves][64];
   __shared__ uint32_t s_base[kWaves][64];   // global tile id of the rect's first tile
   __shared__ uint32_t s_nx[kWaves][64];     // rect width in tiles
   __shared__ uint32_t s_tx[kWaves][64];     // tiles per row of the entry's view
   __shared__ uint32_t s_org[kWaves][64];    // rect origin (tx0 | ty0 << 16)
   __shared__ uint32_t s_wh[kWaves][64];     // view size (W | H << 16)
-  __shared__ double s_geo[kWaves][64][7];   // u, w, a, b, c, -b/c, -b/a
-  __shared__ double s_lim[kWaves][64];      // -2 tau
+  __shared__ CutoffGeo s_geo[kWaves][64];
   const int w = threadIdx.x / 64;
   const unsigned lane = __lane_id();
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = e < n_entries;
-  uint32_t cnt = 0, off = 0, rid = 0;
+  uint32_t cnt = 0, off = 0, rid = 0, cand = 0;
+  ushort4 rc = make_ushort4(0, 0, 0, 0);
   if (valid) {
     rid = order[e];
     cnt = counts[e];
     off = offsets[e];
+    if (cnt) {
+      rc = rect[rid];
+      cand = (uint32_t)(rc.y - rc.x + 1) * (uint32_t)(rc.w - rc.z + 1);
+    }
   }
-  // lanes past the last entry take the wave's end offset
-  uint32_t end = valid ? off + cnt : 0u;
-  for (int o = 32; o > 0; o >>= 1) end = max(end, (uint32_t)__shfl_xor((int)end, o));
-  if (!valid) off = end;
-  s_off[w][lane] = off;
+  // output range of the wave: from its first entry's offset to its last entry's end
+  uint32_t lo_off = valid ? off : 0xffffffffu, hi_end = valid ? off + cnt : 0u;
+  for (int o = 32; o > 0; o >>= 1) {
+    lo_off = min(lo_off, (uint32_t)__shfl_xor((int)lo_off, o));
+    hi_end = max(hi_end, (uint32_t)__shfl_xor((int)hi_end, o));
+  }
+  const uint32_t incl = wave_incl_scan(cand);
+  s_cp[w][lane + 1] = incl;
+  if (lane == 0) s_cp[w][0] = 0u;
   s_rid[w][lane] = rid;
-  if (lane == 0) s_off[w][64] = end;
-  if (cnt) {
-    const ushort4 rc = rect[rid];
+  if (cand) {
     const ViewDev& cv = views[rid / (uint32_t)n];
     s_base[w][lane] = (uint32_t)cv.tile_off + (uint32_t)rc.z * (uint32_t)cv.tiles_x + rc.x;
     s_nx[w][lane] = (uint32_t)(rc.y - rc.x + 1);
     s_tx[w][lane] = (uint32_t)cv.tiles_x;
     if (cull) {
-      const Record& r = rec[rid];
-      const double a = r.a, b = r.b, c = r.c;
       s_org[w][lane] = (uint32_t)rc.x | ((uint32_t)rc.z << 16);
       s_wh[w][lane] = (uint32_t)cv.W | ((uint32_t)cv.H << 16);
-      s_geo[w][lane][0] = r.u;
-      s_geo[w][lane][1] = r.w;
-      s_geo[w][lane][2] = a;
-      s_geo[w][lane][3] = b;
-      s_geo[w][lane][4] = c;
-      s_geo[w][lane][5] = -b / c;
-      s_geo[w][lane][6] = -b / a;
-      s_lim[w][lane] = -2.0 * (double)r.tau;
+      s_geo[w][lane] = cutoff_geo(rec[rid]);
     }
   }
-  __syncthreads();
-  const uint32_t start = s_off[w][0];
-  if (end > K) return;                     // never for a consistent scan; guards the writes
-  for (uint32_t q = start + lane; q < end; q += 64) {
-    // largest l with s_off[l] <= q (entries without pairs share their successor's offset)
-    int lo = 0, hi = 63;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_off[w][mid] <= q) lo = mid; else hi = mid - 1;
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t C = s_cp[w][64];
+  if (hi_end > K || C == 0u) return;        // never past K for a consistent scan; guards the writes
+  uint32_t pos = lo_off;
+  for (uint32_t cb = 0; cb < C; cb += 64) {
+    const uint32_t q = cb + lane;
+    bool keep = false;
+    uint32_t tile = 0, r = 0;
+    if (q < C) {
+      const int lo = entry_of(s_cp[w], q);
+      uint32_t tx, ty;
+      rect_cell(q - s_cp[w][lo], s_nx[w][lo], tx, ty);
+      tile = s_base[w][lo] + ty * s_tx[w][lo] + tx;
+      r = s_rid[w][lo];
+      keep = true;
+      if (cull) {
+        const uint32_t org = s_org[w][lo], wh = s_wh[w][lo];
+        keep = tile_meets_cutoff(s_geo[w][lo], (int)((org & 0xffffu) + tx), (int)((org >> 16) + ty), T,
+                                 (int)(wh & 0xffffu), (int)(wh >> 16));
+      }
     }
-    const uint32_t local = q - s_off[w][lo];
-    const uint32_t nx = s_nx[w][lo];
-    uint32_t ty = (uint32_t)((float)local / (float)nx);
-    if (ty * nx > local) --ty;
-    else if ((ty + 1) * nx <= local) ++ty;
-    const uint32_t tx = local - ty * nx;
-    uint32_t tile = s_base[w][lo] + ty * s_tx[w][lo] + tx;
-    if (cull) {
-      const double* gp = s_geo[w][lo];
-      const uint32_t org = s_org[w][lo], wh = s_wh[w][lo];
-      const int gx = (int)((org & 0xffffu) + tx), gy = (int)((org >> 16) + ty);
-      const double x0 = (double)(gx * T) + 0.5;
-      const double x1 = fmin((double)(gx * T) + ((double)T - 0.5), (double)(wh & 0xffffu) - 0.5);
-      const double y0 = (double)(gy * T) + 0.5;
-      const double y1 = fmin((double)(gy * T) + ((double)T - 0.5), (double)(wh >> 16) - 0.5);
-      const double qm = box_min_q(gp[2], gp[3], gp[4], gp[5], gp[6], x0 - gp[0], x1 - gp[0], y0 - gp[1], y1 - gp[1]);
-      if (!(qm <= s_lim[w][lo])) tile = n_tiles;
+    const uint64_t kmask = __ballot(keep);
+    if (keep) {
+      const uint32_t dst = pos + (uint32_t)__popcll(kmask & lanemask_lt());
+      if (dst < hi_end) {
+        pair_tile[dst] = tile;
+        pair_rec[dst] = r;
+      }
     }
-    pair_tile[q] = tile;
-    pair_rec[q] = s_rid[w][lo];
+    pos += (uint32_t)__popcll(kmask);
   }
 }
 
@@ -510,13 +581,20 @@ hipError_t launch_scan_touched(const uint32_t* order, const uint32_t* touched, s
 
 hipError_t launch_emit_pairs(const uint32_t* order, const uint32_t* counts, const uint32_t* offsets,
                              const ushort4* rect, const Record* rec, size_t n_entries, int n, const ViewDev* views,
-                             int V, size_t K, uint32_t n_tiles, int cull, int tile, uint32_t* pair_tile,
-                             uint32_t* pair_rec, hipStream_t s) {
-  (void)V;
+                             size_t K, int cull, int tile, uint32_t* pair_tile, uint32_t* pair_rec, hipStream_t s) {
   if (n_entries == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n_entries + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, order, counts, offsets, rect, rec, n_entries, n,
-                     views, K, n_tiles, cull, tile, pair_tile, pair_rec);
+                     views, K, cull, tile, pair_tile, pair_rec);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_kept(const uint32_t* touched, const ushort4* rect, const Record* rec, size_t n_entries, int n,
+                             const ViewDev* views, int tile, uint32_t* kept, hipStream_t s) {
+  if (n_entries == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((n_entries + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_count_kept, dim3(blocks), dim3(kThreads), 0, s, touched, rect, rec, n_entries, n, views, tile,
+                     kept);
   return hipGetLastError();
 }
 

@@ -81,13 +81,10 @@ def run_gpu(scene, upstream=None, loss=False, cull=None, tile=16):
 
 
 def valid_pairs(g):
-    """Sorted pairs that belong to a tile (culled pairs carry tile id n_tiles)."""
+    """Sorted pairs, their values and views; every pair belongs to a tile."""
     tiles = (g["keys"] >> np.uint64(32)).astype(np.int64)
-    ok = tiles < g["n_tiles"]
-    n_ok = int(ok.sum())
-    assert ok[:n_ok].all(), "culled pairs must sort after every real tile"
-    assert (tiles[n_ok:] == g["n_tiles"]).all()
-    return g["keys"][:n_ok], g["values"][:n_ok], g["pair_view"][:n_ok]
+    assert (tiles < g["n_tiles"]).all(), "every listed pair belongs to a tile"
+    return g["keys"], g["values"], g["pair_view"]
 
 
 def masked_upstream(up, amb_maps):
