@@ -166,7 +166,15 @@ def serving_leg(n_arrivals, time_scale, slots):
         fld = Field(st.initial, st.sh_degree, capacity=st.initial.shape[1])
         eng = Engine(fld, max_slots=s, t_i=200, seed=5, w_l1=0.47, w_dssim=0.12, w_load=0.41)
         t = time.perf_counter()
-        stats = eng.run(st.arrivals, targets, time_scale=time_scale)
+        done = [0]
+
+        def progress(job, name=name, t0=t):
+            done[0] += 1
+            if done[0] % 20 == 0:
+                print(f"[bench] serving {name}: {done[0]}/{n_arrivals} arrivals done "
+                      f"({time.perf_counter() - t0:.1f}s)", file=sys.stderr, flush=True)
+
+        stats = eng.run(st.arrivals, targets, time_scale=time_scale, on_job_done=progress)
         eng.close()
         out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in stats.summary().items()}
         print(f"[bench] serving {name}: {json.dumps(out[name])} ({time.perf_counter() - t:.1f}s)", file=sys.stderr,

@@ -280,12 +280,14 @@ class Engine:
         return out
 
     # ---- the loop ----
-    def run(self, arrivals, targets: Sequence[torch.Tensor], time_scale: float = 1.0) -> ServeStats:
+    def run(self, arrivals, targets: Sequence[torch.Tensor], time_scale: float = 1.0,
+            on_job_done=None) -> ServeStats:
         """Serve a stream.  arrivals: objects with .time (s), .cam, .overlap (with
         the earlier images), .block (new Gaussians); targets: the images as device
         tensors, in arrival order.  Arrival times are multiplied by time_scale and
         measured from the start of the call; a job's latency runs from its arrival
-        to the end of the step that completes its last iteration."""
+        to the end of the step that completes its last iteration.  on_job_done(job)
+        is called as each job completes."""
         pending = deque(range(len(arrivals)))
         active: List[Job] = []
         st = self.stats
@@ -316,6 +318,8 @@ class Engine:
                     j.done = t
                     st.latencies.append(t - j.arrival)
                     active.remove(j)
+                    if on_job_done is not None:
+                        on_job_done(j)
         self._sync()
         st.makespan = time.perf_counter() - t0
         st.field_growths = self.field.growths
