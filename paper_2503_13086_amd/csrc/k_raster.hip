@@ -1,35 +1,40 @@
 // Tile rasterizer forward and backward for gfx950.
 //
-// Forward (Sec. III Eq. 2): one 256-thread workgroup (four wave64s) per 16x16
-// tile, one thread per pixel, each wavefront owning an 8x8 quadrant.  The tile's
-// depth-ordered list is walked in batches of 256 records staged in LDS; every
-// pixel reads each staged record by LDS broadcast, so a record fetched from HBM
-// once serves all 256 pixels.  While staging, each record also gets the bounding
-// box of its cutoff ellipse; each wavefront then tests the batch against its
-// quadrant (one record per lane, four ballots) and walks only the records whose
-// box meets it.  A wavefront stops when all its pixels have stopped blending,
-// the workgroup when all four have.  Screen centres arrive in FP64 and are made
-// relative to the tile origin while staging, so per-pixel offsets are accurate
-// fp32 numbers at any image size.
+// Forward (Sec. III Eq. 2): one workgroup of T x T threads per T x T tile
+// (T = 8, 16 or 32), one thread per pixel, each wavefront owning an 8x8 block.
+// The tile's depth-ordered list is walked in batches of T^2 records staged in LDS;
+// every pixel reads each staged record by LDS broadcast, so a record fetched from
+// HBM once serves the whole tile.  While staging, each record also gets the
+// bounding box of its cutoff ellipse; each wavefront then tests the batch against
+// its block (one record per lane, one ballot per 64 records) and walks only the
+// records whose box meets it.  A wavefront stops when all its pixels have stopped
+// blending, the workgroup when all have.  Screen centres arrive in FP64 and are
+// made relative to the tile origin while staging, so per-pixel offsets are
+// accurate fp32 numbers at any image size.
 //
-// Backward (Sec. IV-E): the same tiling and per-quadrant candidate sets, walking
-// each list back to front from the last position any pixel of the tile blended
-// (each wavefront starts at the last position its own pixels blended).  Each pixel recovers its transmittance with
-// one reciprocal per Gaussian and keeps the colour accumulated behind it.  Per
-// Gaussian, nine per-pixel values (the moments of dL/d(exponent) over dx, dy,
-// dx^2, dx dy, dy^2, then opacity and colour partials) are summed across the
-// wavefront by a reduce-scatter (CDNA4 permlane swaps across halves and row
-// pairs, then DPP row sums) and across the four wavefronts with LDS atomics; the
-// moments become centre and conic partials once per tile, and each workgroup
-// issues one global atomic per (tile, Gaussian, component) instead of one per
-// (pixel, Gaussian, component).  Wavefronts in which no pixel blended a Gaussian
-// skip it.
+// Backward (Sec. IV-E): the same tiling and per-block candidate sets, walking each
+// list back to front from the last position any pixel of the tile blended (each
+// wavefront starts at the last position its own pixels blended).  Each pixel
+// recovers its transmittance with one reciprocal per Gaussian and keeps the colour
+// accumulated behind it.  Per Gaussian, nine per-pixel values (the moments of
+// dL/d(exponent) over dx, dy, dx^2, dx dy, dy^2, then opacity and colour partials)
+// are summed across the wavefront by a reduce-scatter (CDNA4 permlane swaps across
+// halves and row pairs, then DPP row sums) and across the wavefronts with LDS
+// adds; the moments become centre and conic partials once per tile, and each
+// workgroup issues one global atomic per (tile, Gaussian, component) instead of
+// one per (pixel, Gaussian, component), consecutive lanes taking consecutive
+// components so a wavefront's atomics share cache lines.  Wavefronts in which no
+// pixel blended a Gaussian skip it.
 #include "gs_internal.h"
 
 #pragma clang fp contract(off)
 
 namespace gsk {
 namespace {
+
+// Wave-wide mask of a per-lane predicate (the compiler keeps the predicate in a
+// scalar mask instead of round-tripping it through a vector register).
+__device__ inline uint64_t wave_mask(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ inline int view_of_tile(const ViewDev* __restrict__ views, int V, int tile) {
   int v = 0;
@@ -124,7 +129,7 @@ __device__ inline void quadrant_masks(const float4* s0, const float4* s1, const 
       const float u = s0[j].x, w = s0[j].y, ex = s1[j].w, ey = s2[j].w;
       hit = u + ex >= qx && u - ex <= qx + 7.0f && w + ey >= qy && w - ey <= qy + 7.0f;
     }
-    mask[k] = __ballot(hit);
+    mask[k] = wave_mask(hit);
   }
 }
 
@@ -158,7 +163,7 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict_
       }
     }
     __syncthreads();
-    if (__ballot(!done) != 0ull) {
+    if (wave_mask(!done) != 0ull) {
       uint64_t mask[NM];
       quadrant_masks<NM>(s0, s1, s2, (int)m, qx, qy, mask);
       // straight-line per-Gaussian update; lanes that skip or have stopped keep their state
@@ -174,7 +179,7 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict_
           const float dx = a0.x - fx, dy = a0.y - fy;
           const float p2 = gauss_power2(a0.z, a0.w, a1.x, dx, dy);
           const bool pass = !done && p2 <= 0.0f && p2 >= a1.z;
-          if (__ballot(pass) == 0ull) continue;   // no pixel of this wave takes it
+          if (wave_mask(pass) == 0ull) continue;   // no pixel of this wave takes it
           const float4 a2 = s2[j];
           const float alpha = fminf(kAlphaMax, a1.y * __builtin_amdgcn_exp2f(p2));
           const float Tn = Tr * (1.0f - alpha);
@@ -189,7 +194,7 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict_
           A += blend ? alpha : 0.0f;
           cnt += blend ? 1u : 0u;
           lastp = blend ? pos0 + j : lastp;
-          if (__ballot(stop) != 0ull && __ballot(!done) == 0ull) {   // every pixel of this wavefront stopped
+          if (wave_mask(stop) != 0ull && wave_mask(!done) == 0ull) {   // every pixel of this wavefront stopped
             live = false;
             break;
           }
@@ -338,7 +343,7 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
         const float dx = a0.x - fx, dy = a0.y - fy;
         const float p2 = gauss_power2(a0.z, a0.w, a1.x, dx, dy);
         const bool on = tg.inside && (uint32_t)(beg + j) < lp && p2 <= 0.0f && p2 >= a1.z;
-        if (__ballot(on) == 0ull) continue;    // no pixel of this wave blended it
+        if (wave_mask(on) == 0ull) continue;    // no pixel of this wave blended it
         // straight-line update; lanes that did not blend this Gaussian keep their state
         // and contribute zeros
         const float4 a2 = s2[j];

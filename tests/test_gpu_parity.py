@@ -183,12 +183,12 @@ def test_adam_parity():
         tP, tG, tM, tV = dev(P), dev(G), dev(M), dev(Vv)
         tS = torch.as_tensor(step.view(np.int32)).cuda()
         rz.preprocess(tP, sc.n, 1, sc.cams)
-        vis = (rz.buffer(2).cpu().numpy().reshape(3, sc.n) > 0)
         rz.adam_step(tG, tM, tV, tS, lr, scale, group_mask=0b1)
         out = [t.cpu().numpy() for t in (tP, tM, tV)] + [tS.cpu().numpy().view(np.uint32)]
     finally:
         rz.close()
     n = sc.n
+    vis = np.stack([p["touched"] > 0 for p in oracle.project_views(sc.params, n, 1, sc.cams)])
     p1, m1, v1, s1 = oracle.adam_step(P[:, :n], G[:, :n], M[:, :n], Vv[:, :n], step[:n], lr, view_scale=scale,
                                       visible=vis, group_mask=0b1)
     assert np.array_equal(out[3][:n].astype(np.int64), s1)
