@@ -19,8 +19,8 @@
 // accumulated behind it.  Per Gaussian, nine per-pixel values (the moments of
 // dL/d(exponent) over dx, dy, dx^2, dx dy, dy^2, then opacity and colour partials)
 // are summed across the wavefront by a reduce-scatter (CDNA4 permlane swaps across
-// halves and row pairs, then DPP row sums) and across the wavefronts with LDS
-// adds; the moments become centre and conic partials once per tile, and each
+// halves and row pairs, then DPP exchanges within rows) and across the wavefronts
+// with LDS adds; the moments become centre and conic partials once per tile, and each
 // workgroup issues one global atomic per (tile, Gaussian, component) instead of
 // one per (pixel, Gaussian, component), consecutive lanes taking consecutive
 // components so a wavefront's atomics share cache lines.  Wavefronts in which no
@@ -233,38 +233,68 @@ __device__ inline float fold16(float a, float b) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// Sum over the 16 lanes of each row, valid in the row's lane 15 (DPP row shifts).
-__device__ inline float row_sum(float v) {
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));  // row_shr:1
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, true));  // row_shr:2
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xf, 0xf, true));  // row_shr:4
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, true));  // row_shr:8
-  return v;
+// Lane l receives v from the lane the DPP control names (row_ror:8 = 0x128: lane
+// l ^ 8 of its row; row_half_mirror = 0x141: lane 7 - l of its half-row;
+// quad_perm [2,3,0,1] = 0x4E and [1,0,3,2] = 0xB1: lanes l ^ 2 and l ^ 1).
+template <int CTRL>
+__device__ inline float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
 }
 
-// Reduce-scatter of nine per-lane values over the wave, added into acc[0..8].
-// Halving folds across wave halves and row pairs leave each row holding the
-// partial sums of distinct values (3 registers instead of 9), a row sum finishes
-// them in lane 15 of each row, and four lanes add their sums into LDS with three
-// instructions: row r of the first register holds value {0, 2, 1, 3}[r], of the
-// second that value + 4, and row 0 of the third holds value 8.
-__device__ inline void wave_reduce9_to_lds(const float (&v)[kGrad2D], float* acc) {
+// a + b across the partner lanes of a DPP permutation that pairs each lane with
+// one whose selector bit `hi` differs: lanes with hi clear keep the sum of a over
+// the pair, lanes with hi set the sum of b.
+template <int CTRL>
+__device__ inline float fold_dpp(float a, float b, bool hi) {
+  const float own = hi ? b : a, give = hi ? a : b;
+  return own + dpp<CTRL>(give);
+}
+
+// Reduce-scatter of nine per-lane values over the wave, added into acc[0..8]
+// (mine = acc + this lane's slot).
+// Each level halves the registers by pairing lanes whose selector bit differs
+// (across wave halves, across row pairs, across half-rows, across the halves of
+// each half-row by mirroring), then two quad permutations finish the sums: every
+// group of four lanes then holds one total.  The lane of each group with
+// slot >= 0 adds it into LDS (nine lanes, one instruction): with r = row, h = lane
+// bit 3, q = lane bit 2, value {0, 2, 1, 3}[r] + 4h sits where q = 0 and value 8
+// where r = h = 0, q = 1.
+typedef __attribute__((address_space(3))) float LdsFloat;
+
+__device__ inline void wave_reduce9_to_lds(const float (&v)[kGrad2D], LdsFloat* mine, int slot, bool bit3,
+                                           bool bit2) {
   const float b0 = fold32(v[0], v[1]);
   const float b1 = fold32(v[2], v[3]);
   const float b2 = fold32(v[4], v[5]);
   const float b3 = fold32(v[6], v[7]);
   const float b4 = fold32(v[8], 0.0f);
-  const float c0 = row_sum(fold16(b0, b1));
-  const float c1 = row_sum(fold16(b2, b3));
-  const float c2 = row_sum(fold16(b4, 0.0f));
-  const unsigned lane = __lane_id();
-  if ((lane & 15u) == 15u) {
-    const unsigned row = lane >> 4;
-    const unsigned k0 = ((row & 1u) << 1) | (row >> 1);
-    atomicAdd(acc + k0, c0);
-    atomicAdd(acc + k0 + 4, c1);
-    if (row == 0) atomicAdd(acc + 8, c2);
-  }
+  const float c0 = fold16(b0, b1);
+  const float c1 = fold16(b2, b3);
+  const float c2 = fold16(b4, 0.0f);
+  const float d0 = fold_dpp<0x128>(c0, c1, bit3);
+  const float d1 = c2 + dpp<0x128>(c2);
+  float e = fold_dpp<0x141>(d0, d1, bit2);
+  e += dpp<0x4E>(e);
+  e += dpp<0xB1>(e);
+  if (slot >= 0) __hip_atomic_fetch_add(mine, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Byte offset of row j of the [NT][kGrad2D] float accumulator, formed on the scalar
+// unit (j is uniform); left to itself the compiler folds it into a 64-bit vector
+// multiply-add of the lane's address.
+__device__ inline uint32_t acc_row_offset(int j) {
+  static_assert(kGrad2D * sizeof(float) == 36, "accumulator row size");
+  uint32_t off;
+  asm("s_mul_i32 %0, %1, 36" : "=s"(off) : "s"(__builtin_amdgcn_readfirstlane(j)));
+  return off;
+}
+
+// The LDS slot wave_reduce9_to_lds adds from this lane (-1: none).
+__device__ inline int reduce9_slot(unsigned lane) {
+  if (lane & 3u) return -1;
+  const unsigned r = lane >> 4, h = (lane >> 3) & 1u, q = (lane >> 2) & 1u;
+  if (q == 0u) return (int)((((r & 1u) << 1) | (r >> 1)) + 4u * h);
+  return (r == 0u && h == 0u) ? 8 : -1;
 }
 
 template <int T>
@@ -288,7 +318,10 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
   const float fx = (float)tg.lx, fy = (float)tg.ly;
   const float qx = (float)(tg.lx & ~7), qy = (float)(tg.ly & ~7);
 
-  float Tr = 0.0f, S0 = 0.0f, S1 = 0.0f, S2 = 0.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, gG = 0.0f;
+  // Sg = sum over channels of dL/dcolour times the colour accumulated behind the
+  // current Gaussian (background included): the only form in which that colour
+  // enters dL/dalpha.
+  float Tr = 0.0f, Sg = 0.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, gG = 0.0f;
   uint32_t lp = 0;
   if (tg.inside) {
     const size_t hw = (size_t)cv.W * cv.H;
@@ -301,13 +334,17 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
     g1 = gimg[hw + pix];
     g2 = gimg[2 * hw + pix];
     if (dL_dG) gG = dL_dG[gp];
-    S0 = Tr * cv.bg[0];
-    S1 = Tr * cv.bg[1];
-    S2 = Tr * cv.bg[2];
+    Sg = Tr * __fmaf_rn(g2, cv.bg[2], __fmaf_rn(g1, cv.bg[1], g0 * cv.bg[0]));
   }
   uint32_t mx = lp;
   for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
   const int wave_last = (int)mx;           // this wave never needs list positions >= wave_last
+  const unsigned lane = __lane_id();
+  const int slot = reduce9_slot(lane);
+  const bool bit3 = (lane & 8u) != 0u, bit2 = (lane & 4u) != 0u;
+  // 32-bit LDS byte address of this lane's slot in acc[0] (plain integer arithmetic
+  // in the loop: the compiler would otherwise form the address in 64 bits)
+  const uint32_t my_acc_addr = (uint32_t)(uintptr_t)((LdsFloat*)&acc[0][0] + (slot < 0 ? 0 : slot));
   if (__lane_id() == 0) smax[threadIdx.x / 64] = mx;
   for (int k = 0; k < kGrad2D; ++k) acc[threadIdx.x][k] = 0.0f;
   __syncthreads();
@@ -340,13 +377,13 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
         const int j = 64 * k + b;
         const float4 a0 = s0[j];
         const float4 a1 = s1[j];
+        const float4 a2 = s2[j];
         const float dx = a0.x - fx, dy = a0.y - fy;
         const float p2 = gauss_power2(a0.z, a0.w, a1.x, dx, dy);
-        const bool on = tg.inside && (uint32_t)(beg + j) < lp && p2 <= 0.0f && p2 >= a1.z;
+        const bool on = (uint32_t)(beg + j) < lp && p2 <= 0.0f && p2 >= a1.z;
         if (wave_mask(on) == 0ull) continue;    // no pixel of this wave blended it
         // straight-line update; lanes that did not blend this Gaussian keep their state
         // and contribute zeros
-        const float4 a2 = s2[j];
         const float G = __builtin_amdgcn_exp2f(p2);
         const float og = a1.y * G;
         const bool capped = og > kAlphaMax;
@@ -357,27 +394,25 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
         // Per pixel: colour partials, opacity partial and the moments of the exponent's
         // derivative dpow over (dx, dy, dx^2, dx dy, dy^2); the centre and conic
         // partials are fixed linear maps of these moments (applied once per tile).
-        // dL/dalpha collects the colour terms and gG, the load-balancing gradient of
-        // the pixel's soft count (each blended alpha enters it with weight 1).
-        float p[kGrad2D];
-        p[6] = g0 * wgt;
-        p[7] = g1 * wgt;
-        p[8] = g2 * wgt;
-        float dLda = __fmaf_rn(g0, __fmaf_rn(-S0, ri, a2.x * Tr), gG);
-        dLda = __fmaf_rn(g1, __fmaf_rn(-S1, ri, a2.y * Tr), dLda);
-        dLda = __fmaf_rn(g2, __fmaf_rn(-S2, ri, a2.z * Tr), dLda);
+        // dL/dalpha = T (g . colour) - Sg / (1 - alpha) + gG, gG being the
+        // load-balancing gradient of the pixel's soft count (each blended alpha enters
+        // it with weight 1).
+        const float cg = __fmaf_rn(g2, a2.z, __fmaf_rn(g1, a2.y, g0 * a2.x));
+        float dLda = __fmaf_rn(Tr, cg, __fmaf_rn(-Sg, ri, gG));
         dLda = (on && !capped) ? dLda : 0.0f;  // a capped alpha has zero derivative
-        S0 = __fmaf_rn(a2.x, wgt, S0);
-        S1 = __fmaf_rn(a2.y, wgt, S1);
-        S2 = __fmaf_rn(a2.z, wgt, S2);
+        Sg = __fmaf_rn(cg, wgt, Sg);
         const float dpow = dLda * og;           // dL/d(exponent)
-        p[5] = dLda * G;
+        float p[kGrad2D];
         p[0] = dpow * dx;
         p[1] = dpow * dy;
         p[2] = p[0] * dx;
         p[3] = p[0] * dy;
         p[4] = p[1] * dy;
-        wave_reduce9_to_lds(p, acc[j]);
+        p[5] = dLda * G;
+        p[6] = g0 * wgt;
+        p[7] = g1 * wgt;
+        p[8] = g2 * wgt;
+        wave_reduce9_to_lds(p, (LdsFloat*)(uintptr_t)(my_acc_addr + acc_row_offset(j)), slot, bit3, bit2);
       }
     }
     __syncthreads();
