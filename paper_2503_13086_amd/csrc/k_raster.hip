@@ -87,7 +87,8 @@ __device__ inline TileGeom tile_geom(const ViewDev* __restrict__ views, int V, i
 // sqrt(-2 tau a / det), det = ac - b^2 taken in FP64 (the fp32 entries multiply
 // exactly there), widened by 1e-4 relative + 0.01 px so that the per-pixel fp32
 // test never passes a pixel outside the box.
-//   q0 = (u', w', A, B)   q1 = (C, o, tau', ex)   q2 = (r, g, b, ey)
+//   q0 = (u', w', A, B)   q1 = (C, tau', ex, ey)   q2 = (o, r, g, b)
+// (the per-pixel test reads q0 and q1.xy, a blend q2).
 __device__ inline void stage(const Record* __restrict__ rec, uint32_t rid, double ox, double oy, float4& q0,
                              float4& q1, float4& q2) {
   const Record* r = rec + rid;
@@ -102,16 +103,16 @@ __device__ inline void stage(const Record* __restrict__ rec, uint32_t rid, doubl
     ey = (float)(sqrt(L * (double)c.x) * (1.0 + 1e-4) + 0.01);
   }
   q0 = make_float4((float)(uw.x - ox), (float)(uw.y - oy), (-0.5f * c.x) * kLog2e, (-c.y) * kLog2e);
-  q1 = make_float4((-0.5f * c.z) * kLog2e, c.w, d.x * kLog2e, ex);
-  q2 = make_float4(d.y, d.z, d.w, ey);
+  q1 = make_float4((-0.5f * c.z) * kLog2e, d.x * kLog2e, ex, ey);
+  q2 = make_float4(c.w, d.y, d.z, d.w);
 }
 
 // Placeholder for an entry that belongs to no Gaussian (never for a consistent
 // sort): no pixel accepts it and no quadrant lists it.
 __device__ inline void stage_empty(float4& q0, float4& q1, float4& q2) {
   q0 = make_float4(0.f, 0.f, 0.f, 0.f);
-  q1 = make_float4(0.f, 0.f, 1.f, -1.f);
-  q2 = make_float4(0.f, 0.f, 0.f, -1.f);
+  q1 = make_float4(0.f, 1.f, -1.f, -1.f);
+  q2 = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 // Ballots of the staged records [0, m) whose cutoff box meets this wavefront's
@@ -126,7 +127,7 @@ __device__ inline void quadrant_masks(const float4* s0, const float4* s1, const 
     const int j = lane + 64 * k;
     bool hit = false;
     if (j < m) {
-      const float u = s0[j].x, w = s0[j].y, ex = s1[j].w, ey = s2[j].w;
+      const float u = s0[j].x, w = s0[j].y, ex = s1[j].z, ey = s1[j].w;
       hit = u + ex >= qx && u - ex <= qx + 7.0f && w + ey >= qy && w - ey <= qy + 7.0f;
     }
     mask[k] = wave_mask(hit);
@@ -150,7 +151,10 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict_
   const float qx = (float)(tg.lx & ~7), qy = (float)(tg.ly & ~7);
   float Tr = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, A = 0.0f;
   uint32_t cnt = 0, lastp = 0;
-  bool done = !tg.inside;
+  // A pixel takes a Gaussian while its exponent lies in [cutoff, pmax]: pmax is 0
+  // while the pixel blends and -inf once it has stopped (or lies outside the
+  // image), which keeps the test two plain comparisons.
+  float pmax = tg.inside ? 0.0f : -INFINITY;
   for (uint32_t base = rg.x; base < rg.y; base += NT) {
     const uint32_t m = min((uint32_t)NT, rg.y - base);
     __syncthreads();
@@ -163,7 +167,7 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict_
       }
     }
     __syncthreads();
-    if (wave_mask(!done) != 0ull) {
+    if (wave_mask(pmax == 0.0f) != 0ull) {
       uint64_t mask[NM];
       quadrant_masks<NM>(s0, s1, s2, (int)m, qx, qy, mask);
       // straight-line per-Gaussian update; lanes that skip or have stopped keep their state
@@ -178,30 +182,30 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict_
           const float4 a1 = s1[j];
           const float dx = a0.x - fx, dy = a0.y - fy;
           const float p2 = gauss_power2(a0.z, a0.w, a1.x, dx, dy);
-          const bool pass = !done && p2 <= 0.0f && p2 >= a1.z;
-          if (wave_mask(pass) == 0ull) continue;   // no pixel of this wave takes it
-          const float4 a2 = s2[j];
-          const float alpha = fminf(kAlphaMax, a1.y * __builtin_amdgcn_exp2f(p2));
-          const float Tn = Tr * (1.0f - alpha);
-          const bool stop = pass && Tn < kTMin;
-          const bool blend = pass && !stop;
-          done = done || stop;
-          const float wgt = blend ? alpha * Tr : 0.0f;
-          C0 = __fmaf_rn(a2.x, wgt, C0);
-          C1 = __fmaf_rn(a2.y, wgt, C1);
-          C2 = __fmaf_rn(a2.z, wgt, C2);
-          Tr = blend ? Tn : Tr;
-          A += blend ? alpha : 0.0f;
-          cnt += blend ? 1u : 0u;
-          lastp = blend ? pos0 + j : lastp;
-          if (wave_mask(stop) != 0ull && wave_mask(!done) == 0ull) {   // every pixel of this wavefront stopped
-            live = false;
-            break;
+          const bool pass = p2 <= pmax && p2 >= a1.y;
+          if (wave_mask(pass) != 0ull) {
+            const float4 a2 = s2[j];
+            const float alpha = fminf(kAlphaMax, a2.x * __builtin_amdgcn_exp2f(p2));
+            const float Tn = Tr * (1.0f - alpha);
+            const bool stop = pass && Tn < kTMin;
+            const bool blend = pass && !stop;
+            pmax = stop ? -INFINITY : pmax;
+            const float wgt = blend ? alpha * Tr : 0.0f;
+            C0 = __fmaf_rn(a2.y, wgt, C0);
+            C1 = __fmaf_rn(a2.z, wgt, C1);
+            C2 = __fmaf_rn(a2.w, wgt, C2);
+            Tr = blend ? Tn : Tr;
+            A += blend ? alpha : 0.0f;
+            cnt += blend ? 1u : 0u;
+            lastp = blend ? pos0 + j : lastp;
+            // leave the batch once every pixel of this wavefront has stopped
+            mk = wave_mask(pmax == 0.0f) == 0ull ? 0ull : mk;
           }
         }
+        live = wave_mask(pmax == 0.0f) != 0ull;
       }
     }
-    if (__syncthreads_and(done)) break;
+    if (__syncthreads_and(pmax < 0.0f)) break;
   }
   if (tg.inside) {
     const ViewDev& cv = views[tg.v];
@@ -369,6 +373,7 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
     // whose cutoff box meets its quadrant, walked back to front
     uint64_t mask[NM];
     quadrant_masks<NM>(s0, s1, s2, min(m, wave_last - beg), qx, qy, mask);
+    const uint32_t lrel = lp > (uint32_t)beg ? lp - (uint32_t)beg : 0u;   // batch positions this pixel blended
     for (int k = NM - 1; k >= 0; --k) {
       uint64_t mk = mask[k];
       while (mk) {
@@ -380,12 +385,12 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
         const float4 a2 = s2[j];
         const float dx = a0.x - fx, dy = a0.y - fy;
         const float p2 = gauss_power2(a0.z, a0.w, a1.x, dx, dy);
-        const bool on = (uint32_t)(beg + j) < lp && p2 <= 0.0f && p2 >= a1.z;
+        const bool on = (uint32_t)j < lrel && p2 <= 0.0f && p2 >= a1.y;
         if (wave_mask(on) == 0ull) continue;    // no pixel of this wave blended it
         // straight-line update; lanes that did not blend this Gaussian keep their state
         // and contribute zeros
         const float G = __builtin_amdgcn_exp2f(p2);
-        const float og = a1.y * G;
+        const float og = a2.x * G;
         const bool capped = og > kAlphaMax;
         const float alpha = capped ? kAlphaMax : og;
         const float ri = __builtin_amdgcn_rcpf(1.0f - alpha);
@@ -397,7 +402,7 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
         // dL/dalpha = T (g . colour) - Sg / (1 - alpha) + gG, gG being the
         // load-balancing gradient of the pixel's soft count (each blended alpha enters
         // it with weight 1).
-        const float cg = __fmaf_rn(g2, a2.z, __fmaf_rn(g1, a2.y, g0 * a2.x));
+        const float cg = __fmaf_rn(g2, a2.w, __fmaf_rn(g1, a2.z, g0 * a2.y));
         float dLda = __fmaf_rn(Tr, cg, __fmaf_rn(-Sg, ri, gG));
         dLda = (on && !capped) ? dLda : 0.0f;  // a capped alpha has zero derivative
         Sg = __fmaf_rn(cg, wgt, Sg);
