@@ -193,12 +193,14 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const ViewDev* __restrict__ vi
         const float sxx = m[2][j] - mx * mx, syy = m[3][j] - my * my, sxy = m[4][j] - mx * my;
         const float N1 = 2.0f * mx * my + kC1, N2 = 2.0f * sxy + kC2;
         const float D1 = mx * mx + my * my + kC1, D2 = sxx + syy + kC2;
-        const float den = D1 * D2;
-        const float S = (N1 * N2) / den;
+        // hardware reciprocals (1 ulp): D1, D2 >= C1 > 0
+        const float r1 = __builtin_amdgcn_rcpf(D1), r2 = __builtin_amdgcn_rcpf(D2);
+        const float rden = r1 * r2;
+        const float S = (N1 * N2) * rden;
         const size_t p = (size_t)py * cv.W + px;
-        ac[p] = 2.0f * my * (N2 - N1) / den + 2.0f * mx * S * (1.0f / D2 - 1.0f / D1);
-        ac[p + hw] = -S / D2;
-        ac[p + 2 * hw] = 2.0f * N1 / den;
+        ac[p] = 2.0f * my * (N2 - N1) * rden + 2.0f * mx * S * (r2 - r1);
+        ac[p + hw] = -S * r2;
+        ac[p + 2 * hw] = 2.0f * N1 * rden;
         const float xv = sin_[0][(r0 + j + R) * HS + col + R];
         const float yv = sin_[1][(r0 + j + R) * HS + col + R];
         sl1 += fabs((double)(xv - yv));
