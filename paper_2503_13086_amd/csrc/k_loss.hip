@@ -13,8 +13,9 @@
 // respect to the windowed statistics (mx, E[x^2], E[xy]) are
 //   A = 2 my (N2 - N1) / (D1 D2) + 2 mx S (1/D2 - 1/D1),  B = -S / D2,
 //   Cc = 2 N1 / (D1 D2),
-// and dS_mean/dx = (window * A + 2 x (window * B) + y (window * Cc)) / N.  The first
-// kernel stores A, B, Cc; the second filters them the same way (the window is
+// and dS_mean/dx = (window * A + 2 x (window * B) + y (window * Cc)) / N, with 1/D1
+// and 1/D2 taken once per pixel from the hardware reciprocal.  The first kernel
+// stores A, B, Cc; the second filters them the same way (the window is
 // symmetric) and adds the L1 term.  Loss sums are reduced per tile in FP64.
 //
 // The load-balancing term of Eq. 9 (kernels at the end) works on the soft
