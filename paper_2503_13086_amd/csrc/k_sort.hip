@@ -44,9 +44,10 @@ __device__ inline uint64_t match_digit(uint32_t d, bool valid) {
 }
 
 // Per-workgroup digit histogram.  Wave w of a workgroup owns items
-// [base + 1024 w, base + 1024 (w + 1)); per 64-item round the leader lane of each
-// digit group adds the group's size to the wave's own counter (distinct
-// addresses, no atomics).
+// [base + 1024 w, base + 1024 (w + 1)) and counts them into its own LDS counters
+// with non-returning atomic adds (no dependence from one 64-item round to the
+// next); a round whose valid items all share one digit (the common case for the
+// high digits of clustered keys) is added by one lane.
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys, size_t n, int shift,
                                                           uint32_t* __restrict__ hist, int n_blocks) {
   __shared__ uint32_t hw[kWaves][kRadix];
@@ -56,18 +57,21 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
   const size_t base = (size_t)blockIdx.x * kSortTileItems + (size_t)w * (kItems * 64) + __lane_id();
   uint32_t kk[kItems];
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {   // all loads in flight before any ranking
+  for (int r = 0; r < kItems; ++r) {   // all loads in flight before any counting
     const size_t i = base + (size_t)r * 64;
     kk[r] = i < n ? keys[i] : 0u;
   }
-  const uint64_t lt = lanemask_lt();
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const bool valid = base + (size_t)r * 64 < n;
     const uint32_t d = (kk[r] >> shift) & 0xffu;
-    const uint64_t peers = match_digit(d, valid);
-    if (valid && (peers & lt) == 0) hw[w][d] += (uint32_t)__popcll(peers);
-    __builtin_amdgcn_wave_barrier();   // the leaders' updates precede the next round's reads
+    const uint64_t vmask = __ballot(valid);
+    const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
+    if (__ballot(valid && d == d0) == vmask) {
+      if (__lane_id() == 0 && vmask) atomicAdd(&hw[w][d0], (uint32_t)__popcll(vmask));
+    } else if (valid) {
+      atomicAdd(&hw[w][d], 1u);
+    }
   }
   __syncthreads();
   uint32_t t = 0;
