@@ -58,6 +58,17 @@ struct TileLoc {
   int v, x0, y0;
 };
 
+// Workgroups are dealt to the chip's 8 XCDs round-robin (workgroup b runs on XCD
+// b mod 8), each XCD with its own L2.  Workgroup b takes tile (b mod 8) * chunk +
+// b / 8, so every XCD walks a contiguous range of tiles and the halo rows that
+// neighbouring tiles share are fetched into one L2.  Tiles past the end (at most
+// 7 workgroups) return at once.
+constexpr int kXcds = 8;
+
+__host__ __device__ inline int xcd_tile_chunk(int n_tiles) { return (n_tiles + kXcds - 1) / kXcds; }
+
+__device__ inline int xcd_tile(int b, int n_tiles) { return (b % kXcds) * xcd_tile_chunk(n_tiles) + b / kXcds; }
+
 __device__ inline TileLoc loss_tile(const ViewDev* __restrict__ views, const LossTiles& lt, int V, int tile) {
   int v = 0;
   while (v + 1 < V && tile >= lt.off[v + 1]) ++v;
@@ -83,7 +94,9 @@ __global__ __launch_bounds__(256) void k_l1(const ViewDev* __restrict__ views, i
                                              const float* __restrict__ x, const float* __restrict__ y, float w_l1,
                                              float* __restrict__ grad, double2* __restrict__ partials) {
   __shared__ double sh[4];
-  const TileLoc t = loss_tile(views, lt, V, blockIdx.x);
+  const int tile = xcd_tile(blockIdx.x, lt.off[V]);
+  if (tile >= lt.off[V]) return;
+  const TileLoc t = loss_tile(views, lt, V, tile);
   const ViewDev& cv = views[t.v];
   const size_t hw = (size_t)cv.W * cv.H;
   const size_t base = 3 * (size_t)cv.pix_off;
@@ -100,7 +113,7 @@ __global__ __launch_bounds__(256) void k_l1(const ViewDev* __restrict__ views, i
     }
   }
   const double tot = block_sum_d(s, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = make_double2(tot, 0.0);
+  if (threadIdx.x == 0) partials[tile] = make_double2(tot, 0.0);
 }
 
 // Horizontal pass: out[q][r][c] (r < HALO, c < LT) = sum_k w[k] f_q(r, c + k) where the
@@ -165,7 +178,9 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const ViewDev* __restrict__ vi
   __shared__ float sin_[2][HALO * HS];
   __shared__ float hbuf[5][HALO * LT];
   __shared__ double sh[4];
-  const TileLoc t = loss_tile(views, lt, V, blockIdx.x);
+  const int tile = xcd_tile(blockIdx.x, lt.off[V]);
+  if (tile >= lt.off[V]) return;
+  const TileLoc t = loss_tile(views, lt, V, tile);
   const ViewDev& cv = views[t.v];
   const size_t hw = (size_t)cv.W * cv.H;
   const size_t base = 3 * (size_t)cv.pix_off;
@@ -212,7 +227,7 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const ViewDev* __restrict__ vi
   }
   const double t1 = block_sum_d(sl1, sh);
   const double t2 = block_sum_d(sss, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = make_double2(t1, t2);
+  if (threadIdx.x == 0) partials[tile] = make_double2(t1, t2);
 }
 
 __global__ __launch_bounds__(256) void k_ssim_bwd(const ViewDev* __restrict__ views, int V, LossTiles lt,
@@ -221,7 +236,9 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const ViewDev* __restrict__ vi
                                                    float* __restrict__ grad) {
   __shared__ float sin_[3][HALO * HS];
   __shared__ float hbuf[3][HALO * LT];
-  const TileLoc t = loss_tile(views, lt, V, blockIdx.x);
+  const int tile = xcd_tile(blockIdx.x, lt.off[V]);
+  if (tile >= lt.off[V]) return;
+  const TileLoc t = loss_tile(views, lt, V, tile);
   const ViewDev& cv = views[t.v];
   const size_t hw = (size_t)cv.W * cv.H;
   const size_t base = 3 * (size_t)cv.pix_off;
@@ -389,11 +406,12 @@ hipError_t launch_loss_dev(const ViewDev* dviews, const ViewDev* hviews, int V, 
   lt.off[V] = t;
   double2* part = reinterpret_cast<double2*>(partials);
   const bool ssim = w_dssim != 0.0f;
+  const dim3 grid(kXcds * xcd_tile_chunk(t));   // >= t workgroups, see xcd_tile
   if (!ssim) {
-    hipLaunchKernelGGL(k_l1, dim3(t), dim3(256), 0, s, dviews, V, lt, color, target, w_l1, dL_dcolor, part);
+    hipLaunchKernelGGL(k_l1, grid, dim3(256), 0, s, dviews, V, lt, color, target, w_l1, dL_dcolor, part);
   } else {
-    hipLaunchKernelGGL(k_ssim_fwd, dim3(t), dim3(256), 0, s, dviews, V, lt, color, target, aux, win, part);
-    hipLaunchKernelGGL(k_ssim_bwd, dim3(t), dim3(256), 0, s, dviews, V, lt, color, target, aux, win, w_l1, w_dssim,
+    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, s, dviews, V, lt, color, target, aux, win, part);
+    hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, s, dviews, V, lt, color, target, aux, win, w_l1, w_dssim,
                        dL_dcolor);
   }
   if (loss_out)
