@@ -277,30 +277,38 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
   if ((st = ensure(c, c->total, 8, s)) != GS_OK) return st;
   if ((st = ensure(c, c->hist, sort_hist_words(NV) * 4, s)) != GS_OK) return st;
   if ((st = ensure(c, c->digit_tot, 256 * 4, s)) != GS_OK) return st;
-  // depth order of all (view, Gaussian) entries (invisible ones carry the largest key)
+  const bool cull = c->cull == GS_CULL_ELLIPSE;
+  // pairs per entry: the rect's tiles, or with culling the tiles whose pixel-centre
+  // box meets the cutoff region (counted in index order, coalesced)
+  const uint32_t* per_entry = c->touched.as<uint32_t>();
+  if (cull) {
+    Prof pr(c, GS_K_SCAN, s);
+    if ((st = ensure(c, c->kept, NV * 4, s)) != GS_OK) return st;
+    GS_HIP(c, launch_count_kept(c->touched.as<uint32_t>(), c->rect.as<ushort4>(), c->rec.as<Record>(), NV, c->n,
+                                c->views.as<ViewDev>(), c->tile, c->kept.as<uint32_t>(), s));
+    per_entry = c->kept.as<uint32_t>();
+  }
+  // depth order of all (view, Gaussian) entries (invisible ones carry the largest
+  // key); up to 2^24 entries the sorted values also carry each entry's pair count
+  const bool packed = NV <= kPackMaxEntries;
   {
     Prof pr(c, GS_K_DEPTH_SORT, s);
     GS_HIP(c, hipMemcpyAsync(c->dkey[0].p, c->depth.p, NV * 4, hipMemcpyDeviceToDevice, s));
-    GS_HIP(c, launch_iota(c->dval[0].as<uint32_t>(), NV, s));
+    if (packed) {
+      GS_HIP(c, launch_pack_order(per_entry, NV, c->dval[0].as<uint32_t>(), s));
+    } else {
+      GS_HIP(c, launch_iota(c->dval[0].as<uint32_t>(), NV, s));
+    }
     SortScratch sc{c->hist.as<uint32_t>(), c->digit_tot.as<uint32_t>()};
     GS_HIP(c, radix_sort_pairs(c->dkey[0].as<uint32_t>(), c->dval[0].as<uint32_t>(), c->dkey[1].as<uint32_t>(),
                                c->dval[1].as<uint32_t>(), NV, 32, sc, &c->depth_in_b, s));
   }
   const uint32_t* order = c->dval[c->depth_in_b].as<uint32_t>();
-  const bool cull = c->cull == GS_CULL_ELLIPSE;
   {
     Prof pr(c, GS_K_SCAN, s);
-    // pairs per entry: the rect's tiles, or with culling the tiles whose pixel-centre
-    // box meets the cutoff region (counted in index order, coalesced)
-    const uint32_t* per_entry = c->touched.as<uint32_t>();
-    if (cull) {
-      if ((st = ensure(c, c->kept, NV * 4, s)) != GS_OK) return st;
-      GS_HIP(c, launch_count_kept(c->touched.as<uint32_t>(), c->rect.as<ushort4>(), c->rec.as<Record>(), NV, c->n,
-                                  c->views.as<ViewDev>(), c->tile, c->kept.as<uint32_t>(), s));
-      per_entry = c->kept.as<uint32_t>();
-    }
-    GS_HIP(c, launch_scan_touched(order, per_entry, NV, c->counts.as<uint32_t>(), c->offsets.as<uint32_t>(),
-                                  c->blocksums.as<uint32_t>(), c->total.as<unsigned long long>(), s));
+    GS_HIP(c, launch_scan_touched(order, packed ? 1 : 0, per_entry, NV, c->counts.as<uint32_t>(),
+                                  c->offsets.as<uint32_t>(), c->blocksums.as<uint32_t>(),
+                                  c->total.as<unsigned long long>(), s));
   }
   GS_HIP(c, hipMemcpyAsync(c->h_total, c->total.p, 8, hipMemcpyDeviceToHost, s));
   GS_HIP(c, hipStreamSynchronize(s));
@@ -314,7 +322,8 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
   if ((st = ensure(c, c->ranges, (size_t)c->n_tiles * 8, s)) != GS_OK) return st;
   {
     Prof pr(c, GS_K_EMIT, s);
-    GS_HIP(c, launch_emit_pairs(order, c->counts.as<uint32_t>(), c->offsets.as<uint32_t>(), c->rect.as<ushort4>(),
+    GS_HIP(c, launch_emit_pairs(order, packed ? 1 : 0, c->counts.as<uint32_t>(), c->offsets.as<uint32_t>(),
+                                c->rect.as<ushort4>(),
                                 c->rec.as<Record>(), NV, c->n, c->views.as<ViewDev>(), (size_t)K, cull ? 1 : 0,
                                 c->tile, c->pkey[0].as<uint32_t>(), c->pval[0].as<uint32_t>(), s));
   }

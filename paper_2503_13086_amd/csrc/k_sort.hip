@@ -226,6 +226,16 @@ __global__ void k_iota(uint32_t* __restrict__ p, size_t n) {
     p[i] = (uint32_t)i;
 }
 
+// p[e] = e | min(count[e], 255) << 24 (n <= 2^24): the depth sort then carries
+// each entry's pair count with its index, and the scan in depth order reads it
+// without a gather.
+__global__ void k_pack_order(const uint32_t* __restrict__ count, size_t n, uint32_t* __restrict__ p) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t c = count[i];
+    p[i] = (uint32_t)i | ((c < kPackSat ? c : kPackSat) << kPackShift);
+  }
+}
+
 // ---- exclusive scan of touched[order[e]] ----
 constexpr int kScanItems = 4096;
 
@@ -241,9 +251,11 @@ __device__ inline uint32_t block_sum_u32(uint32_t x, uint32_t* sh) {
 
 // Block sums of touched[order[e]]; the gathered counts are stored in depth order
 // (counts[e]) so the later passes read them contiguously.
+// With packed != 0 the order entries carry min(count, 255) in their top byte (see
+// k_pack_order) and only the saturated ones gather their count.
 __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t* __restrict__ order,
                                                            const uint32_t* __restrict__ touched, size_t n,
-                                                           uint32_t* __restrict__ counts,
+                                                           int packed, uint32_t* __restrict__ counts,
                                                            uint32_t* __restrict__ block_sums) {
   __shared__ uint32_t sh[kWaves];
   const size_t base = (size_t)blockIdx.x * kScanItems;
@@ -251,7 +263,14 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t* __rest
   for (int r = 0; r < kScanItems / kThreads; ++r) {
     const size_t i = base + (size_t)r * kThreads + threadIdx.x;
     if (i < n) {
-      const uint32_t c = touched[order[i]];
+      const uint32_t o = order[i];
+      uint32_t c;
+      if (packed) {
+        c = o >> kPackShift;
+        if (c == kPackSat) c = touched[o & kPackRidMask];
+      } else {
+        c = touched[o];
+      }
       counts[i] = c;
       s += c;
     }
@@ -415,7 +434,7 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
 // the cutoff region (the test k_count_kept made, so the kept counts and offsets
 // agree), and kept candidates are written in order at running positions taken
 // from a ballot: writes are coalesced and large rects are shared by the wave.
-__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ order,
+__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ order, uint32_t rid_mask,
                                                     const uint32_t* __restrict__ counts,
                                                     const uint32_t* __restrict__ offsets,
                                                     const ushort4* __restrict__ rect,
@@ -438,7 +457,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
   uint32_t cnt = 0, off = 0, rid = 0, cand = 0;
   ushort4 rc = make_ushort4(0, 0, 0, 0);
   if (valid) {
-    rid = order[e];
+    rid = order[e] & rid_mask;
     cnt = counts[e];
     off = offsets[e];
     if (cnt) {
@@ -572,23 +591,30 @@ hipError_t launch_iota(uint32_t* p, size_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_pack_order(const uint32_t* count, size_t n, uint32_t* p, hipStream_t s) {
+  if (n > kPackMaxEntries) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pack_order, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, count, n, p);
+  return hipGetLastError();
+}
+
 size_t scan_block_words(size_t n) { return (n + kScanItems - 1) / kScanItems + 1; }
 
-hipError_t launch_scan_touched(const uint32_t* order, const uint32_t* touched, size_t n, uint32_t* counts,
+hipError_t launch_scan_touched(const uint32_t* order, int packed, const uint32_t* touched, size_t n, uint32_t* counts,
                                uint32_t* offsets, uint32_t* block_sums, unsigned long long* total, hipStream_t s) {
   const int nb = (int)((n + kScanItems - 1) / kScanItems);
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, s, order, touched, n, counts, block_sums);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, s, order, touched, n, packed, counts, block_sums);
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, block_sums, nb, total);
   hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kThreads), 0, s, counts, n, block_sums, offsets);
   return hipGetLastError();
 }
 
-hipError_t launch_emit_pairs(const uint32_t* order, const uint32_t* counts, const uint32_t* offsets,
+hipError_t launch_emit_pairs(const uint32_t* order, int packed, const uint32_t* counts, const uint32_t* offsets,
                              const ushort4* rect, const Record* rec, size_t n_entries, int n, const ViewDev* views,
                              size_t K, int cull, int tile, uint32_t* pair_tile, uint32_t* pair_rec, hipStream_t s) {
   if (n_entries == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n_entries + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, order, counts, offsets, rect, rec, n_entries, n,
+  hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, order, packed ? kPackRidMask : 0xffffffffu, counts,
+                     offsets, rect, rec, n_entries, n,
                      views, K, cull, tile, pair_tile, pair_rec);
   return hipGetLastError();
 }
