@@ -40,7 +40,7 @@ struct gs_ctx {
   DevBuf dkey[2], dval[2], counts, offsets, blocksums, total, hist, digit_tot;
   DevBuf pkey[2], pval[2], ranges;
   DevBuf tfinal, ncontrib, last, grad2d, lossp, aux;
-  DevBuf asum, dG, loadp, loadst, kept;
+  DevBuf asum, dG, loadp, loadst, kept, emitinfo;
   bool load_pending = false;   // dG holds a load-balancing gradient for the current forward
   ViewDev* h_views = nullptr;
   unsigned long long* h_total = nullptr;
@@ -87,7 +87,7 @@ std::vector<DevBuf*> all_bufs(gs_ctx* c) {
   return {&c->views, &c->rec, &c->depth, &c->touched, &c->rect, &c->dkey[0], &c->dkey[1], &c->dval[0],
           &c->dval[1], &c->counts, &c->offsets, &c->blocksums, &c->total, &c->hist, &c->digit_tot, &c->pkey[0],
           &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->tfinal, &c->ncontrib, &c->last,
-          &c->grad2d, &c->lossp, &c->aux, &c->asum, &c->dG, &c->loadp, &c->loadst, &c->kept};
+          &c->grad2d, &c->lossp, &c->aux, &c->asum, &c->dG, &c->loadp, &c->loadst, &c->kept, &c->emitinfo};
 }
 
 hipEvent_t next_event(gs_ctx* c) {
@@ -284,8 +284,10 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
   if (cull) {
     Prof pr(c, GS_K_SCAN, s);
     if ((st = ensure(c, c->kept, NV * 4, s)) != GS_OK) return st;
+    if ((st = ensure(c, c->emitinfo, NV * sizeof(EmitInfo), s)) != GS_OK) return st;
     GS_HIP(c, launch_count_kept(c->touched.as<uint32_t>(), c->rect.as<ushort4>(), c->rec.as<Record>(), NV, c->n,
-                                c->views.as<ViewDev>(), c->tile, c->kept.as<uint32_t>(), s));
+                                c->views.as<ViewDev>(), c->tile, c->kept.as<uint32_t>(), c->emitinfo.as<EmitInfo>(),
+                                s));
     per_entry = c->kept.as<uint32_t>();
   }
   // depth order of all (view, Gaussian) entries (invisible ones carry the largest
@@ -325,7 +327,8 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
     GS_HIP(c, launch_emit_pairs(order, packed ? 1 : 0, c->counts.as<uint32_t>(), c->offsets.as<uint32_t>(),
                                 c->rect.as<ushort4>(),
                                 c->rec.as<Record>(), NV, c->n, c->views.as<ViewDev>(), (size_t)K, cull ? 1 : 0,
-                                c->tile, c->pkey[0].as<uint32_t>(), c->pval[0].as<uint32_t>(), s));
+                                c->tile, cull ? c->emitinfo.as<EmitInfo>() : nullptr, c->pkey[0].as<uint32_t>(),
+                                c->pval[0].as<uint32_t>(), s));
   }
   {
     Prof pr(c, GS_K_TILE_SORT, s);

@@ -128,14 +128,22 @@ hipError_t launch_scan_touched(const uint32_t* order, int packed, const uint32_t
                                uint32_t* offsets, uint32_t* block_sums, unsigned long long* total, hipStream_t s);
 // kept[e] = tiles of entry e's rect whose pixel-centre box meets its cutoff region
 // (entries in index order; rect tile count in touched)
+// What emission fetches per culled entry: its tile rect and, for rects of at most
+// 64 tiles, which of them the cutoff region meets (bit i: the rect's i-th tile in
+// row-major order).
+struct alignas(16) EmitInfo {
+  ushort4 rect;
+  uint64_t bits;
+};
 hipError_t launch_count_kept(const uint32_t* touched, const ushort4* rect, const Record* rec, size_t n_entries, int n,
-                             const ViewDev* views, int tile, uint32_t* kept, hipStream_t s);
+                             const ViewDev* views, int tile, uint32_t* kept, EmitInfo* info, hipStream_t s);
 // pairs of the depth-ordered entries order[0..n_entries): counts/offsets are the
 // scanned per-entry pair counts; cull != 0 keeps only the rect tiles that meet the
 // cutoff region (counts must then be the kept counts)
 hipError_t launch_emit_pairs(const uint32_t* order, int packed, const uint32_t* counts, const uint32_t* offsets,
                              const ushort4* rect, const Record* rec, size_t n_entries, int n, const ViewDev* views,
-                             size_t K, int cull, int tile, uint32_t* pair_tile, uint32_t* pair_rec, hipStream_t s);
+                             size_t K, int cull, int tile, const EmitInfo* info, uint32_t* pair_tile,
+                             uint32_t* pair_rec, hipStream_t s);
 hipError_t launch_ranges(const uint32_t* pair_tile, size_t K, uint2* ranges, int n_tiles, hipStream_t s);
 hipError_t launch_compose_keys(const uint32_t* pair_tile, const uint32_t* pair_rec, const uint32_t* depth,
                                size_t K, int n, size_t n_rec, unsigned long long* keys, uint32_t* values,

@@ -369,28 +369,34 @@ __device__ inline uint32_t wave_incl_scan(uint32_t x) {
 // Kept pairs per entry (index order, coalesced reads): the tiles of the entry's
 // rect whose pixel-centre box meets its cutoff region.  The wave's candidates are
 // spread over its lanes; runs of one entry within 64 candidates are counted with
-// ballots by the run's first lane.
+// ballots by the run's first lane.  Each entry also gets a 16-byte EmitInfo: its
+// rect and, when it has at most 64 candidates, the outcome of every test (bit i
+// for the rect's i-th tile, row-major), which is all emission then has to fetch.
 __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restrict__ touched,
                                                           const ushort4* __restrict__ rect,
                                                           const Record* __restrict__ rec, size_t n_entries, int n,
                                                           const ViewDev* __restrict__ views, int T,
-                                                          uint32_t* __restrict__ kept) {
+                                                          uint32_t* __restrict__ kept,
+                                                          EmitInfo* __restrict__ info) {
   __shared__ uint32_t s_cp[kWaves][65];
   __shared__ uint32_t s_nx[kWaves][64];
   __shared__ uint32_t s_org[kWaves][64];    // rect origin (tx0 | ty0 << 16)
   __shared__ uint32_t s_wh[kWaves][64];     // view size (W | H << 16)
   __shared__ uint32_t s_k[kWaves][64];
+  __shared__ uint64_t s_bits[kWaves][64];
   __shared__ CutoffGeo s_geo[kWaves][64];
   const int w = threadIdx.x / 64;
   const unsigned lane = __lane_id();
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t cand = e < n_entries ? touched[e] : 0u;
+  ushort4 rc = make_ushort4(0, 0, 0, 0);
   const uint32_t incl = wave_incl_scan(cand);
   s_cp[w][lane + 1] = incl;
   if (lane == 0) s_cp[w][0] = 0u;
   s_k[w][lane] = 0u;
+  s_bits[w][lane] = 0ull;
   if (cand) {
-    const ushort4 rc = rect[e];
+    rc = rect[e];
     const ViewDev& cv = views[e / (size_t)n];
     s_nx[w][lane] = (uint32_t)(rc.y - rc.x + 1);
     s_org[w][lane] = (uint32_t)rc.x | ((uint32_t)rc.z << 16);
@@ -421,25 +427,36 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
       const unsigned next = above ? (unsigned)__builtin_ctzll(above) : 64u;
       const uint64_t run = (next == 64u ? ~0ull : ((1ull << next) - 1ull)) & (~0ull << lane);
       s_k[w][lo] += (uint32_t)__popcll(pmask & run);
+      if (s_cp[w][lo + 1] - s_cp[w][lo] <= 64u)   // the run's outcomes at their rect positions
+        s_bits[w][lo] |= ((pmask & run) >> lane) << (q - s_cp[w][lo]);
     }
     __builtin_amdgcn_wave_barrier();
   }
-  if (e < n_entries) kept[e] = s_k[w][lane];
+  if (e < n_entries) {
+    kept[e] = s_k[w][lane];
+    EmitInfo in;
+    in.rect = rc;
+    in.bits = s_bits[w][lane];
+    info[e] = in;
+  }
 }
 
 // Pair emission, one wave per 64 consecutive depth-ordered entries.  The wave's
 // pairs occupy one contiguous output range.  Its candidates (rect tiles of its
 // entries, entry by entry, row-major) are spread over the lanes in rounds of 64;
 // with culling on, a candidate is kept only if its tile's pixel-centre box meets
-// the cutoff region (the test k_count_kept made, so the kept counts and offsets
-// agree), and kept candidates are written in order at running positions taken
-// from a ballot: writes are coalesced and large rects are shared by the wave.
+// the cutoff region (k_count_kept's outcome bits for entries of at most 64
+// candidates, the same test repeated for larger ones, so the kept counts and
+// offsets agree), and kept candidates are written in order at running positions
+// taken from a ballot: writes are coalesced and large rects are shared by the wave.
+// With culling the entry's rect comes from its EmitInfo (one 16-byte fetch).
 __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ order, uint32_t rid_mask,
                                                     const uint32_t* __restrict__ counts,
                                                     const uint32_t* __restrict__ offsets,
                                                     const ushort4* __restrict__ rect,
                                                     const Record* __restrict__ rec, size_t n_entries, int n,
                                                     const ViewDev* __restrict__ views, size_t K, int cull, int T,
+                                                    const EmitInfo* __restrict__ info,
                                                     uint32_t* __restrict__ pair_tile,
                                                     uint32_t* __restrict__ pair_rec) {
   __shared__ uint32_t s_cp[kWaves][65];
@@ -449,19 +466,27 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
   __shared__ uint32_t s_tx[kWaves][64];     // tiles per row of the entry's view
   __shared__ uint32_t s_org[kWaves][64];    // rect origin (tx0 | ty0 << 16)
   __shared__ uint32_t s_wh[kWaves][64];     // view size (W | H << 16)
+  __shared__ uint64_t s_bits[kWaves][64];   // test outcomes (entries of <= 64 candidates)
   __shared__ CutoffGeo s_geo[kWaves][64];
   const int w = threadIdx.x / 64;
   const unsigned lane = __lane_id();
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = e < n_entries;
   uint32_t cnt = 0, off = 0, rid = 0, cand = 0;
+  uint64_t bits = 0ull;
   ushort4 rc = make_ushort4(0, 0, 0, 0);
   if (valid) {
     rid = order[e] & rid_mask;
     cnt = counts[e];
     off = offsets[e];
     if (cnt) {
-      rc = rect[rid];
+      if (cull) {
+        const EmitInfo in = info[rid];
+        rc = in.rect;
+        bits = in.bits;
+      } else {
+        rc = rect[rid];
+      }
       cand = (uint32_t)(rc.y - rc.x + 1) * (uint32_t)(rc.w - rc.z + 1);
     }
   }
@@ -481,9 +506,12 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
     s_nx[w][lane] = (uint32_t)(rc.y - rc.x + 1);
     s_tx[w][lane] = (uint32_t)cv.tiles_x;
     if (cull) {
-      s_org[w][lane] = (uint32_t)rc.x | ((uint32_t)rc.z << 16);
-      s_wh[w][lane] = (uint32_t)cv.W | ((uint32_t)cv.H << 16);
-      s_geo[w][lane] = cutoff_geo(rec[rid]);
+      s_bits[w][lane] = bits;
+      if (cand > 64u) {
+        s_org[w][lane] = (uint32_t)rc.x | ((uint32_t)rc.z << 16);
+        s_wh[w][lane] = (uint32_t)cv.W | ((uint32_t)cv.H << 16);
+        s_geo[w][lane] = cutoff_geo(rec[rid]);
+      }
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -502,9 +530,14 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
       r = s_rid[w][lo];
       keep = true;
       if (cull) {
-        const uint32_t org = s_org[w][lo], wh = s_wh[w][lo];
-        keep = tile_meets_cutoff(s_geo[w][lo], (int)((org & 0xffffu) + tx), (int)((org >> 16) + ty), T,
-                                 (int)(wh & 0xffffu), (int)(wh >> 16));
+        const uint32_t li = q - s_cp[w][lo];
+        if (s_cp[w][lo + 1] - s_cp[w][lo] <= 64u) {
+          keep = ((s_bits[w][lo] >> li) & 1ull) != 0ull;
+        } else {
+          const uint32_t org = s_org[w][lo], wh = s_wh[w][lo];
+          keep = tile_meets_cutoff(s_geo[w][lo], (int)((org & 0xffffu) + tx), (int)((org >> 16) + ty), T,
+                                   (int)(wh & 0xffffu), (int)(wh >> 16));
+        }
       }
     }
     const uint64_t kmask = __ballot(keep);
@@ -610,21 +643,22 @@ hipError_t launch_scan_touched(const uint32_t* order, int packed, const uint32_t
 
 hipError_t launch_emit_pairs(const uint32_t* order, int packed, const uint32_t* counts, const uint32_t* offsets,
                              const ushort4* rect, const Record* rec, size_t n_entries, int n, const ViewDev* views,
-                             size_t K, int cull, int tile, uint32_t* pair_tile, uint32_t* pair_rec, hipStream_t s) {
+                             size_t K, int cull, int tile, const EmitInfo* info, uint32_t* pair_tile,
+                             uint32_t* pair_rec, hipStream_t s) {
   if (n_entries == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n_entries + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, order, packed ? kPackRidMask : 0xffffffffu, counts,
                      offsets, rect, rec, n_entries, n,
-                     views, K, cull, tile, pair_tile, pair_rec);
+                     views, K, cull, tile, info, pair_tile, pair_rec);
   return hipGetLastError();
 }
 
 hipError_t launch_count_kept(const uint32_t* touched, const ushort4* rect, const Record* rec, size_t n_entries, int n,
-                             const ViewDev* views, int tile, uint32_t* kept, hipStream_t s) {
+                             const ViewDev* views, int tile, uint32_t* kept, EmitInfo* info, hipStream_t s) {
   if (n_entries == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n_entries + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_count_kept, dim3(blocks), dim3(kThreads), 0, s, touched, rect, rec, n_entries, n, views, tile,
-                     kept);
+                     kept, info);
   return hipGetLastError();
 }
 
