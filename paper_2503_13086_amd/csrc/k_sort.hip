@@ -335,23 +335,43 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t* __restr
   }
 }
 
-// Cooperative walk over the candidate pairs of 64 consecutive entries, one wave:
-// entry l of the wave has cand[l] candidates (the tiles of its rect, row-major);
-// s_cp holds the inclusive prefix of the candidate counts with s_cp[0] = 0 at
-// index 0 (s_cp[l + 1] = candidates of entries 0..l).  Returns the entry of
-// candidate q (largest l with s_cp[l] <= q).
-__device__ inline int entry_of(const uint32_t* s_cp, uint32_t q) {
-  int lo = 0, hi = 63;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (s_cp[mid] <= q) lo = mid; else hi = mid - 1;
-  }
-  return lo;
+// Inclusive max over lanes 0..l (DPP: shifts within rows of 16 lanes, then the
+// last lane of a row broadcast into the rows after it); -1 is the identity.
+__device__ inline int wave_incl_max(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xf, 0xf, false));   // row_shr:1
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xf, 0xf, false));   // row_shr:2
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xf, 0xf, false));   // row_shr:4
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xf, 0xf, false));   // row_shr:8
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xa, 0xf, false));   // row_bcast:15 into rows 1, 3
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xc, 0xf, false));   // row_bcast:31 into rows 2, 3
+  return v;
 }
 
-// (tile column, row) offsets of candidate `local` in a rect nx tiles wide
+// Cooperative walk over the candidate pairs of 64 consecutive entries, one wave:
+// entry l of the wave (lane l) has cand candidates (the tiles of its rect,
+// row-major) starting at the wave-exclusive prefix excl; a round covers the
+// candidates [cb, cb + 64), candidate cb + k on lane k.  Returns the entry that
+// owns this lane's candidate: each entry starting inside the round marks its start
+// in the wave's 64-slot scratch `own`, and a lane takes the last mark at or before
+// it (`carry`, the owner of the previous round's last candidate, when the round
+// opens inside an entry).  Lanes past the last candidate get a meaningless value.
+__device__ inline int round_owner(uint32_t excl, uint32_t cand, uint32_t cb, int* own, int carry) {
+  const unsigned lane = __lane_id();
+  own[lane] = -1;
+  __builtin_amdgcn_wave_barrier();
+  if (cand != 0u && excl >= cb && excl - cb < 64u) own[excl - cb] = (int)lane;
+  __builtin_amdgcn_wave_barrier();
+  const int mark = own[lane];
+  __builtin_amdgcn_wave_barrier();
+  const int o = wave_incl_max(lane == 0u && mark < 0 ? carry : mark);
+  return o < 0 ? 0 : o;   // only lanes past the last candidate could see no mark
+}
+
+// (tile column, row) offsets of candidate `local` in a rect nx tiles wide: the
+// quotient from the hardware reciprocal (within one of the true one for the
+// counts here, below 2^24), then corrected.
 __device__ inline void rect_cell(uint32_t local, uint32_t nx, uint32_t& tx, uint32_t& ty) {
-  ty = (uint32_t)((float)local / (float)nx);
+  ty = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)nx));
   if (ty * nx > local) --ty;
   else if ((ty + 1) * nx <= local) ++ty;
   tx = local - ty * nx;
@@ -384,6 +404,7 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
   __shared__ uint32_t s_wh[kWaves][64];     // view size (W | H << 16)
   __shared__ uint32_t s_k[kWaves][64];
   __shared__ uint64_t s_bits[kWaves][64];
+  __shared__ int s_own[kWaves][64];
   __shared__ CutoffGeo s_geo[kWaves][64];
   const int w = threadIdx.x / 64;
   const unsigned lane = __lane_id();
@@ -405,21 +426,24 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
   }
   __builtin_amdgcn_wave_barrier();
   const uint32_t C = s_cp[w][64];
+  int carry = 0;
   for (uint32_t cb = 0; cb < C; cb += 64) {
     const uint32_t q = cb + lane;
     const bool valid = q < C;
+    const int owner = round_owner(incl - cand, cand, cb, s_own[w], carry);
+    carry = __builtin_amdgcn_readlane(owner, 63);
     int lo = 0;
-    bool pass = false;
+    bool pass = false, first = false;
     if (valid) {
-      lo = entry_of(s_cp[w], q);
+      lo = owner;
+      const uint32_t li = q - s_cp[w][lo];
+      first = lane == 0 || li == 0u;          // this lane opens its entry's run in the round
       uint32_t tx, ty;
-      rect_cell(q - s_cp[w][lo], s_nx[w][lo], tx, ty);
+      rect_cell(li, s_nx[w][lo], tx, ty);
       const uint32_t org = s_org[w][lo], wh = s_wh[w][lo];
       pass = tile_meets_cutoff(s_geo[w][lo], (int)((org & 0xffffu) + tx), (int)((org >> 16) + ty), T,
                                (int)(wh & 0xffffu), (int)(wh >> 16));
     }
-    const int prev = __shfl_up(lo, 1);
-    const bool first = valid && (lane == 0 || prev != lo);
     const uint64_t fmask = __ballot(first);
     const uint64_t pmask = __ballot(pass);
     if (first) {
@@ -467,6 +491,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
   __shared__ uint32_t s_org[kWaves][64];    // rect origin (tx0 | ty0 << 16)
   __shared__ uint32_t s_wh[kWaves][64];     // view size (W | H << 16)
   __shared__ uint64_t s_bits[kWaves][64];   // test outcomes (entries of <= 64 candidates)
+  __shared__ int s_own[kWaves][64];         // round_owner scratch
   __shared__ CutoffGeo s_geo[kWaves][64];
   const int w = threadIdx.x / 64;
   const unsigned lane = __lane_id();
@@ -518,12 +543,15 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
   const uint32_t C = s_cp[w][64];
   if (hi_end > K || C == 0u) return;        // never past K for a consistent scan; guards the writes
   uint32_t pos = lo_off;
+  int carry = 0;
   for (uint32_t cb = 0; cb < C; cb += 64) {
     const uint32_t q = cb + lane;
     bool keep = false;
     uint32_t tile = 0, r = 0;
+    const int owner = round_owner(incl - cand, cand, cb, s_own[w], carry);
+    carry = __builtin_amdgcn_readlane(owner, 63);
     if (q < C) {
-      const int lo = entry_of(s_cp[w], q);
+      const int lo = owner;
       uint32_t tx, ty;
       rect_cell(q - s_cp[w][lo], s_nx[w][lo], tx, ty);
       tile = s_base[w][lo] + ty * s_tx[w][lo] + tx;
