@@ -37,7 +37,7 @@ struct gs_ctx {
   int depth_in_b = 0, pairs_in_b = 0;
   int cull = GS_CULL_ELLIPSE;
   DevBuf views, rec, depth, touched, rect;
-  DevBuf dkey[2], dval[2], counts, offsets, blocksums, total, hist, digit_tot;
+  DevBuf dkey[2], dval[2], counts, offsets, blocksums, total, hist;
   DevBuf pkey[2], pval[2], ranges;
   DevBuf tfinal, ncontrib, last, grad2d, lossp, aux;
   DevBuf asum, dG, loadp, loadst, kept, emitinfo;
@@ -85,7 +85,7 @@ gs_status ensure(gs_ctx* c, DevBuf& b, size_t bytes, hipStream_t s) {
 
 std::vector<DevBuf*> all_bufs(gs_ctx* c) {
   return {&c->views, &c->rec, &c->depth, &c->touched, &c->rect, &c->dkey[0], &c->dkey[1], &c->dval[0],
-          &c->dval[1], &c->counts, &c->offsets, &c->blocksums, &c->total, &c->hist, &c->digit_tot, &c->pkey[0],
+          &c->dval[1], &c->counts, &c->offsets, &c->blocksums, &c->total, &c->hist, &c->pkey[0],
           &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->tfinal, &c->ncontrib, &c->last,
           &c->grad2d, &c->lossp, &c->aux, &c->asum, &c->dG, &c->loadp, &c->loadst, &c->kept, &c->emitinfo};
 }
@@ -276,7 +276,6 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
   if ((st = ensure(c, c->blocksums, scan_block_words(NV) * 4, s)) != GS_OK) return st;
   if ((st = ensure(c, c->total, 8, s)) != GS_OK) return st;
   if ((st = ensure(c, c->hist, sort_hist_words(NV) * 4, s)) != GS_OK) return st;
-  if ((st = ensure(c, c->digit_tot, 256 * 4, s)) != GS_OK) return st;
   const bool cull = c->cull == GS_CULL_ELLIPSE;
   // pairs per entry: the rect's tiles, or with culling the tiles whose pixel-centre
   // box meets the cutoff region (counted in index order, coalesced)
@@ -301,7 +300,7 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
     } else {
       GS_HIP(c, launch_iota(c->dval[0].as<uint32_t>(), NV, s));
     }
-    SortScratch sc{c->hist.as<uint32_t>(), c->digit_tot.as<uint32_t>()};
+    SortScratch sc{c->hist.as<uint32_t>()};
     GS_HIP(c, radix_sort_pairs(c->dkey[0].as<uint32_t>(), c->dval[0].as<uint32_t>(), c->dkey[1].as<uint32_t>(),
                                c->dval[1].as<uint32_t>(), NV, 32, sc, &c->depth_in_b, s));
   }
@@ -332,7 +331,7 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
   }
   {
     Prof pr(c, GS_K_TILE_SORT, s);
-    SortScratch sc{c->hist.as<uint32_t>(), c->digit_tot.as<uint32_t>()};
+    SortScratch sc{c->hist.as<uint32_t>()};
     const int bits = ceil_log2((uint64_t)c->n_tiles) < 1 ? 1 : ceil_log2((uint64_t)c->n_tiles);
     GS_HIP(c, radix_sort_pairs(c->pkey[0].as<uint32_t>(), c->pval[0].as<uint32_t>(), c->pkey[1].as<uint32_t>(),
                                c->pval[1].as<uint32_t>(), K, bits, sc, &c->pairs_in_b, s));

@@ -103,8 +103,7 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_
 // radix sort of (uint32 key, uint32 value) pairs on bits [0, bits) of the key;
 // returns which buffer (0: *_a, 1: *_b) holds the result
 struct SortScratch {
-  uint32_t* hist;      // 256 * max_blocks
-  uint32_t* digit_tot; // 256
+  uint32_t* hist;      // sort_hist_words(n): block-major digit table, chunk sums, digit bases
 };
 constexpr int kSortTileItems = 4096;
 size_t sort_hist_words(size_t n);

@@ -76,63 +76,105 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
   __syncthreads();
   uint32_t t = 0;
   for (int i = 0; i < kWaves; ++i) t += hw[i][threadIdx.x];
-  hist[(size_t)threadIdx.x * n_blocks + blockIdx.x] = t;
+  hist[(size_t)blockIdx.x * kRadix + threadIdx.x] = t;
 }
 
-// digit_tot[d] = sum over blocks of hist[d][*]
-__global__ __launch_bounds__(kThreads) void k_radix_digit_totals(const uint32_t* __restrict__ hist, int n_blocks,
-                                                                  uint32_t* __restrict__ digit_tot) {
-  __shared__ uint32_t part[kWaves];
-  const uint32_t* row = hist + (size_t)blockIdx.x * n_blocks;
-  uint32_t s = 0;
-  for (int b = threadIdx.x; b < n_blocks; b += kThreads) s += row[b];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if (__lane_id() == 0) part[threadIdx.x / 64] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t t = 0;
-    for (int w = 0; w < kWaves; ++w) t += part[w];
-    digit_tot[blockIdx.x] = t;
-  }
+// The histogram table is block-major, hist[b * 256 + d].  Its scan, per digit d
+// the count of items with a smaller digit plus those of digit d in earlier blocks,
+// runs over chunks of kScanChunk blocks: column sums per chunk, one workgroup
+// scanning the chunk sums and the digit totals, and a per-chunk running sum.
+// Every pass reads rows of 256 counters (coalesced).
+constexpr int kScanChunk = 16;
+constexpr int kChunkScanThreads = 1024;                       // k_radix_chunk_scan: 4 threads per digit
+constexpr int kChunkParts = kChunkScanThreads / kRadix;
+
+__global__ __launch_bounds__(kRadix) void k_radix_chunk_sums(const uint32_t* __restrict__ hist, int n_blocks,
+                                                              uint32_t* __restrict__ chunk_sum) {
+  const int b0 = blockIdx.x * kScanChunk;
+  uint32_t x[kScanChunk];
+#pragma unroll
+  for (int k = 0; k < kScanChunk; ++k)   // all loads in flight before the sum
+    x[k] = b0 + k < n_blocks ? hist[(size_t)(b0 + k) * kRadix + threadIdx.x] : 0u;
+  uint32_t t = 0;
+#pragma unroll
+  for (int k = 0; k < kScanChunk; ++k) t += x[k];
+  chunk_sum[(size_t)blockIdx.x * kRadix + threadIdx.x] = t;
 }
 
-// In-place exclusive scan of row d of hist (over blocks), offset by the number of
-// items with a smaller digit.
-__global__ __launch_bounds__(kThreads) void k_radix_scan_rows(uint32_t* __restrict__ hist, int n_blocks,
-                                                               const uint32_t* __restrict__ digit_tot) {
-  __shared__ uint32_t wsum[kWaves];
-  __shared__ uint32_t carry;
-  const int d = blockIdx.x;
-  // base = sum of digit_tot[0..d)
-  uint32_t v = threadIdx.x < (unsigned)d ? digit_tot[threadIdx.x] : 0u;
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  if (__lane_id() == 0) wsum[threadIdx.x / 64] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t t = 0;
-    for (int w = 0; w < kWaves; ++w) t += wsum[w];
-    carry = t;
+// One workgroup, kChunkParts threads per digit d, each owning a contiguous part of
+// the chunks: exclusive prefix of the chunk sums over chunks (part sums combined
+// through LDS), then the exclusive scan of the digit totals over digits, stored in
+// digit_base.
+__global__ __launch_bounds__(kChunkScanThreads) void k_radix_chunk_scan(uint32_t* __restrict__ chunk_sum,
+                                                                         int n_chunks,
+                                                                         uint32_t* __restrict__ digit_base) {
+  __shared__ uint32_t part[kChunkParts][kRadix];
+  __shared__ uint32_t wsum[kRadix / 64];
+  const int d = threadIdx.x % kRadix, pi = threadIdx.x / kRadix;
+  const int per = (n_chunks + kChunkParts - 1) / kChunkParts;
+  const int c0 = pi * per, c1 = min(c0 + per, n_chunks);
+  uint32_t run = 0;
+  for (int c = c0; c < c1; c += 8) {   // eight loads in flight per step
+    uint32_t x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = c + k < c1 ? chunk_sum[(size_t)(c + k) * kRadix + d] : 0u;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) run += x[k];
   }
+  part[pi][d] = run;
   __syncthreads();
-  uint32_t* row = hist + (size_t)d * n_blocks;
-  for (int b0 = 0; b0 < n_blocks; b0 += kThreads) {
-    const int b = b0 + threadIdx.x;
-    const uint32_t x = b < n_blocks ? row[b] : 0u;
-    // inclusive wave scan
-    uint32_t incl = x;
+  uint32_t pre = 0, tot = 0;
+  for (int j = 0; j < kChunkParts; ++j) {
+    const uint32_t v = part[j][d];
+    pre += j < pi ? v : 0u;
+    tot += v;
+  }
+  run = pre;
+  for (int c = c0; c < c1; c += 8) {
+    uint32_t x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = c + k < c1 ? chunk_sum[(size_t)(c + k) * kRadix + d] : 0u;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (c + k < c1) chunk_sum[(size_t)(c + k) * kRadix + d] = run;
+      run += x[k];
+    }
+  }
+  if (pi == 0) {   // the first kRadix threads: exclusive scan of the digit totals
+    uint32_t incl = tot;
     for (int off = 1; off < 64; off <<= 1) {
       const uint32_t y = __shfl_up(incl, off);
       if ((int)__lane_id() >= off) incl += y;
     }
-    __syncthreads();
-    if (__lane_id() == 63) wsum[threadIdx.x / 64] = incl;
-    __syncthreads();
+    if (__lane_id() == 63) wsum[d / 64] = incl;
+  }
+  __syncthreads();
+  if (pi == 0) {
+    uint32_t incl = tot;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(incl, off);
+      if ((int)__lane_id() >= off) incl += y;
+    }
     uint32_t wpre = 0;
-    for (int w = 0; w < (int)(threadIdx.x / 64); ++w) wpre += wsum[w];
-    const uint32_t c = carry;
-    if (b < n_blocks) row[b] = c + wpre + incl - x;
-    __syncthreads();
-    if (threadIdx.x == kThreads - 1) carry = c + wpre + incl;
+    for (int w = 0; w < d / 64; ++w) wpre += wsum[w];
+    digit_base[d] = wpre + incl - tot;
+  }
+}
+
+// hist[b][d] <- start of block b's run of digit d in the pass's output.
+__global__ __launch_bounds__(kRadix) void k_radix_chunk_apply(uint32_t* __restrict__ hist, int n_blocks,
+                                                               const uint32_t* __restrict__ chunk_sum,
+                                                               const uint32_t* __restrict__ digit_base) {
+  const int b0 = blockIdx.x * kScanChunk;
+  uint32_t x[kScanChunk];
+#pragma unroll
+  for (int k = 0; k < kScanChunk; ++k)
+    x[k] = b0 + k < n_blocks ? hist[(size_t)(b0 + k) * kRadix + threadIdx.x] : 0u;
+  uint32_t run = digit_base[threadIdx.x] + chunk_sum[(size_t)blockIdx.x * kRadix + threadIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanChunk; ++k) {
+    if (b0 + k < n_blocks) hist[(size_t)(b0 + k) * kRadix + threadIdx.x] = run;
+    run += x[k];
   }
 }
 
@@ -155,7 +197,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
   const int tid = threadIdx.x;
   const int wave = tid / 64;
   for (int w = 0; w < kWaves; ++w) wc[w][tid] = 0;
-  goff[tid] = offsets[(size_t)tid * n_blocks + blockIdx.x];
+  goff[tid] = offsets[(size_t)blockIdx.x * kRadix + tid];
   __syncthreads();
 
   const size_t base = (size_t)blockIdx.x * kSortTileItems + (size_t)wave * (kItems * 64) + __lane_id();
@@ -580,21 +622,30 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
   }
 }
 
-// Tile boundaries in the sorted tile ids; each thread scans 8 consecutive ids.
+// Tile boundaries in the sorted tile ids: each thread takes 4 consecutive ids (one
+// 16-byte load) and the id before them.
 __global__ void k_ranges(const uint32_t* __restrict__ tile, size_t K, uint2* __restrict__ ranges, uint32_t n_tiles) {
-  const size_t i0 = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
+  const size_t i0 = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (i0 >= K) return;
+  uint32_t t[4];
+  if (i0 + 4 <= K) {
+    const uint4 v = *reinterpret_cast<const uint4*>(tile + i0);
+    t[0] = v.x; t[1] = v.y; t[2] = v.z; t[3] = v.w;
+  } else {
+    for (int k = 0; k < 4; ++k) t[k] = i0 + k < K ? tile[i0 + k] : 0xffffffffu;
+  }
   uint32_t prev = i0 == 0 ? 0xffffffffu : tile[i0 - 1];
-  const size_t i1 = i0 + 8 < K ? i0 + 8 : K;
-  for (size_t i = i0; i < i1; ++i) {
-    const uint32_t t = tile[i];
-    if (t != prev) {
-      if (t < n_tiles) ranges[t].x = (uint32_t)i;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const size_t i = i0 + k;
+    if (i >= K) break;
+    if (t[k] != prev) {
+      if (t[k] < n_tiles) ranges[t[k]].x = (uint32_t)i;
       if (prev < n_tiles) ranges[prev].y = (uint32_t)i;
     }
-    prev = t;
+    prev = t[k];
+    if (i + 1 == K && prev < n_tiles) ranges[prev].y = (uint32_t)K;
   }
-  if (i1 == K && prev < n_tiles) ranges[prev].y = (uint32_t)K;
 }
 
 // mode 0: keys + values, mode 1: views of the pairs
@@ -621,21 +672,27 @@ unsigned grid_for(size_t n, unsigned threads, unsigned cap = 1u << 20) {
 
 }  // namespace
 
-size_t sort_hist_words(size_t n) { return (size_t)kRadix * ((n + kSortTileItems - 1) / kSortTileItems + 1); }
+size_t sort_hist_words(size_t n) {
+  const size_t nb = (n + kSortTileItems - 1) / kSortTileItems;
+  return (size_t)kRadix * (nb + (nb + kScanChunk - 1) / kScanChunk + 1);   // table, chunk sums, digit bases
+}
 
 hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, size_t n,
                             int bits, SortScratch scratch, int* result_in_b, hipStream_t s) {
   *result_in_b = 0;
   if (n == 0 || bits <= 0) return hipSuccess;
   const int n_blocks = (int)((n + kSortTileItems - 1) / kSortTileItems);
+  const int n_chunks = (n_blocks + kScanChunk - 1) / kScanChunk;
+  uint32_t* chunk_sum = scratch.hist + (size_t)kRadix * n_blocks;
+  uint32_t* digit_base = chunk_sum + (size_t)kRadix * n_chunks;
   uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
   int in_b = 0;
   for (int shift = 0; shift < bits; shift += 8) {
     hipLaunchKernelGGL(k_radix_hist, dim3(n_blocks), dim3(kThreads), 0, s, ki, n, shift, scratch.hist, n_blocks);
-    hipLaunchKernelGGL(k_radix_digit_totals, dim3(kRadix), dim3(kThreads), 0, s, scratch.hist, n_blocks,
-                       scratch.digit_tot);
-    hipLaunchKernelGGL(k_radix_scan_rows, dim3(kRadix), dim3(kThreads), 0, s, scratch.hist, n_blocks,
-                       scratch.digit_tot);
+    hipLaunchKernelGGL(k_radix_chunk_sums, dim3(n_chunks), dim3(kRadix), 0, s, scratch.hist, n_blocks, chunk_sum);
+    hipLaunchKernelGGL(k_radix_chunk_scan, dim3(1), dim3(kChunkScanThreads), 0, s, chunk_sum, n_chunks, digit_base);
+    hipLaunchKernelGGL(k_radix_chunk_apply, dim3(n_chunks), dim3(kRadix), 0, s, scratch.hist, n_blocks, chunk_sum,
+                       digit_base);
     hipLaunchKernelGGL(k_radix_scatter, dim3(n_blocks), dim3(kThreads), 0, s, ki, vi, n, shift, scratch.hist,
                        n_blocks, ko, vo);
     uint32_t* t;
@@ -693,7 +750,7 @@ hipError_t launch_count_kept(const uint32_t* touched, const ushort4* rect, const
 hipError_t launch_ranges(const uint32_t* pair_tile, size_t K, uint2* ranges, int n_tiles, hipStream_t s) {
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, (size_t)n_tiles * 2, s);
   if (e != hipSuccess || K == 0) return e;
-  const unsigned blocks = (unsigned)((K + 8 * 256 - 1) / (8 * 256));
+  const unsigned blocks = (unsigned)((K + 4 * 256 - 1) / (4 * 256));
   hipLaunchKernelGGL(k_ranges, dim3(blocks), dim3(256), 0, s, pair_tile, K, ranges, (uint32_t)n_tiles);
   return hipGetLastError();
 }
