@@ -314,8 +314,12 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(const float* __restrict_
   float gSig[3][3] = {{0.f}};          // symmetric dL/dSigma accumulated over views
   float go = 0.f;                      // dL/dopacity
   float gf[3 * K];                     // dL/dSH
+  float f[3 * K];                      // SH coefficients, held across the views
 #pragma unroll
-  for (int i = 0; i < 3 * K; ++i) gf[i] = 0.f;
+  for (int i = 0; i < 3 * K; ++i) {
+    gf[i] = 0.f;
+    f[i] = P[(size_t)(11 + i) * stride + g];
+  }
 
   for (int v = 0; v < V; ++v) {
     const size_t idx = (size_t)v * n + g;
@@ -336,11 +340,6 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(const float* __restrict_
     const float d0 = G.m[0] - oc[0], d1 = G.m[1] - oc[1], d2 = G.m[2] - oc[2];
     const float dn = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
     const float dir[3] = {d0 / dn, d1 / dn, d2 / dn};
-    // SH coefficients are re-read per view (cache hits) instead of being held in
-    // registers across the loop; the empty asm keeps the compiler from hoisting
-    // the loads out of it
-    const float* fp = P + (size_t)11 * stride + g;
-    asm volatile("" : "+v"(fp));
     float Y[16];
     sh_eval<float>(D, dir[0], dir[1], dir[2], Y);
     float graw[3];
@@ -348,7 +347,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(const float* __restrict_
     for (int ch = 0; ch < 3; ++ch) {
       float acc = 0.5f;
 #pragma unroll
-      for (int k = 0; k < K; ++k) acc += fp[(size_t)(3 * k + ch) * stride] * Y[k];
+      for (int k = 0; k < K; ++k) acc += f[3 * k + ch] * Y[k];
       graw[ch] = acc < 0.0f ? 0.0f : grgb[ch];
     }
     float gY[16];
@@ -358,7 +357,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(const float* __restrict_
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
         gf[3 * k + ch] += graw[ch] * Y[k];
-        gY[k] += graw[ch] * fp[(size_t)(3 * k + ch) * stride];
+        gY[k] += graw[ch] * f[3 * k + ch];
       }
     }
     float gdir[3];
