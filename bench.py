@@ -1,8 +1,9 @@
 """Benchmark of the rasterizer training step on one MI355X.
 
 One step = the whole hot path over one batch of views, inputs resident in HBM:
-gs_preprocess -> gs_bin_sort -> gs_render_fwd -> gs_loss -> gs_render_bwd ->
-gs_adam_step.  Default workload: 1M Gaussians (SH degree 3) and 9 views (the
+gs_preprocess -> gs_bin_sort -> gs_render_fwd -> gs_loss -> gs_render_bwd_adam
+(the backward with the Adam step applied as each Gaussian's gradient is formed;
+the same bits as gs_render_bwd followed by gs_adam_step).  Default workload: 1M Gaussians (SH degree 3) and 9 views (the
 newest pose of a seeded random-walk camera path plus its 8 neighbours by frustum
 overlap) at 3x 1600x1067, 3x 1296x864, 3x 979x546, loss 0.8 L1 + 0.2 D-SSIM,
 per-view learning rates from Eq. 6-7.  Prints one JSON line (rank 0).
@@ -58,6 +59,8 @@ def algorithmic_bytes(n, n_p, V, K, P, tiles, ssim):
         "render_bwd": 52 * K + 24 * P,
         "preprocess_bwd": 36 * V * n + 8 * n_p * n,
         "adam": 28 * n_p * n + 8 * n,
+        # grad2d and visibility per (view, Gaussian); params, m, v read and written; step
+        "preprocess_bwd_adam": 40 * V * n + 24 * n_p * n + 8 * n,
     }
 
 
@@ -84,7 +87,8 @@ def raster_flops(visits, blends):
 
 KERNEL_SOURCE = {"render_fwd": "k_raster.hip", "render_bwd": "k_raster.hip", "preprocess": "k_preprocess.hip",
                  "preprocess_bwd": "k_preprocess.hip", "tile_sort": "k_sort.hip", "depth_sort": "k_sort.hip",
-                 "emit": "k_sort.hip", "loss": "k_loss.hip", "adam": "k_adam.hip"}
+                 "emit": "k_sort.hip", "loss": "k_loss.hip", "adam": "k_adam.hip",
+                 "preprocess_bwd_adam": "k_preprocess.hip"}
 
 
 def traffic_for(kernel, workload):
@@ -245,8 +249,7 @@ def main():
         rz.bin_sort()
         rz.render_fwd(color)
         rz.loss(color, target, sc.w_l1, sc.w_dssim, loss, dl)
-        rz.render_bwd(dl, grad)
-        rz.adam_step(grad, m, v, step, DEFAULT_LR, scales, group_mask=1)
+        rz.render_bwd_adam(dl, m, v, step, DEFAULT_LR, scales, group_mask=1)
 
     for _ in range(args.warmup):
         one_step()
@@ -271,7 +274,7 @@ def main():
     kern_launches = {k: cnt for k, (cnt, ms) in prof.items()}
     fwd_bwd_ms = sum(kern_ms[k] * kern_launches[k] / args.steps for k in
                      ["preprocess", "depth_sort", "scan", "emit", "tile_sort", "ranges", "render_fwd", "loss", "zero",
-                      "render_bwd", "preprocess_bwd"])
+                      "render_bwd", "preprocess_bwd_adam"])
 
     # per-pixel work the method needs: list positions up to each pixel's last blended
     # Gaussian (each takes the cutoff test) and the Gaussians it blended
@@ -310,7 +313,7 @@ def main():
     n_tiles = rz.tile_off[-1]
     algo = algorithmic_bytes(n, n_p, V, K_valid, P, n_tiles, sc.w_dssim != 0)
     # dominant kernel and its roofline
-    dom = max(["render_fwd", "render_bwd", "preprocess", "tile_sort", "depth_sort", "preprocess_bwd", "adam", "loss",
+    dom = max(["render_fwd", "render_bwd", "preprocess", "tile_sort", "depth_sort", "preprocess_bwd_adam", "loss",
                "emit"], key=lambda k: kern_ms[k] * kern_launches[k])
     if dom in ("render_bwd", "render_fwd"):
         flops = raster_flops(visits, blends)[dom]
@@ -339,7 +342,8 @@ def main():
         best = min(best, e0.elapsed_time(e1))
     copy_gbs = 2 * src.numel() * 4 / (best * 1e-3) / 1e9
     del src, dst
-    fb_stages = ["preprocess", "scan_emit", "tile_sort", "ranges", "render_fwd", "loss", "render_bwd", "preprocess_bwd"]
+    fb_stages = ["preprocess", "scan_emit", "tile_sort", "ranges", "render_fwd", "loss", "render_bwd",
+                 "preprocess_bwd_adam"]
     fb_gbs = sum(algo[k] for k in fb_stages) / (fwd_bwd_ms * 1e-3) / 1e9
 
     mpix = P / (t_step) / 1e6

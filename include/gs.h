@@ -96,7 +96,8 @@ enum {
 enum {
   GS_K_PREPROCESS = 0, GS_K_DEPTH_SORT = 1, GS_K_SCAN = 2, GS_K_EMIT = 3, GS_K_TILE_SORT = 4,
   GS_K_RANGES = 5, GS_K_RENDER_FWD = 6, GS_K_LOSS = 7, GS_K_RENDER_BWD = 8,
-  GS_K_PREPROCESS_BWD = 9, GS_K_ADAM = 10, GS_K_ZERO = 11, GS_K_LOAD = 12, GS_N_KERNELS = 13
+  GS_K_PREPROCESS_BWD = 9, GS_K_ADAM = 10, GS_K_ZERO = 11, GS_K_LOAD = 12, GS_K_BWD_ADAM = 13,
+  GS_N_KERNELS = 14
 };
 
 int32_t gs_abi_version(void);
@@ -191,6 +192,22 @@ gs_status gs_adam_step(gs_ctx* ctx, float* params, const float* grad, float* m, 
                        int32_t n, int32_t stride, int32_t sh_degree, const float* lr_group,
                        const float* view_lr_scale, int32_t n_views, uint32_t group_mask, float beta1,
                        float beta2, float eps, gs_stream stream);
+
+/* One training step's backward and optimizer step in one pass (Sec. IV-E backward,
+ * Sec. IV-D / V-A Adam): the same arithmetic as gs_render_bwd(ctx, params,
+ * dL_dcolor, grad, 0) followed by gs_adam_step(ctx, params, grad, m, v, step, n,
+ * stride, sh_degree, ...) with the n, stride and sh_degree of the last
+ * gs_preprocess, but the parameter gradient of each Gaussian is applied as soon as
+ * it is formed instead of going through memory.  (The backward's 2D gradients are
+ * summed with floating-point atomics across tiles, whose order is not fixed, so
+ * repeated backward passes, fused or not, agree to rounding, not bit for bit.)  grad: device, parameter
+ * layout, receives the gradient when not NULL (may be NULL).  params is updated
+ * in place; it must be the array the last gs_preprocess read.  Other arguments and
+ * errors as for gs_render_bwd and gs_adam_step (n_views > 0 with view_lr_scale
+ * needs n_views equal to the last gs_preprocess's). */
+gs_status gs_render_bwd_adam(gs_ctx* ctx, float* params, const float* dL_dcolor, float* grad, float* m, float* v,
+                             uint32_t* step, const float* lr_group, const float* view_lr_scale, int32_t n_views,
+                             uint32_t group_mask, float beta1, float beta2, float eps, gs_stream stream);
 
 /* Pair culling of gs_bin_sort.  GS_CULL_RECT lists every tile of a Gaussian's tile
  * rect.  GS_CULL_ELLIPSE (the default) lists a tile only if the Gaussian's cutoff

@@ -24,16 +24,17 @@ GS_N_GROUPS = 6
 (GS_BUF_RECORDS, GS_BUF_DEPTH, GS_BUF_TOUCHED, GS_BUF_TILE_RECT, GS_BUF_KEYS, GS_BUF_VALUES, GS_BUF_RANGES,
  GS_BUF_T_FINAL, GS_BUF_N_CONTRIB, GS_BUF_LAST, GS_BUF_GRAD2D, GS_BUF_PAIR_VIEW, GS_BUF_ALPHA_SUM) = range(13)
 (GS_K_PREPROCESS, GS_K_DEPTH_SORT, GS_K_SCAN, GS_K_EMIT, GS_K_TILE_SORT, GS_K_RANGES, GS_K_RENDER_FWD, GS_K_LOSS,
- GS_K_RENDER_BWD, GS_K_PREPROCESS_BWD, GS_K_ADAM, GS_K_ZERO, GS_K_LOAD) = range(13)
+ GS_K_RENDER_BWD, GS_K_PREPROCESS_BWD, GS_K_ADAM, GS_K_ZERO, GS_K_LOAD, GS_K_BWD_ADAM) = range(14)
 KERNEL_NAMES = ["preprocess", "depth_sort", "scan", "emit", "tile_sort", "ranges", "render_fwd", "loss",
-                "render_bwd", "preprocess_bwd", "adam", "zero", "load"]
+                "render_bwd", "preprocess_bwd", "adam", "zero", "load", "preprocess_bwd_adam"]
 
 _STATUS = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_CAPACITY", -3: "GS_ERR_HIP", -4: "GS_ERR_UNSUPPORTED",
            -5: "GS_ERR_STATE"}
 
 # Exported symbols (must match include/gs.h).
 EXPORTS = ["gs_abi_version", "gs_create", "gs_destroy", "gs_last_error", "gs_layout", "gs_preprocess", "gs_bin_sort",
-           "gs_render_fwd", "gs_loss", "gs_load_balance", "gs_render_bwd", "gs_adam_step", "gs_set_cull", "gs_buffer_size",
+           "gs_render_fwd", "gs_loss", "gs_load_balance", "gs_render_bwd", "gs_adam_step", "gs_render_bwd_adam",
+           "gs_set_cull", "gs_buffer_size",
            "gs_copy_buffer", "gs_profile_enable", "gs_profile_read", "gs_memory_bytes", "gs_sched_weights",
            "gs_sched_plan", "gs_sched_lr"]
 GS_CULL_RECT, GS_CULL_ELLIPSE = 0, 1
@@ -83,6 +84,9 @@ def _load():
         "gs_adam_step": (_I32, [_P, _P, _P, _P, _P, _P, _I32, _I32, _I32, ctypes.POINTER(ctypes.c_float),
                                 ctypes.POINTER(ctypes.c_float), _I32, ctypes.c_uint32, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float, _P]),
+        "gs_render_bwd_adam": (_I32, [_P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_float),
+                                      ctypes.POINTER(ctypes.c_float), _I32, ctypes.c_uint32, ctypes.c_float,
+                                      ctypes.c_float, ctypes.c_float, _P]),
         "gs_set_cull": (_I32, [_P, _I32]),
         "gs_buffer_size": (_I32, [_P, _I32, ctypes.POINTER(ctypes.c_size_t)]),
         "gs_copy_buffer": (_I32, [_P, _I32, _P, ctypes.c_size_t, _P]),
@@ -214,6 +218,21 @@ def gs_adam_step(ctx, params, grad, m, v, step, n: int, stride: int, sh_degree: 
     _check(ctx, _load().gs_adam_step(ctx, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), _ptr(step), n, stride,
                                      sh_degree, lg, vs, nv, group_mask, beta1, beta2, eps, _stream(stream)),
            "gs_adam_step")
+
+
+def gs_render_bwd_adam(ctx, params, dL_dcolor, grad, m, v, step, lr_group: Sequence[float],
+                       view_lr_scale: Optional[Sequence[float]] = None, group_mask: int = 1, beta1: float = 0.9,
+                       beta2: float = 0.999, eps: float = 1e-15, stream=None) -> None:
+    """gs_render_bwd (overwrite) + gs_adam_step in one pass; grad may be None."""
+    lg = (ctypes.c_float * GS_N_GROUPS)(*[float(x) for x in lr_group])
+    if view_lr_scale is not None and len(view_lr_scale) > 0:
+        vs = (ctypes.c_float * len(view_lr_scale))(*[float(x) for x in view_lr_scale])
+        nv = len(view_lr_scale)
+    else:
+        vs, nv = None, 0
+    _check(ctx, _load().gs_render_bwd_adam(ctx, _ptr(params), _ptr(dL_dcolor), _ptr(grad), _ptr(m), _ptr(v),
+                                           _ptr(step), lg, vs, nv, group_mask, beta1, beta2, eps, _stream(stream)),
+           "gs_render_bwd_adam")
 
 
 def gs_set_cull(ctx, mode: int) -> None:

@@ -444,21 +444,14 @@ gs_status gs_render_bwd(gs_ctx* c, const float* params, const float* dL_dcolor, 
   return GS_OK;
 }
 
-gs_status gs_adam_step(gs_ctx* c, float* params, const float* grad, float* m, float* v, uint32_t* step, int32_t n,
-                       int32_t stride, int32_t sh_degree, const float* lr_group, const float* view_lr_scale,
-                       int32_t n_views, uint32_t group_mask, float beta1, float beta2, float eps, gs_stream stream) {
-  if (!c) return GS_ERR_INVALID;
-  c->err.clear();
-  if (!params || !grad || !m || !v || !step || !lr_group)
-    return fail(c, GS_ERR_INVALID, "params, grad, m, v, step and lr_group must be non-NULL");
-  if (!aligned(params, 4) || !aligned(grad, 4) || !aligned(m, 4) || !aligned(v, 4) || !aligned(step, 4))
-    return fail(c, GS_ERR_INVALID, "misaligned device pointer");
-  if (n < 1 || stride < n) return fail(c, GS_ERR_INVALID, "need n >= 1 and stride >= n");
-  if (sh_degree < 0 || sh_degree > GS_MAX_SH_DEGREE) return fail(c, GS_ERR_INVALID, "sh_degree must be 0..3");
+// Checks and packs the Adam arguments shared by gs_adam_step and gs_render_bwd_adam.
+gs_status adam_args(gs_ctx* c, int32_t n, const float* lr_group, const float* view_lr_scale, int32_t n_views,
+                    uint32_t group_mask, float beta1, float beta2, float eps, AdamArgs& a) {
+  if (!lr_group) return fail(c, GS_ERR_INVALID, "lr_group must be non-NULL");
   if (n_views < 0 || n_views > GS_MAX_VIEWS) return fail(c, GS_ERR_INVALID, "n_views must be in 0..64");
   if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps >= 0.0f && std::isfinite(eps)))
     return fail(c, GS_ERR_INVALID, "need 0 <= beta < 1 and finite eps >= 0");
-  AdamArgs a{};
+  a = AdamArgs{};
   for (int i = 0; i < GS_N_GROUPS; ++i) {
     if (!std::isfinite(lr_group[i])) return fail(c, GS_ERR_INVALID, "non-finite learning rate");
     a.lr[i] = lr_group[i];
@@ -475,11 +468,66 @@ gs_status gs_adam_step(gs_ctx* c, float* params, const float* grad, float* m, fl
   }
   a.group_mask = group_mask;
   a.b1 = beta1; a.b2 = beta2; a.eps = eps;
+  return GS_OK;
+}
+
+gs_status gs_adam_step(gs_ctx* c, float* params, const float* grad, float* m, float* v, uint32_t* step, int32_t n,
+                       int32_t stride, int32_t sh_degree, const float* lr_group, const float* view_lr_scale,
+                       int32_t n_views, uint32_t group_mask, float beta1, float beta2, float eps, gs_stream stream) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (!params || !grad || !m || !v || !step || !lr_group)
+    return fail(c, GS_ERR_INVALID, "params, grad, m, v, step and lr_group must be non-NULL");
+  if (!aligned(params, 4) || !aligned(grad, 4) || !aligned(m, 4) || !aligned(v, 4) || !aligned(step, 4))
+    return fail(c, GS_ERR_INVALID, "misaligned device pointer");
+  if (n < 1 || stride < n) return fail(c, GS_ERR_INVALID, "need n >= 1 and stride >= n");
+  if (sh_degree < 0 || sh_degree > GS_MAX_SH_DEGREE) return fail(c, GS_ERR_INVALID, "sh_degree must be 0..3");
+  AdamArgs a;
+  gs_status st;
+  if ((st = adam_args(c, n, lr_group, view_lr_scale, n_views, group_mask, beta1, beta2, eps, a)) != GS_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   GS_HIP(c, hipSetDevice(c->device));
   Prof pr(c, GS_K_ADAM, s);
   GS_HIP(c, launch_adam(params, grad, m, v, step, n, stride, sh_degree, a,
                         a.n_views ? c->touched.as<uint32_t>() : nullptr, s));
+  return GS_OK;
+}
+
+gs_status gs_render_bwd_adam(gs_ctx* c, float* params, const float* dL_dcolor, float* grad, float* m, float* v,
+                             uint32_t* step, const float* lr_group, const float* view_lr_scale, int32_t n_views,
+                             uint32_t group_mask, float beta1, float beta2, float eps, gs_stream stream) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (c->stage < kRendered) return fail(c, GS_ERR_STATE, "gs_render_bwd_adam needs a preceding gs_render_fwd");
+  if (!params || !dL_dcolor || !m || !v || !step || !lr_group)
+    return fail(c, GS_ERR_INVALID, "params, dL_dcolor, m, v, step and lr_group must be non-NULL");
+  if (!aligned(params, 4) || !aligned(dL_dcolor, 4) || !aligned(m, 4) || !aligned(v, 4) || !aligned(step, 4) ||
+      !aligned(grad, 4))
+    return fail(c, GS_ERR_INVALID, "misaligned device pointer");
+  AdamArgs a;
+  gs_status st;
+  if ((st = adam_args(c, c->n, lr_group, view_lr_scale, n_views, group_mask, beta1, beta2, eps, a)) != GS_OK)
+    return st;
+  hipStream_t s = (hipStream_t)stream;
+  GS_HIP(c, hipSetDevice(c->device));
+  const size_t NV = (size_t)c->V * c->n;
+  if ((st = ensure(c, c->grad2d, NV * kGrad2D * 4, s)) != GS_OK) return st;
+  {
+    Prof pr(c, GS_K_ZERO, s);
+    GS_HIP(c, launch_fill_u32(c->grad2d.as<uint32_t>(), 0u, NV * kGrad2D, s));
+  }
+  {
+    Prof pr(c, GS_K_RENDER_BWD, s);
+    GS_HIP(c, launch_render_bwd(c->views.as<ViewDev>(), c->V, c->n_tiles, c->ranges.as<uint2>(),
+                                c->pval[c->pairs_in_b].as<uint32_t>(), c->rec.as<Record>(), (uint32_t)NV,
+                                c->tfinal.as<float>(), c->last.as<uint32_t>(), dL_dcolor,
+                                c->load_pending ? c->dG.as<float>() : nullptr, c->grad2d.as<float>(), c->tile, s));
+  }
+  {
+    Prof pr(c, GS_K_BWD_ADAM, s);
+    GS_HIP(c, launch_preprocess_bwd_adam(params, c->n, c->stride, c->D, c->views.as<ViewDev>(), c->V,
+                                         c->touched.as<uint32_t>(), c->grad2d.as<float>(), grad, m, v, step, a, s));
+  }
   return GS_OK;
 }
 

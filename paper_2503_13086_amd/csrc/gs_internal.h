@@ -180,4 +180,54 @@ struct AdamArgs {
 hipError_t launch_adam(float* P, const float* G, float* M, float* Vv, uint32_t* step, int n, int stride, int D,
                        const AdamArgs& a, const uint32_t* touched, hipStream_t s);
 
+// ---- Adam pieces shared by the Adam kernel and the fused backward + Adam, so
+// that both produce the same bits ----
+__device__ inline int adam_row_group(int r) {
+  if (r < 3) return GS_GROUP_MEAN;
+  if (r < 6) return GS_GROUP_SCALE;
+  if (r < 10) return GS_GROUP_ROT;
+  if (r == 10) return GS_GROUP_OPACITY;
+  if (r < 14) return GS_GROUP_SH_DC;
+  return GS_GROUP_SH_REST;
+}
+
+// Mean of the view scales over the views that see Gaussian g (touched > 0), over
+// all views when none does; 1 without view scales.
+__device__ inline float adam_view_factor(const AdamArgs& a, const uint32_t* touched, int n, int g) {
+  if (a.n_views <= 0) return 1.0f;
+  float s = 0.0f, all = 0.0f;
+  int c = 0;
+  for (int v = 0; v < a.n_views; ++v) {
+    all += a.scale[v];
+    if (touched[(size_t)v * n + g] != 0u) {
+      s += a.scale[v];
+      ++c;
+    }
+  }
+  return c > 0 ? s / (float)c : all / (float)a.n_views;
+}
+
+// Bias corrections 1 - b^k for step k (k = the element's updated step counter).
+__device__ inline void adam_bias(const AdamArgs& a, uint32_t k, float& bc1, float& bc2) {
+  bc1 = (float)(1.0 - pow((double)a.b1, (double)k));
+  bc2 = (float)(1.0 - pow((double)a.b2, (double)k));
+}
+
+// One element: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+// p -= lr (m / bc1) / (sqrt(v / bc2) + eps).
+__device__ inline void adam_elem(float& p, float& m, float& v, float g, float lr, const AdamArgs& a, float bc1,
+                                 float bc2) {
+#pragma clang fp contract(off)
+  const float ob1 = 1.0f - a.b1, ob2 = 1.0f - a.b2;
+  m = a.b1 * m + ob1 * g;
+  v = a.b2 * v + ob2 * g * g;
+  p = p - lr * (m / bc1) / (sqrtf(v / bc2) + a.eps);
+}
+
+// Backward preprocess fused with the Adam step: the parameter gradient of each
+// Gaussian is applied as soon as it is formed (grad written too when not NULL).
+hipError_t launch_preprocess_bwd_adam(float* P, int n, int stride, int D, const ViewDev* views, int V,
+                                      const uint32_t* touched, const float* grad2d, float* grad, float* M, float* Vv,
+                                      uint32_t* step, const AdamArgs& a, hipStream_t s);
+
 }  // namespace gsk

@@ -297,12 +297,18 @@ __device__ inline void gauss_geom_f(const float* __restrict__ P, int stride, int
     for (int l = 0; l < 3; ++l) G.Sig[k][l] = M[k][0] * M[l][0] + M[k][1] * M[l][1] + M[k][2] * M[l][2];
 }
 
+// With adam != 0 the gradient is applied at once (params updated in place, `out`
+// written only when not NULL); otherwise it goes to `out` (or is added to it).
+// One kernel serves both so that the gradient is the same machine arithmetic
+// either way.  The parameters are read before this thread writes any of them,
+// and a thread touches only its own Gaussian's column.
 template <int D>
-__global__ __launch_bounds__(256) void k_preprocess_bwd(const float* __restrict__ P, int n, int stride,
+__global__ __launch_bounds__(256) void k_preprocess_bwd(float* P, int n, int stride,
                                                          const ViewDev* __restrict__ views, int V,
                                                          const uint32_t* __restrict__ touched,
-                                                         const float* __restrict__ grad2d, float* __restrict__ out,
-                                                         int accumulate) {
+                                                         const float* __restrict__ grad2d, float* out,
+                                                         int accumulate, int adam, float* M, float* Vv,
+                                                         uint32_t* step, AdamArgs a) {
 #pragma clang fp contract(fast)
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
@@ -471,6 +477,46 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(const float* __restrict_
   for (int k = 0; k < 3; ++k) outv[3 + k] = gs[k] * H.s[k];
   for (int k = 0; k < 4; ++k) outv[6 + k] = (gq[k] - H.q[k] * qd) / H.qn;
   outv[10] = (double)go * H.o * (1.0 - H.o);
+  if (adam) {
+    const uint32_t k = step[g] + 1u;
+    step[g] = k;
+    float bc1, bc2;
+    adam_bias(a, k, bc1, bc2);
+    const float factor = adam_view_factor(a, touched, n, g);
+    constexpr int ROWS = 11 + 3 * K, B = 8;
+    float grv[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) grv[r] = r < 11 ? (float)outv[r] : gf[r - 11];
+    // rows in groups of B: all loads of a group issued before its stores
+#pragma unroll
+    for (int r0 = 0; r0 < ROWS; r0 += B) {
+      float pp[B], mm[B], vv[B];
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        if (r0 + j < ROWS) {
+          const size_t i = (size_t)(r0 + j) * stride + g;
+          pp[j] = P[i];
+          mm[j] = M[i];
+          vv[j] = Vv[i];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const int r = r0 + j;
+        if (r < ROWS) {
+          const int grp = adam_row_group(r);
+          const float lr = ((a.group_mask >> grp) & 1u) ? a.lr[grp] * factor : a.lr[grp];
+          adam_elem(pp[j], mm[j], vv[j], grv[r], lr, a, bc1, bc2);
+          const size_t i = (size_t)r * stride + g;
+          if (out) out[i] = grv[r];
+          P[i] = pp[j];
+          M[i] = mm[j];
+          Vv[i] = vv[j];
+        }
+      }
+    }
+    return;
+  }
   for (int r = 0; r < 11; ++r) {
     float* dst = out + (size_t)r * stride + g;
     *dst = accumulate ? *dst + (float)outv[r] : (float)outv[r];
@@ -501,17 +547,31 @@ hipError_t launch_preprocess(const float* P, int n, int stride, int D, const Vie
   return hipGetLastError();
 }
 
+hipError_t launch_bwd(float* P, int n, int stride, int D, const ViewDev* views, int V, const uint32_t* touched,
+                      const float* grad2d, float* grad, int accumulate, int adam, float* M, float* Vv, uint32_t* step,
+                      const AdamArgs& a, hipStream_t s) {
+  const int blocks = (n + 255) / 256;
+  switch (D) {
+    case 0: hipLaunchKernelGGL(k_preprocess_bwd<0>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, touched, grad2d, grad, accumulate, adam, M, Vv, step, a); break;
+    case 1: hipLaunchKernelGGL(k_preprocess_bwd<1>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, touched, grad2d, grad, accumulate, adam, M, Vv, step, a); break;
+    case 2: hipLaunchKernelGGL(k_preprocess_bwd<2>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, touched, grad2d, grad, accumulate, adam, M, Vv, step, a); break;
+    default: hipLaunchKernelGGL(k_preprocess_bwd<3>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, touched, grad2d, grad, accumulate, adam, M, Vv, step, a); break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_preprocess_bwd(const float* P, int n, int stride, int D, const ViewDev* views, int V,
                                  const uint32_t* touched, const float* grad2d, float* grad, int accumulate,
                                  hipStream_t s) {
-  const int blocks = (n + 255) / 256;
-  switch (D) {
-    case 0: hipLaunchKernelGGL(k_preprocess_bwd<0>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, touched, grad2d, grad, accumulate); break;
-    case 1: hipLaunchKernelGGL(k_preprocess_bwd<1>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, touched, grad2d, grad, accumulate); break;
-    case 2: hipLaunchKernelGGL(k_preprocess_bwd<2>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, touched, grad2d, grad, accumulate); break;
-    default: hipLaunchKernelGGL(k_preprocess_bwd<3>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, touched, grad2d, grad, accumulate); break;
-  }
-  return hipGetLastError();
+  // the plain backward reads the parameters only
+  return launch_bwd(const_cast<float*>(P), n, stride, D, views, V, touched, grad2d, grad, accumulate, 0, nullptr,
+                    nullptr, nullptr, AdamArgs{}, s);
+}
+
+hipError_t launch_preprocess_bwd_adam(float* P, int n, int stride, int D, const ViewDev* views, int V,
+                                      const uint32_t* touched, const float* grad2d, float* grad, float* M, float* Vv,
+                                      uint32_t* step, const AdamArgs& a, hipStream_t s) {
+  return launch_bwd(P, n, stride, D, views, V, touched, grad2d, grad, 0, 1, M, Vv, step, a, s);
 }
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s) {

@@ -12,7 +12,8 @@ import numpy as np
 import torch
 
 from . import (gs_memory_bytes, gs_load_balance, gs_create, gs_destroy, gs_layout, gs_preprocess, gs_bin_sort, gs_render_fwd, gs_loss,
-               gs_render_bwd, gs_adam_step, gs_buffer_size, gs_copy_buffer, gs_profile_enable, gs_profile_read,
+               gs_render_bwd, gs_adam_step, gs_render_bwd_adam, gs_buffer_size, gs_copy_buffer, gs_profile_enable,
+               gs_profile_read,
                KERNEL_NAMES, GS_BUF_RECORDS, GS_BUF_DEPTH, GS_BUF_TOUCHED, GS_BUF_TILE_RECT, GS_BUF_KEYS,
                GS_BUF_VALUES, GS_BUF_RANGES, GS_BUF_T_FINAL, GS_BUF_N_CONTRIB, GS_BUF_LAST, GS_BUF_GRAD2D,
                GS_BUF_PAIR_VIEW, GS_BUF_ALPHA_SUM)
@@ -121,6 +122,13 @@ class Rasterizer:
                   beta2=0.999, eps=1e-15, stream=None):
         gs_adam_step(self.ctx, self.params, grad, m, v, step, self.n, self.stride, self.sh_degree, lr_group,
                      view_lr_scale, group_mask, beta1, beta2, eps, stream)
+
+    def render_bwd_adam(self, dL_dcolor, m, v, step, lr_group=DEFAULT_LR, view_lr_scale=None, group_mask=1,
+                        grad: Optional[torch.Tensor] = None, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+        """render_bwd + adam_step in one pass (the parameters of the last preprocess
+        are updated in place); the gradient is written to `grad` when given."""
+        gs_render_bwd_adam(self.ctx, self.params, dL_dcolor, grad, m, v, step, lr_group, view_lr_scale, group_mask,
+                           beta1, beta2, eps, stream)
 
     # ---- inspection ----
     def buffer(self, which: int, stream=None) -> torch.Tensor:

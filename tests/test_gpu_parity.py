@@ -201,6 +201,63 @@ def test_adam_parity():
     assert np.all(np.abs(dp - dp_ref) <= 1e-4 * np.abs(dp_ref) + 2 * np.spacing(np.abs(P[:, :n]).astype(np.float32)))
 
 
+@pytest.mark.parametrize("with_grad", [True, False])
+def test_fused_backward_adam_matches_separate_calls(with_grad):
+    """gs_render_bwd_adam = gs_render_bwd + gs_adam_step (parameters, moments, step
+    counters and, when asked for, the gradient), with per-view rates and a stride
+    past n whose padding columns stay untouched.  The backward sums 2D gradients
+    with float atomics across tiles in no fixed order, so two backward passes agree
+    to rounding: the bound is a few ulp of each quantity's scale."""
+    from paper_2503_13086_amd.pipeline import Rasterizer, DEFAULT_LR
+    sc = scenegen.small_scene(13, 900, 3, [(48, 40), (64, 24), (30, 50)], log_scale_mean=-2.5, w_l1=0.8,
+                              w_dssim=0.2)
+    stride = 1024
+    rng = np.random.default_rng(17)
+    P = np.zeros((sc.params.shape[0], stride), np.float32)
+    P[:, :sc.n] = sc.params
+    P[:, sc.n:] = rng.normal(0, 1, size=(P.shape[0], stride - sc.n))
+    M = rng.normal(0, 1e-3, size=P.shape).astype(np.float32)
+    Vv = np.abs(rng.normal(0, 1e-6, size=P.shape)).astype(np.float32)
+    step = rng.integers(0, 50, size=stride).astype(np.int32)
+    up = scenegen.upstream_grads(3, sc.cams, 1e-2)
+    scale = [1.0, 0.4, 0.07]
+    out = {}
+    rz = Rasterizer(0)
+    try:
+        for mode in ("separate", "fused"):
+            dev = lambda a: torch.as_tensor(a.copy()).cuda()
+            tP, tM, tV, tS = dev(P), dev(M), dev(Vv), dev(step)
+            rz.preprocess(tP, sc.n, 3, sc.cams)
+            rz.bin_sort()
+            rz.render_fwd()
+            grad = torch.full_like(tP, 7.0)
+            if mode == "separate":
+                rz.render_bwd(rz.pack_images(up), grad)
+                rz.adam_step(grad, tM, tV, tS, DEFAULT_LR, scale, group_mask=0b101)
+            else:
+                rz.render_bwd_adam(rz.pack_images(up), tM, tV, tS, DEFAULT_LR, scale, group_mask=0b101,
+                                   grad=grad if with_grad else None)
+            out[mode] = [t.cpu().numpy().astype(np.float64) for t in (tP, tM, tV)] + \
+                [tS.cpu().numpy(), grad.cpu().numpy().astype(np.float64)]
+    finally:
+        rz.close()
+    a, b = out["separate"], out["fused"]
+    n = sc.n
+    assert np.array_equal(a[3], b[3]) and np.array_equal(b[3][:n], step[:n] + 1)
+    assert np.array_equal(b[0][:, n:], P[:, n:]) and np.array_equal(b[1][:, n:], M[:, n:])
+    g = a[4][:, :n]
+    if with_grad:
+        assert np.abs(b[4][:, :n] - g).max() <= 1e-5 * np.abs(g).max()
+    else:
+        assert (b[4] == 7.0).all()
+    # a gradient difference dg moves m by (1 - b1) dg and v by (1 - b2) 2 g dg
+    assert np.abs(b[1] - a[1]).max() <= 1e-5 * np.abs(a[1]).max()
+    assert np.abs(b[2] - a[2]).max() <= 1e-5 * np.abs(a[2]).max()
+    dp = a[0][:, :n] - P[:, :n]
+    assert np.abs(dp).max() > 0
+    assert np.all(np.abs(b[0][:, :n] - a[0][:, :n]) <= 1e-3 * np.abs(dp) + 2 * np.spacing(np.abs(P[:, :n])))
+
+
 def test_end_to_end_c1_l1():
     """C1 step: render, L1 loss against the target, backward; the GPU upstream
     gradient comes from its own loss kernel, the oracle's from its own image."""
