@@ -35,8 +35,9 @@ def _run(cmd):
 
 
 # Per-source flags.  The raster kernels' LDS and global atomics take per-lane
-# addresses by design; the compiler's wave-level atomic combining would turn the
-# one uniform-address LDS add of the backward's reduction into a read-lane loop.
+# addresses by design; the compiler's wave-level atomic combining (which funnels an
+# atomic through a read-lane loop when it can prove the address uniform) has
+# nothing to gain there and is switched off for that file.
 EXTRA = {"k_raster.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
 
 
