@@ -260,12 +260,14 @@ class Engine:
             load = self._load[: len(views)]
             rz.load_balance(self.w_load, load)
             loss = loss + load
-        rz.render_bwd(dl, fld.grad)
         out = None
         if record:
+            rz.render_bwd(dl, fld.grad)
             out = {"views": views, "color": [x.clone() for x in rz.image_views(color)], "loss": loss.clone(),
                    "grad": fld.grad[:, : fld.n].clone(), "pairs": K}
-        rz.adam_step(fld.grad, fld.m, fld.v, fld.step, self.lr_group, scales, self.group_mask)
+            rz.adam_step(fld.grad, fld.m, fld.v, fld.step, self.lr_group, scales, self.group_mask)
+        else:   # the same update with the gradient applied as it is formed
+            rz.render_bwd_adam(dl, fld.m, fld.v, fld.step, self.lr_group, scales, self.group_mask)
         for j, v in zip(jobs, views):
             self.trained[v] += 1
             j.next += 1

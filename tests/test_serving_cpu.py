@@ -44,6 +44,9 @@ class FakeRasterizer:
     def adam_step(self, grad, m, v, step, lr_group, view_lr_scale=None, group_mask=1, **kw):
         self.calls.append(("adam", list(view_lr_scale), [id(c) for c in self.cams]))
 
+    def render_bwd_adam(self, dL_dcolor, m, v, step, lr_group, view_lr_scale=None, group_mask=1, **kw):
+        self.calls.append(("adam", list(view_lr_scale), [id(c) for c in self.cams]))
+
     def image_views(self, flat):
         out, a = [], 0
         for c in self.cams:
