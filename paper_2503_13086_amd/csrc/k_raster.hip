@@ -190,12 +190,13 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict_
             const bool stop = pass && Tn < kTMin;
             const bool blend = pass && !stop;
             pmax = stop ? -INFINITY : pmax;
-            const float wgt = blend ? alpha * Tr : 0.0f;
+            const float ab = blend ? alpha : 0.0f;  // this pixel's alpha, 0 if it did not blend
+            const float wgt = ab * Tr;
             C0 = __fmaf_rn(a2.y, wgt, C0);
             C1 = __fmaf_rn(a2.z, wgt, C1);
             C2 = __fmaf_rn(a2.w, wgt, C2);
             Tr = blend ? Tn : Tr;
-            A += blend ? alpha : 0.0f;
+            A += ab;
             cnt += blend ? 1u : 0u;
             lastp = blend ? pos0 + j : lastp;
             // leave the batch once every pixel of this wavefront has stopped
@@ -392,10 +393,12 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
         const float G = __builtin_amdgcn_exp2f(p2);
         const float og = a2.x * G;
         const bool capped = og > kAlphaMax;
-        const float alpha = capped ? kAlphaMax : og;
+        // alpha of this pixel, 0 where it did not blend: then 1 / (1 - alpha) = 1
+        // exactly and transmittance and weight need no select
+        const float alpha = on ? fminf(og, kAlphaMax) : 0.0f;
         const float ri = __builtin_amdgcn_rcpf(1.0f - alpha);
-        Tr = on ? Tr * ri : Tr;                // transmittance in front of this Gaussian
-        const float wgt = on ? alpha * Tr : 0.0f;
+        Tr = Tr * ri;                          // transmittance in front of this Gaussian
+        const float wgt = alpha * Tr;
         // Per pixel: colour partials, opacity partial and the moments of the exponent's
         // derivative dpow over (dx, dy, dx^2, dx dy, dy^2); the centre and conic
         // partials are fixed linear maps of these moments (applied once per tile).

@@ -161,6 +161,26 @@ def test_argument_checks():
                             [1e-3] * 6, [1.0, 1.0], beta1=0.9)             # 2 view scales, 1 view
         assert e.value.status == gs.GS_ERR_STATE
         assert "n_views" in gs.gs_last_error(rz.ctx)
+        S = torch.zeros(10, dtype=torch.int32).cuda()
+        img = rz.new_image(0.0)
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_render_bwd_adam(rz.ctx, P, img, None, P, P, S, [1e-3] * 6)   # before render_fwd
+        assert e.value.status == gs.GS_ERR_STATE
+        rz.preprocess(P, 10, 0)
+        rz.bin_sort()
+        rz.render_fwd()
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_render_bwd_adam(rz.ctx, P, img, None, None, P, S, [1e-3] * 6)   # m missing
+        assert e.value.status == gs.GS_ERR_INVALID
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_render_bwd_adam(rz.ctx, P, img, P.data_ptr() + 2, P, P, S, [1e-3] * 6)   # misaligned grad
+        assert e.value.status == gs.GS_ERR_INVALID
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_render_bwd_adam(rz.ctx, P, img, None, P, P, S, [1e-3] * 6, beta1=1.0)
+        assert e.value.status == gs.GS_ERR_INVALID
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_render_bwd_adam(rz.ctx, P, img, None, P, P, S, [1e-3] * 6, [1.0, 1.0])   # 2 scales, 1 view
+        assert e.value.status == gs.GS_ERR_STATE
     finally:
         rz.close()
 
