@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const ViewDev* __restrict__ vi
                                                    const float* __restrict__ x, const float* __restrict__ y,
                                                    float* __restrict__ aux, Win win, double2* __restrict__ partials) {
   __shared__ float sin_[2][HALO * HS];
-  __shared__ float hbuf[5][HALO * LT];
+  __shared__ float hbuf[3][HALO * LT];   // the five maps in two rounds (3 + 2): 30 KB of LDS
   __shared__ double sh[4];
   const int tile = xcd_tile(blockIdx.x, lt.off[V]);
   if (tile >= lt.off[V]) return;
@@ -190,16 +190,33 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const ViewDev* __restrict__ vi
     const float* src[2] = {x + base + ch * hw, y + base + ch * hw};
     stage_halo<2>(sin_, src, cv.W, cv.H, t.x0, t.y0);
     __syncthreads();
-    hpass<2, 5>(sin_, hbuf, win, [](const float* v, float* f) {
-      f[0] = v[0];
-      f[1] = v[1];
-      f[2] = v[0] * v[0];
-      f[3] = v[1] * v[1];
-      f[4] = v[0] * v[1];
-    });
-    __syncthreads();
     float m[5][VSEG];
-    vpass<5>(hbuf, win, col, r0, m);
+    {
+      hpass<2, 3>(sin_, hbuf, win, [](const float* v, float* f) {
+        f[0] = v[0];
+        f[1] = v[1];
+        f[2] = v[0] * v[0];
+      });
+      __syncthreads();
+      float mm[3][VSEG];
+      vpass<3>(hbuf, win, col, r0, mm);
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int j = 0; j < VSEG; ++j) m[q][j] = mm[q][j];
+      __syncthreads();
+      hpass<2, 2>(sin_, hbuf, win, [](const float* v, float* f) {
+        f[0] = v[1] * v[1];
+        f[1] = v[0] * v[1];
+      });
+      __syncthreads();
+      float mn[2][VSEG];
+      vpass<2>(hbuf, win, col, r0, mn);
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int j = 0; j < VSEG; ++j) m[3 + q][j] = mn[q][j];
+    }
     float* ac = aux + (size_t)cv.pix_off * 9 + (size_t)ch * 3 * hw;
 #pragma unroll
     for (int j = 0; j < VSEG; ++j) {
