@@ -252,7 +252,7 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const ViewDev* __restrict__ vi
                                                    const float* __restrict__ aux, Win win, float w_l1, float w_dssim,
                                                    float* __restrict__ grad) {
   __shared__ float sin_[3][HALO * HS];
-  __shared__ float hbuf[3][HALO * LT];
+  __shared__ float hbuf[1][HALO * LT];   // the three maps filtered one after another: 27 KB of LDS
   const int tile = xcd_tile(blockIdx.x, lt.off[V]);
   if (tile >= lt.off[V]) return;
   const TileLoc t = loss_tile(views, lt, V, tile);
@@ -266,14 +266,17 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const ViewDev* __restrict__ vi
     const float* src[3] = {ac, ac + hw, ac + 2 * hw};
     stage_halo<3>(sin_, src, cv.W, cv.H, t.x0, t.y0);
     __syncthreads();
-    hpass<3, 3>(sin_, hbuf, win, [](const float* v, float* f) {
-      f[0] = v[0];
-      f[1] = v[1];
-      f[2] = v[2];
-    });
-    __syncthreads();
     float m[3][VSEG];
-    vpass<3>(hbuf, win, col, r0, m);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      hpass<1, 1>(sin_ + q, hbuf, win, [](const float* v, float* f) { f[0] = v[0]; });
+      __syncthreads();
+      float mq[1][VSEG];
+      vpass<1>(hbuf, win, col, r0, mq);
+#pragma unroll
+      for (int j = 0; j < VSEG; ++j) m[q][j] = mq[0][j];
+      __syncthreads();
+    }
 #pragma unroll
     for (int j = 0; j < VSEG; ++j) {
       const int px = t.x0 + col, py = t.y0 + r0 + j;
