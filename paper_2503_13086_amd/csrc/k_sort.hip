@@ -81,23 +81,33 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
 
 // The histogram table is block-major, hist[b * 256 + d].  Its scan, per digit d
 // the count of items with a smaller digit plus those of digit d in earlier blocks,
-// runs over chunks of kScanChunk blocks: column sums per chunk, one workgroup
+// runs over chunks of blocks (at most kMaxChunks chunks): column sums per chunk, one workgroup
 // scanning the chunk sums and the digit totals, and a per-chunk running sum.
 // Every pass reads rows of 256 counters (coalesced).
-constexpr int kScanChunk = 16;
+constexpr int kScanChunk = 16;                               // smallest chunk, and the load batch
+constexpr int kMaxChunks = 128;                              // chunks grow so there are at most this many
 constexpr int kChunkScanThreads = 1024;                       // k_radix_chunk_scan: 4 threads per digit
 constexpr int kChunkParts = kChunkScanThreads / kRadix;
 
+// Blocks per chunk for n_blocks blocks: a multiple of kScanChunk, at least kScanChunk.
+inline int chunk_blocks(int n_blocks) {
+  int cs = (n_blocks + kMaxChunks - 1) / kMaxChunks;
+  cs = (cs + kScanChunk - 1) / kScanChunk * kScanChunk;
+  return cs < kScanChunk ? kScanChunk : cs;
+}
+
 __global__ __launch_bounds__(kRadix) void k_radix_chunk_sums(const uint32_t* __restrict__ hist, int n_blocks,
-                                                              uint32_t* __restrict__ chunk_sum) {
-  const int b0 = blockIdx.x * kScanChunk;
-  uint32_t x[kScanChunk];
-#pragma unroll
-  for (int k = 0; k < kScanChunk; ++k)   // all loads in flight before the sum
-    x[k] = b0 + k < n_blocks ? hist[(size_t)(b0 + k) * kRadix + threadIdx.x] : 0u;
+                                                              int cs, uint32_t* __restrict__ chunk_sum) {
+  const int b0 = blockIdx.x * cs, b1 = min(b0 + cs, n_blocks);
   uint32_t t = 0;
+  for (int b = b0; b < b1; b += kScanChunk) {
+    uint32_t x[kScanChunk];
 #pragma unroll
-  for (int k = 0; k < kScanChunk; ++k) t += x[k];
+    for (int k = 0; k < kScanChunk; ++k)   // a batch of loads in flight before the sum
+      x[k] = b + k < b1 ? hist[(size_t)(b + k) * kRadix + threadIdx.x] : 0u;
+#pragma unroll
+    for (int k = 0; k < kScanChunk; ++k) t += x[k];
+  }
   chunk_sum[(size_t)blockIdx.x * kRadix + threadIdx.x] = t;
 }
 
@@ -162,19 +172,21 @@ __global__ __launch_bounds__(kChunkScanThreads) void k_radix_chunk_scan(uint32_t
 }
 
 // hist[b][d] <- start of block b's run of digit d in the pass's output.
-__global__ __launch_bounds__(kRadix) void k_radix_chunk_apply(uint32_t* __restrict__ hist, int n_blocks,
+__global__ __launch_bounds__(kRadix) void k_radix_chunk_apply(uint32_t* __restrict__ hist, int n_blocks, int cs,
                                                                const uint32_t* __restrict__ chunk_sum,
                                                                const uint32_t* __restrict__ digit_base) {
-  const int b0 = blockIdx.x * kScanChunk;
-  uint32_t x[kScanChunk];
-#pragma unroll
-  for (int k = 0; k < kScanChunk; ++k)
-    x[k] = b0 + k < n_blocks ? hist[(size_t)(b0 + k) * kRadix + threadIdx.x] : 0u;
+  const int b0 = blockIdx.x * cs, b1 = min(b0 + cs, n_blocks);
   uint32_t run = digit_base[threadIdx.x] + chunk_sum[(size_t)blockIdx.x * kRadix + threadIdx.x];
+  for (int b = b0; b < b1; b += kScanChunk) {
+    uint32_t x[kScanChunk];
 #pragma unroll
-  for (int k = 0; k < kScanChunk; ++k) {
-    if (b0 + k < n_blocks) hist[(size_t)(b0 + k) * kRadix + threadIdx.x] = run;
-    run += x[k];
+    for (int k = 0; k < kScanChunk; ++k)
+      x[k] = b + k < b1 ? hist[(size_t)(b + k) * kRadix + threadIdx.x] : 0u;
+#pragma unroll
+    for (int k = 0; k < kScanChunk; ++k) {
+      if (b + k < b1) hist[(size_t)(b + k) * kRadix + threadIdx.x] = run;
+      run += x[k];
+    }
   }
 }
 
@@ -682,16 +694,18 @@ hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b
   *result_in_b = 0;
   if (n == 0 || bits <= 0) return hipSuccess;
   const int n_blocks = (int)((n + kSortTileItems - 1) / kSortTileItems);
-  const int n_chunks = (n_blocks + kScanChunk - 1) / kScanChunk;
+  const int cs = chunk_blocks(n_blocks);
+  const int n_chunks = (n_blocks + cs - 1) / cs;
   uint32_t* chunk_sum = scratch.hist + (size_t)kRadix * n_blocks;
   uint32_t* digit_base = chunk_sum + (size_t)kRadix * n_chunks;
   uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
   int in_b = 0;
   for (int shift = 0; shift < bits; shift += 8) {
     hipLaunchKernelGGL(k_radix_hist, dim3(n_blocks), dim3(kThreads), 0, s, ki, n, shift, scratch.hist, n_blocks);
-    hipLaunchKernelGGL(k_radix_chunk_sums, dim3(n_chunks), dim3(kRadix), 0, s, scratch.hist, n_blocks, chunk_sum);
+    hipLaunchKernelGGL(k_radix_chunk_sums, dim3(n_chunks), dim3(kRadix), 0, s, scratch.hist, n_blocks, cs,
+                       chunk_sum);
     hipLaunchKernelGGL(k_radix_chunk_scan, dim3(1), dim3(kChunkScanThreads), 0, s, chunk_sum, n_chunks, digit_base);
-    hipLaunchKernelGGL(k_radix_chunk_apply, dim3(n_chunks), dim3(kRadix), 0, s, scratch.hist, n_blocks, chunk_sum,
+    hipLaunchKernelGGL(k_radix_chunk_apply, dim3(n_chunks), dim3(kRadix), 0, s, scratch.hist, n_blocks, cs, chunk_sum,
                        digit_base);
     hipLaunchKernelGGL(k_radix_scatter, dim3(n_blocks), dim3(kThreads), 0, s, ki, vi, n, shift, scratch.hist,
                        n_blocks, ko, vo);
