@@ -4,10 +4,9 @@
 // (T = 8, 16 or 32), one thread per pixel, each wavefront owning an 8x8 block.
 // The tile's depth-ordered list is walked in batches of T^2 records staged in LDS;
 // every pixel reads each staged record by LDS broadcast, so a record fetched from
-// HBM once serves the whole tile.  While staging, each record also gets the
-// bounding box of its cutoff ellipse; each wavefront then tests the batch against
-// its block (one record per lane, one ballot per 64 records) and walks only the
-// records whose box meets it.  A wavefront stops when all its pixels have stopped
+// HBM once serves the whole tile.  Each wavefront tests the staged batch against
+// its block (one record per lane, one ballot per 64 records: does the cutoff
+// ellipse meet the block's pixel centres) and walks only the records that do.  A wavefront stops when all its pixels have stopped
 // blending, the workgroup when all have.  Screen centres arrive in FP64 and are
 // made relative to the tile origin while staging, so per-pixel offsets are
 // accurate fp32 numbers at any image size.
@@ -81,13 +80,16 @@ __device__ inline TileGeom tile_geom(const ViewDev* __restrict__ views, int V, i
 
 // Stage record `rid` for a tile with origin (ox, oy): centre relative to the tile,
 // exponent coefficients and cutoff in base-2 units (the exponent's sign and the
-// cutoff test are unchanged by the positive factor), opacity, colour, and the
-// half-widths (ex, ey) of the bounding box of the cutoff region
-// {a dx^2 + 2 b dx dy + c dy^2 <= -2 tau}: sqrt(-2 tau c / det) and
-// sqrt(-2 tau a / det), det = ac - b^2 taken in FP64 (the fp32 entries multiply
-// exactly there), widened by 1e-4 relative + 0.01 px so that the per-pixel fp32
-// test never passes a pixel outside the box.
-//   q0 = (u', w', A, B)   q1 = (C, tau', ex, ey)   q2 = (o, r, g, b)
+// cutoff test are unchanged by the positive factor), opacity, colour, and two
+// values for the block test below: the slope kC = -b / c of the line on which the
+// exponent peaks along vertical lines, and a cutoff tau_c = tau' (1 + 1e-5 kappa)
+// slightly below the pixel test's, kappa = (sqrt(ac) + |b|)^2 / (ac - b^2) bounding
+// (|A dx^2| + |B dx dy| + |C dy^2|) / |exponent|, so that fp32 rounding in either
+// test can never make the block test drop a Gaussian a pixel accepts.  det and kappa
+// are taken in FP64 (the fp32 entries multiply exactly there); a conic that is not
+// clearly positive definite (det <= 0 or kappa >= 1e4) gets tau_c = -inf, so every
+// block lists it.
+//   q0 = (u', w', A, B)   q1 = (C, tau', tau_c, kC)   q2 = (o, r, g, b)
 // (the per-pixel test reads q0 and q1.xy, a blend q2).
 __device__ inline void stage(const Record* __restrict__ rec, uint32_t rid, double ox, double oy, float4& q0,
                              float4& q1, float4& q2) {
@@ -96,39 +98,58 @@ __device__ inline void stage(const Record* __restrict__ rec, uint32_t rid, doubl
   const float4 c = reinterpret_cast<const float4*>(r)[1];
   const float4 d = reinterpret_cast<const float4*>(r)[2];
   const double det = (double)c.x * (double)c.z - (double)c.y * (double)c.y;
-  float ex = 3.0e38f, ey = 3.0e38f;
+  const float tau2 = d.x * kLog2e;
+  float tc = -INFINITY, kc = 0.0f;
   if (det > 0.0) {
-    const double L = -2.0 * (double)d.x / det;
-    ex = (float)(sqrt(L * (double)c.z) * (1.0 + 1e-4) + 0.01);
-    ey = (float)(sqrt(L * (double)c.x) * (1.0 + 1e-4) + 0.01);
+    const double s = sqrt((double)c.x * (double)c.z) + fabs((double)c.y);
+    const double kappa = s * s / det;
+    if (kappa < 1e4) tc = (float)((double)tau2 * (1.0 + 1e-5 * kappa));
+    kc = -c.y / c.z;
   }
   q0 = make_float4((float)(uw.x - ox), (float)(uw.y - oy), (-0.5f * c.x) * kLog2e, (-c.y) * kLog2e);
-  q1 = make_float4((-0.5f * c.z) * kLog2e, d.x * kLog2e, ex, ey);
+  q1 = make_float4((-0.5f * c.z) * kLog2e, tau2, tc, kc);
   q2 = make_float4(c.w, d.y, d.z, d.w);
 }
 
 // Placeholder for an entry that belongs to no Gaussian (never for a consistent
-// sort): no pixel accepts it and no quadrant lists it.
+// sort): no pixel accepts it and no block lists it.
 __device__ inline void stage_empty(float4& q0, float4& q1, float4& q2) {
   q0 = make_float4(0.f, 0.f, 0.f, 0.f);
-  q1 = make_float4(0.f, 1.f, -1.f, -1.f);
+  q1 = make_float4(0.f, 1.f, INFINITY, 0.f);
   q2 = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-// Ballots of the staged records [0, m) whose cutoff box meets this wavefront's
+// Ballots of the staged records [0, m) whose cutoff ellipse meets this wavefront's
 // 8x8 block of pixel centres [qx, qx + 7] x [qy, qy + 7] (tile-relative); bit b
-// of mask[k] is record 64 k + b.
+// of mask[k] is record 64 k + b.  The pixels' offsets u' - x, w' - y fill the box
+// [x0, x1] x [y0, y1] (same fp32 subtractions as the pixel test), and the largest
+// exponent over that box lies on the edge dx = xn (the box's nearest value to 0),
+// where it peaks at dy = kC xn, or on the edge dy = yn, peak dx = kA yn (a concave
+// quadratic's maximum over a box is at its centre, or on an edge next to the
+// nearest corner); any point of the box bounds that maximum from below, so the
+// rounding of the peak positions only costs the second-order loss already
+// covered by tau_c.
 template <int NM>
-__device__ inline void quadrant_masks(const float4* s0, const float4* s1, const float4* s2, int m, float qx,
-                                      float qy, uint64_t (&mask)[NM]) {
+__device__ inline void quadrant_masks(const float4* s0, const float4* s1, int m, float qx, float qy,
+                                      uint64_t (&mask)[NM]) {
   const int lane = (int)__lane_id();
 #pragma unroll
   for (int k = 0; k < NM; ++k) {
     const int j = lane + 64 * k;
     bool hit = false;
     if (j < m) {
-      const float u = s0[j].x, w = s0[j].y, ex = s1[j].z, ey = s1[j].w;
-      hit = u + ex >= qx && u - ex <= qx + 7.0f && w + ey >= qy && w - ey <= qy + 7.0f;
+      const float4 a0 = s0[j];
+      const float4 a1 = s1[j];
+      const float x0 = a0.x - (qx + 7.0f), x1 = a0.x - qx;
+      const float y0 = a0.y - (qy + 7.0f), y1 = a0.y - qy;
+      const float xn = fminf(fmaxf(0.0f, x0), x1);
+      const float yn = fminf(fmaxf(0.0f, y0), y1);
+      const float ka = (-0.5f * a0.w) * __builtin_amdgcn_rcpf(a0.z);
+      const float dy1 = fminf(fmaxf(xn * a1.w, y0), y1);
+      const float dx2 = fminf(fmaxf(yn * ka, x0), x1);
+      const float f1 = gauss_power2(a0.z, a0.w, a1.x, xn, dy1);
+      const float f2 = gauss_power2(a0.z, a0.w, a1.x, dx2, yn);
+      hit = fmaxf(f1, f2) >= a1.z;
     }
     mask[k] = wave_mask(hit);
   }
@@ -169,7 +190,7 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict_
     __syncthreads();
     if (wave_mask(pmax == 0.0f) != 0ull) {
       uint64_t mask[NM];
-      quadrant_masks<NM>(s0, s1, s2, (int)m, qx, qy, mask);
+      quadrant_masks<NM>(s0, s1, (int)m, qx, qy, mask);
       // straight-line per-Gaussian update; lanes that skip or have stopped keep their state
       const uint32_t pos0 = base - rg.x + 1;
       bool live = true;
@@ -371,9 +392,9 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
     }
     __syncthreads();
     // records this wavefront may need: positions below its own last blended one
-    // whose cutoff box meets its quadrant, walked back to front
+    // whose cutoff ellipse meets its block, walked back to front
     uint64_t mask[NM];
-    quadrant_masks<NM>(s0, s1, s2, min(m, wave_last - beg), qx, qy, mask);
+    quadrant_masks<NM>(s0, s1, min(m, wave_last - beg), qx, qy, mask);
     const uint32_t lrel = lp > (uint32_t)beg ? lp - (uint32_t)beg : 0u;   // batch positions this pixel blended
     for (int k = NM - 1; k >= 0; --k) {
       uint64_t mk = mask[k];
