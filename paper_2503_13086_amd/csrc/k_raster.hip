@@ -18,7 +18,8 @@
 // accumulated behind it.  Per Gaussian, nine per-pixel values (the moments of
 // dL/d(exponent) over dx, dy, dx^2, dx dy, dy^2, then opacity and colour partials)
 // are summed across the wavefront by a reduce-scatter (CDNA4 permlane swaps across
-// halves and row pairs, then DPP exchanges within rows) and across the wavefronts
+// halves and row pairs, then DPP exchanges within rows; the Gaussians a wavefront
+// blends are taken two at a time, sharing the last levels) and across the wavefronts
 // with LDS adds; the moments become centre and conic partials once per tile, and each
 // workgroup issues one global atomic per (tile, Gaussian, component) instead of
 // one per (pixel, Gaussian, component), consecutive lanes taking consecutive
@@ -276,33 +277,57 @@ __device__ inline float fold_dpp(float a, float b, bool hi) {
   return own + dpp<CTRL>(give);
 }
 
-// Reduce-scatter of nine per-lane values over the wave, added into acc[0..8]
-// (mine = acc + this lane's slot).
+// Reduce-scatter of nine per-lane values over the wave, added into an LDS row.
 // Each level halves the registers by pairing lanes whose selector bit differs
 // (across wave halves, across row pairs, across half-rows, across the halves of
-// each half-row by mirroring), then two quad permutations finish the sums: every
-// group of four lanes then holds one total.  The lane of each group with
-// slot >= 0 adds it into LDS (nine lanes, one instruction): with r = row, h = lane
-// bit 3, q = lane bit 2, value {0, 2, 1, 3}[r] + 4h sits where q = 0 and value 8
-// where r = h = 0, q = 1.
+// each half-row by mirroring), then quad permutations finish the sums.  The first
+// eight values go through the first three levels on their own (reduce8_part);
+// the ninth joins there.  A record alone (reduce9_tail) ends with every group of
+// four lanes holding one total, and the lane of each group with slot >= 0 adds it
+// into LDS (nine lanes, one instruction): with r = row, h = lane bit 3, q = lane
+// bit 2, value {0, 2, 1, 3}[r] + 4h sits where q = 0 and value 8 where r = h = 0,
+// q = 1.  Two records (reduce18_tail) share the last three levels: every pair of
+// lanes then holds one of the 18 totals (the second record's at lane bit 2 set,
+// both ninth values at lane bit 1 set), which costs 45 instructions instead of 56.
 typedef __attribute__((address_space(3))) float LdsFloat;
 
-__device__ inline void wave_reduce9_to_lds(const float (&v)[kGrad2D], LdsFloat* mine, int slot, bool bit3,
-                                           bool bit2) {
+__device__ inline float reduce8_part(const float (&v)[kGrad2D], bool bit3) {
   const float b0 = fold32(v[0], v[1]);
   const float b1 = fold32(v[2], v[3]);
   const float b2 = fold32(v[4], v[5]);
   const float b3 = fold32(v[6], v[7]);
-  const float b4 = fold32(v[8], 0.0f);
   const float c0 = fold16(b0, b1);
   const float c1 = fold16(b2, b3);
-  const float c2 = fold16(b4, 0.0f);
-  const float d0 = fold_dpp<0x128>(c0, c1, bit3);
+  return fold_dpp<0x128>(c0, c1, bit3);
+}
+
+__device__ inline void lds_add(uint32_t addr, float x) {
+  __hip_atomic_fetch_add((LdsFloat*)(uintptr_t)addr, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// d = reduce8_part of the record's first eight values, v8 its ninth; lanes with
+// `add` add their total at addr (row and column included).
+__device__ inline void reduce9_tail(float d, float v8, uint32_t addr, bool add, bool bit2) {
+  const float c2 = fold16(fold32(v8, 0.0f), 0.0f);
   const float d1 = c2 + dpp<0x128>(c2);
-  float e = fold_dpp<0x141>(d0, d1, bit2);
+  float e = fold_dpp<0x141>(d, d1, bit2);
   e += dpp<0x4E>(e);
   e += dpp<0xB1>(e);
-  if (slot >= 0) __hip_atomic_fetch_add(mine, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  if (add) lds_add(addr, e);
+}
+
+// Records a and b (parts da, db, ninth values a8, b8) reduced together; lanes that
+// hold a total of a add it at addr_a, those holding one of b at addr_b.
+__device__ inline void reduce18_tail(float da, float a8, float db, float b8, uint32_t addr_a, uint32_t addr_b,
+                                     bool add_a, bool add_b, bool bit2, bool bit1) {
+  const float m2 = fold16(fold32(a8, b8), 0.0f);
+  const float m3 = m2 + dpp<0x128>(m2);
+  const float e0 = fold_dpp<0x141>(da, db, bit2);
+  const float e1 = m3 + dpp<0x141>(m3);
+  float f = fold_dpp<0x4E>(e0, e1, bit1);
+  f += dpp<0xB1>(f);
+  if (add_a) lds_add(addr_a, f);
+  if (add_b) lds_add(addr_b, f);
 }
 
 // Byte offset of row j of the [NT][kGrad2D] float accumulator, formed on the scalar
@@ -315,12 +340,22 @@ __device__ inline uint32_t acc_row_offset(int j) {
   return off;
 }
 
-// The LDS slot wave_reduce9_to_lds adds from this lane (-1: none).
+// The accumulator column reduce9_tail adds from this lane (-1: none).
 __device__ inline int reduce9_slot(unsigned lane) {
   if (lane & 3u) return -1;
   const unsigned r = lane >> 4, h = (lane >> 3) & 1u, q = (lane >> 2) & 1u;
   if (q == 0u) return (int)((((r & 1u) << 1) | (r >> 1)) + 4u * h);
   return (r == 0u && h == 0u) ? 8 : -1;
+}
+
+// The total reduce18_tail leaves in this lane for it to add: 0-8 for the first
+// record's columns, 9-17 for the second's (-1: none).
+__device__ inline int reduce18_slot(unsigned lane) {
+  if (lane & 1u) return -1;
+  const unsigned r = lane >> 4, h = (lane >> 3) & 1u, q = (lane >> 2) & 1u;
+  if ((lane & 2u) == 0u) return (int)((((r & 1u) << 1) | (r >> 1)) + 4u * h + 9u * q);
+  if (h == 0u && q == 0u && (r & 1u) == 0u) return r == 0u ? 8 : 17;
+  return -1;
 }
 
 template <int T>
@@ -366,11 +401,15 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
   for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
   const int wave_last = (int)mx;           // this wave never needs list positions >= wave_last
   const unsigned lane = __lane_id();
-  const int slot = reduce9_slot(lane);
-  const bool bit3 = (lane & 8u) != 0u, bit2 = (lane & 4u) != 0u;
-  // 32-bit LDS byte address of this lane's slot in acc[0] (plain integer arithmetic
-  // in the loop: the compiler would otherwise form the address in 64 bits)
-  const uint32_t my_acc_addr = (uint32_t)(uintptr_t)((LdsFloat*)&acc[0][0] + (slot < 0 ? 0 : slot));
+  const int slot = reduce9_slot(lane), slot18 = reduce18_slot(lane);
+  const bool bit3 = (lane & 8u) != 0u, bit2 = (lane & 4u) != 0u, bit1 = (lane & 2u) != 0u;
+  const bool add9 = slot >= 0, add_a = slot18 >= 0 && slot18 < kGrad2D, add_b = slot18 >= kGrad2D;
+  // 32-bit LDS byte addresses of this lane's columns in acc[0] for the two
+  // reductions (plain integer arithmetic in the loop: the compiler would otherwise
+  // form the address in 64 bits)
+  const uint32_t acc0 = (uint32_t)(uintptr_t)(LdsFloat*)&acc[0][0];
+  const uint32_t col9 = acc0 + 4u * (uint32_t)(slot < 0 ? 0 : slot);
+  const uint32_t col18 = acc0 + 4u * (uint32_t)(slot18 < 0 ? 0 : slot18 % kGrad2D);
   if (__lane_id() == 0) smax[threadIdx.x / 64] = mx;
   for (int k = 0; k < kGrad2D; ++k) acc[threadIdx.x][k] = 0.0f;
   __syncthreads();
@@ -398,6 +437,10 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
     const uint32_t lrel = lp > (uint32_t)beg ? lp - (uint32_t)beg : 0u;   // batch positions this pixel blended
     for (int k = NM - 1; k >= 0; --k) {
       uint64_t mk = mask[k];
+      // blended records are reduced two at a time: the first waits (as the first
+      // three levels of its reduction and its ninth value) for the next
+      float da = 0.0f, a8 = 0.0f;
+      int ja = -1;
       while (mk) {
         const int b = 63 - __builtin_clzll(mk);
         mk &= ~(1ull << b);
@@ -441,8 +484,18 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
         p[6] = g0 * wgt;
         p[7] = g1 * wgt;
         p[8] = g2 * wgt;
-        wave_reduce9_to_lds(p, (LdsFloat*)(uintptr_t)(my_acc_addr + acc_row_offset(j)), slot, bit3, bit2);
+        const float d = reduce8_part(p, bit3);
+        if (ja < 0) {
+          da = d;
+          a8 = p[8];
+          ja = j;
+        } else {
+          reduce18_tail(da, a8, d, p[8], col18 + acc_row_offset(ja), col18 + acc_row_offset(j), add_a, add_b, bit2,
+                        bit1);
+          ja = -1;
+        }
       }
+      if (ja >= 0) reduce9_tail(da, a8, col9 + acc_row_offset(ja), add9, bit2);
     }
     __syncthreads();
     if ((int)threadIdx.x < m) {
