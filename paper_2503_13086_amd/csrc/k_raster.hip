@@ -46,9 +46,10 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 
 // Base-2 exponent of the 2D Gaussian at offset (dx, dy): with A = -a/2, B = -b,
-// C = -c/2 pre-scaled by log2(e), e^power = 2^result.
+// C = -c/2 pre-scaled by log2(e), e^power = 2^result, taken as
+// dx (A dx + B dy) + C dy^2 (five operations).
 __device__ inline float gauss_power2(float A, float B, float C, float dx, float dy) {
-  return __fmaf_rn(A * dx, dx, __fmaf_rn(C * dy, dy, (B * dx) * dy));
+  return __fmaf_rn(C * dy, dy, dx * __fmaf_rn(B, dy, A * dx));
 }
 
 struct TileGeom {
@@ -143,11 +144,12 @@ __device__ inline void quadrant_masks(const float4* s0, const float4* s1, int m,
       const float4 a1 = s1[j];
       const float x0 = a0.x - (qx + 7.0f), x1 = a0.x - qx;
       const float y0 = a0.y - (qy + 7.0f), y1 = a0.y - qy;
-      const float xn = fminf(fmaxf(0.0f, x0), x1);
-      const float yn = fminf(fmaxf(0.0f, y0), y1);
+      // (x0 <= x1 and y0 <= y1: a median of three is a clamp)
+      const float xn = __builtin_amdgcn_fmed3f(0.0f, x0, x1);
+      const float yn = __builtin_amdgcn_fmed3f(0.0f, y0, y1);
       const float ka = (-0.5f * a0.w) * __builtin_amdgcn_rcpf(a0.z);
-      const float dy1 = fminf(fmaxf(xn * a1.w, y0), y1);
-      const float dx2 = fminf(fmaxf(yn * ka, x0), x1);
+      const float dy1 = __builtin_amdgcn_fmed3f(xn * a1.w, y0, y1);
+      const float dx2 = __builtin_amdgcn_fmed3f(yn * ka, x0, x1);
       const float f1 = gauss_power2(a0.z, a0.w, a1.x, xn, dy1);
       const float f2 = gauss_power2(a0.z, a0.w, a1.x, dx2, yn);
       hit = fmaxf(f1, f2) >= a1.z;
