@@ -292,25 +292,26 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const ViewDev* __restrict__ vi
   }
 }
 
-__global__ void k_loss_final(const ViewDev* __restrict__ views, int V, LossTiles lt,
-                             const double2* __restrict__ partials, float w_l1, float w_dssim, int ssim,
-                             double* __restrict__ out) {
+// One workgroup per view: the view's tile partials summed in FP64.
+__global__ __launch_bounds__(256) void k_loss_final(const ViewDev* __restrict__ views, LossTiles lt,
+                                                     const double2* __restrict__ partials, float w_l1,
+                                                     float w_dssim, int ssim, double* __restrict__ out) {
   __shared__ double sh[4];
-  for (int v = 0; v < V; ++v) {
-    const ViewDev& cv = views[v];
-    double a = 0.0, b = 0.0;
-    for (int t = lt.off[v] + threadIdx.x; t < lt.off[v + 1]; t += blockDim.x) {
-      a += partials[t].x;
-      b += partials[t].y;
-    }
-    a = block_sum_d(a, sh);
-    b = block_sum_d(b, sh);
-    if (threadIdx.x == 0) {
-      const double N = 3.0 * (double)cv.W * (double)cv.H;
-      double l = (double)w_l1 * a / N;
-      if (ssim) l += (double)w_dssim * (1.0 - b / N);
-      out[v] = l;
-    }
+  const int v = blockIdx.x;
+  const ViewDev& cv = views[v];
+  double a = 0.0, b = 0.0;
+  for (int t = lt.off[v] + threadIdx.x; t < lt.off[v + 1]; t += blockDim.x) {
+    const double2 pt = partials[t];
+    a += pt.x;
+    b += pt.y;
+  }
+  a = block_sum_d(a, sh);
+  b = block_sum_d(b, sh);
+  if (threadIdx.x == 0) {
+    const double N = 3.0 * (double)cv.W * (double)cv.H;
+    double l = (double)w_l1 * a / N;
+    if (ssim) l += (double)w_dssim * (1.0 - b / N);
+    out[v] = l;
   }
 }
 
@@ -435,7 +436,7 @@ hipError_t launch_loss_dev(const ViewDev* dviews, const ViewDev* hviews, int V, 
                        dL_dcolor);
   }
   if (loss_out)
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, dviews, V, lt, part, w_l1, w_dssim, ssim ? 1 : 0,
+    hipLaunchKernelGGL(k_loss_final, dim3(V), dim3(256), 0, s, dviews, lt, part, w_l1, w_dssim, ssim ? 1 : 0,
                        loss_out);
   return hipGetLastError();
 }

@@ -87,10 +87,11 @@ __device__ inline TileGeom tile_geom(const ViewDev* __restrict__ views, int V, i
 // exponent peaks along vertical lines, and a cutoff tau_c = tau' (1 + 1e-5 kappa)
 // slightly below the pixel test's, kappa = (sqrt(ac) + |b|)^2 / (ac - b^2) bounding
 // (|A dx^2| + |B dx dy| + |C dy^2|) / |exponent|, so that fp32 rounding in either
-// test can never make the block test drop a Gaussian a pixel accepts.  det and kappa
-// are taken in FP64 (the fp32 entries multiply exactly there); a conic that is not
-// clearly positive definite (det <= 0 or kappa >= 1e4) gets tau_c = -inf, so every
-// block lists it.
+// test can never make the block test drop a Gaussian a pixel accepts.  det is taken
+// in FP64 (the fp32 entries multiply exactly there), kappa and kC in fp32 from it
+// (their relative errors, ~1e-6, only move the margin by as much of itself); a conic
+// that is not clearly positive definite (det <= 0 or kappa >= 1e4) gets
+// tau_c = -inf, so every block lists it.
 //   q0 = (u', w', A, B)   q1 = (C, tau', tau_c, kC)   q2 = (o, r, g, b)
 // (the per-pixel test reads q0 and q1.xy, a blend q2).
 __device__ inline void stage(const Record* __restrict__ rec, uint32_t rid, double ox, double oy, float4& q0,
@@ -103,10 +104,10 @@ __device__ inline void stage(const Record* __restrict__ rec, uint32_t rid, doubl
   const float tau2 = d.x * kLog2e;
   float tc = -INFINITY, kc = 0.0f;
   if (det > 0.0) {
-    const double s = sqrt((double)c.x * (double)c.z) + fabs((double)c.y);
-    const double kappa = s * s / det;
-    if (kappa < 1e4) tc = (float)((double)tau2 * (1.0 + 1e-5 * kappa));
-    kc = -c.y / c.z;
+    const float s = __builtin_amdgcn_sqrtf(c.x * c.z) + fabsf(c.y);
+    const float kappa = (s * s) * __builtin_amdgcn_rcpf((float)det);
+    if (kappa < 1e4f) tc = tau2 * (1.0f + 1e-5f * kappa);
+    kc = -c.y * __builtin_amdgcn_rcpf(c.z);
   }
   q0 = make_float4((float)(uw.x - ox), (float)(uw.y - oy), (-0.5f * c.x) * kLog2e, (-c.y) * kLog2e);
   q1 = make_float4((-0.5f * c.z) * kLog2e, tau2, tc, kc);
