@@ -302,7 +302,7 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
     }
     SortScratch sc{c->hist.as<uint32_t>()};
     GS_HIP(c, radix_sort_pairs(c->dkey[0].as<uint32_t>(), c->dval[0].as<uint32_t>(), c->dkey[1].as<uint32_t>(),
-                               c->dval[1].as<uint32_t>(), NV, 32, sc, &c->depth_in_b, s));
+                               c->dval[1].as<uint32_t>(), NV, 32, 0, sc, &c->depth_in_b, s));
   }
   const uint32_t* order = c->dval[c->depth_in_b].as<uint32_t>();
   {
@@ -333,8 +333,10 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
     Prof pr(c, GS_K_TILE_SORT, s);
     SortScratch sc{c->hist.as<uint32_t>()};
     const int bits = ceil_log2((uint64_t)c->n_tiles) < 1 ? 1 : ceil_log2((uint64_t)c->n_tiles);
+    // record indices are below NV: up to 2^24 entries the two tile passes move one
+    // packed word between them
     GS_HIP(c, radix_sort_pairs(c->pkey[0].as<uint32_t>(), c->pval[0].as<uint32_t>(), c->pkey[1].as<uint32_t>(),
-                               c->pval[1].as<uint32_t>(), K, bits, sc, &c->pairs_in_b, s));
+                               c->pval[1].as<uint32_t>(), K, bits, packed ? 1 : 0, sc, &c->pairs_in_b, s));
   }
   {
     Prof pr(c, GS_K_RANGES, s);

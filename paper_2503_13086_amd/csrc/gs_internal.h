@@ -101,14 +101,16 @@ hipError_t launch_preprocess_bwd(const float* P, int n, int stride, int D, const
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
 
 // radix sort of (uint32 key, uint32 value) pairs on bits [0, bits) of the key;
-// returns which buffer (0: *_a, 1: *_b) holds the result
+// returns which buffer (0: *_a, 1: *_b) holds the result.  vals24: every value is
+// below 2^24 (then keys of 9 to 16 bits take two passes that move one packed word
+// between them, and the result is in *_a; vals_b is not touched)
 struct SortScratch {
   uint32_t* hist;      // sort_hist_words(n): block-major digit table, chunk sums, digit bases
 };
 constexpr int kSortTileItems = 4096;
 size_t sort_hist_words(size_t n);
 hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, size_t n,
-                            int bits, SortScratch scratch, int* result_in_b, hipStream_t s);
+                            int bits, int vals24, SortScratch scratch, int* result_in_b, hipStream_t s);
 hipError_t launch_iota(uint32_t* p, size_t n, hipStream_t s);
 // Depth-sort values that carry the entry's pair count: index in the low 24 bits,
 // min(count, 255) in the top byte (255: read the count from the per-entry array).

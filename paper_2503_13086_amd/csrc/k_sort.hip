@@ -195,13 +195,37 @@ __global__ __launch_bounds__(kRadix) void k_radix_chunk_apply(uint32_t* __restri
 // wave from ballot peer masks and the wave's running digit counters (no barrier per
 // round), across waves from the counters' prefix.  The workgroup then places its
 // items in LDS in digit order and writes each digit's run contiguously.
+//
+// Two-pass sorts of keys below 2^16 with values below 2^24 move one word per item
+// between the passes: the first pass (kScatterPack, digit = key bits 0-7) writes
+// (key >> 8) << 24 | value to keys_out only; the second (kScatterUnpack, digit =
+// word bits 24-31, i.e. key bits 8-15) reads those words and restores the key's low
+// byte from the item's position, its input being ordered by that byte: position i
+// holds the largest d with low_base[d] <= i, low_base being the first pass's digit
+// starts.
+constexpr int kScatterPlain = 0, kScatterPack = 1, kScatterUnpack = 2;
+
+// Largest d in [0, 256) with base[d] <= i (base nondecreasing, base[0] = 0).
+__device__ inline uint32_t digit_at(const uint32_t* base, uint32_t i) {
+  uint32_t lo = 0;
+#pragma unroll
+  for (uint32_t step = kRadix / 2; step > 0; step >>= 1)
+    if (base[lo + step] <= i) lo += step;
+  return lo;
+}
+
+template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __restrict__ keys_in,
                                                              const uint32_t* __restrict__ vals_in, size_t n, int shift,
-                                                             const uint32_t* __restrict__ offsets, int n_blocks,
+                                                             const uint32_t* __restrict__ offsets,
+                                                             const uint32_t* __restrict__ low_base,
                                                              uint32_t* __restrict__ keys_out,
                                                              uint32_t* __restrict__ vals_out) {
   __shared__ uint32_t s_keys[kSortTileItems];
-  __shared__ uint32_t s_vals[kSortTileItems];
+  __shared__ uint32_t s_vals[MODE == kScatterPack ? 1 : kSortTileItems];
+  __shared__ uint8_t s_dig[MODE == kScatterPack ? kSortTileItems : 1];   // packed words lose the digit
+  __shared__ uint32_t s_low[MODE == kScatterUnpack ? kRadix : 1];
+  __shared__ uint32_t s_lowblk[2];
   __shared__ uint32_t wc[kWaves][kRadix];   // per-wave running digit counts
   __shared__ uint32_t lstart[kRadix];       // workgroup-local start of each digit
   __shared__ uint32_t goff[kRadix];         // global start of this workgroup's run of each digit
@@ -210,15 +234,38 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
   const int wave = tid / 64;
   for (int w = 0; w < kWaves; ++w) wc[w][tid] = 0;
   goff[tid] = offsets[(size_t)blockIdx.x * kRadix + tid];
+  const size_t blk0 = (size_t)blockIdx.x * kSortTileItems;
+  const size_t valid_items = n > blk0 ? (n - blk0 < (size_t)kSortTileItems ? n - blk0 : (size_t)kSortTileItems) : 0;
+  if (MODE == kScatterUnpack) {
+    s_low[tid] = low_base[tid];
+    __syncthreads();
+    // low bytes of the workgroup's first and last items (equal unless the
+    // workgroup straddles a digit boundary)
+    if (tid < 2 && valid_items > 0) s_lowblk[tid] = digit_at(s_low, (uint32_t)(blk0 + (tid ? valid_items - 1 : 0)));
+  }
   __syncthreads();
 
-  const size_t base = (size_t)blockIdx.x * kSortTileItems + (size_t)wave * (kItems * 64) + __lane_id();
+  const size_t base = blk0 + (size_t)wave * (kItems * 64) + __lane_id();
   uint32_t k[kItems], v[kItems], rank[kItems];
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {   // all loads in flight before any ranking
     const size_t i = base + (size_t)r * 64;
     k[r] = i < n ? keys_in[i] : 0xffffffffu;
-    v[r] = i < n ? vals_in[i] : 0u;
+    if (MODE != kScatterUnpack) v[r] = i < n ? vals_in[i] : 0u;
+  }
+  if (MODE == kScatterUnpack) {
+    const uint32_t l0 = s_lowblk[0], l1 = s_lowblk[1];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const size_t i = base + (size_t)r * 64;
+      if (i < n) {
+        const uint32_t low = l0 == l1 ? l0 : digit_at(s_low, (uint32_t)i);
+        v[r] = k[r] & 0x00ffffffu;
+        k[r] = ((k[r] >> 24) << 8) | low;
+      } else {
+        v[r] = 0u;
+      }
+    }
   }
   const uint64_t lt = lanemask_lt();
 #pragma unroll
@@ -252,25 +299,28 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
     lstart[tid] = wpre + incl - tot;
     __syncthreads();
   }
-  const size_t blk0 = (size_t)blockIdx.x * kSortTileItems;
-  const size_t valid_items = n > blk0 ? (n - blk0 < (size_t)kSortTileItems ? n - blk0 : (size_t)kSortTileItems) : 0;
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     if (base + (size_t)r * 64 < n) {
       const uint32_t d = (k[r] >> shift) & 0xffu;
       const uint32_t pos = lstart[d] + wc[wave][d] + rank[r];
-      s_keys[pos] = k[r];
-      s_vals[pos] = v[r];
+      if (MODE == kScatterPack) {
+        s_keys[pos] = ((k[r] >> 8) << 24) | v[r];
+        s_dig[pos] = (uint8_t)d;
+      } else {
+        s_keys[pos] = k[r];
+        s_vals[pos] = v[r];
+      }
     }
   }
   __syncthreads();
   for (uint32_t p = tid; p < valid_items; p += kThreads) {
     const uint32_t key = s_keys[p];
-    const uint32_t d = (key >> shift) & 0xffu;
+    const uint32_t d = MODE == kScatterPack ? (uint32_t)s_dig[p] : (key >> shift) & 0xffu;
     const size_t dst = (size_t)goff[d] + (p - lstart[d]);
     if (dst < n) {   // always true for a consistent histogram; guards the write
       keys_out[dst] = key;
-      vals_out[dst] = s_vals[p];
+      if (MODE != kScatterPack) vals_out[dst] = s_vals[p];
     }
   }
 }
@@ -686,29 +736,45 @@ unsigned grid_for(size_t n, unsigned threads, unsigned cap = 1u << 20) {
 
 size_t sort_hist_words(size_t n) {
   const size_t nb = (n + kSortTileItems - 1) / kSortTileItems;
-  return (size_t)kRadix * (nb + (nb + kScanChunk - 1) / kScanChunk + 1);   // table, chunk sums, digit bases
+  // table, chunk sums, digit bases of a pass and of the pass before it
+  return (size_t)kRadix * (nb + (nb + kScanChunk - 1) / kScanChunk + 2);
 }
 
 hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, size_t n,
-                            int bits, SortScratch scratch, int* result_in_b, hipStream_t s) {
+                            int bits, int vals24, SortScratch scratch, int* result_in_b, hipStream_t s) {
   *result_in_b = 0;
   if (n == 0 || bits <= 0) return hipSuccess;
   const int n_blocks = (int)((n + kSortTileItems - 1) / kSortTileItems);
   const int cs = chunk_blocks(n_blocks);
   const int n_chunks = (n_blocks + cs - 1) / cs;
   uint32_t* chunk_sum = scratch.hist + (size_t)kRadix * n_blocks;
-  uint32_t* digit_base = chunk_sum + (size_t)kRadix * n_chunks;
+  uint32_t* digit_base[2] = {chunk_sum + (size_t)kRadix * n_chunks, chunk_sum + (size_t)kRadix * (n_chunks + 1)};
+  // digit table, its scan and the digit starts of the pass at `shift`, into digit_base[db]
+  auto scan_pass = [&](const uint32_t* keys, int shift, int db) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(n_blocks), dim3(kThreads), 0, s, keys, n, shift, scratch.hist, n_blocks);
+    hipLaunchKernelGGL(k_radix_chunk_sums, dim3(n_chunks), dim3(kRadix), 0, s, scratch.hist, n_blocks, cs,
+                       chunk_sum);
+    hipLaunchKernelGGL(k_radix_chunk_scan, dim3(1), dim3(kChunkScanThreads), 0, s, chunk_sum, n_chunks,
+                       digit_base[db]);
+    hipLaunchKernelGGL(k_radix_chunk_apply, dim3(n_chunks), dim3(kRadix), 0, s, scratch.hist, n_blocks, cs, chunk_sum,
+                       digit_base[db]);
+  };
+  if (bits > 8 && bits <= 16 && vals24) {
+    // two passes moving one packed word between them; the result lands in *_a
+    scan_pass(keys_a, 0, 0);
+    hipLaunchKernelGGL(k_radix_scatter<kScatterPack>, dim3(n_blocks), dim3(kThreads), 0, s, keys_a, vals_a, n, 0,
+                       scratch.hist, nullptr, keys_b, nullptr);
+    scan_pass(keys_b, 24, 1);
+    hipLaunchKernelGGL(k_radix_scatter<kScatterUnpack>, dim3(n_blocks), dim3(kThreads), 0, s, keys_b, nullptr, n, 8,
+                       scratch.hist, digit_base[0], keys_a, vals_a);
+    return hipGetLastError();
+  }
   uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
   int in_b = 0;
   for (int shift = 0; shift < bits; shift += 8) {
-    hipLaunchKernelGGL(k_radix_hist, dim3(n_blocks), dim3(kThreads), 0, s, ki, n, shift, scratch.hist, n_blocks);
-    hipLaunchKernelGGL(k_radix_chunk_sums, dim3(n_chunks), dim3(kRadix), 0, s, scratch.hist, n_blocks, cs,
-                       chunk_sum);
-    hipLaunchKernelGGL(k_radix_chunk_scan, dim3(1), dim3(kChunkScanThreads), 0, s, chunk_sum, n_chunks, digit_base);
-    hipLaunchKernelGGL(k_radix_chunk_apply, dim3(n_chunks), dim3(kRadix), 0, s, scratch.hist, n_blocks, cs, chunk_sum,
-                       digit_base);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(n_blocks), dim3(kThreads), 0, s, ki, vi, n, shift, scratch.hist,
-                       n_blocks, ko, vo);
+    scan_pass(ki, shift, 0);
+    hipLaunchKernelGGL(k_radix_scatter<kScatterPlain>, dim3(n_blocks), dim3(kThreads), 0, s, ki, vi, n, shift,
+                       scratch.hist, nullptr, ko, vo);
     uint32_t* t;
     t = ki; ki = ko; ko = t;
     t = vi; vi = vo; vo = t;
