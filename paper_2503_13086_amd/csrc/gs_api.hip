@@ -37,7 +37,7 @@ struct gs_ctx {
   int depth_in_b = 0, pairs_in_b = 0;
   int cull = GS_CULL_ELLIPSE;
   DevBuf views, rec, depth, touched, rect;
-  DevBuf dkey[2], dval[2], counts, offsets, blocksums, total, hist;
+  DevBuf dkey[2], dval[2], groupsums, blocksums, total, hist;
   DevBuf pkey[2], pval[2], ranges;
   DevBuf tfinal, ncontrib, last, grad2d, lossp, aux;
   DevBuf asum, dG, loadp, loadst, kept, emitinfo;
@@ -85,7 +85,7 @@ gs_status ensure(gs_ctx* c, DevBuf& b, size_t bytes, hipStream_t s) {
 
 std::vector<DevBuf*> all_bufs(gs_ctx* c) {
   return {&c->views, &c->rec, &c->depth, &c->touched, &c->rect, &c->dkey[0], &c->dkey[1], &c->dval[0],
-          &c->dval[1], &c->counts, &c->offsets, &c->blocksums, &c->total, &c->hist, &c->pkey[0],
+          &c->dval[1], &c->groupsums, &c->blocksums, &c->total, &c->hist, &c->pkey[0],
           &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->tfinal, &c->ncontrib, &c->last,
           &c->grad2d, &c->lossp, &c->aux, &c->asum, &c->dG, &c->loadp, &c->loadst, &c->kept, &c->emitinfo};
 }
@@ -271,8 +271,7 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
     if ((st = ensure(c, c->dkey[i], NV * 4, s)) != GS_OK) return st;
     if ((st = ensure(c, c->dval[i], NV * 4, s)) != GS_OK) return st;
   }
-  if ((st = ensure(c, c->offsets, NV * 4, s)) != GS_OK) return st;
-  if ((st = ensure(c, c->counts, NV * 4, s)) != GS_OK) return st;
+  if ((st = ensure(c, c->groupsums, scan_group_words(NV) * 4, s)) != GS_OK) return st;
   if ((st = ensure(c, c->blocksums, scan_block_words(NV) * 4, s)) != GS_OK) return st;
   if ((st = ensure(c, c->total, 8, s)) != GS_OK) return st;
   if ((st = ensure(c, c->hist, sort_hist_words(NV) * 4, s)) != GS_OK) return st;
@@ -294,22 +293,17 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
   const bool packed = NV <= kPackMaxEntries;
   {
     Prof pr(c, GS_K_DEPTH_SORT, s);
-    GS_HIP(c, hipMemcpyAsync(c->dkey[0].p, c->depth.p, NV * 4, hipMemcpyDeviceToDevice, s));
-    if (packed) {
-      GS_HIP(c, launch_pack_order(per_entry, NV, c->dval[0].as<uint32_t>(), s));
-    } else {
-      GS_HIP(c, launch_iota(c->dval[0].as<uint32_t>(), NV, s));
-    }
     SortScratch sc{c->hist.as<uint32_t>()};
-    GS_HIP(c, radix_sort_pairs(c->dkey[0].as<uint32_t>(), c->dval[0].as<uint32_t>(), c->dkey[1].as<uint32_t>(),
-                               c->dval[1].as<uint32_t>(), NV, 32, 0, sc, &c->depth_in_b, s));
+    GS_HIP(c, radix_sort_depth(c->depth.as<uint32_t>(), packed ? per_entry : nullptr, c->dkey[0].as<uint32_t>(),
+                               c->dval[0].as<uint32_t>(), c->dkey[1].as<uint32_t>(), c->dval[1].as<uint32_t>(), NV,
+                               sc, s));
+    c->depth_in_b = 0;
   }
   const uint32_t* order = c->dval[c->depth_in_b].as<uint32_t>();
   {
     Prof pr(c, GS_K_SCAN, s);
-    GS_HIP(c, launch_scan_touched(order, packed ? 1 : 0, per_entry, NV, c->counts.as<uint32_t>(),
-                                  c->offsets.as<uint32_t>(), c->blocksums.as<uint32_t>(),
-                                  c->total.as<unsigned long long>(), s));
+    GS_HIP(c, launch_scan_touched(order, packed ? 1 : 0, per_entry, NV, c->groupsums.as<uint32_t>(),
+                                  c->blocksums.as<uint32_t>(), c->total.as<unsigned long long>(), s));
   }
   GS_HIP(c, hipMemcpyAsync(c->h_total, c->total.p, 8, hipMemcpyDeviceToHost, s));
   GS_HIP(c, hipStreamSynchronize(s));
@@ -323,8 +317,8 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
   if ((st = ensure(c, c->ranges, (size_t)c->n_tiles * 8, s)) != GS_OK) return st;
   {
     Prof pr(c, GS_K_EMIT, s);
-    GS_HIP(c, launch_emit_pairs(order, packed ? 1 : 0, c->counts.as<uint32_t>(), c->offsets.as<uint32_t>(),
-                                c->rect.as<ushort4>(),
+    GS_HIP(c, launch_emit_pairs(order, packed ? 1 : 0, per_entry, c->groupsums.as<uint32_t>(),
+                                c->blocksums.as<uint32_t>(), c->rect.as<ushort4>(),
                                 c->rec.as<Record>(), NV, c->n, c->views.as<ViewDev>(), (size_t)K, cull ? 1 : 0,
                                 c->tile, cull ? c->emitinfo.as<EmitInfo>() : nullptr, c->pkey[0].as<uint32_t>(),
                                 c->pval[0].as<uint32_t>(), s));

@@ -111,7 +111,10 @@ constexpr int kSortTileItems = 4096;
 size_t sort_hist_words(size_t n);
 hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, size_t n,
                             int bits, int vals24, SortScratch scratch, int* result_in_b, hipStream_t s);
-hipError_t launch_iota(uint32_t* p, size_t n, hipStream_t s);
+// Stable sort of the entries 0..n-1 by depth[e] (32-bit keys, read only): values
+// e, with count given e | min(count[e], 255) << 24 (n <= 2^24); result in *_a
+hipError_t radix_sort_depth(const uint32_t* depth, const uint32_t* count, uint32_t* keys_a, uint32_t* vals_a,
+                            uint32_t* keys_b, uint32_t* vals_b, size_t n, SortScratch scratch, hipStream_t s);
 // Depth-sort values that carry the entry's pair count: index in the low 24 bits,
 // min(count, 255) in the top byte (255: read the count from the per-entry array).
 // Used when the entries number at most 2^24.
@@ -119,14 +122,15 @@ constexpr size_t kPackMaxEntries = (size_t)1 << 24;
 constexpr int kPackShift = 24;
 constexpr uint32_t kPackSat = 255u;
 constexpr uint32_t kPackRidMask = 0x00ffffffu;
-hipError_t launch_pack_order(const uint32_t* count, size_t n, uint32_t* p, hipStream_t s);
 
-// counts[e] = touched[order[e]] and its exclusive scan over e; total written to *total
+// Scan of the depth-ordered counts touched[order[e]]: group_sums[g] = sum over the
+// 64 entries [64 g, 64 g + 64) (scan_group_words(n) words), block_sums[b] = the
+// exclusive prefix at entry 4096 b (scan_block_words(n) words), *total = the sum
+// (packed != 0: order entries come from radix_sort_depth with counts)
 size_t scan_block_words(size_t n);
-// counts[i] = touched[order[i]]; offsets = exclusive prefix of counts; *total = sum
-// (packed != 0: order entries come from launch_pack_order)
-hipError_t launch_scan_touched(const uint32_t* order, int packed, const uint32_t* touched, size_t n, uint32_t* counts,
-                               uint32_t* offsets, uint32_t* block_sums, unsigned long long* total, hipStream_t s);
+inline size_t scan_group_words(size_t n) { return (n + 63) / 64; }
+hipError_t launch_scan_touched(const uint32_t* order, int packed, const uint32_t* touched, size_t n,
+                               uint32_t* group_sums, uint32_t* block_sums, unsigned long long* total, hipStream_t s);
 // kept[e] = tiles of entry e's rect whose pixel-centre box meets its cutoff region
 // (entries in index order; rect tile count in touched)
 // What emission fetches per culled entry: its tile rect and, for rects of at most
@@ -138,13 +142,13 @@ struct alignas(16) EmitInfo {
 };
 hipError_t launch_count_kept(const uint32_t* touched, const ushort4* rect, const Record* rec, size_t n_entries, int n,
                              const ViewDev* views, int tile, uint32_t* kept, EmitInfo* info, hipStream_t s);
-// pairs of the depth-ordered entries order[0..n_entries): counts/offsets are the
-// scanned per-entry pair counts; cull != 0 keeps only the rect tiles that meet the
-// cutoff region (counts must then be the kept counts)
-hipError_t launch_emit_pairs(const uint32_t* order, int packed, const uint32_t* counts, const uint32_t* offsets,
-                             const ushort4* rect, const Record* rec, size_t n_entries, int n, const ViewDev* views,
-                             size_t K, int cull, int tile, const EmitInfo* info, uint32_t* pair_tile,
-                             uint32_t* pair_rec, hipStream_t s);
+// pairs of the depth-ordered entries order[0..n_entries): touched, group_sums and
+// block_sums as scanned by launch_scan_touched; cull != 0 keeps only the rect tiles
+// that meet the cutoff region (touched must then be the kept counts)
+hipError_t launch_emit_pairs(const uint32_t* order, int packed, const uint32_t* touched, const uint32_t* group_sums,
+                             const uint32_t* block_off, const ushort4* rect, const Record* rec, size_t n_entries,
+                             int n, const ViewDev* views, size_t K, int cull, int tile, const EmitInfo* info,
+                             uint32_t* pair_tile, uint32_t* pair_rec, hipStream_t s);
 hipError_t launch_ranges(const uint32_t* pair_tile, size_t K, uint2* ranges, int n_tiles, hipStream_t s);
 hipError_t launch_compose_keys(const uint32_t* pair_tile, const uint32_t* pair_rec, const uint32_t* depth,
                                size_t K, int n, size_t n_rec, unsigned long long* keys, uint32_t* values,

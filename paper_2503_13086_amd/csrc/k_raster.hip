@@ -87,10 +87,11 @@ __device__ inline TileGeom tile_geom(const ViewDev* __restrict__ views, int V, i
 // exponent peaks along vertical lines, and a cutoff tau_c = tau' (1 + 1e-5 kappa)
 // slightly below the pixel test's, kappa = (sqrt(ac) + |b|)^2 / (ac - b^2) bounding
 // (|A dx^2| + |B dx dy| + |C dy^2|) / |exponent|, so that fp32 rounding in either
-// test can never make the block test drop a Gaussian a pixel accepts.  det is taken
-// in FP64 (the fp32 entries multiply exactly there), kappa and kC in fp32 from it
-// (their relative errors, ~1e-6, only move the margin by as much of itself); a conic
-// that is not clearly positive definite (det <= 0 or kappa >= 1e4) gets
+// test can never make the block test drop a Gaussian a pixel accepts.  det = ac - b^2
+// is one fused multiply-add (error below ulp(b^2), so below 2e-4 det wherever
+// kappa < 1e4, and every conic with det <= 0 yields det < ulp(b^2), kappa > 1e4);
+// kappa and kC are fp32 too (their errors only move the margin by as much of itself).
+// A conic that is not clearly positive definite (det <= 0 or kappa >= 1e4) gets
 // tau_c = -inf, so every block lists it.
 //   q0 = (u', w', A, B)   q1 = (C, tau', tau_c, kC)   q2 = (o, r, g, b)
 // (the per-pixel test reads q0 and q1.xy, a blend q2).
@@ -100,12 +101,12 @@ __device__ inline void stage(const Record* __restrict__ rec, uint32_t rid, doubl
   const double2 uw = *reinterpret_cast<const double2*>(r);
   const float4 c = reinterpret_cast<const float4*>(r)[1];
   const float4 d = reinterpret_cast<const float4*>(r)[2];
-  const double det = (double)c.x * (double)c.z - (double)c.y * (double)c.y;
+  const float det = __fmaf_rn(c.x, c.z, -(c.y * c.y));
   const float tau2 = d.x * kLog2e;
   float tc = -INFINITY, kc = 0.0f;
-  if (det > 0.0) {
+  if (det > 0.0f) {
     const float s = __builtin_amdgcn_sqrtf(c.x * c.z) + fabsf(c.y);
-    const float kappa = (s * s) * __builtin_amdgcn_rcpf((float)det);
+    const float kappa = (s * s) * __builtin_amdgcn_rcpf(det);
     if (kappa < 1e4f) tc = tau2 * (1.0f + 1e-5f * kappa);
     kc = -c.y * __builtin_amdgcn_rcpf(c.z);
   }

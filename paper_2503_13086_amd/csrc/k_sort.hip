@@ -203,7 +203,10 @@ __global__ __launch_bounds__(kRadix) void k_radix_chunk_apply(uint32_t* __restri
 // byte from the item's position, its input being ordered by that byte: position i
 // holds the largest d with low_base[d] <= i, low_base being the first pass's digit
 // starts.
-constexpr int kScatterPlain = 0, kScatterPack = 1, kScatterUnpack = 2;
+// The first pass of a depth sort (kScatterIota) reads its keys from the caller's
+// array and forms the values itself: the entry index, with vals_in (per-entry pair
+// counts) given also min(count, 255) << 24.
+constexpr int kScatterPlain = 0, kScatterPack = 1, kScatterUnpack = 2, kScatterIota = 3;
 
 // Largest d in [0, 256) with base[d] <= i (base nondecreasing, base[0] = 0).
 __device__ inline uint32_t digit_at(const uint32_t* base, uint32_t i) {
@@ -251,7 +254,12 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
   for (int r = 0; r < kItems; ++r) {   // all loads in flight before any ranking
     const size_t i = base + (size_t)r * 64;
     k[r] = i < n ? keys_in[i] : 0xffffffffu;
-    if (MODE != kScatterUnpack) v[r] = i < n ? vals_in[i] : 0u;
+    if (MODE == kScatterIota) {
+      const uint32_t c = vals_in && i < n ? vals_in[i] : 0u;
+      v[r] = (uint32_t)i | (vals_in ? (c < kPackSat ? c : kPackSat) << kPackShift : 0u);
+    } else if (MODE != kScatterUnpack) {
+      v[r] = i < n ? vals_in[i] : 0u;
+    }
   }
   if (MODE == kScatterUnpack) {
     const uint32_t l0 = s_lowblk[0], l1 = s_lowblk[1];
@@ -325,21 +333,6 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
   }
 }
 
-__global__ void k_iota(uint32_t* __restrict__ p, size_t n) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    p[i] = (uint32_t)i;
-}
-
-// p[e] = e | min(count[e], 255) << 24 (n <= 2^24): the depth sort then carries
-// each entry's pair count with its index, and the scan in depth order reads it
-// without a gather.
-__global__ void k_pack_order(const uint32_t* __restrict__ count, size_t n, uint32_t* __restrict__ p) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const uint32_t c = count[i];
-    p[i] = (uint32_t)i | ((c < kPackSat ? c : kPackSat) << kPackShift);
-  }
-}
-
 // ---- exclusive scan of touched[order[e]] ----
 constexpr int kScanItems = 4096;
 
@@ -353,33 +346,43 @@ __device__ inline uint32_t block_sum_u32(uint32_t x, uint32_t* sh) {
   return t;
 }
 
-// Block sums of touched[order[e]]; the gathered counts are stored in depth order
-// (counts[e]) so the later passes read them contiguously.
-// With packed != 0 the order entries carry min(count, 255) in their top byte (see
-// k_pack_order) and only the saturated ones gather their count.
+// Count of depth-ordered entry e: touched[order[e]].  With packed != 0 the order
+// entries carry min(count, 255) in their top byte (see radix_sort_depth) and only the
+// saturated ones gather their count.
+__device__ inline uint32_t entry_count(uint32_t o, int packed, const uint32_t* __restrict__ touched) {
+  if (!packed) return touched[o];
+  const uint32_t c = o >> kPackShift;
+  return c == kPackSat ? touched[o & kPackRidMask] : c;
+}
+
+// Sums of the counts of every 64 consecutive depth-ordered entries (group_sums,
+// one per wave of the emission) and of every kScanItems entries (block_sums).
+// Thread t takes 16 consecutive entries (four 16-byte loads), four lanes a group.
 __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t* __restrict__ order,
                                                            const uint32_t* __restrict__ touched, size_t n,
-                                                           int packed, uint32_t* __restrict__ counts,
+                                                           int packed, uint32_t* __restrict__ group_sums,
                                                            uint32_t* __restrict__ block_sums) {
+  static_assert(kScanItems == 16 * kThreads, "16 entries per thread");
   __shared__ uint32_t sh[kWaves];
-  const size_t base = (size_t)blockIdx.x * kScanItems;
-  uint32_t s = 0;
-  for (int r = 0; r < kScanItems / kThreads; ++r) {
-    const size_t i = base + (size_t)r * kThreads + threadIdx.x;
-    if (i < n) {
-      const uint32_t o = order[i];
-      uint32_t c;
-      if (packed) {
-        c = o >> kPackShift;
-        if (c == kPackSat) c = touched[o & kPackRidMask];
-      } else {
-        c = touched[o];
-      }
-      counts[i] = c;
-      s += c;
-    }
+  const size_t e0 = (size_t)blockIdx.x * kScanItems + 16 * (size_t)threadIdx.x;
+  uint32_t c = 0;
+  if (e0 + 16 <= n) {
+    const uint4* o4 = reinterpret_cast<const uint4*>(order + e0);
+    uint4 q[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = o4[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      c += entry_count(q[k].x, packed, touched) + entry_count(q[k].y, packed, touched) +
+           entry_count(q[k].z, packed, touched) + entry_count(q[k].w, packed, touched);
+  } else {
+    for (size_t i = e0; i < n && i < e0 + 16; ++i) c += entry_count(order[i], packed, touched);
   }
-  const uint32_t t = block_sum_u32(s, sh);
+  c += __shfl_xor(c, 1);
+  c += __shfl_xor(c, 2);
+  const bool lead = (threadIdx.x & 3u) == 0u;
+  if (lead && e0 < n) group_sums[e0 / 64] = c;
+  const uint32_t t = block_sum_u32(lead ? c : 0u, sh);
   if (threadIdx.x == 0) block_sums[blockIdx.x] = t;
 }
 
@@ -409,34 +412,6 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t* __restrict__ blo
     __syncthreads();
   }
   if (threadIdx.x == 0) *total = carry;
-}
-
-__global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t* __restrict__ counts, size_t n,
-                                                          const uint32_t* __restrict__ block_off,
-                                                          uint32_t* __restrict__ offsets) {
-  __shared__ uint32_t wsum[kWaves];
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = block_off[blockIdx.x];
-  __syncthreads();
-  const size_t base = (size_t)blockIdx.x * kScanItems;
-  for (int r = 0; r < kScanItems / kThreads; ++r) {
-    const size_t i = base + (size_t)r * kThreads + threadIdx.x;
-    const uint32_t x = i < n ? counts[i] : 0u;
-    uint32_t incl = x;
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t y = __shfl_up(incl, off);
-      if ((int)__lane_id() >= off) incl += y;
-    }
-    if (__lane_id() == 63) wsum[threadIdx.x / 64] = incl;
-    __syncthreads();
-    uint32_t wpre = 0;
-    for (int w = 0; w < (int)(threadIdx.x / 64); ++w) wpre += wsum[w];
-    const uint32_t c = carry;
-    if (i < n) offsets[i] = c + wpre + incl - x;
-    __syncthreads();
-    if (threadIdx.x == kThreads - 1) carry = c + wpre + incl;
-    __syncthreads();
-  }
 }
 
 // Inclusive max over lanes 0..l (DPP: shifts within rows of 16 lanes, then the
@@ -578,9 +553,10 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
 // offsets agree), and kept candidates are written in order at running positions
 // taken from a ballot: writes are coalesced and large rects are shared by the wave.
 // With culling the entry's rect comes from its EmitInfo (one 16-byte fetch).
-__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ order, uint32_t rid_mask,
-                                                    const uint32_t* __restrict__ counts,
-                                                    const uint32_t* __restrict__ offsets,
+__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ order, int packed,
+                                                    const uint32_t* __restrict__ touched,
+                                                    const uint32_t* __restrict__ group_sums,
+                                                    const uint32_t* __restrict__ block_off,
                                                     const ushort4* __restrict__ rect,
                                                     const Record* __restrict__ rec, size_t n_entries, int n,
                                                     const ViewDev* __restrict__ views, size_t K, int cull, int T,
@@ -601,13 +577,13 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
   const unsigned lane = __lane_id();
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = e < n_entries;
-  uint32_t cnt = 0, off = 0, rid = 0, cand = 0;
+  uint32_t cnt = 0, rid = 0, cand = 0;
   uint64_t bits = 0ull;
   ushort4 rc = make_ushort4(0, 0, 0, 0);
   if (valid) {
-    rid = order[e] & rid_mask;
-    cnt = counts[e];
-    off = offsets[e];
+    const uint32_t o = order[e];
+    rid = packed ? o & kPackRidMask : o;
+    cnt = packed ? o >> kPackShift : touched[rid];   // nonzero iff the entry has pairs
     if (cnt) {
       if (cull) {
         const EmitInfo in = info[rid];
@@ -618,12 +594,6 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
       }
       cand = (uint32_t)(rc.y - rc.x + 1) * (uint32_t)(rc.w - rc.z + 1);
     }
-  }
-  // output range of the wave: from its first entry's offset to its last entry's end
-  uint32_t lo_off = valid ? off : 0xffffffffu, hi_end = valid ? off + cnt : 0u;
-  for (int o = 32; o > 0; o >>= 1) {
-    lo_off = min(lo_off, (uint32_t)__shfl_xor((int)lo_off, o));
-    hi_end = max(hi_end, (uint32_t)__shfl_xor((int)hi_end, o));
   }
   const uint32_t incl = wave_incl_scan(cand);
   s_cp[w][lane + 1] = incl;
@@ -645,7 +615,16 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
   }
   __builtin_amdgcn_wave_barrier();
   const uint32_t C = s_cp[w][64];
-  if (hi_end > K || C == 0u) return;        // never past K for a consistent scan; guards the writes
+  if (C == 0u) return;
+  // output range of the wave (group g of 64 entries, valid since C > 0): the start
+  // of its scan block plus the sums of the block's earlier groups, then its own sum
+  const size_t g = ((size_t)blockIdx.x * blockDim.x + (size_t)w * 64) / 64;
+  const size_t gb = g & ~(size_t)(kScanItems / 64 - 1);
+  uint32_t before = gb + lane < g ? group_sums[gb + lane] : 0u;
+  for (int o = 32; o > 0; o >>= 1) before += (uint32_t)__shfl_xor((int)before, o);
+  const uint32_t lo_off = block_off[g / (kScanItems / 64)] + before;
+  const uint32_t hi_end = lo_off + group_sums[g];
+  if (hi_end > K || hi_end < lo_off) return;   // never for a consistent scan; guards the writes
   uint32_t pos = lo_off;
   int carry = 0;
   for (uint32_t cb = 0; cb < C; cb += 64) {
@@ -740,41 +719,55 @@ size_t sort_hist_words(size_t n) {
   return (size_t)kRadix * (nb + (nb + kScanChunk - 1) / kScanChunk + 2);
 }
 
+namespace {
+// Digit table of the pass at `shift` over keys, its scan, and the digit starts into
+// digit_base[db] (two slots: a pass and the one before it).
+struct PassScan {
+  size_t n;
+  int n_blocks, cs, n_chunks;
+  uint32_t *hist, *chunk_sum, *digit_base[2];
+  PassScan(size_t n_, SortScratch sc) : n(n_) {
+    n_blocks = (int)((n + kSortTileItems - 1) / kSortTileItems);
+    cs = chunk_blocks(n_blocks);
+    n_chunks = (n_blocks + cs - 1) / cs;
+    hist = sc.hist;
+    chunk_sum = hist + (size_t)kRadix * n_blocks;
+    digit_base[0] = chunk_sum + (size_t)kRadix * n_chunks;
+    digit_base[1] = digit_base[0] + kRadix;
+  }
+  void run(const uint32_t* keys, int shift, int db, hipStream_t s) const {
+    hipLaunchKernelGGL(k_radix_hist, dim3(n_blocks), dim3(kThreads), 0, s, keys, n, shift, hist, n_blocks);
+    hipLaunchKernelGGL(k_radix_chunk_sums, dim3(n_chunks), dim3(kRadix), 0, s, hist, n_blocks, cs, chunk_sum);
+    hipLaunchKernelGGL(k_radix_chunk_scan, dim3(1), dim3(kChunkScanThreads), 0, s, chunk_sum, n_chunks,
+                       digit_base[db]);
+    hipLaunchKernelGGL(k_radix_chunk_apply, dim3(n_chunks), dim3(kRadix), 0, s, hist, n_blocks, cs, chunk_sum,
+                       digit_base[db]);
+  }
+};
+}  // namespace
+
 hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, size_t n,
                             int bits, int vals24, SortScratch scratch, int* result_in_b, hipStream_t s) {
   *result_in_b = 0;
   if (n == 0 || bits <= 0) return hipSuccess;
-  const int n_blocks = (int)((n + kSortTileItems - 1) / kSortTileItems);
-  const int cs = chunk_blocks(n_blocks);
-  const int n_chunks = (n_blocks + cs - 1) / cs;
-  uint32_t* chunk_sum = scratch.hist + (size_t)kRadix * n_blocks;
-  uint32_t* digit_base[2] = {chunk_sum + (size_t)kRadix * n_chunks, chunk_sum + (size_t)kRadix * (n_chunks + 1)};
-  // digit table, its scan and the digit starts of the pass at `shift`, into digit_base[db]
-  auto scan_pass = [&](const uint32_t* keys, int shift, int db) {
-    hipLaunchKernelGGL(k_radix_hist, dim3(n_blocks), dim3(kThreads), 0, s, keys, n, shift, scratch.hist, n_blocks);
-    hipLaunchKernelGGL(k_radix_chunk_sums, dim3(n_chunks), dim3(kRadix), 0, s, scratch.hist, n_blocks, cs,
-                       chunk_sum);
-    hipLaunchKernelGGL(k_radix_chunk_scan, dim3(1), dim3(kChunkScanThreads), 0, s, chunk_sum, n_chunks,
-                       digit_base[db]);
-    hipLaunchKernelGGL(k_radix_chunk_apply, dim3(n_chunks), dim3(kRadix), 0, s, scratch.hist, n_blocks, cs, chunk_sum,
-                       digit_base[db]);
-  };
+  const PassScan ps(n, scratch);
+  const dim3 grid(ps.n_blocks);
   if (bits > 8 && bits <= 16 && vals24) {
     // two passes moving one packed word between them; the result lands in *_a
-    scan_pass(keys_a, 0, 0);
-    hipLaunchKernelGGL(k_radix_scatter<kScatterPack>, dim3(n_blocks), dim3(kThreads), 0, s, keys_a, vals_a, n, 0,
-                       scratch.hist, nullptr, keys_b, nullptr);
-    scan_pass(keys_b, 24, 1);
-    hipLaunchKernelGGL(k_radix_scatter<kScatterUnpack>, dim3(n_blocks), dim3(kThreads), 0, s, keys_b, nullptr, n, 8,
-                       scratch.hist, digit_base[0], keys_a, vals_a);
+    ps.run(keys_a, 0, 0, s);
+    hipLaunchKernelGGL(k_radix_scatter<kScatterPack>, grid, dim3(kThreads), 0, s, keys_a, vals_a, n, 0, ps.hist,
+                       nullptr, keys_b, nullptr);
+    ps.run(keys_b, 24, 1, s);
+    hipLaunchKernelGGL(k_radix_scatter<kScatterUnpack>, grid, dim3(kThreads), 0, s, keys_b, nullptr, n, 8, ps.hist,
+                       ps.digit_base[0], keys_a, vals_a);
     return hipGetLastError();
   }
   uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
   int in_b = 0;
   for (int shift = 0; shift < bits; shift += 8) {
-    scan_pass(ki, shift, 0);
-    hipLaunchKernelGGL(k_radix_scatter<kScatterPlain>, dim3(n_blocks), dim3(kThreads), 0, s, ki, vi, n, shift,
-                       scratch.hist, nullptr, ko, vo);
+    ps.run(ki, shift, 0, s);
+    hipLaunchKernelGGL(k_radix_scatter<kScatterPlain>, grid, dim3(kThreads), 0, s, ki, vi, n, shift, ps.hist,
+                       nullptr, ko, vo);
     uint32_t* t;
     t = ki; ki = ko; ko = t;
     t = vi; vi = vo; vo = t;
@@ -784,37 +777,46 @@ hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b
   return hipGetLastError();
 }
 
-hipError_t launch_iota(uint32_t* p, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, p, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_pack_order(const uint32_t* count, size_t n, uint32_t* p, hipStream_t s) {
-  if (n > kPackMaxEntries) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pack_order, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, count, n, p);
-  return hipGetLastError();
+hipError_t radix_sort_depth(const uint32_t* depth, const uint32_t* count, uint32_t* keys_a, uint32_t* vals_a,
+                            uint32_t* keys_b, uint32_t* vals_b, size_t n, SortScratch scratch, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (count && n > kPackMaxEntries) return hipErrorInvalidValue;
+  const PassScan ps(n, scratch);
+  const dim3 grid(ps.n_blocks);
+  ps.run(depth, 0, 0, s);
+  hipLaunchKernelGGL(k_radix_scatter<kScatterIota>, grid, dim3(kThreads), 0, s, depth, count, n, 0, ps.hist, nullptr,
+                     keys_b, vals_b);
+  uint32_t *ki = keys_b, *vi = vals_b, *ko = keys_a, *vo = vals_a;
+  for (int shift = 8; shift < 32; shift += 8) {
+    ps.run(ki, shift, 0, s);
+    hipLaunchKernelGGL(k_radix_scatter<kScatterPlain>, grid, dim3(kThreads), 0, s, ki, vi, n, shift, ps.hist,
+                       nullptr, ko, vo);
+    uint32_t* t;
+    t = ki; ki = ko; ko = t;
+    t = vi; vi = vo; vo = t;
+  }
+  return hipGetLastError();   // three passes after the first: the result is in *_a
 }
 
 size_t scan_block_words(size_t n) { return (n + kScanItems - 1) / kScanItems + 1; }
 
-hipError_t launch_scan_touched(const uint32_t* order, int packed, const uint32_t* touched, size_t n, uint32_t* counts,
-                               uint32_t* offsets, uint32_t* block_sums, unsigned long long* total, hipStream_t s) {
+hipError_t launch_scan_touched(const uint32_t* order, int packed, const uint32_t* touched, size_t n,
+                               uint32_t* group_sums, uint32_t* block_sums, unsigned long long* total, hipStream_t s) {
   const int nb = (int)((n + kScanItems - 1) / kScanItems);
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, s, order, touched, n, packed, counts, block_sums);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, s, order, touched, n, packed, group_sums,
+                     block_sums);
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, block_sums, nb, total);
-  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kThreads), 0, s, counts, n, block_sums, offsets);
   return hipGetLastError();
 }
 
-hipError_t launch_emit_pairs(const uint32_t* order, int packed, const uint32_t* counts, const uint32_t* offsets,
-                             const ushort4* rect, const Record* rec, size_t n_entries, int n, const ViewDev* views,
-                             size_t K, int cull, int tile, const EmitInfo* info, uint32_t* pair_tile,
-                             uint32_t* pair_rec, hipStream_t s) {
+hipError_t launch_emit_pairs(const uint32_t* order, int packed, const uint32_t* touched, const uint32_t* group_sums,
+                             const uint32_t* block_off, const ushort4* rect, const Record* rec, size_t n_entries,
+                             int n, const ViewDev* views, size_t K, int cull, int tile, const EmitInfo* info,
+                             uint32_t* pair_tile, uint32_t* pair_rec, hipStream_t s) {
   if (n_entries == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n_entries + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, order, packed ? kPackRidMask : 0xffffffffu, counts,
-                     offsets, rect, rec, n_entries, n,
-                     views, K, cull, tile, info, pair_tile, pair_rec);
+  hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, order, packed, touched, group_sums, block_off, rect,
+                     rec, n_entries, n, views, K, cull, tile, info, pair_tile, pair_rec);
   return hipGetLastError();
 }
 
