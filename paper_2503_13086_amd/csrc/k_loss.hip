@@ -6,7 +6,8 @@
 // output tiles (256 threads); each workgroup stages the 42x42 halo of a channel
 // in LDS and applies the separable window in two register-blocked passes: a
 // thread filters 8 consecutive columns of a row (reading 18 staged values once),
-// then 4 consecutive rows of a column.
+// then 4 consecutive rows of a column, one windowed map at a time (the LDS holds
+// the staged planes and one half-filtered map).
 //
 // Backward: with N1 = 2 mx my + C1, N2 = 2 sxy + C2, D1 = mx^2 + my^2 + C1,
 // D2 = sxx + syy + C2 and S = N1 N2 / (D1 D2), the per-pixel partials of S with
@@ -172,11 +173,30 @@ __device__ inline void vpass(const float (*in)[HALO * LT], const Win& win, int c
   }
 }
 
+// One windowed map of the staged planes (form makes its value from theirs) for
+// this thread's VSEG outputs; the workgroup's LDS map buffer is free again on return.
+template <int NIN, class F>
+__device__ inline void window_map(const float (*in)[HALO * HS], float (*hb)[HALO * LT], const Win& win, int col,
+                                  int r0, F form, float (&res)[VSEG]) {
+  hpass<NIN, 1>(in, hb, win, form);
+  __syncthreads();
+  float mq[1][VSEG];
+  vpass<1>(hb, win, col, r0, mq);
+  // the sums are formed here: left alone, the compiler sinks them into the
+  // per-pixel branches at the end and keeps every loaded tap live until then
+#pragma unroll
+  for (int j = 0; j < VSEG; ++j) {
+    res[j] = mq[0][j];
+    asm volatile("" : "+v"(res[j]));
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void k_ssim_fwd(const ViewDev* __restrict__ views, int V, LossTiles lt,
                                                    const float* __restrict__ x, const float* __restrict__ y,
                                                    float* __restrict__ aux, Win win, double2* __restrict__ partials) {
   __shared__ float sin_[2][HALO * HS];
-  __shared__ float hbuf[3][HALO * LT];   // the five maps in two rounds (3 + 2): 30 KB of LDS
+  __shared__ float hbuf[1][HALO * LT];   // the five maps one after another: 20 KB of LDS
   __shared__ double sh[4];
   const int tile = xcd_tile(blockIdx.x, lt.off[V]);
   if (tile >= lt.off[V]) return;
@@ -191,32 +211,11 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const ViewDev* __restrict__ vi
     stage_halo<2>(sin_, src, cv.W, cv.H, t.x0, t.y0);
     __syncthreads();
     float m[5][VSEG];
-    {
-      hpass<2, 3>(sin_, hbuf, win, [](const float* v, float* f) {
-        f[0] = v[0];
-        f[1] = v[1];
-        f[2] = v[0] * v[0];
-      });
-      __syncthreads();
-      float mm[3][VSEG];
-      vpass<3>(hbuf, win, col, r0, mm);
-#pragma unroll
-      for (int q = 0; q < 3; ++q)
-#pragma unroll
-        for (int j = 0; j < VSEG; ++j) m[q][j] = mm[q][j];
-      __syncthreads();
-      hpass<2, 2>(sin_, hbuf, win, [](const float* v, float* f) {
-        f[0] = v[1] * v[1];
-        f[1] = v[0] * v[1];
-      });
-      __syncthreads();
-      float mn[2][VSEG];
-      vpass<2>(hbuf, win, col, r0, mn);
-#pragma unroll
-      for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int j = 0; j < VSEG; ++j) m[3 + q][j] = mn[q][j];
-    }
+    window_map<2>(sin_, hbuf, win, col, r0, [](const float* v, float* f) { f[0] = v[0]; }, m[0]);
+    window_map<2>(sin_, hbuf, win, col, r0, [](const float* v, float* f) { f[0] = v[1]; }, m[1]);
+    window_map<2>(sin_, hbuf, win, col, r0, [](const float* v, float* f) { f[0] = v[0] * v[0]; }, m[2]);
+    window_map<2>(sin_, hbuf, win, col, r0, [](const float* v, float* f) { f[0] = v[1] * v[1]; }, m[3]);
+    window_map<2>(sin_, hbuf, win, col, r0, [](const float* v, float* f) { f[0] = v[0] * v[1]; }, m[4]);
     float* ac = aux + (size_t)cv.pix_off * 9 + (size_t)ch * 3 * hw;
 #pragma unroll
     for (int j = 0; j < VSEG; ++j) {
@@ -268,15 +267,8 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const ViewDev* __restrict__ vi
     __syncthreads();
     float m[3][VSEG];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      hpass<1, 1>(sin_ + q, hbuf, win, [](const float* v, float* f) { f[0] = v[0]; });
-      __syncthreads();
-      float mq[1][VSEG];
-      vpass<1>(hbuf, win, col, r0, mq);
-#pragma unroll
-      for (int j = 0; j < VSEG; ++j) m[q][j] = mq[0][j];
-      __syncthreads();
-    }
+    for (int q = 0; q < 3; ++q)
+      window_map<1>(sin_ + q, hbuf, win, col, r0, [](const float* v, float* f) { f[0] = v[0]; }, m[q]);
 #pragma unroll
     for (int j = 0; j < VSEG; ++j) {
       const int px = t.x0 + col, py = t.y0 + r0 + j;
