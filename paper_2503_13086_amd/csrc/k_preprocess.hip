@@ -6,10 +6,11 @@
 // conic, extent 3 sqrt(lambda_max), tile rect, cutoff exponent and SH colour.
 // One thread per Gaussian reads its parameters once (planar rows, coalesced) and
 // loops over the views, so parameter traffic does not grow with the view count.
-// Everything is evaluated in FP64: CDNA4 issues FP64 FMA at the non-packed FP32
-// rate and this kernel is bound by HBM traffic, so the FP64 arithmetic is hidden,
-// and depth, screen position and extent come out exactly as an IEEE FP64
-// evaluation in the same operation order (contraction is off in this file).
+// The geometry is evaluated in FP64 (CDNA4 issues FP64 FMA at the non-packed FP32
+// rate), so depth, screen position and extent come out exactly as an IEEE FP64
+// evaluation in the same operation order (contraction is off in this file); the
+// SH colour, which no discrete decision depends on, is fp32 (FP64 coefficients
+// held across the view loop cost 96 registers).
 //
 // Backward: one thread per Gaussian recomputes the forward quantities per view in
 // fp32 (gradients carry no discrete decision; visibility is the forward's
@@ -212,13 +213,14 @@ __device__ inline void project(const Gauss& G, const ViewDev& V, Proj& p) {
   p.ty0 = j0 / V.tile; p.ty1 = j1 / V.tile;
 }
 
-__device__ inline void camera_dir(const Gauss& G, const ViewDev& V, double dir[3], double& dn) {
-  double oc[3];
-  for (int k = 0; k < 3; ++k)
-    oc[k] = -(((double)V.R[k] * V.t[0] + (double)V.R[3 + k] * V.t[1]) + (double)V.R[6 + k] * V.t[2]);
-  const double d0 = G.m[0] - oc[0], d1 = G.m[1] - oc[1], d2 = G.m[2] - oc[2];
-  dn = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
-  dir[0] = d0 / dn; dir[1] = d1 / dn; dir[2] = d2 / dn;
+// Unit direction from the camera centre to the Gaussian in fp32 (feeds only the
+// SH colour).
+__device__ inline void camera_dir_f(const float m[3], const ViewDev& V, float dir[3]) {
+  float oc[3];
+  for (int k = 0; k < 3; ++k) oc[k] = -((V.R[k] * V.t[0] + V.R[3 + k] * V.t[1]) + V.R[6 + k] * V.t[2]);
+  const float d0 = m[0] - oc[0], d1 = m[1] - oc[1], d2 = m[2] - oc[2];
+  const float inv = 1.0f / sqrtf((d0 * d0 + d1 * d1) + d2 * d2);
+  dir[0] = d0 * inv; dir[1] = d1 * inv; dir[2] = d2 * inv;
 }
 
 template <int D>
@@ -236,6 +238,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ P,
   float f[3 * K];
 #pragma unroll
   for (int i = 0; i < 3 * K; ++i) f[i] = P[(size_t)(11 + i) * stride + g];
+  const float m[3] = {(float)G.m[0], (float)G.m[1], (float)G.m[2]};
   for (int v = 0; v < V; ++v) {
     const ViewDev& cv = views[v];
     Proj p;
@@ -247,17 +250,18 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ P,
       rect[idx] = make_ushort4(0, 0, 0, 0);
       continue;
     }
-    double dir[3], dn;
-    camera_dir(G, cv, dir, dn);
-    double Y[16];
+    // colour in fp32 (no discrete decision depends on it; error a few 1e-7)
+    float dir[3];
+    camera_dir_f(m, cv, dir);
+    float Y[16];
     sh_eval(D, dir[0], dir[1], dir[2], Y);
-    double col[3];
+    float col[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-      double acc = 0.5;
+      float acc = 0.5f;
 #pragma unroll
-      for (int k = 0; k < K; ++k) acc += (double)f[3 * k + ch] * Y[k];
-      col[ch] = acc < 0.0 ? 0.0 : acc;
+      for (int k = 0; k < K; ++k) acc = __fmaf_rn(f[3 * k + ch], Y[k], acc);
+      col[ch] = acc < 0.0f ? 0.0f : acc;
     }
     depth[idx] = __float_as_uint((float)p.tz);
     touched[idx] = (uint32_t)((p.tx1 - p.tx0 + 1) * (p.ty1 - p.ty0 + 1));
@@ -267,7 +271,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ P,
     r2[0] = make_double2(p.u, p.w);
     float4* r4 = reinterpret_cast<float4*>(rec + idx);
     r4[1] = make_float4((float)p.a, (float)p.b, (float)p.c, (float)G.o);
-    r4[2] = make_float4((float)tau, (float)col[0], (float)col[1], (float)col[2]);
+    r4[2] = make_float4((float)tau, col[0], col[1], col[2]);
   }
 }
 
