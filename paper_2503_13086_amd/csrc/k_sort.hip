@@ -553,6 +553,8 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
 // offsets agree), and kept candidates are written in order at running positions
 // taken from a ballot: writes are coalesced and large rects are shared by the wave.
 // With culling the entry's rect comes from its EmitInfo (one 16-byte fetch).
+constexpr int kEmitGeoSlots = 8;   // per wave: LDS for the geometry of its large entries
+
 __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ order, int packed,
                                                     const uint32_t* __restrict__ touched,
                                                     const uint32_t* __restrict__ group_sums,
@@ -572,7 +574,8 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
   __shared__ uint32_t s_wh[kWaves][64];     // view size (W | H << 16)
   __shared__ uint64_t s_bits[kWaves][64];   // test outcomes (entries of <= 64 candidates)
   __shared__ int s_own[kWaves][64];         // round_owner scratch
-  __shared__ CutoffGeo s_geo[kWaves][64];
+  __shared__ int s_slot[kWaves][64];        // entry's s_geo slot (-1: none)
+  __shared__ CutoffGeo s_geo[kWaves][kEmitGeoSlots];
   const int w = threadIdx.x / 64;
   const unsigned lane = __lane_id();
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -599,6 +602,13 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
   s_cp[w][lane + 1] = incl;
   if (lane == 0) s_cp[w][0] = 0u;
   s_rid[w][lane] = rid;
+  // entries of more than 64 candidates repeat the cutoff test: the first
+  // kEmitGeoSlots of the wave keep its geometry in LDS, any others re-derive it per
+  // candidate from the record
+  const bool large = cull && cand > 64u;
+  const uint64_t large_mask = __ballot(large);
+  const int slot = (int)__popcll(large_mask & lanemask_lt());
+  s_slot[w][lane] = large && slot < kEmitGeoSlots ? slot : -1;
   if (cand) {
     const ViewDev& cv = views[rid / (uint32_t)n];
     s_base[w][lane] = (uint32_t)cv.tile_off + (uint32_t)rc.z * (uint32_t)cv.tiles_x + rc.x;
@@ -606,10 +616,10 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
     s_tx[w][lane] = (uint32_t)cv.tiles_x;
     if (cull) {
       s_bits[w][lane] = bits;
-      if (cand > 64u) {
+      if (large) {
         s_org[w][lane] = (uint32_t)rc.x | ((uint32_t)rc.z << 16);
         s_wh[w][lane] = (uint32_t)cv.W | ((uint32_t)cv.H << 16);
-        s_geo[w][lane] = cutoff_geo(rec[rid]);
+        if (slot < kEmitGeoSlots) s_geo[w][slot] = cutoff_geo(rec[rid]);
       }
     }
   }
@@ -646,7 +656,9 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
           keep = ((s_bits[w][lo] >> li) & 1ull) != 0ull;
         } else {
           const uint32_t org = s_org[w][lo], wh = s_wh[w][lo];
-          keep = tile_meets_cutoff(s_geo[w][lo], (int)((org & 0xffffu) + tx), (int)((org >> 16) + ty), T,
+          const int sl = s_slot[w][lo];
+          const CutoffGeo geo = sl >= 0 ? s_geo[w][sl] : cutoff_geo(rec[r]);
+          keep = tile_meets_cutoff(geo, (int)((org & 0xffffu) + tx), (int)((org >> 16) + ty), T,
                                    (int)(wh & 0xffffu), (int)(wh >> 16));
         }
       }

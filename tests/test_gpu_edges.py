@@ -188,12 +188,20 @@ def test_argument_checks():
 def test_bin_sort_counts_past_255():
     """Gaussians spanning hundreds of tiles: per-entry pair counts above 255 (the
     depth sort's values carry counts only up to 255; larger ones are read back from
-    the per-entry array).  Keys, values and ranges bit-exact against the oracle."""
+    the per-entry array), and emission waves (64 depth-ordered entries) holding more
+    entries of over 64 candidate tiles than emission keeps in LDS (8; the rest re-derive
+    their test geometry from the record).  Keys, values and ranges bit-exact against
+    the oracle."""
     sc = scenegen.small_scene(21, 120, 0, [(1024, 768)], log_scale_mean=-1.2)
     projs = oracle.project_views(sc.params, sc.n, 0, sc.cams)
     b = oracle.bin_pairs(projs, sc.cams, 16, cull="ellipse")
     per_g = np.bincount(b["values"].astype(np.int64), minlength=sc.n)
     assert per_g.max() > 255 and (per_g > 0).sum() >= 50
+    p0 = projs[0]
+    vis = np.nonzero(p0["visible"])[0]
+    order = vis[np.lexsort((vis, p0["depth_bits"][vis]))]
+    large = (p0["touched"][order] > 64).astype(np.int64)
+    assert max(large[i:i + 64].sum() for i in range(0, len(order), 64)) > 8
     g = gu.run_gpu(sc)
     assert g["K"] == len(b["keys"])
     assert np.array_equal(g["keys"], b["keys"])
