@@ -217,30 +217,38 @@ __device__ inline uint32_t digit_at(const uint32_t* base, uint32_t i) {
   return lo;
 }
 
+// The scatter runs 512 threads (8 items each) on the same 4096-item tiles as the
+// histogram: half the registers per thread of a 256-thread tile, so twice the
+// wavefronts in flight.
+constexpr int kScatterThreads = 512;
+constexpr int kScatterWaves = kScatterThreads / 64;
+constexpr int kScatterItems = kSortTileItems / kScatterThreads;
+
 template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __restrict__ keys_in,
-                                                             const uint32_t* __restrict__ vals_in, size_t n, int shift,
-                                                             const uint32_t* __restrict__ offsets,
-                                                             const uint32_t* __restrict__ low_base,
-                                                             uint32_t* __restrict__ keys_out,
-                                                             uint32_t* __restrict__ vals_out) {
+__global__ __launch_bounds__(kScatterThreads) void k_radix_scatter(const uint32_t* __restrict__ keys_in,
+                                                                    const uint32_t* __restrict__ vals_in, size_t n,
+                                                                    int shift, const uint32_t* __restrict__ offsets,
+                                                                    const uint32_t* __restrict__ low_base,
+                                                                    uint32_t* __restrict__ keys_out,
+                                                                    uint32_t* __restrict__ vals_out) {
   __shared__ uint32_t s_keys[kSortTileItems];
   __shared__ uint32_t s_vals[MODE == kScatterPack ? 1 : kSortTileItems];
   __shared__ uint8_t s_dig[MODE == kScatterPack ? kSortTileItems : 1];   // packed words lose the digit
   __shared__ uint32_t s_low[MODE == kScatterUnpack ? kRadix : 1];
   __shared__ uint32_t s_lowblk[2];
-  __shared__ uint32_t wc[kWaves][kRadix];   // per-wave running digit counts
-  __shared__ uint32_t lstart[kRadix];       // workgroup-local start of each digit
-  __shared__ uint32_t goff[kRadix];         // global start of this workgroup's run of each digit
-  __shared__ uint32_t wsum[kWaves];
+  __shared__ uint32_t wc[kScatterWaves][kRadix];   // per-wave running digit counts
+  __shared__ uint32_t lstart[kRadix];              // workgroup-local start of each digit
+  __shared__ uint32_t goff[kRadix];                // global start of this workgroup's run of each digit
+  __shared__ uint32_t wsum[kRadix / 64];
   const int tid = threadIdx.x;
   const int wave = tid / 64;
-  for (int w = 0; w < kWaves; ++w) wc[w][tid] = 0;
-  goff[tid] = offsets[(size_t)blockIdx.x * kRadix + tid];
+  const bool digit_thread = tid < kRadix;          // threads 0-255 own one digit each
+  for (int i = tid; i < kScatterWaves * kRadix; i += kScatterThreads) (&wc[0][0])[i] = 0;
+  if (digit_thread) goff[tid] = offsets[(size_t)blockIdx.x * kRadix + tid];
   const size_t blk0 = (size_t)blockIdx.x * kSortTileItems;
   const size_t valid_items = n > blk0 ? (n - blk0 < (size_t)kSortTileItems ? n - blk0 : (size_t)kSortTileItems) : 0;
   if (MODE == kScatterUnpack) {
-    s_low[tid] = low_base[tid];
+    if (digit_thread) s_low[tid] = low_base[tid];
     __syncthreads();
     // low bytes of the workgroup's first and last items (equal unless the
     // workgroup straddles a digit boundary)
@@ -248,10 +256,10 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
   }
   __syncthreads();
 
-  const size_t base = blk0 + (size_t)wave * (kItems * 64) + __lane_id();
-  uint32_t k[kItems], v[kItems], rank[kItems];
+  const size_t base = blk0 + (size_t)wave * (kScatterItems * 64) + __lane_id();
+  uint32_t k[kScatterItems], v[kScatterItems], rank[kScatterItems];
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {   // all loads in flight before any ranking
+  for (int r = 0; r < kScatterItems; ++r) {   // all loads in flight before any ranking
     const size_t i = base + (size_t)r * 64;
     k[r] = i < n ? keys_in[i] : 0xffffffffu;
     if (MODE == kScatterIota) {
@@ -264,7 +272,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
   if (MODE == kScatterUnpack) {
     const uint32_t l0 = s_lowblk[0], l1 = s_lowblk[1];
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < kScatterItems; ++r) {
       const size_t i = base + (size_t)r * 64;
       if (i < n) {
         const uint32_t low = l0 == l1 ? l0 : digit_at(s_low, (uint32_t)i);
@@ -277,7 +285,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
   }
   const uint64_t lt = lanemask_lt();
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
+  for (int r = 0; r < kScatterItems; ++r) {
     const bool valid = base + (size_t)r * 64 < n;
     const uint32_t d = (k[r] >> shift) & 0xffu;
     const uint64_t peers = match_digit(d, valid);
@@ -286,29 +294,31 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
     __builtin_amdgcn_wave_barrier();   // the leaders' updates precede the next round's reads
   }
   __syncthreads();
-  // per digit: totals over waves (into wc[.][d] as exclusive wave prefixes) and the
-  // exclusive scan over digits of the totals
-  {
-    uint32_t tot = 0;
-    for (int w = 0; w < kWaves; ++w) {
+  // per digit (threads 0-255, whole wavefronts): totals over waves (into wc[.][d] as
+  // exclusive wave prefixes) and the exclusive scan over digits of the totals
+  uint32_t tot = 0, incl = 0;
+  if (digit_thread) {
+    for (int w = 0; w < kScatterWaves; ++w) {
       const uint32_t c = wc[w][tid];
       wc[w][tid] = tot;
       tot += c;
     }
-    uint32_t incl = tot;
+    incl = tot;
     for (int off = 1; off < 64; off <<= 1) {
       const uint32_t y = __shfl_up(incl, off);
       if ((int)__lane_id() >= off) incl += y;
     }
     if (__lane_id() == 63) wsum[wave] = incl;
-    __syncthreads();
+  }
+  __syncthreads();
+  if (digit_thread) {
     uint32_t wpre = 0;
     for (int w = 0; w < wave; ++w) wpre += wsum[w];
     lstart[tid] = wpre + incl - tot;
-    __syncthreads();
   }
+  __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
+  for (int r = 0; r < kScatterItems; ++r) {
     if (base + (size_t)r * 64 < n) {
       const uint32_t d = (k[r] >> shift) & 0xffu;
       const uint32_t pos = lstart[d] + wc[wave][d] + rank[r];
@@ -322,7 +332,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
     }
   }
   __syncthreads();
-  for (uint32_t p = tid; p < valid_items; p += kThreads) {
+  for (uint32_t p = tid; p < valid_items; p += kScatterThreads) {
     const uint32_t key = s_keys[p];
     const uint32_t d = MODE == kScatterPack ? (uint32_t)s_dig[p] : (key >> shift) & 0xffu;
     const size_t dst = (size_t)goff[d] + (p - lstart[d]);
@@ -767,10 +777,10 @@ hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b
   if (bits > 8 && bits <= 16 && vals24) {
     // two passes moving one packed word between them; the result lands in *_a
     ps.run(keys_a, 0, 0, s);
-    hipLaunchKernelGGL(k_radix_scatter<kScatterPack>, grid, dim3(kThreads), 0, s, keys_a, vals_a, n, 0, ps.hist,
+    hipLaunchKernelGGL(k_radix_scatter<kScatterPack>, grid, dim3(kScatterThreads), 0, s, keys_a, vals_a, n, 0, ps.hist,
                        nullptr, keys_b, nullptr);
     ps.run(keys_b, 24, 1, s);
-    hipLaunchKernelGGL(k_radix_scatter<kScatterUnpack>, grid, dim3(kThreads), 0, s, keys_b, nullptr, n, 8, ps.hist,
+    hipLaunchKernelGGL(k_radix_scatter<kScatterUnpack>, grid, dim3(kScatterThreads), 0, s, keys_b, nullptr, n, 8, ps.hist,
                        ps.digit_base[0], keys_a, vals_a);
     return hipGetLastError();
   }
@@ -778,7 +788,7 @@ hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b
   int in_b = 0;
   for (int shift = 0; shift < bits; shift += 8) {
     ps.run(ki, shift, 0, s);
-    hipLaunchKernelGGL(k_radix_scatter<kScatterPlain>, grid, dim3(kThreads), 0, s, ki, vi, n, shift, ps.hist,
+    hipLaunchKernelGGL(k_radix_scatter<kScatterPlain>, grid, dim3(kScatterThreads), 0, s, ki, vi, n, shift, ps.hist,
                        nullptr, ko, vo);
     uint32_t* t;
     t = ki; ki = ko; ko = t;
@@ -796,12 +806,12 @@ hipError_t radix_sort_depth(const uint32_t* depth, const uint32_t* count, uint32
   const PassScan ps(n, scratch);
   const dim3 grid(ps.n_blocks);
   ps.run(depth, 0, 0, s);
-  hipLaunchKernelGGL(k_radix_scatter<kScatterIota>, grid, dim3(kThreads), 0, s, depth, count, n, 0, ps.hist, nullptr,
+  hipLaunchKernelGGL(k_radix_scatter<kScatterIota>, grid, dim3(kScatterThreads), 0, s, depth, count, n, 0, ps.hist, nullptr,
                      keys_b, vals_b);
   uint32_t *ki = keys_b, *vi = vals_b, *ko = keys_a, *vo = vals_a;
   for (int shift = 8; shift < 32; shift += 8) {
     ps.run(ki, shift, 0, s);
-    hipLaunchKernelGGL(k_radix_scatter<kScatterPlain>, grid, dim3(kThreads), 0, s, ki, vi, n, shift, ps.hist,
+    hipLaunchKernelGGL(k_radix_scatter<kScatterPlain>, grid, dim3(kScatterThreads), 0, s, ki, vi, n, shift, ps.hist,
                        nullptr, ko, vo);
     uint32_t* t;
     t = ki; ki = ko; ko = t;
