@@ -89,6 +89,36 @@ __device__ inline bool tile_meets_cutoff(const CutoffGeo& g, int gx, int gy, int
   if (dx0 <= 0.0 && dx1 >= 0.0 && dy0 <= 0.0 && dy1 >= 0.0) best = 0.0;
   return best <= g.lim;
 }
+// The same decision in fp32 where it is clear: 1 keep, 0 drop, -1 too close to call
+// (then tile_meets_cutoff decides).  The box offsets are taken in FP64 and rounded
+// (signs, hence the inside test, exact); the four edge minima are evaluated at the
+// same clamp points in fp32.  Against the FP64 value, rounding of the offsets, the
+// products and the clamp points stays below 8 ulp of S, S = (|a| + |b|) Dx^2 +
+// (|b| + |c|) Dy^2 bounding |a dx^2| + 2 |b dx dy| + |c dy^2| over the box (Dx, Dy
+// the largest offsets); a result within 1e-5 S + 1e-6 |lim| of the limit is
+// left undecided.
+__device__ inline int tile_cutoff_fast(const CutoffGeo& g, int gx, int gy, int T, int W, int H) {
+#pragma clang fp contract(off)
+  const float dx0 = (float)(((double)(gx * T) + 0.5) - g.u);
+  const float dx1 = (float)(fmin((double)(gx * T) + ((double)T - 0.5), (double)W - 0.5) - g.u);
+  const float dy0 = (float)(((double)(gy * T) + 0.5) - g.w);
+  const float dy1 = (float)(fmin((double)(gy * T) + ((double)T - 0.5), (double)H - 0.5) - g.w);
+  if (dx0 <= 0.0f && dx1 >= 0.0f && dy0 <= 0.0f && dy1 >= 0.0f) return g.lim >= 0.0 ? 1 : 0;   // best = 0
+  const float a = (float)g.a, b = (float)g.b, c = (float)g.c, nbc = (float)g.nbc, nba = (float)g.nba;
+  auto q = [&](float dx, float dy) { return ((a * dx) * dx + ((2.0f * b) * dx) * dy) + (c * dy) * dy; };
+  float best = q(dx0, __builtin_amdgcn_fmed3f(nbc * dx0, dy0, dy1));
+  best = fminf(best, q(dx1, __builtin_amdgcn_fmed3f(nbc * dx1, dy0, dy1)));
+  best = fminf(best, q(__builtin_amdgcn_fmed3f(nba * dy0, dx0, dx1), dy0));
+  best = fminf(best, q(__builtin_amdgcn_fmed3f(nba * dy1, dx0, dx1), dy1));
+  const float Dx = fmaxf(fabsf(dx0), fabsf(dx1)), Dy = fmaxf(fabsf(dy0), fabsf(dy1));
+  const float S = (fabsf(a) + fabsf(b)) * (Dx * Dx) + (fabsf(b) + fabsf(c)) * (Dy * Dy);
+  const float lim = (float)g.lim;
+  const float margin = 1e-5f * S + 1e-6f * fabsf(lim) + 1e-30f;
+  if (best <= lim - margin) return 1;
+  if (best > lim + margin) return 0;
+  return -1;
+}
+
 __host__ __device__ inline int n_params(int D) { return 11 + 3 * n_sh(D); }
 
 // ---- launchers (each file defines its own) ----

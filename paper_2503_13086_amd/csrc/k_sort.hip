@@ -530,8 +530,11 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
       uint32_t tx, ty;
       rect_cell(li, s_nx[w][lo], tx, ty);
       const uint32_t org = s_org[w][lo], wh = s_wh[w][lo];
-      pass = tile_meets_cutoff(s_geo[w][lo], (int)((org & 0xffffu) + tx), (int)((org >> 16) + ty), T,
-                               (int)(wh & 0xffffu), (int)(wh >> 16));
+      const CutoffGeo& geo = s_geo[w][lo];
+      const int gx = (int)((org & 0xffffu) + tx), gy = (int)((org >> 16) + ty);
+      const int W = (int)(wh & 0xffffu), H = (int)(wh >> 16);
+      const int fast = tile_cutoff_fast(geo, gx, gy, T, W, H);
+      pass = fast >= 0 ? fast != 0 : tile_meets_cutoff(geo, gx, gy, T, W, H);
     }
     const uint64_t fmask = __ballot(first);
     const uint64_t pmask = __ballot(pass);
