@@ -264,6 +264,16 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const ViewDev* __restrict__ vi
     const float* ac = aux + (size_t)cv.pix_off * 9 + (size_t)ch * 3 * hw;
     const float* src[3] = {ac, ac + hw, ac + 2 * hw};
     stage_halo<3>(sin_, src, cv.W, cv.H, t.x0, t.y0);
+    // this thread's image values, fetched now so the loads overlap the filtering
+    float xs[VSEG], ys[VSEG];
+#pragma unroll
+    for (int j = 0; j < VSEG; ++j) {
+      const int px = t.x0 + col, py = t.y0 + r0 + j;
+      const bool in = px < cv.W && py < cv.H;
+      const size_t p = base + ch * hw + (size_t)py * cv.W + px;
+      xs[j] = in ? x[p] : 0.0f;
+      ys[j] = in ? y[p] : 0.0f;
+    }
     __syncthreads();
     float m[3][VSEG];
 #pragma unroll
@@ -274,7 +284,7 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const ViewDev* __restrict__ vi
       const int px = t.x0 + col, py = t.y0 + r0 + j;
       if (px < cv.W && py < cv.H) {
         const size_t p = base + ch * hw + (size_t)py * cv.W + px;
-        const float xv = x[p], yv = y[p];
+        const float xv = xs[j], yv = ys[j];
         const float d = xv - yv;
         const float l1 = w_l1 * invN * (float)((d > 0.0f) - (d < 0.0f));
         grad[p] = l1 - w_dssim * invN * (m[0][j] + 2.0f * xv * m[1][j] + yv * m[2][j]);
