@@ -134,7 +134,7 @@ __device__ inline void stage_empty(float4& q0, float4& q1, float4& q2) {
 // rounding of the peak positions only costs the second-order loss already
 // covered by tau_c.
 template <int NM>
-__device__ inline void quadrant_masks(const float4* s0, const float4* s1, int m, float qx, float qy,
+__device__ inline void block_masks(const float4* s0, const float4* s1, int m, float qx, float qy,
                                       uint64_t (&mask)[NM]) {
   const int lane = (int)__lane_id();
 #pragma unroll
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict_
     __syncthreads();
     if (wave_mask(pmax == 0.0f) != 0ull) {
       uint64_t mask[NM];
-      quadrant_masks<NM>(s0, s1, (int)m, qx, qy, mask);
+      block_masks<NM>(s0, s1, (int)m, qx, qy, mask);
       // straight-line per-Gaussian update; lanes that skip or have stopped keep their state
       const uint32_t pos0 = base - rg.x + 1;
       bool live = true;
@@ -437,7 +437,7 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
     // records this wavefront may need: positions below its own last blended one
     // whose cutoff ellipse meets its block, walked back to front
     uint64_t mask[NM];
-    quadrant_masks<NM>(s0, s1, min(m, wave_last - beg), qx, qy, mask);
+    block_masks<NM>(s0, s1, min(m, wave_last - beg), qx, qy, mask);
     const uint32_t lrel = lp > (uint32_t)beg ? lp - (uint32_t)beg : 0u;   // batch positions this pixel blended
     for (int k = NM - 1; k >= 0; --k) {
       uint64_t mk = mask[k];
