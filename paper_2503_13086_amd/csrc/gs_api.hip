@@ -43,6 +43,7 @@ struct gs_ctx {
   DevBuf asum, dG, loadp, loadst, kept, emitinfo;
   bool load_pending = false;   // dG holds a load-balancing gradient for the current forward
   ViewDev* h_views = nullptr;
+  bool views_valid = false;   // the device views equal hviews
   unsigned long long* h_total = nullptr;
   hipEvent_t views_ev = nullptr;
   bool views_ev_pending = false;
@@ -243,11 +244,20 @@ gs_status gs_preprocess(gs_ctx* c, const float* params, int32_t n, int32_t strid
   if ((st = ensure(c, c->depth, NV * 4, s)) != GS_OK) return st;
   if ((st = ensure(c, c->touched, NV * 4, s)) != GS_OK) return st;
   if ((st = ensure(c, c->rect, NV * 8, s)) != GS_OK) return st;
-  if (c->views_ev_pending) GS_HIP(c, hipEventSynchronize(c->views_ev));
-  std::memcpy(c->h_views, hv.data(), sizeof(ViewDev) * n_views);
-  GS_HIP(c, hipMemcpyAsync(c->views.p, c->h_views, sizeof(ViewDev) * n_views, hipMemcpyHostToDevice, s));
-  GS_HIP(c, hipEventRecord(c->views_ev, s));
-  c->views_ev_pending = true;
+  // the device copy of the views is only refreshed when they change (a training
+  // loop passes the same cameras every step; an upload costs a copy dispatch)
+  const bool same_views = c->views_valid && (int32_t)c->hviews.size() == n_views &&
+                          std::memcmp(c->hviews.data(), hv.data(), sizeof(ViewDev) * n_views) == 0;
+  if (!same_views) {
+    c->views_valid = false;
+    if (c->views_ev_pending) GS_HIP(c, hipEventSynchronize(c->views_ev));
+    std::memcpy(c->h_views, hv.data(), sizeof(ViewDev) * n_views);
+    GS_HIP(c, hipMemcpyAsync(c->views.p, c->h_views, sizeof(ViewDev) * n_views, hipMemcpyHostToDevice, s));
+    GS_HIP(c, hipEventRecord(c->views_ev, s));
+    c->views_ev_pending = true;
+    c->hviews = hv;   // what the device copy holds from here on
+    c->views_valid = true;
+  }
   {
     Prof pr(c, GS_K_PREPROCESS, s);
     GS_HIP(c, launch_preprocess(params, n, stride, sh_degree, c->views.as<ViewDev>(), n_views, c->rec.as<Record>(),

@@ -237,3 +237,33 @@ def test_batched_beyond_packed_depth_values():
     finally:
         rz.close()
     assert K == k_single and K > 0
+
+
+@pytest.mark.gpu
+def test_views_reused_or_changed_between_calls():
+    """The device copy of the views is refreshed only when they change: repeating,
+    switching and switching back the cameras on one context renders every call bit
+    for bit like a fresh context does."""
+    from paper_2503_13086_amd.pipeline import Rasterizer, params_to_device
+    sc = scenegen.small_scene(41, 3000, 1, [(96, 64), (80, 72)])
+    a, b = [sc.cams[0]], [sc.cams[1]]
+
+    def fresh(cams):
+        rz = Rasterizer(0)
+        try:
+            rz.preprocess(params_to_device(sc.params), sc.n, 1, cams)
+            rz.bin_sort()
+            return rz.render_fwd().clone()
+        finally:
+            rz.close()
+
+    ref = {"a": fresh(a), "b": fresh(b)}
+    rz = Rasterizer(0)
+    try:
+        P = params_to_device(sc.params)
+        for name in ("a", "a", "b", "a", "b", "b"):
+            rz.preprocess(P, sc.n, 1, a if name == "a" else b)
+            rz.bin_sort()
+            assert torch.equal(rz.render_fwd(), ref[name]), name
+    finally:
+        rz.close()
