@@ -36,6 +36,20 @@ namespace {
 // scalar mask instead of round-tripping it through a vector register).
 __device__ inline uint64_t wave_mask(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+
+// Tile of workgroup b.  Workgroups are dealt to the chip's 8 XCDs round-robin (b
+// runs on XCD b mod 8, each XCD with its own L2); XCD x takes the runs x, x + 8,
+// ... of 32 consecutive tiles, so neighbouring tiles, which stage mostly the same
+// records, meet in one L2, while the short runs keep the work per XCD even (1%
+// faster backward than plain tile order; whole contiguous eighths were slower).
+// The grid is rounded up to whole rounds of runs; workgroups past the last tile
+// return at once.
+constexpr int kXcdRun = 32;
+__device__ inline int xcd_raster_tile(int b) {
+  const int x = b % 8, q = b / 8;
+  return ((q / kXcdRun) * 8 + x) * kXcdRun + q % kXcdRun;
+}
+
 __device__ inline int view_of_tile(const ViewDev* __restrict__ views, int V, int tile) {
   int v = 0;
   while (v + 1 < V && tile >= views[v + 1].tile_off) ++v;
@@ -161,7 +175,7 @@ __device__ inline void block_masks(const float4* s0, const float4* s1, int m, fl
 }
 
 template <int T>
-__global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict__ views, int V,
+__global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict__ views, int V, int n_tiles_total,
                                                     const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ pair_rec,
                                                     const Record* __restrict__ rec, uint32_t n_rec,
@@ -170,7 +184,8 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict_
                                                     uint32_t* __restrict__ last, float* __restrict__ asum) {
   constexpr int NT = T * T, NM = NT / 64;
   __shared__ float4 s0[NT], s1[NT], s2[NT];
-  const int tile = blockIdx.x;
+  const int tile = xcd_raster_tile((int)blockIdx.x);
+  if (tile >= n_tiles_total) return;
   const TileGeom tg = tile_geom<T>(views, V, tile);
   const uint2 rg = ranges[tile];
   const float fx = (float)tg.lx, fy = (float)tg.ly;
@@ -363,7 +378,7 @@ __device__ inline int reduce18_slot(unsigned lane) {
 }
 
 template <int T>
-__global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict__ views, int V,
+__global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict__ views, int V, int n_tiles_total,
                                                     const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ pair_rec,
                                                     const Record* __restrict__ rec, uint32_t n_rec,
@@ -376,7 +391,8 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
   __shared__ uint32_t srid[NT];
   __shared__ float acc[NT][kGrad2D];
   __shared__ uint32_t smax[NM];
-  const int tile = blockIdx.x;
+  const int tile = xcd_raster_tile((int)blockIdx.x);
+  if (tile >= n_tiles_total) return;
   const TileGeom tg = tile_geom<T>(views, V, tile);
   const ViewDev& cv = views[tg.v];
   const uint2 rg = ranges[tile];
@@ -540,18 +556,18 @@ hipError_t launch_render_fwd(const ViewDev* views, int V, int n_tiles, const uin
                              const Record* rec, uint32_t n_rec, float* color, float* t_final, uint32_t* n_contrib,
                              uint32_t* last, float* asum, int tile, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  const dim3 grid(n_tiles);
+  const dim3 grid((unsigned)((n_tiles + 8 * kXcdRun - 1) / (8 * kXcdRun) * (8 * kXcdRun)));
   switch (tile) {
     case 8:
-      hipLaunchKernelGGL(k_render_fwd<8>, grid, dim3(64), 0, s, views, V, ranges, pair_rec, rec, n_rec, color, t_final,
+      hipLaunchKernelGGL(k_render_fwd<8>, grid, dim3(64), 0, s, views, V, n_tiles, ranges, pair_rec, rec, n_rec, color, t_final,
                          n_contrib, last, asum);
       break;
     case 16:
-      hipLaunchKernelGGL(k_render_fwd<16>, grid, dim3(256), 0, s, views, V, ranges, pair_rec, rec, n_rec, color,
+      hipLaunchKernelGGL(k_render_fwd<16>, grid, dim3(256), 0, s, views, V, n_tiles, ranges, pair_rec, rec, n_rec, color,
                          t_final, n_contrib, last, asum);
       break;
     case 32:
-      hipLaunchKernelGGL(k_render_fwd<32>, grid, dim3(1024), 0, s, views, V, ranges, pair_rec, rec, n_rec, color,
+      hipLaunchKernelGGL(k_render_fwd<32>, grid, dim3(1024), 0, s, views, V, n_tiles, ranges, pair_rec, rec, n_rec, color,
                          t_final, n_contrib, last, asum);
       break;
     default: return hipErrorInvalidValue;
@@ -563,18 +579,18 @@ hipError_t launch_render_bwd(const ViewDev* views, int V, int n_tiles, const uin
                              const Record* rec, uint32_t n_rec, const float* t_final, const uint32_t* last,
                              const float* dL_dcolor, const float* dL_dG, float* grad2d, int tile, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  const dim3 grid(n_tiles);
+  const dim3 grid((unsigned)((n_tiles + 8 * kXcdRun - 1) / (8 * kXcdRun) * (8 * kXcdRun)));
   switch (tile) {
     case 8:
-      hipLaunchKernelGGL(k_render_bwd<8>, grid, dim3(64), 0, s, views, V, ranges, pair_rec, rec, n_rec, t_final, last,
+      hipLaunchKernelGGL(k_render_bwd<8>, grid, dim3(64), 0, s, views, V, n_tiles, ranges, pair_rec, rec, n_rec, t_final, last,
                          dL_dcolor, dL_dG, grad2d);
       break;
     case 16:
-      hipLaunchKernelGGL(k_render_bwd<16>, grid, dim3(256), 0, s, views, V, ranges, pair_rec, rec, n_rec, t_final,
+      hipLaunchKernelGGL(k_render_bwd<16>, grid, dim3(256), 0, s, views, V, n_tiles, ranges, pair_rec, rec, n_rec, t_final,
                          last, dL_dcolor, dL_dG, grad2d);
       break;
     case 32:
-      hipLaunchKernelGGL(k_render_bwd<32>, grid, dim3(1024), 0, s, views, V, ranges, pair_rec, rec, n_rec, t_final,
+      hipLaunchKernelGGL(k_render_bwd<32>, grid, dim3(1024), 0, s, views, V, n_tiles, ranges, pair_rec, rec, n_rec, t_final,
                          last, dL_dcolor, dL_dG, grad2d);
       break;
     default: return hipErrorInvalidValue;
