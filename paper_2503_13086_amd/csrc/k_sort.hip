@@ -240,12 +240,20 @@ __global__ __launch_bounds__(kScatterThreads) void k_radix_scatter(const uint32_
   __shared__ uint32_t lstart[kRadix];              // workgroup-local start of each digit
   __shared__ uint32_t goff[kRadix];                // global start of this workgroup's run of each digit
   __shared__ uint32_t wsum[kRadix / 64];
+  // Workgroups are dealt to the 8 XCDs round-robin; XCD x takes the contiguous
+  // eighth x of the tiles, so each digit's output run of an eighth is written
+  // through one L2 (the lines shared by neighbouring tiles' runs merge there instead
+  // of reaching HBM as partial writes from two XCDs).  Grid: 8 x ceil(tiles / 8).
+  const int n_tiles_sort = (int)((n + kSortTileItems - 1) / kSortTileItems);
+  const int eighth = (n_tiles_sort + 7) / 8;
+  const int blk = (int)(blockIdx.x % 8) * eighth + (int)(blockIdx.x / 8);
+  if (blk >= n_tiles_sort) return;
   const int tid = threadIdx.x;
   const int wave = tid / 64;
   const bool digit_thread = tid < kRadix;          // threads 0-255 own one digit each
   for (int i = tid; i < kScatterWaves * kRadix; i += kScatterThreads) (&wc[0][0])[i] = 0;
-  if (digit_thread) goff[tid] = offsets[(size_t)blockIdx.x * kRadix + tid];
-  const size_t blk0 = (size_t)blockIdx.x * kSortTileItems;
+  if (digit_thread) goff[tid] = offsets[(size_t)blk * kRadix + tid];
+  const size_t blk0 = (size_t)blk * kSortTileItems;
   const size_t valid_items = n > blk0 ? (n - blk0 < (size_t)kSortTileItems ? n - blk0 : (size_t)kSortTileItems) : 0;
   if (MODE == kScatterUnpack) {
     if (digit_thread) s_low[tid] = low_base[tid];
@@ -776,7 +784,7 @@ hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b
   *result_in_b = 0;
   if (n == 0 || bits <= 0) return hipSuccess;
   const PassScan ps(n, scratch);
-  const dim3 grid(ps.n_blocks);
+  const dim3 grid((unsigned)(8 * ((ps.n_blocks + 7) / 8)));   // the scatter's XCD-ordered grid
   if (bits > 8 && bits <= 16 && vals24) {
     // two passes moving one packed word between them; the result lands in *_a
     ps.run(keys_a, 0, 0, s);
@@ -807,7 +815,7 @@ hipError_t radix_sort_depth(const uint32_t* depth, const uint32_t* count, uint32
   if (n == 0) return hipSuccess;
   if (count && n > kPackMaxEntries) return hipErrorInvalidValue;
   const PassScan ps(n, scratch);
-  const dim3 grid(ps.n_blocks);
+  const dim3 grid((unsigned)(8 * ((ps.n_blocks + 7) / 8)));   // the scatter's XCD-ordered grid
   ps.run(depth, 0, 0, s);
   hipLaunchKernelGGL(k_radix_scatter<kScatterIota>, grid, dim3(kScatterThreads), 0, s, depth, count, n, 0, ps.hist, nullptr,
                      keys_b, vals_b);
