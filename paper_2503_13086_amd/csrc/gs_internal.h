@@ -71,6 +71,27 @@ __device__ inline CutoffGeo cutoff_geo(const Record& r) {
   return g;
 }
 
+// What the fp32 clear-case test reads (40 bytes instead of 64): the centre in FP64,
+// the rest as the fp32 roundings of the FP64 values of cutoff_geo.
+struct CutoffGeoF {
+  double u, w;
+  float a, b, c, nbc, nba, lim;
+};
+
+__device__ inline CutoffGeoF cutoff_geo_f(const Record& r) {
+  const CutoffGeo g = cutoff_geo(r);
+  CutoffGeoF f;
+  f.u = g.u;
+  f.w = g.w;
+  f.a = (float)g.a;
+  f.b = (float)g.b;
+  f.c = (float)g.c;
+  f.nbc = (float)g.nbc;
+  f.nba = (float)g.nba;
+  f.lim = (float)g.lim;
+  return f;
+}
+
 __device__ inline double cutoff_qform(double a, double b, double c, double dx, double dy) {
 #pragma clang fp contract(off)
   return ((a * dx) * dx + ((2.0 * b) * dx) * dy) + (c * dy) * dy;
@@ -97,14 +118,14 @@ __device__ inline bool tile_meets_cutoff(const CutoffGeo& g, int gx, int gy, int
 // (|b| + |c|) Dy^2 bounding |a dx^2| + 2 |b dx dy| + |c dy^2| over the box (Dx, Dy
 // the largest offsets); a result within 1e-5 S + 1e-6 |lim| of the limit is
 // left undecided.
-__device__ inline int tile_cutoff_fast(const CutoffGeo& g, int gx, int gy, int T, int W, int H) {
+__device__ inline int tile_cutoff_fast(const CutoffGeoF& g, int gx, int gy, int T, int W, int H) {
 #pragma clang fp contract(off)
   const float dx0 = (float)(((double)(gx * T) + 0.5) - g.u);
   const float dx1 = (float)(fmin((double)(gx * T) + ((double)T - 0.5), (double)W - 0.5) - g.u);
   const float dy0 = (float)(((double)(gy * T) + 0.5) - g.w);
   const float dy1 = (float)(fmin((double)(gy * T) + ((double)T - 0.5), (double)H - 0.5) - g.w);
-  if (dx0 <= 0.0f && dx1 >= 0.0f && dy0 <= 0.0f && dy1 >= 0.0f) return g.lim >= 0.0 ? 1 : 0;   // best = 0
-  const float a = (float)g.a, b = (float)g.b, c = (float)g.c, nbc = (float)g.nbc, nba = (float)g.nba;
+  if (dx0 <= 0.0f && dx1 >= 0.0f && dy0 <= 0.0f && dy1 >= 0.0f) return g.lim >= 0.0f ? 1 : 0;   // best = 0
+  const float a = g.a, b = g.b, c = g.c, nbc = g.nbc, nba = g.nba;
   auto q = [&](float dx, float dy) { return ((a * dx) * dx + ((2.0f * b) * dx) * dy) + (c * dy) * dy; };
   float best = q(dx0, __builtin_amdgcn_fmed3f(nbc * dx0, dy0, dy1));
   best = fminf(best, q(dx1, __builtin_amdgcn_fmed3f(nbc * dx1, dy0, dy1)));
@@ -112,7 +133,7 @@ __device__ inline int tile_cutoff_fast(const CutoffGeo& g, int gx, int gy, int T
   best = fminf(best, q(__builtin_amdgcn_fmed3f(nba * dy1, dx0, dx1), dy1));
   const float Dx = fmaxf(fabsf(dx0), fabsf(dx1)), Dy = fmaxf(fabsf(dy0), fabsf(dy1));
   const float S = (fabsf(a) + fabsf(b)) * (Dx * Dx) + (fabsf(b) + fabsf(c)) * (Dy * Dy);
-  const float lim = (float)g.lim;
+  const float lim = g.lim;
   const float margin = 1e-5f * S + 1e-6f * fabsf(lim) + 1e-30f;
   if (best <= lim - margin) return 1;
   if (best > lim + margin) return 0;

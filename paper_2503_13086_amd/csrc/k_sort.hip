@@ -502,7 +502,7 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
   __shared__ uint32_t s_k[kWaves][64];
   __shared__ uint64_t s_bits[kWaves][64];
   __shared__ int s_own[kWaves][64];
-  __shared__ CutoffGeo s_geo[kWaves][64];
+  __shared__ CutoffGeoF s_geo[kWaves][64];    // fp32 clear-case geometry (the FP64 one is re-derived when needed)
   const int w = threadIdx.x / 64;
   const unsigned lane = __lane_id();
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -519,7 +519,7 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
     s_nx[w][lane] = (uint32_t)(rc.y - rc.x + 1);
     s_org[w][lane] = (uint32_t)rc.x | ((uint32_t)rc.z << 16);
     s_wh[w][lane] = (uint32_t)cv.W | ((uint32_t)cv.H << 16);
-    s_geo[w][lane] = cutoff_geo(rec[e]);
+    s_geo[w][lane] = cutoff_geo_f(rec[e]);
   }
   __builtin_amdgcn_wave_barrier();
   const uint32_t C = s_cp[w][64];
@@ -538,11 +538,11 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
       uint32_t tx, ty;
       rect_cell(li, s_nx[w][lo], tx, ty);
       const uint32_t org = s_org[w][lo], wh = s_wh[w][lo];
-      const CutoffGeo& geo = s_geo[w][lo];
       const int gx = (int)((org & 0xffffu) + tx), gy = (int)((org >> 16) + ty);
       const int W = (int)(wh & 0xffffu), H = (int)(wh >> 16);
-      const int fast = tile_cutoff_fast(geo, gx, gy, T, W, H);
-      pass = fast >= 0 ? fast != 0 : tile_meets_cutoff(geo, gx, gy, T, W, H);
+      const int fast = tile_cutoff_fast(s_geo[w][lo], gx, gy, T, W, H);
+      pass = fast >= 0 ? fast != 0
+                       : tile_meets_cutoff(cutoff_geo(rec[e - lane + (unsigned)lo]), gx, gy, T, W, H);
     }
     const uint64_t fmask = __ballot(first);
     const uint64_t pmask = __ballot(pass);
