@@ -30,7 +30,7 @@ constexpr int LT = 32;              // output tile edge
 constexpr int R = 5;                // window radius
 constexpr int TAPS = 2 * R + 1;
 constexpr int HALO = LT + 2 * R;    // 42
-constexpr int HS = HALO + 1;        // LDS row stride (odd, spreads banks)
+constexpr int HS = HALO;            // LDS row stride (unpadded: the backward then fits six workgroups per CU)
 constexpr int HSEG = 8;             // horizontal outputs per thread
 constexpr int VSEG = 4;             // vertical outputs per thread
 constexpr float kC1 = 0.01f * 0.01f;
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const ViewDev* __restrict__ vi
                                                    const float* __restrict__ aux, Win win, float w_l1, float w_dssim,
                                                    float* __restrict__ grad) {
   __shared__ float sin_[3][HALO * HS];
-  __shared__ float hbuf[1][HALO * LT];   // the three maps filtered one after another: 27 KB of LDS
+  __shared__ float hbuf[1][HALO * LT];   // the three maps filtered one after another: 26 KB of LDS
   const int tile = xcd_tile(blockIdx.x, lt.off[V]);
   if (tile >= lt.off[V]) return;
   const TileLoc t = loss_tile(views, lt, V, tile);
