@@ -192,7 +192,9 @@ __device__ inline void window_map(const float (*in)[HALO * HS], float (*hb)[HALO
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_ssim_fwd(const ViewDev* __restrict__ views, int V, LossTiles lt,
+// Register budgets: 8 waves per SIMD for the forward (59 VGPRs; left alone the
+// compiler takes 68 and runs 7), 6 for the backward (its LDS allows 6 workgroups).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_ssim_fwd(const ViewDev* __restrict__ views, int V, LossTiles lt,
                                                    const float* __restrict__ x, const float* __restrict__ y,
                                                    float* __restrict__ aux, Win win, double2* __restrict__ partials) {
   __shared__ float sin_[2][HALO * HS];
@@ -246,7 +248,7 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const ViewDev* __restrict__ vi
   if (threadIdx.x == 0) partials[tile] = make_double2(t1, t2);
 }
 
-__global__ __launch_bounds__(256) void k_ssim_bwd(const ViewDev* __restrict__ views, int V, LossTiles lt,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_ssim_bwd(const ViewDev* __restrict__ views, int V, LossTiles lt,
                                                    const float* __restrict__ x, const float* __restrict__ y,
                                                    const float* __restrict__ aux, Win win, float w_l1, float w_dssim,
                                                    float* __restrict__ grad) {
