@@ -81,8 +81,10 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
 
 // The histogram table is block-major, hist[b * 256 + d].  Its scan, per digit d
 // the count of items with a smaller digit plus those of digit d in earlier blocks,
-// runs over chunks of blocks (at most kMaxChunks chunks): column sums per chunk, one workgroup
-// scanning the chunk sums and the digit totals, and a per-chunk running sum.
+// runs over chunks of blocks (at most kMaxChunks chunks) and is left in three
+// parts that the scatter adds (DigitStarts): the running sum within each chunk (in
+// place in the table) with the chunk's column sums, then one workgroup turning the
+// chunk sums into prefixes over chunks and scanning the digit totals.
 // Every pass reads rows of 256 counters (coalesced).
 constexpr int kScanChunk = 16;                               // smallest chunk, and the load batch
 constexpr int kMaxChunks = 128;                              // chunks grow so there are at most this many
@@ -96,19 +98,24 @@ inline int chunk_blocks(int n_blocks) {
   return cs < kScanChunk ? kScanChunk : cs;
 }
 
-__global__ __launch_bounds__(kRadix) void k_radix_chunk_sums(const uint32_t* __restrict__ hist, int n_blocks,
-                                                              int cs, uint32_t* __restrict__ chunk_sum) {
+// hist[b][d] <- digit d's count over the blocks of b's chunk before b;
+// chunk_sum[c][d] <- its count over the whole chunk c.
+__global__ __launch_bounds__(kRadix) void k_radix_chunk_sums(uint32_t* __restrict__ hist, int n_blocks, int cs,
+                                                              uint32_t* __restrict__ chunk_sum) {
   const int b0 = blockIdx.x * cs, b1 = min(b0 + cs, n_blocks);
-  uint32_t t = 0;
+  uint32_t run = 0;
   for (int b = b0; b < b1; b += kScanChunk) {
     uint32_t x[kScanChunk];
 #pragma unroll
-    for (int k = 0; k < kScanChunk; ++k)   // a batch of loads in flight before the sum
+    for (int k = 0; k < kScanChunk; ++k)   // a batch of loads in flight before the stores
       x[k] = b + k < b1 ? hist[(size_t)(b + k) * kRadix + threadIdx.x] : 0u;
 #pragma unroll
-    for (int k = 0; k < kScanChunk; ++k) t += x[k];
+    for (int k = 0; k < kScanChunk; ++k) {
+      if (b + k < b1) hist[(size_t)(b + k) * kRadix + threadIdx.x] = run;
+      run += x[k];
+    }
   }
-  chunk_sum[(size_t)blockIdx.x * kRadix + threadIdx.x] = t;
+  chunk_sum[(size_t)blockIdx.x * kRadix + threadIdx.x] = run;
 }
 
 // One workgroup, kChunkParts threads per digit d, each owning a contiguous part of
@@ -171,24 +178,14 @@ __global__ __launch_bounds__(kChunkScanThreads) void k_radix_chunk_scan(uint32_t
   }
 }
 
-// hist[b][d] <- start of block b's run of digit d in the pass's output.
-__global__ __launch_bounds__(kRadix) void k_radix_chunk_apply(uint32_t* __restrict__ hist, int n_blocks, int cs,
-                                                               const uint32_t* __restrict__ chunk_sum,
-                                                               const uint32_t* __restrict__ digit_base) {
-  const int b0 = blockIdx.x * cs, b1 = min(b0 + cs, n_blocks);
-  uint32_t run = digit_base[threadIdx.x] + chunk_sum[(size_t)blockIdx.x * kRadix + threadIdx.x];
-  for (int b = b0; b < b1; b += kScanChunk) {
-    uint32_t x[kScanChunk];
-#pragma unroll
-    for (int k = 0; k < kScanChunk; ++k)
-      x[k] = b + k < b1 ? hist[(size_t)(b + k) * kRadix + threadIdx.x] : 0u;
-#pragma unroll
-    for (int k = 0; k < kScanChunk; ++k) {
-      if (b + k < b1) hist[(size_t)(b + k) * kRadix + threadIdx.x] = run;
-      run += x[k];
-    }
-  }
-}
+// Start of block b's run of digit d in a pass's output: the three parts the scan
+// leaves, added by the scatter.
+struct DigitStarts {
+  const uint32_t* in_chunk;     // [b][d]: over the earlier blocks of b's chunk
+  const uint32_t* chunk_pre;    // [c][d]: over the earlier chunks
+  const uint32_t* digit_base;   // [d]: items with a smaller digit
+  int cs;                       // blocks per chunk
+};
 
 // Stable scatter of one digit pass.  Items are ranked in workgroup order (wave w
 // owns items [base + 1024 w, base + 1024 (w + 1)), then round, then lane): within a
@@ -227,7 +224,7 @@ constexpr int kScatterItems = kSortTileItems / kScatterThreads;
 template <int MODE>
 __global__ __launch_bounds__(kScatterThreads) void k_radix_scatter(const uint32_t* __restrict__ keys_in,
                                                                     const uint32_t* __restrict__ vals_in, size_t n,
-                                                                    int shift, const uint32_t* __restrict__ offsets,
+                                                                    int shift, const DigitStarts starts,
                                                                     const uint32_t* __restrict__ low_base,
                                                                     uint32_t* __restrict__ keys_out,
                                                                     uint32_t* __restrict__ vals_out) {
@@ -252,7 +249,9 @@ __global__ __launch_bounds__(kScatterThreads) void k_radix_scatter(const uint32_
   const int wave = tid / 64;
   const bool digit_thread = tid < kRadix;          // threads 0-255 own one digit each
   for (int i = tid; i < kScatterWaves * kRadix; i += kScatterThreads) (&wc[0][0])[i] = 0;
-  if (digit_thread) goff[tid] = offsets[(size_t)blk * kRadix + tid];
+  if (digit_thread)
+    goff[tid] = starts.in_chunk[(size_t)blk * kRadix + tid] +
+                starts.chunk_pre[(size_t)(blk / starts.cs) * kRadix + tid] + starts.digit_base[tid];
   const size_t blk0 = (size_t)blk * kSortTileItems;
   const size_t valid_items = n > blk0 ? (n - blk0 < (size_t)kSortTileItems ? n - blk0 : (size_t)kSortTileItems) : 0;
   if (MODE == kScatterUnpack) {
@@ -753,8 +752,9 @@ size_t sort_hist_words(size_t n) {
 }
 
 namespace {
-// Digit table of the pass at `shift` over keys, its scan, and the digit starts into
-// digit_base[db] (two slots: a pass and the one before it).
+// Digit table of the pass at `shift` over keys and its scan, the digit starts into
+// digit_base[db] (two slots: a pass and the one before it); starts(db) hands the
+// scan's parts to the scatter.
 struct PassScan {
   size_t n;
   int n_blocks, cs, n_chunks;
@@ -773,9 +773,8 @@ struct PassScan {
     hipLaunchKernelGGL(k_radix_chunk_sums, dim3(n_chunks), dim3(kRadix), 0, s, hist, n_blocks, cs, chunk_sum);
     hipLaunchKernelGGL(k_radix_chunk_scan, dim3(1), dim3(kChunkScanThreads), 0, s, chunk_sum, n_chunks,
                        digit_base[db]);
-    hipLaunchKernelGGL(k_radix_chunk_apply, dim3(n_chunks), dim3(kRadix), 0, s, hist, n_blocks, cs, chunk_sum,
-                       digit_base[db]);
   }
+  DigitStarts starts(int db) const { return DigitStarts{hist, chunk_sum, digit_base[db], cs}; }
 };
 }  // namespace
 
@@ -788,10 +787,10 @@ hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b
   if (bits > 8 && bits <= 16 && vals24) {
     // two passes moving one packed word between them; the result lands in *_a
     ps.run(keys_a, 0, 0, s);
-    hipLaunchKernelGGL(k_radix_scatter<kScatterPack>, grid, dim3(kScatterThreads), 0, s, keys_a, vals_a, n, 0, ps.hist,
+    hipLaunchKernelGGL(k_radix_scatter<kScatterPack>, grid, dim3(kScatterThreads), 0, s, keys_a, vals_a, n, 0, ps.starts(0),
                        nullptr, keys_b, nullptr);
     ps.run(keys_b, 24, 1, s);
-    hipLaunchKernelGGL(k_radix_scatter<kScatterUnpack>, grid, dim3(kScatterThreads), 0, s, keys_b, nullptr, n, 8, ps.hist,
+    hipLaunchKernelGGL(k_radix_scatter<kScatterUnpack>, grid, dim3(kScatterThreads), 0, s, keys_b, nullptr, n, 8, ps.starts(1),
                        ps.digit_base[0], keys_a, vals_a);
     return hipGetLastError();
   }
@@ -799,7 +798,7 @@ hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b
   int in_b = 0;
   for (int shift = 0; shift < bits; shift += 8) {
     ps.run(ki, shift, 0, s);
-    hipLaunchKernelGGL(k_radix_scatter<kScatterPlain>, grid, dim3(kScatterThreads), 0, s, ki, vi, n, shift, ps.hist,
+    hipLaunchKernelGGL(k_radix_scatter<kScatterPlain>, grid, dim3(kScatterThreads), 0, s, ki, vi, n, shift, ps.starts(0),
                        nullptr, ko, vo);
     uint32_t* t;
     t = ki; ki = ko; ko = t;
@@ -817,12 +816,12 @@ hipError_t radix_sort_depth(const uint32_t* depth, const uint32_t* count, uint32
   const PassScan ps(n, scratch);
   const dim3 grid((unsigned)(8 * ((ps.n_blocks + 7) / 8)));   // the scatter's XCD-ordered grid
   ps.run(depth, 0, 0, s);
-  hipLaunchKernelGGL(k_radix_scatter<kScatterIota>, grid, dim3(kScatterThreads), 0, s, depth, count, n, 0, ps.hist, nullptr,
+  hipLaunchKernelGGL(k_radix_scatter<kScatterIota>, grid, dim3(kScatterThreads), 0, s, depth, count, n, 0, ps.starts(0), nullptr,
                      keys_b, vals_b);
   uint32_t *ki = keys_b, *vi = vals_b, *ko = keys_a, *vo = vals_a;
   for (int shift = 8; shift < 32; shift += 8) {
     ps.run(ki, shift, 0, s);
-    hipLaunchKernelGGL(k_radix_scatter<kScatterPlain>, grid, dim3(kScatterThreads), 0, s, ki, vi, n, shift, ps.hist,
+    hipLaunchKernelGGL(k_radix_scatter<kScatterPlain>, grid, dim3(kScatterThreads), 0, s, ki, vi, n, shift, ps.starts(0),
                        nullptr, ko, vo);
     uint32_t* t;
     t = ki; ki = ko; ko = t;
