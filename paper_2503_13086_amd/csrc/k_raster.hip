@@ -386,11 +386,13 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
                                                     const uint32_t* __restrict__ last,
                                                     const float* __restrict__ dL_dcolor,
                                                     const float* __restrict__ dL_dG, float* __restrict__ grad2d) {
-  constexpr int NT = T * T, NM = NT / 64;
-  __shared__ float4 s0[NT], s1[NT], s2[NT];
-  __shared__ uint32_t srid[NT];
-  __shared__ float acc[NT][kGrad2D];
-  __shared__ uint32_t smax[NM];
+  // records are staged NB at a time, half the tile's threads (at least 64): 11 KB of
+  // LDS at T = 16, so registers rather than LDS set the occupancy (8 waves per SIMD)
+  constexpr int NT = T * T, NB = NT >= 128 ? NT / 2 : NT, NM = NB / 64, NW = NT / 64;
+  __shared__ float4 s0[NB], s1[NB], s2[NB];
+  __shared__ uint32_t srid[NB];
+  __shared__ float acc[NB][kGrad2D];
+  __shared__ uint32_t smax[NW];
   const int tile = xcd_raster_tile((int)blockIdx.x);
   if (tile >= n_tiles_total) return;
   const TileGeom tg = tile_geom<T>(views, V, tile);
@@ -431,13 +433,14 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
   const uint32_t col9 = acc0 + 4u * (uint32_t)(slot < 0 ? 0 : slot);
   const uint32_t col18 = acc0 + 4u * (uint32_t)(slot18 < 0 ? 0 : slot18 % kGrad2D);
   if (__lane_id() == 0) smax[threadIdx.x / 64] = mx;
-  for (int k = 0; k < kGrad2D; ++k) acc[threadIdx.x][k] = 0.0f;
+  if ((int)threadIdx.x < NB)
+    for (int k = 0; k < kGrad2D; ++k) acc[threadIdx.x][k] = 0.0f;
   __syncthreads();
   int jmax = 0;
-  for (int w = 0; w < NM; ++w) jmax = max(jmax, (int)smax[w]);
+  for (int w = 0; w < NW; ++w) jmax = max(jmax, (int)smax[w]);
 
-  for (int end = jmax; end > 0; end -= NT) {
-    const int beg = end > NT ? end - NT : 0;
+  for (int end = jmax; end > 0; end -= NB) {
+    const int beg = end > NB ? end - NB : 0;
     const int m = end - beg;
     __syncthreads();
     if ((int)threadIdx.x < m) {
