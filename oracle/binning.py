@@ -13,8 +13,7 @@ With cull="ellipse" a pair is listed only if the Gaussian's cutoff region
 {d : a dx^2 + 2 b dx dy + c dy^2 <= -2 tau} (exactly the pixels where the cutoff
 rule can pass) meets the box spanned by the tile's pixel centres; the other pairs
 of the rect contribute nothing to any pixel of their tile.  The test is evaluated
-in FP64 on the per-splat values as stored for rasterization (conic and cutoff
-rounded to fp32, centre in FP64), so it is reproducible.  The minimum of the
+in FP64 on the FP64 centre, conic and cutoff of geometry.py.  The minimum of the
 quadratic over the box is 0 when the centre lies inside, else the smallest of its
 minima along the four edges (each a clamped 1-D minimiser).
 """
@@ -23,10 +22,6 @@ from __future__ import annotations
 import numpy as np
 
 from .geometry import tile_layout
-
-
-def _f32(x):
-    return np.asarray(x, np.float64).astype(np.float32).astype(np.float64)
 
 
 def box_min_q(a, b, c, dx0, dx1, dy0, dy1):
@@ -53,10 +48,10 @@ def ellipse_meets_tile(p, g, tx, ty, W, H, tile):
     and tiles (tx, ty) (arrays of equal length)."""
     u = p["u"].detach().numpy()[g]
     w = p["w"].detach().numpy()[g]
-    a = _f32(p["a"].detach().numpy()[g])
-    b = _f32(p["b"].detach().numpy()[g])
-    c = _f32(p["c"].detach().numpy()[g])
-    L = -2.0 * _f32(p["tau"].detach().numpy()[g])
+    a = p["a"].detach().numpy()[g]
+    b = p["b"].detach().numpy()[g]
+    c = p["c"].detach().numpy()[g]
+    L = -2.0 * p["tau"].detach().numpy()[g]
     x0 = tx * tile + 0.5
     x1 = np.minimum(tx * tile + (tile - 0.5), W - 0.5)
     y0 = ty * tile + 0.5

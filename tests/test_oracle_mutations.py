@@ -12,6 +12,7 @@ from oracle import geometry, composite, sh, loss, grad, adam, binning, schedule
 import tests.test_oracle_geometry as TG
 import tests.test_oracle_render as TR
 import tests.test_oracle_grad_loss_adam as TL
+import tests.test_oracle_margins as TM
 
 _MODS = {"geometry": geometry, "composite": composite, "sh": sh, "loss": loss, "grad": grad, "adam": adam,
          "binning": binning, "schedule": schedule}
@@ -98,7 +99,8 @@ MUTATIONS = [
     ("binning", "    nbc = -b / c\n", "    nbc = b / c\n", [(TG.test_box_min_matches_dense_sampling, ())]),
     ("binning", "    return np.where(inside, 0.0, best)", "    return best",
      [(TG.test_box_min_matches_dense_sampling, ())]),
-    ("binning", "L = -2.0 * _f32(", "L = -1.0 * _f32(", [(TG.test_ellipse_culling_keeps_every_contributing_tile, (16,))]),
+    ("binning", 'L = -2.0 * p["tau"]', 'L = -1.0 * p["tau"]',
+     [(TG.test_ellipse_culling_keeps_every_contributing_tile, (16,))]),
     ("binning", "order = np.lexsort((gg, dp, tl))", "order = np.lexsort((dp, gg, tl))",
      [(TG.test_binning_sorted_and_ranges, ())]),
     ("adam", "return np.where(cnt > 0, s / np.maximum(cnt, 1), vs.mean())", "return np.where(cnt > 0, s, vs.mean())",
@@ -120,6 +122,24 @@ MUTATIONS = [
      [(TL.test_param_grads_with_load_term_finite_differences, ())]),
     ("schedule", "rest = [i for i in range(n) if i not in share] or list(range(n))",
      "rest = list(range(n))", [(TL.test_schedule_iteration_plan, ())]),
+    # decision margins (what the parity tests set aside)
+    ("composite", "m_cut = (power - q[\"tau\"][None, :]).abs() / (q[\"tau\"][None, :].abs() + s_abs)",
+     "m_cut = (power - q[\"tau\"][None, :]).abs() / (q[\"tau\"][None, :].abs())",
+     [(TM.test_cap_and_sign_margins_single_splat, ())]),
+    ("composite", "m_cut = (power - q[\"tau\"][None, :]).abs()", "m_cut = (power - q[\"tau\"][None, :])",
+     [(TM.test_cutoff_margin_flags_every_cutoff_flip, ())]),
+    ("composite", "upto = torch.arange(G)[None, :] <= stop_col[:, None]",
+     "upto = torch.arange(G)[None, :] < stop_col[:, None]", [(TM.test_cutoff_margin_covers_the_stopping_splat, ())]),
+    ("composite", "s_abs = 0.5 * (a.abs() * dx * dx + c.abs() * dy * dy) + (b * dx * dy).abs()",
+     "s_abs = 0.5 * (a.abs() * dx * dx + c.abs() * dy * dy) + (b * dx * dy)",
+     [(TM.test_cap_and_sign_margins_single_splat, ())]),
+    ("composite", "m_cap = (og - alpha_max).abs() / alpha_max", "m_cap = (og - alpha_max) / alpha_max",
+     [(TM.test_cap_and_sign_margins_single_splat, ())]),
+    ("composite", "(t_min * sens.clamp(min=1.0))", "(t_min * 1.0)", [(TM.test_stop_margin_flags_every_stop_flip, ())]),
+    ("composite", "m_T = ((T_incl - t_min).abs()", "m_T = ((T_incl - t_min)",
+     [(TM.test_stop_margin_flags_every_stop_flip, ())]),
+    ("composite", 'out["m_T"] = torch.where(upto_c, m_T, inf)', 'out["m_T"] = torch.where(blended, m_T, inf)',
+     [(TM.test_stop_margin_flags_every_stop_flip, ())]),
 ]
 
 
