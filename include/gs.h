@@ -134,9 +134,32 @@ gs_status gs_preprocess(gs_ctx* ctx, const float* params, int32_t n, int32_t str
 /* Per-tile depth-ordered lists (tile rasterizer of the original 3DGS): one pair
  * per (visible Gaussian, tile of its rect; see gs_set_cull), ordered by ascending
  * (global tile, fp32 depth, Gaussian index), and each tile's [start, end) range.
- * Synchronises with `stream` once to learn the pair count K, which is written to
- * *n_pairs_out when it is not NULL.  GS_ERR_CAPACITY if K >= 2^32. */
+ * Reads the parameter array of the last gs_preprocess (unchanged since) when the
+ * fp32 cutoff test cannot decide a pair (see gs_set_cull).
+ * n_pairs_out not NULL: waits for the stream once to learn the pair count K and
+ * writes it there (GS_ERR_CAPACITY if K >= 2^32).  n_pairs_out NULL: does not wait
+ * (except on a context's first binning, which sizes the pair buffers): K stays on
+ * the device, and if it exceeds the pair buffers (or 2^32 - 1) the kernels of this
+ * binning and of the rendering after it do nothing, gs_adam_step and
+ * gs_render_bwd_adam leave every buffer untouched, and gs_sync_status reports
+ * GS_ERR_CAPACITY with the size needed; the next gs_bin_sort grows the buffers to
+ * it (it also learns of the failure without gs_sync_status once the stream has
+ * passed it). */
 gs_status gs_bin_sort(gs_ctx* ctx, int64_t* n_pairs_out, gs_stream stream);
+
+/* Device-side conditions of the last gs_bin_sort, which the kernels record
+ * without stopping the host: waits for `stream`, then returns GS_OK or the error
+ * the kernels recorded (GS_ERR_CAPACITY: the pair buffers, or the store of exact
+ * cutoff outcomes, were too small; gs_last_error names the sizes needed).  The
+ * failed step's images, gradients and pair lists are void; the next gs_bin_sort
+ * sizes the buffers to fit. */
+gs_status gs_sync_status(gs_ctx* ctx, gs_stream stream);
+
+/* Sizes the pair buffers for exactly n_pairs pairs (at least 1), so that later
+ * gs_bin_sort calls need not wait for the device to size them; a binning with more
+ * pairs fails as described at gs_bin_sort.  Waits for `stream` before freeing the
+ * old buffers. */
+gs_status gs_reserve_pairs(gs_ctx* ctx, int64_t n_pairs, gs_stream stream);
 
 /* Sec. III Eq. 2: front-to-back alpha blending of every pixel of every view.  Per
  * pixel, in list order: skip Gaussians whose exponent is > 0 or < tau,
@@ -212,11 +235,15 @@ gs_status gs_render_bwd_adam(gs_ctx* ctx, float* params, const float* dL_dcolor,
 /* Pair culling of gs_bin_sort.  GS_CULL_RECT lists every tile of a Gaussian's tile
  * rect.  GS_CULL_ELLIPSE (the default) lists a tile only if the Gaussian's cutoff
  * region {a dx^2 + 2 b dx dy + c dy^2 <= -2 tau} meets the box spanned by the
- * tile's pixel centres (tested in FP64 on the stored conic, cutoff and centre);
- * the other pairs of the rect can blend into no pixel of their tile, so images
- * and gradients are the same in both modes.  K (and every pair buffer) then
- * counts only the listed pairs.  Takes effect at the next gs_bin_sort. */
-enum { GS_CULL_RECT = 0, GS_CULL_ELLIPSE = 1 };
+ * tile's pixel centres, decided on the FP64 centre, conic and cutoff of the
+ * projection (an fp32 test decides where the outcome is clear by a margin; the
+ * rest, a few in 10^4, recompute the FP64 values from the parameters); the other
+ * pairs of the rect can blend into no pixel of their tile, so images and
+ * gradients are the same in both modes.  K (and every pair buffer) then counts
+ * only the listed pairs.  GS_CULL_ELLIPSE_EXACT lists the same pairs with every
+ * test taken on the recomputed FP64 values (slower; for checking the fp32 path).
+ * Takes effect at the next gs_bin_sort. */
+enum { GS_CULL_RECT = 0, GS_CULL_ELLIPSE = 1, GS_CULL_ELLIPSE_EXACT = 2 };
 gs_status gs_set_cull(gs_ctx* ctx, int32_t mode);
 
 /* Size in bytes of a context buffer (GS_BUF_*) for the current state. */

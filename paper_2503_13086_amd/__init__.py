@@ -34,10 +34,10 @@ _STATUS = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_CAPACITY", -3: "GS_ERR_
 # Exported symbols (must match include/gs.h).
 EXPORTS = ["gs_abi_version", "gs_create", "gs_destroy", "gs_last_error", "gs_layout", "gs_preprocess", "gs_bin_sort",
            "gs_render_fwd", "gs_loss", "gs_load_balance", "gs_render_bwd", "gs_adam_step", "gs_render_bwd_adam",
-           "gs_set_cull", "gs_buffer_size",
+           "gs_set_cull", "gs_buffer_size", "gs_sync_status", "gs_reserve_pairs",
            "gs_copy_buffer", "gs_profile_enable", "gs_profile_read", "gs_memory_bytes", "gs_sched_weights",
            "gs_sched_plan", "gs_sched_lr"]
-GS_CULL_RECT, GS_CULL_ELLIPSE = 0, 1
+GS_CULL_RECT, GS_CULL_ELLIPSE, GS_CULL_ELLIPSE_EXACT = 0, 1, 2
 
 
 class GsError(RuntimeError):
@@ -77,6 +77,8 @@ def _load():
                              ctypes.POINTER(ctypes.c_int64)]),
         "gs_preprocess": (_I32, [_P, _P, _I32, _I32, _I32, ctypes.POINTER(GsCamera), _I32, _I32, _P]),
         "gs_bin_sort": (_I32, [_P, ctypes.POINTER(ctypes.c_int64), _P]),
+        "gs_sync_status": (_I32, [_P, _P]),
+        "gs_reserve_pairs": (_I32, [_P, ctypes.c_int64, _P]),
         "gs_render_fwd": (_I32, [_P, _P, _P]),
         "gs_loss": (_I32, [_P, _P, _P, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
         "gs_render_bwd": (_I32, [_P, _P, _P, _P, _I32, _P]),
@@ -182,10 +184,24 @@ def gs_preprocess(ctx, params, n: int, stride: int, sh_degree: int, cams: Sequen
                                       _stream(stream)), "gs_preprocess")
 
 
-def gs_bin_sort(ctx, stream=None) -> int:
+def gs_bin_sort(ctx, stream=None, count: bool = True) -> Optional[int]:
+    """Returns K when count is True (the call then waits for the device); with
+    count False K stays on the device and None is returned."""
+    if not count:
+        _check(ctx, _load().gs_bin_sort(ctx, None, _stream(stream)), "gs_bin_sort")
+        return None
     k = ctypes.c_int64(0)
     _check(ctx, _load().gs_bin_sort(ctx, ctypes.byref(k), _stream(stream)), "gs_bin_sort")
     return k.value
+
+
+def gs_sync_status(ctx, stream=None) -> None:
+    """Raises GsError (GS_ERR_CAPACITY) when the last binning ran out of room."""
+    _check(ctx, _load().gs_sync_status(ctx, _stream(stream)), "gs_sync_status")
+
+
+def gs_reserve_pairs(ctx, n_pairs: int, stream=None) -> None:
+    _check(ctx, _load().gs_reserve_pairs(ctx, int(n_pairs), _stream(stream)), "gs_reserve_pairs")
 
 
 def gs_render_fwd(ctx, color, stream=None) -> None:

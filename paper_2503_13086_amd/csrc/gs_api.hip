@@ -29,10 +29,16 @@ struct gs_ctx {
   std::string err;
   int stage = kNone;
   int n = 0, stride = 0, D = 0, V = 0;
+  const float* params = nullptr;   // parameter array of the last gs_preprocess (read by gs_bin_sort)
   int n_tiles = 0;
   int tile = kTile;
   int64_t P = 0;
-  uint64_t K = 0;
+  mutable uint64_t K = 0;          // pairs of the last binning, once known on the host
+  mutable bool K_known = false;    // false after a gs_bin_sort that did not wait for K
+  size_t pair_cap = 0;             // pairs the pair buffers hold
+  size_t pair_want = 0;            // pairs a failed binning needed (grow before the next)
+  size_t redo_cap = 0;             // words of redo_bits
+  size_t redo_want = 0;
   std::vector<ViewDev> hviews;
   int depth_in_b = 0, pairs_in_b = 0;
   int cull = GS_CULL_ELLIPSE;
@@ -40,13 +46,17 @@ struct gs_ctx {
   DevBuf dkey[2], dval[2], groupsums, blocksums, total, hist;
   DevBuf pkey[2], pval[2], ranges;
   DevBuf tfinal, ncontrib, last, grad2d, lossp, aux;
-  DevBuf asum, dG, loadp, loadst, kept, emitinfo;
+  DevBuf asum, dG, loadp, loadst, kept, emitinfo, redo_list, redo_bits, status;
+  DevStatus* h_status = nullptr;   // host mirror of the device status, written by the binning's last check
+  DevStatus* d_mirror = nullptr;   // its device-side address
   bool load_pending = false;   // dG holds a load-balancing gradient for the current forward
   ViewDev* h_views = nullptr;
   bool views_valid = false;   // the device views equal hviews
   unsigned long long* h_total = nullptr;
   hipEvent_t views_ev = nullptr;
   bool views_ev_pending = false;
+  hipEvent_t status_ev = nullptr;  // recorded after the binning's check wrote the mirror
+  bool status_ev_pending = false;
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[GS_N_KERNELS];
   std::vector<hipEvent_t> pool;
@@ -88,7 +98,8 @@ std::vector<DevBuf*> all_bufs(gs_ctx* c) {
   return {&c->views, &c->rec, &c->depth, &c->touched, &c->rect, &c->dkey[0], &c->dkey[1], &c->dval[0],
           &c->dval[1], &c->groupsums, &c->blocksums, &c->total, &c->hist, &c->pkey[0],
           &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->tfinal, &c->ncontrib, &c->last,
-          &c->grad2d, &c->lossp, &c->aux, &c->asum, &c->dG, &c->loadp, &c->loadst, &c->kept, &c->emitinfo};
+          &c->grad2d, &c->lossp, &c->aux, &c->asum, &c->dG, &c->loadp, &c->loadst, &c->kept, &c->emitinfo,
+          &c->redo_list, &c->redo_bits, &c->status};
 }
 
 hipEvent_t next_event(gs_ctx* c) {
@@ -169,6 +180,38 @@ void build_views(const gs_camera* cams, int n_views, int tile, std::vector<ViewD
   *P = poff;
 }
 
+// Takes in the host mirror of the device status, written by the last binning's
+// check: the sizes a failed binning needed (the next gs_bin_sort grows to them)
+// and K.  Returns the status code, with a message for an error.
+gs_status absorb_status(gs_ctx* c) {
+  const DevStatus m = *c->h_status;
+  if (m.code != GS_OK) {
+    if (m.need_pairs > c->pair_cap && (size_t)m.need_pairs > c->pair_want) c->pair_want = (size_t)m.need_pairs;
+    if (m.need_redo > c->redo_cap && (size_t)m.need_redo > c->redo_want) c->redo_want = (size_t)m.need_redo;
+    c->K = 0;
+    c->K_known = true;
+    char buf[256];
+    std::snprintf(buf, sizeof(buf),
+                  "the last binning ran out of room (%llu pairs needed, %zu held; %llu outcome words needed, %zu "
+                  "held); its results are void and the next gs_bin_sort grows the buffers",
+                  m.need_pairs, c->pair_cap, m.need_redo, c->redo_cap);
+    return fail(c, (gs_status)m.code, buf);
+  }
+  c->K = m.n_eff;
+  c->K_known = true;
+  return GS_OK;
+}
+
+// K of the last binning on the host: waits for the device when the binning did not.
+gs_status resolve_pairs(const gs_ctx* cc) {
+  gs_ctx* c = const_cast<gs_ctx*>(cc);
+  if (c->K_known || c->stage < kBinned) return GS_OK;
+  GS_HIP(c, hipSetDevice(c->device));
+  GS_HIP(c, hipEventSynchronize(c->status_ev));
+  c->status_ev_pending = false;
+  return absorb_status(c);
+}
+
 }  // namespace
 
 extern "C" {
@@ -185,10 +228,18 @@ gs_status gs_create(gs_ctx** out, int32_t device) {
   c->device = device;
   if (hipHostMalloc((void**)&c->h_views, sizeof(ViewDev) * GS_MAX_VIEWS, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_total, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
-      hipEventCreateWithFlags(&c->views_ev, hipEventDisableTiming) != hipSuccess) {
+      hipHostMalloc((void**)&c->h_status, sizeof(DevStatus), hipHostMallocMapped | hipHostMallocCoherent) !=
+          hipSuccess ||
+      hipHostGetDevicePointer((void**)&c->d_mirror, c->h_status, 0) != hipSuccess ||
+      hipEventCreateWithFlags(&c->views_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->status_ev, hipEventDisableTiming) != hipSuccess ||
+      hipMalloc(&c->status.p, sizeof(DevStatus)) != hipSuccess ||
+      hipMemset(c->status.p, 0, sizeof(DevStatus)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     gs_destroy(c);
     return GS_ERR_HIP;
   }
+  c->status.cap = sizeof(DevStatus);
+  std::memset(c->h_status, 0, sizeof(DevStatus));
   *out = c;
   return GS_OK;
 }
@@ -201,7 +252,9 @@ void gs_destroy(gs_ctx* c) {
     if (b->p) (void)hipFree(b->p);
   if (c->h_views) (void)hipHostFree(c->h_views);
   if (c->h_total) (void)hipHostFree(c->h_total);
+  if (c->h_status) (void)hipHostFree(c->h_status);
   if (c->views_ev) (void)hipEventDestroy(c->views_ev);
+  if (c->status_ev) (void)hipEventDestroy(c->status_ev);
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   delete c;
 }
@@ -263,7 +316,7 @@ gs_status gs_preprocess(gs_ctx* c, const float* params, int32_t n, int32_t strid
     GS_HIP(c, launch_preprocess(params, n, stride, sh_degree, c->views.as<ViewDev>(), n_views, c->rec.as<Record>(),
                                 c->depth.as<uint32_t>(), c->touched.as<uint32_t>(), c->rect.as<ushort4>(), s));
   }
-  c->n = n; c->stride = stride; c->D = sh_degree; c->V = n_views;
+  c->n = n; c->stride = stride; c->D = sh_degree; c->V = n_views; c->params = params;
   c->hviews = hv; c->n_tiles = n_tiles; c->tile = tile; c->P = P; c->K = 0;
   c->stage = kProjected;
   return GS_OK;
@@ -277,25 +330,45 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
   GS_HIP(c, hipSetDevice(c->device));
   const size_t NV = (size_t)c->V * c->n;
   gs_status st;
+  // what an earlier binning found too small, if the stream has passed its check
+  // (read without waiting; gs_sync_status reads it after waiting)
+  if (c->status_ev_pending && hipEventQuery(c->status_ev) == hipSuccess) {
+    absorb_status(c);
+    c->status_ev_pending = false;
+  }
   for (int i = 0; i < 2; ++i) {
     if ((st = ensure(c, c->dkey[i], NV * 4, s)) != GS_OK) return st;
     if ((st = ensure(c, c->dval[i], NV * 4, s)) != GS_OK) return st;
   }
   if ((st = ensure(c, c->groupsums, scan_group_words(NV) * 4, s)) != GS_OK) return st;
   if ((st = ensure(c, c->blocksums, scan_block_words(NV) * 4, s)) != GS_OK) return st;
-  if ((st = ensure(c, c->total, 8, s)) != GS_OK) return st;
-  if ((st = ensure(c, c->hist, sort_hist_words(NV) * 4, s)) != GS_OK) return st;
-  const bool cull = c->cull == GS_CULL_ELLIPSE;
+  if ((st = ensure(c, c->hist, sort_hist_words(NV > c->pair_cap ? NV : c->pair_cap) * 4, s)) != GS_OK) return st;
+  DevStatus* dst = c->status.as<DevStatus>();
+  GS_HIP(c, launch_status_reset(dst, s));
+  const bool cull = c->cull != GS_CULL_RECT;
+  const int exact_all = c->cull == GS_CULL_ELLIPSE_EXACT ? 1 : 0;
   // pairs per entry: the rect's tiles, or with culling the tiles whose pixel-centre
-  // box meets the cutoff region (counted in index order, coalesced)
+  // box meets the cutoff region (counted in index order, coalesced; the candidates
+  // the fp32 test cannot decide go to the exact pass)
   const uint32_t* per_entry = c->touched.as<uint32_t>();
   if (cull) {
     Prof pr(c, GS_K_SCAN, s);
     if ((st = ensure(c, c->kept, NV * 4, s)) != GS_OK) return st;
     if ((st = ensure(c, c->emitinfo, NV * sizeof(EmitInfo), s)) != GS_OK) return st;
+    if ((st = ensure(c, c->redo_list, NV * 4, s)) != GS_OK) return st;
+    size_t rw = NV / 64 + 1024;
+    if (rw < c->redo_want) rw = c->redo_want;
+    if (rw > c->redo_cap) {
+      if ((st = ensure(c, c->redo_bits, rw * 4, s)) != GS_OK) return st;
+      c->redo_cap = c->redo_bits.cap / 4;
+    }
     GS_HIP(c, launch_count_kept(c->touched.as<uint32_t>(), c->rect.as<ushort4>(), c->rec.as<Record>(), NV, c->n,
-                                c->views.as<ViewDev>(), c->tile, c->kept.as<uint32_t>(), c->emitinfo.as<EmitInfo>(),
-                                s));
+                                c->views.as<ViewDev>(), c->tile, exact_all, c->kept.as<uint32_t>(),
+                                c->emitinfo.as<EmitInfo>(), dst, c->redo_list.as<uint32_t>(), s));
+    GS_HIP(c, launch_count_redo(c->touched.as<uint32_t>(), c->rect.as<ushort4>(), c->rec.as<Record>(), c->n,
+                                c->views.as<ViewDev>(), c->tile, exact_all, c->params, c->stride,
+                                c->kept.as<uint32_t>(), c->emitinfo.as<EmitInfo>(), dst, c->redo_list.as<uint32_t>(),
+                                c->redo_bits.as<uint32_t>(), c->redo_cap, s));
     per_entry = c->kept.as<uint32_t>();
   }
   // depth order of all (view, Gaussian) entries (invisible ones carry the largest
@@ -313,24 +386,47 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
   {
     Prof pr(c, GS_K_SCAN, s);
     GS_HIP(c, launch_scan_touched(order, packed ? 1 : 0, per_entry, NV, c->groupsums.as<uint32_t>(),
-                                  c->blocksums.as<uint32_t>(), c->total.as<unsigned long long>(), s));
+                                  c->blocksums.as<uint32_t>(), &dst->n_pairs, s));
   }
-  GS_HIP(c, hipMemcpyAsync(c->h_total, c->total.p, 8, hipMemcpyDeviceToHost, s));
-  GS_HIP(c, hipStreamSynchronize(s));
-  const uint64_t K = *c->h_total;
-  if (K >= (1ull << 32)) return fail(c, GS_ERR_CAPACITY, "more than 2^32 - 1 (tile, Gaussian) pairs");
-  for (int i = 0; i < 2; ++i) {
-    if ((st = ensure(c, c->pkey[i], K * 4 + 4, s)) != GS_OK) return st;
-    if ((st = ensure(c, c->pval[i], K * 4 + 4, s)) != GS_OK) return st;
+  // The pair buffers are sized from K itself when the caller asks for K, on a
+  // context's first binning, and after a binning that found them too small;
+  // otherwise K stays on the device and the kernels below read it there.
+  const bool wait = n_pairs_out != nullptr || c->pair_cap == 0;
+  size_t want = 0;
+  c->K_known = false;
+  if (wait) {
+    GS_HIP(c, hipMemcpyAsync(c->h_total, &dst->n_pairs, 8, hipMemcpyDeviceToHost, s));
+    GS_HIP(c, hipStreamSynchronize(s));
+    const uint64_t K = *c->h_total;
+    if (K >= (1ull << 32)) return fail(c, GS_ERR_CAPACITY, "more than 2^32 - 1 (tile, Gaussian) pairs");
+    c->K = K;
+    c->K_known = true;
+    want = (size_t)K;
   }
-  if ((st = ensure(c, c->hist, sort_hist_words(K > NV ? K : NV) * 4, s)) != GS_OK) return st;
+  if (c->pair_want > want) want = c->pair_want;
+  if (want > c->pair_cap || c->pair_cap == 0) {
+    for (int i = 0; i < 2; ++i) {
+      if ((st = ensure(c, c->pkey[i], want * 4 + 4, s)) != GS_OK) return st;
+      if ((st = ensure(c, c->pval[i], want * 4 + 4, s)) != GS_OK) return st;
+    }
+    size_t cap = c->pkey[0].cap;
+    for (DevBuf* b : {&c->pkey[1], &c->pval[0], &c->pval[1]}) cap = b->cap < cap ? b->cap : cap;
+    c->pair_cap = cap / 4 - 1;
+    c->pair_want = 0;
+    if ((st = ensure(c, c->hist, sort_hist_words(NV > c->pair_cap ? NV : c->pair_cap) * 4, s)) != GS_OK) return st;
+  }
   if ((st = ensure(c, c->ranges, (size_t)c->n_tiles * 8, s)) != GS_OK) return st;
+  GS_HIP(c, launch_check_pairs(dst, c->d_mirror, c->pair_cap, s));
+  GS_HIP(c, hipEventRecord(c->status_ev, s));
+  c->status_ev_pending = true;
+  const unsigned long long* n_eff = &dst->n_eff;
   {
     Prof pr(c, GS_K_EMIT, s);
     GS_HIP(c, launch_emit_pairs(order, packed ? 1 : 0, per_entry, c->groupsums.as<uint32_t>(),
-                                c->blocksums.as<uint32_t>(), c->rect.as<ushort4>(),
-                                c->rec.as<Record>(), NV, c->n, c->views.as<ViewDev>(), (size_t)K, cull ? 1 : 0,
-                                c->tile, cull ? c->emitinfo.as<EmitInfo>() : nullptr, c->pkey[0].as<uint32_t>(),
+                                c->blocksums.as<uint32_t>(), c->rect.as<ushort4>(), c->rec.as<Record>(), NV, c->n,
+                                c->views.as<ViewDev>(), dst, cull ? 1 : 0, c->tile,
+                                cull ? c->emitinfo.as<EmitInfo>() : nullptr,
+                                cull ? c->redo_bits.as<uint32_t>() : nullptr, c->pkey[0].as<uint32_t>(),
                                 c->pval[0].as<uint32_t>(), s));
   }
   {
@@ -340,16 +436,51 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
     // record indices are below NV: up to 2^24 entries the two tile passes move one
     // packed word between them
     GS_HIP(c, radix_sort_pairs(c->pkey[0].as<uint32_t>(), c->pval[0].as<uint32_t>(), c->pkey[1].as<uint32_t>(),
-                               c->pval[1].as<uint32_t>(), K, bits, packed ? 1 : 0, sc, &c->pairs_in_b, s));
+                               c->pval[1].as<uint32_t>(), c->pair_cap, n_eff, bits, packed ? 1 : 0, sc,
+                               &c->pairs_in_b, s));
   }
   {
     Prof pr(c, GS_K_RANGES, s);
-    GS_HIP(c, launch_ranges(c->pkey[c->pairs_in_b].as<uint32_t>(), K, c->ranges.as<uint2>(), c->n_tiles, s));
+    GS_HIP(c, launch_ranges(c->pkey[c->pairs_in_b].as<uint32_t>(), c->pair_cap, n_eff, c->ranges.as<uint2>(),
+                            c->n_tiles, s));
   }
-  c->K = K;
   c->stage = kBinned;
-  if (n_pairs_out) *n_pairs_out = (int64_t)K;
+  if (n_pairs_out) *n_pairs_out = (int64_t)c->K;
   return GS_OK;
+}
+
+gs_status gs_reserve_pairs(gs_ctx* c, int64_t n_pairs, gs_stream stream) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (n_pairs < 1 || n_pairs >= (1ll << 32)) return fail(c, GS_ERR_INVALID, "n_pairs must be in 1..2^32-1");
+  hipStream_t s = (hipStream_t)stream;
+  GS_HIP(c, hipSetDevice(c->device));
+  GS_HIP(c, hipStreamSynchronize(s));
+  for (DevBuf* b : {&c->pkey[0], &c->pkey[1], &c->pval[0], &c->pval[1]}) {
+    if (b->p) GS_HIP(c, hipFree(b->p));
+    b->p = nullptr;
+    b->cap = 0;
+    GS_HIP(c, hipMalloc(&b->p, (size_t)n_pairs * 4 + 4));
+    b->cap = (size_t)n_pairs * 4 + 4;
+  }
+  c->pair_cap = (size_t)n_pairs;
+  c->pair_want = 0;
+  gs_status st = ensure(c, c->hist, sort_hist_words(c->pair_cap) * 4, s);
+  if (st != GS_OK) return st;
+  if (c->stage > kProjected) c->stage = kProjected;   // the pair lists are gone
+  return GS_OK;
+}
+
+gs_status gs_sync_status(gs_ctx* c, gs_stream stream) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  GS_HIP(c, hipSetDevice(c->device));
+  GS_HIP(c, hipStreamSynchronize((hipStream_t)stream));
+  if (c->status_ev_pending) {
+    GS_HIP(c, hipEventSynchronize(c->status_ev));
+    c->status_ev_pending = false;
+  }
+  return absorb_status(c);
 }
 
 gs_status gs_render_fwd(gs_ctx* c, float* color, gs_stream stream) {
@@ -495,7 +626,7 @@ gs_status gs_adam_step(gs_ctx* c, float* params, const float* grad, float* m, fl
   GS_HIP(c, hipSetDevice(c->device));
   Prof pr(c, GS_K_ADAM, s);
   GS_HIP(c, launch_adam(params, grad, m, v, step, n, stride, sh_degree, a,
-                        a.n_views ? c->touched.as<uint32_t>() : nullptr, s));
+                        a.n_views ? c->touched.as<uint32_t>() : nullptr, c->status.as<DevStatus>(), s));
   return GS_OK;
 }
 
@@ -532,7 +663,8 @@ gs_status gs_render_bwd_adam(gs_ctx* c, float* params, const float* dL_dcolor, f
   {
     Prof pr(c, GS_K_BWD_ADAM, s);
     GS_HIP(c, launch_preprocess_bwd_adam(params, c->n, c->stride, c->D, c->views.as<ViewDev>(), c->V,
-                                         c->touched.as<uint32_t>(), c->grad2d.as<float>(), grad, m, v, step, a, s));
+                                         c->touched.as<uint32_t>(), c->grad2d.as<float>(), grad, m, v, step, a,
+                                         c->status.as<DevStatus>(), s));
   }
   return GS_OK;
 }
@@ -540,7 +672,8 @@ gs_status gs_render_bwd_adam(gs_ctx* c, float* params, const float* dL_dcolor, f
 gs_status gs_set_cull(gs_ctx* c, int32_t mode) {
   if (!c) return GS_ERR_INVALID;
   c->err.clear();
-  if (mode != GS_CULL_RECT && mode != GS_CULL_ELLIPSE) return fail(c, GS_ERR_INVALID, "unknown cull mode");
+  if (mode != GS_CULL_RECT && mode != GS_CULL_ELLIPSE && mode != GS_CULL_ELLIPSE_EXACT)
+    return fail(c, GS_ERR_INVALID, "unknown cull mode");
   c->cull = mode;
   if (c->stage > kProjected) c->stage = kProjected;   // pair lists must be rebuilt
   return GS_OK;
@@ -548,6 +681,10 @@ gs_status gs_set_cull(gs_ctx* c, int32_t mode) {
 
 gs_status gs_buffer_size(const gs_ctx* c, int32_t which, size_t* bytes) {
   if (!c || !bytes) return GS_ERR_INVALID;
+  if (which == GS_BUF_KEYS || which == GS_BUF_VALUES || which == GS_BUF_PAIR_VIEW) {
+    const gs_status st = resolve_pairs(c);
+    if (st != GS_OK && st != GS_ERR_CAPACITY) return st;
+  }
   const size_t NV = (size_t)c->V * c->n;
   size_t b = 0;
   switch (which) {

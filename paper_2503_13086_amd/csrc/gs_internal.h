@@ -52,7 +52,10 @@ __host__ __device__ inline int n_sh(int D) { return (D + 1) * (D + 1); }
 // (gx, gy) (edge T, image W x H)?  The minimum of q over the box is 0 when the box
 // holds the centre, else the smallest of the minima along the four edges (clamped
 // 1-D minimisers, nbc = -b/c, nba = -b/a).  FP64, no contraction, fixed operation
-// order: every kernel that asks gets the same answer.
+// order: every kernel that asks gets the same answer.  The pair lists are defined
+// by this test on the FP64 conic and cutoff of the projection (exact_cutoff_geo);
+// cutoff_geo below builds the same structure from a record's fp32 copies, which
+// only the fp32 clear-case test uses.
 struct CutoffGeo {
   double u, w, a, b, c, nbc, nba, lim;
 };
@@ -111,13 +114,14 @@ __device__ inline bool tile_meets_cutoff(const CutoffGeo& g, int gx, int gy, int
   return best <= g.lim;
 }
 // The same decision in fp32 where it is clear: 1 keep, 0 drop, -1 too close to call
-// (then tile_meets_cutoff decides).  The box offsets are taken in FP64 and rounded
-// (signs, hence the inside test, exact); the four edge minima are evaluated at the
-// same clamp points in fp32.  Against the FP64 value, rounding of the offsets, the
-// products and the clamp points stays below 8 ulp of S, S = (|a| + |b|) Dx^2 +
-// (|b| + |c|) Dy^2 bounding |a dx^2| + 2 |b dx dy| + |c dy^2| over the box (Dx, Dy
-// the largest offsets); a result within 1e-5 S + 1e-6 |lim| of the limit is
-// left undecided.
+// (then tile_meets_cutoff on the FP64 conic and cutoff decides).  The box offsets
+// are taken in FP64 and rounded (signs, hence the inside test, exact); the four edge
+// minima are evaluated at the same clamp points in fp32.  Against the FP64 value
+// on the FP64 conic, rounding of the offsets, the products and the clamp points
+// stays below 8 ulp of S, S = (|a| + |b|) Dx^2 + (|b| + |c|) Dy^2 bounding
+// |a dx^2| + 2 |b dx dy| + |c dy^2| over the box (Dx, Dy the largest offsets), and
+// the record's fp32 copies of a, b, c and the cutoff add at most 2^-24 S and
+// 2^-23 |lim|; a result within 1e-5 S + 1e-6 |lim| of the limit is left undecided.
 __device__ inline int tile_cutoff_fast(const CutoffGeoF& g, int gx, int gy, int T, int W, int H) {
 #pragma clang fp contract(off)
   const float dx0 = (float)(((double)(gx * T) + 0.5) - g.u);
@@ -142,6 +146,27 @@ __device__ inline int tile_cutoff_fast(const CutoffGeoF& g, int gx, int gy, int 
 
 __host__ __device__ inline int n_params(int D) { return 11 + 3 * n_sh(D); }
 
+// Device-side status of a context: conditions kernels find while a step runs
+// (reported by gs_sync_status), and the counters of the binning.  Reset at the
+// start of every binning.
+struct DevStatus {
+  int32_t code;                   // GS_OK or the first error (GS_ERR_CAPACITY)
+  uint32_t pad;
+  unsigned long long n_pairs;     // pairs of the last binning (K)
+  unsigned long long n_eff;       // K when the pair buffers hold it, else 0: the later kernels then do nothing
+  unsigned long long need_pairs;  // pairs the last binning needed room for
+  unsigned long long redo_count;  // entries whose cutoff tests the fp32 test left undecided
+  unsigned long long redo_words;  // outcome words handed out to such entries of more than 64 candidates
+  unsigned long long need_redo;   // outcome words they needed
+};
+// EmitInfo.bits of an entry of more than 64 candidates whose outcomes the exact
+// pass stored: this flag | the first of its words in the outcome array.
+constexpr uint64_t kRedoFlag = 1ull << 63;
+
+__device__ inline void status_fail(DevStatus* st, int32_t code) {
+  atomicCAS(&st->code, (int32_t)GS_OK, code);
+}
+
 // ---- launchers (each file defines its own) ----
 hipError_t launch_preprocess(const float* P, int n, int stride, int D, const ViewDev* views, int V,
                              Record* rec, uint32_t* depth, uint32_t* touched, ushort4* rect,
@@ -160,8 +185,11 @@ struct SortScratch {
 };
 constexpr int kSortTileItems = 4096;
 size_t sort_hist_words(size_t n);
+// n_dev (may be NULL): the item count in device memory, read by the kernels (at
+// most n, which sizes the grids); without it n items are sorted.
 hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, size_t n,
-                            int bits, int vals24, SortScratch scratch, int* result_in_b, hipStream_t s);
+                            const unsigned long long* n_dev, int bits, int vals24, SortScratch scratch,
+                            int* result_in_b, hipStream_t s);
 // Stable sort of the entries 0..n-1 by depth[e] (32-bit keys, read only): values
 // e, with count given e | min(count[e], 255) << 24 (n <= 2^24); result in *_a
 hipError_t radix_sort_depth(const uint32_t* depth, const uint32_t* count, uint32_t* keys_a, uint32_t* vals_a,
@@ -191,16 +219,37 @@ struct alignas(16) EmitInfo {
   ushort4 rect;
   uint64_t bits;
 };
+// Entries where the fp32 test leaves some candidate undecided are counted without
+// those candidates and listed in redo_list (count in st->redo_count); the exact
+// pass launch_count_redo then recomputes their FP64 conic and cutoff from the
+// parameters and rewrites their kept count and EmitInfo (for more than 64
+// candidates: kRedoFlag | offset of their outcome bits in redo_bits, which holds
+// redo_cap words; beyond that st reports GS_ERR_CAPACITY).
+// exact_all != 0: no candidate is decided by the fp32 test (every test in FP64).
 hipError_t launch_count_kept(const uint32_t* touched, const ushort4* rect, const Record* rec, size_t n_entries, int n,
-                             const ViewDev* views, int tile, uint32_t* kept, EmitInfo* info, hipStream_t s);
+                             const ViewDev* views, int tile, int exact_all, uint32_t* kept, EmitInfo* info,
+                             DevStatus* st, uint32_t* redo_list, hipStream_t s);
+hipError_t launch_count_redo(const uint32_t* touched, const ushort4* rect, const Record* rec, int n,
+                             const ViewDev* views, int tile, int exact_all, const float* P, int stride,
+                             uint32_t* kept, EmitInfo* info, DevStatus* st, const uint32_t* redo_list,
+                             uint32_t* redo_bits, size_t redo_cap, hipStream_t s);
+hipError_t launch_status_reset(DevStatus* st, hipStream_t s);
+// K against the pair capacity: n_eff = K if K <= cap and K < 2^32, else 0 and
+// GS_ERR_CAPACITY with need_pairs = K; then the status is copied to `mirror`
+// (host-visible memory).
+hipError_t launch_check_pairs(DevStatus* st, DevStatus* mirror, size_t cap, hipStream_t s);
 // pairs of the depth-ordered entries order[0..n_entries): touched, group_sums and
 // block_sums as scanned by launch_scan_touched; cull != 0 keeps only the rect tiles
-// that meet the cutoff region (touched must then be the kept counts)
+// that meet the cutoff region (touched must then be the kept counts); writes only
+// below st->n_eff pairs
 hipError_t launch_emit_pairs(const uint32_t* order, int packed, const uint32_t* touched, const uint32_t* group_sums,
                              const uint32_t* block_off, const ushort4* rect, const Record* rec, size_t n_entries,
-                             int n, const ViewDev* views, size_t K, int cull, int tile, const EmitInfo* info,
-                             uint32_t* pair_tile, uint32_t* pair_rec, hipStream_t s);
-hipError_t launch_ranges(const uint32_t* pair_tile, size_t K, uint2* ranges, int n_tiles, hipStream_t s);
+                             int n, const ViewDev* views, const DevStatus* st, int cull, int tile,
+                             const EmitInfo* info, const uint32_t* redo_bits, uint32_t* pair_tile, uint32_t* pair_rec,
+                             hipStream_t s);
+// ranges of the first min(*n_dev, K_cap) sorted pairs (all K_cap without n_dev)
+hipError_t launch_ranges(const uint32_t* pair_tile, size_t K_cap, const unsigned long long* n_dev, uint2* ranges,
+                         int n_tiles, hipStream_t s);
 hipError_t launch_compose_keys(const uint32_t* pair_tile, const uint32_t* pair_rec, const uint32_t* depth,
                                size_t K, int n, size_t n_rec, unsigned long long* keys, uint32_t* values,
                                uint32_t* views, int mode, hipStream_t s);
@@ -234,8 +283,10 @@ struct AdamArgs {
   uint32_t group_mask;  // groups that take the per-view factor
   float b1, b2, eps;
 };
+// The Adam kernels leave every buffer untouched when st (may be NULL) reports an
+// error: a step whose binning failed must not move the parameters.
 hipError_t launch_adam(float* P, const float* G, float* M, float* Vv, uint32_t* step, int n, int stride, int D,
-                       const AdamArgs& a, const uint32_t* touched, hipStream_t s);
+                       const AdamArgs& a, const uint32_t* touched, const DevStatus* st, hipStream_t s);
 
 // ---- Adam pieces shared by the Adam kernel and the fused backward + Adam, so
 // that both produce the same bits ----
@@ -285,6 +336,6 @@ __device__ inline void adam_elem(float& p, float& m, float& v, float g, float lr
 // Gaussian is applied as soon as it is formed (grad written too when not NULL).
 hipError_t launch_preprocess_bwd_adam(float* P, int n, int stride, int D, const ViewDev* views, int V,
                                       const uint32_t* touched, const float* grad2d, float* grad, float* M, float* Vv,
-                                      uint32_t* step, const AdamArgs& a, hipStream_t s);
+                                      uint32_t* step, const AdamArgs& a, const DevStatus* st, hipStream_t s);
 
 }  // namespace gsk

@@ -5,7 +5,8 @@
 // bias corrections from its own step counter (Gaussians appended later start at
 // step 0) and its view factor (mean of the per-view scales over the views that
 // see it), then streams its parameter rows: each row is a coalesced read of
-// param, grad, m, v and a write of param, m, v.
+// param, grad, m, v and a write of param, m, v.  A step whose binning reported an
+// error on the device (pair buffers too small) writes nothing.
 #include "gs_internal.h"
 
 namespace gsk {
@@ -14,9 +15,11 @@ namespace {
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ P, const float* __restrict__ G,
                                                float* __restrict__ M, float* __restrict__ Vv,
                                                uint32_t* __restrict__ step, int n, int stride, int rows, AdamArgs a,
-                                               const uint32_t* __restrict__ touched) {
+                                               const uint32_t* __restrict__ touched,
+                                               const DevStatus* __restrict__ st) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
+  if (st && st->code != GS_OK) return;
   const uint32_t k = step[g] + 1u;
   step[g] = k;
   float bc1, bc2;
@@ -37,10 +40,10 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ P, const float
 }  // namespace
 
 hipError_t launch_adam(float* P, const float* G, float* M, float* Vv, uint32_t* step, int n, int stride, int D,
-                       const AdamArgs& a, const uint32_t* touched, hipStream_t s) {
+                       const AdamArgs& a, const uint32_t* touched, const DevStatus* st, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, P, G, M, Vv, step, n, stride, n_params(D), a,
-                     touched);
+                     touched, st);
   return hipGetLastError();
 }
 

@@ -538,16 +538,14 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
     __syncthreads();
     // one global atomic per (tile, Gaussian, component); consecutive lanes take
     // consecutive components, so a wavefront's atomics fall on a few cache lines
-    // (32-bit byte offsets from the array base: grad2d holds n_rec * 36 < 2^32 bytes)
+    // (element offsets in 64 bits: n_rec * 9 may pass 2^32 bytes)
     float* af = &acc[0][0];
     for (int i = threadIdx.x; i < m * kGrad2D; i += NT) {
       const int j = i / kGrad2D;
       const uint32_t rid = srid[j];
       const float x = af[i];
-      // rid * 36 + (i - 9 j) * 4, in modular arithmetic
-      const uint32_t off = (rid - (uint32_t)j) * (uint32_t)(kGrad2D * sizeof(float)) + (uint32_t)i * 4u;
       if (x != 0.0f && rid < n_rec)
-        unsafeAtomicAdd(reinterpret_cast<float*>(reinterpret_cast<char*>(grad2d) + off), x);
+        unsafeAtomicAdd(grad2d + ((size_t)rid * kGrad2D + (size_t)(i - kGrad2D * j)), x);
       af[i] = 0.0f;
     }
   }

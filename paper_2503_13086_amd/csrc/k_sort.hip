@@ -14,7 +14,7 @@
 // holding the same digit), per-wave digit counts in LDS and a running count per
 // digit across the workgroup's 16 rounds.  The workgroup then places its items in
 // LDS in digit order and writes each digit's run contiguously to global memory.
-#include "gs_internal.h"
+#include "gs_geom.h"
 
 #pragma clang fp contract(off)
 
@@ -48,9 +48,19 @@ __device__ inline uint64_t match_digit(uint32_t d, bool valid) {
 // with non-returning atomic adds (no dependence from one 64-item round to the
 // next); a round whose valid items all share one digit (the common case for the
 // high digits of clustered keys) is added by one lane.
-__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys, size_t n, int shift,
+// Items to sort: n (the capacity the grids are sized for), or the count in device
+// memory when there is one (never above n).
+__device__ inline size_t item_count(size_t n, const unsigned long long* n_dev) {
+  if (!n_dev) return n;
+  const unsigned long long d = *n_dev;
+  return d < (unsigned long long)n ? (size_t)d : n;
+}
+
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys, size_t n_cap,
+                                                          const unsigned long long* __restrict__ n_dev, int shift,
                                                           uint32_t* __restrict__ hist, int n_blocks) {
   __shared__ uint32_t hw[kWaves][kRadix];
+  const size_t n = item_count(n_cap, n_dev);   // blocks past it count nothing
   const int w = threadIdx.x / 64;
   for (int i = 0; i < kWaves; ++i) hw[i][threadIdx.x] = 0;
   __syncthreads();
@@ -223,7 +233,8 @@ constexpr int kScatterItems = kSortTileItems / kScatterThreads;
 
 template <int MODE>
 __global__ __launch_bounds__(kScatterThreads) void k_radix_scatter(const uint32_t* __restrict__ keys_in,
-                                                                    const uint32_t* __restrict__ vals_in, size_t n,
+                                                                    const uint32_t* __restrict__ vals_in, size_t n_cap,
+                                                                    const unsigned long long* __restrict__ n_dev,
                                                                     int shift, const DigitStarts starts,
                                                                     const uint32_t* __restrict__ low_base,
                                                                     uint32_t* __restrict__ keys_out,
@@ -240,9 +251,12 @@ __global__ __launch_bounds__(kScatterThreads) void k_radix_scatter(const uint32_
   // Workgroups are dealt to the 8 XCDs round-robin; XCD x takes the contiguous
   // eighth x of the tiles, so each digit's output run of an eighth is written
   // through one L2 (the lines shared by neighbouring tiles' runs merge there instead
-  // of reaching HBM as partial writes from two XCDs).  Grid: 8 x ceil(tiles / 8).
+  // of reaching HBM as partial writes from two XCDs).  Grid: 8 x ceil(tiles / 8)
+  // for the capacity; the eighths are those of the actual item count.
+  const size_t n = item_count(n_cap, n_dev);
   const int n_tiles_sort = (int)((n + kSortTileItems - 1) / kSortTileItems);
   const int eighth = (n_tiles_sort + 7) / 8;
+  if ((int)(blockIdx.x / 8) >= eighth) return;
   const int blk = (int)(blockIdx.x % 8) * eighth + (int)(blockIdx.x / 8);
   if (blk >= n_tiles_sort) return;
   const int tid = threadIdx.x;
@@ -491,9 +505,10 @@ __device__ inline uint32_t wave_incl_scan(uint32_t x) {
 __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restrict__ touched,
                                                           const ushort4* __restrict__ rect,
                                                           const Record* __restrict__ rec, size_t n_entries, int n,
-                                                          const ViewDev* __restrict__ views, int T,
+                                                          const ViewDev* __restrict__ views, int T, int exact_all,
                                                           uint32_t* __restrict__ kept,
-                                                          EmitInfo* __restrict__ info) {
+                                                          EmitInfo* __restrict__ info, DevStatus* __restrict__ st,
+                                                          uint32_t* __restrict__ redo_list) {
   __shared__ uint32_t s_cp[kWaves][65];
   __shared__ uint32_t s_nx[kWaves][64];
   __shared__ uint32_t s_org[kWaves][64];    // rect origin (tx0 | ty0 << 16)
@@ -501,7 +516,8 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
   __shared__ uint32_t s_k[kWaves][64];
   __shared__ uint64_t s_bits[kWaves][64];
   __shared__ int s_own[kWaves][64];
-  __shared__ CutoffGeoF s_geo[kWaves][64];    // fp32 clear-case geometry (the FP64 one is re-derived when needed)
+  __shared__ CutoffGeoF s_geo[kWaves][64];    // fp32 clear-case geometry
+  __shared__ uint32_t s_redo[kWaves][64];     // the entry has a candidate the fp32 test cannot decide
   const int w = threadIdx.x / 64;
   const unsigned lane = __lane_id();
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -512,6 +528,7 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
   if (lane == 0) s_cp[w][0] = 0u;
   s_k[w][lane] = 0u;
   s_bits[w][lane] = 0ull;
+  s_redo[w][lane] = 0u;
   if (cand) {
     rc = rect[e];
     const ViewDev& cv = views[e / (size_t)n];
@@ -539,9 +556,9 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
       const uint32_t org = s_org[w][lo], wh = s_wh[w][lo];
       const int gx = (int)((org & 0xffffu) + tx), gy = (int)((org >> 16) + ty);
       const int W = (int)(wh & 0xffffu), H = (int)(wh >> 16);
-      const int fast = tile_cutoff_fast(s_geo[w][lo], gx, gy, T, W, H);
-      pass = fast >= 0 ? fast != 0
-                       : tile_meets_cutoff(cutoff_geo(rec[e - lane + (unsigned)lo]), gx, gy, T, W, H);
+      const int fast = exact_all ? -1 : tile_cutoff_fast(s_geo[w][lo], gx, gy, T, W, H);
+      pass = fast > 0;
+      if (fast < 0) s_redo[w][lo] = 1u;   // decided by the exact pass
     }
     const uint64_t fmask = __ballot(first);
     const uint64_t pmask = __ballot(pass);
@@ -561,7 +578,114 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
     in.rect = rc;
     in.bits = s_bits[w][lane];
     info[e] = in;
+    if (s_redo[w][lane]) redo_list[atomicAdd(&st->redo_count, 1ull)] = (uint32_t)e;
   }
+}
+
+// The exact pass over the entries k_count_kept listed, one wave per entry: the
+// FP64 conic and cutoff are recomputed from the parameters (as the projection
+// computed them) and every candidate the fp32 test cannot decide is decided by
+// tile_meets_cutoff on them; the kept count and EmitInfo are rewritten.  Entries of
+// more than 64 candidates keep their outcome bits in redo_bits (one bit per
+// candidate, 32 per word, from an offset handed out by an atomic counter).
+__global__ __launch_bounds__(kThreads) void k_count_redo(const uint32_t* __restrict__ touched,
+                                                          const ushort4* __restrict__ rect,
+                                                          const Record* __restrict__ rec, int n,
+                                                          const ViewDev* __restrict__ views, int T, int exact_all,
+                                                          const float* __restrict__ P, int stride,
+                                                          uint32_t* __restrict__ kept, EmitInfo* __restrict__ info,
+                                                          DevStatus* __restrict__ st,
+                                                          const uint32_t* __restrict__ redo_list,
+                                                          uint32_t* __restrict__ redo_bits, size_t redo_cap) {
+  const unsigned lane = __lane_id();
+  const unsigned long long cnt = st->redo_count;
+  const size_t waves = (size_t)gridDim.x * (blockDim.x / 64);
+  for (size_t i = (size_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; i < cnt; i += waves) {
+    const uint32_t e = redo_list[i];
+    const int v = (int)(e / (uint32_t)n);
+    const int g = (int)(e - (uint32_t)v * (uint32_t)n);
+    const ViewDev& cv = views[v];
+    const CutoffGeo ex = exact_cutoff_geo(P, stride, g, cv);
+    const CutoffGeoF fg = cutoff_geo_f(rec[e]);
+    const ushort4 rc = rect[e];
+    const uint32_t nx = (uint32_t)(rc.y - rc.x + 1), C = touched[e];
+    const bool large = C > 64u;
+    size_t off = 0;
+    bool room = true;
+    if (large) {
+      const size_t words = (C + 31u) / 32u;
+      unsigned long long o = 0;
+      if (lane == 0) o = atomicAdd(&st->redo_words, (unsigned long long)words);
+      off = (size_t)__shfl((long long)o, 0);
+      if (off + words > redo_cap) {
+        room = false;
+        if (lane == 0) {
+          atomicMax(&st->need_redo, (unsigned long long)(off + words));
+          status_fail(st, GS_ERR_CAPACITY);
+        }
+      }
+    }
+    uint32_t k = 0;
+    uint64_t bits = 0ull;
+    for (uint32_t cb = 0; cb < C; cb += 64u) {
+      const uint32_t li = cb + lane;
+      bool keep = false;
+      if (li < C) {
+        const uint32_t ty = li / nx, tx = li - ty * nx;
+        const int gx = (int)(rc.x + tx), gy = (int)(rc.z + ty);
+        const int f = exact_all ? -1 : tile_cutoff_fast(fg, gx, gy, T, cv.W, cv.H);
+        keep = f >= 0 ? f != 0 : tile_meets_cutoff(ex, gx, gy, T, cv.W, cv.H);
+      }
+      const uint64_t m = __ballot(keep);
+      k += (uint32_t)__popcll(m);
+      if (!large) {
+        bits = m;
+      } else if (room && lane < 2u && cb / 32u + lane < (C + 31u) / 32u) {
+        redo_bits[off + cb / 32u + lane] = (uint32_t)(m >> (32u * lane));
+      }
+    }
+    if (lane == 0) {
+      kept[e] = k;
+      EmitInfo in;
+      in.rect = rc;
+      in.bits = large ? (room ? kRedoFlag | (uint64_t)off : 0ull) : bits;
+      info[e] = in;
+    }
+  }
+}
+
+__global__ void k_status_reset(DevStatus* __restrict__ st) {
+  st->code = GS_OK;
+  st->pad = 0u;
+  st->n_pairs = 0ull;
+  st->n_eff = 0ull;
+  st->need_pairs = 0ull;
+  st->redo_count = 0ull;
+  st->redo_words = 0ull;
+  st->need_redo = 0ull;
+}
+
+// The binning's last status word: checks K against the pair capacity and copies
+// the whole status into the host-visible mirror, which the host reads once the
+// stream has passed this point (without waiting for it).
+__global__ void k_check_pairs(DevStatus* __restrict__ st, DevStatus* __restrict__ mirror, unsigned long long cap) {
+  const unsigned long long K = st->n_pairs;
+  if (K > cap || K >= (1ull << 32)) {
+    st->n_eff = 0ull;
+    st->need_pairs = K;
+    status_fail(st, GS_ERR_CAPACITY);
+  } else {
+    st->n_eff = K;
+  }
+  mirror->n_pairs = K;
+  mirror->n_eff = st->n_eff;
+  mirror->need_pairs = st->need_pairs;
+  mirror->redo_count = st->redo_count;
+  mirror->redo_words = st->redo_words;
+  mirror->need_redo = st->need_redo;
+  mirror->pad = 0u;
+  __threadfence_system();
+  mirror->code = st->code;
 }
 
 // Pair emission, one wave per 64 consecutive depth-ordered entries.  The wave's
@@ -581,8 +705,10 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
                                                     const uint32_t* __restrict__ block_off,
                                                     const ushort4* __restrict__ rect,
                                                     const Record* __restrict__ rec, size_t n_entries, int n,
-                                                    const ViewDev* __restrict__ views, size_t K, int cull, int T,
+                                                    const ViewDev* __restrict__ views,
+                                                    const DevStatus* __restrict__ st, int cull, int T,
                                                     const EmitInfo* __restrict__ info,
+                                                    const uint32_t* __restrict__ redo_bits,
                                                     uint32_t* __restrict__ pair_tile,
                                                     uint32_t* __restrict__ pair_rec) {
   __shared__ uint32_t s_cp[kWaves][65];
@@ -595,7 +721,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
   __shared__ uint64_t s_bits[kWaves][64];   // test outcomes (entries of <= 64 candidates)
   __shared__ int s_own[kWaves][64];         // round_owner scratch
   __shared__ int s_slot[kWaves][64];        // entry's s_geo slot (-1: none)
-  __shared__ CutoffGeo s_geo[kWaves][kEmitGeoSlots];
+  __shared__ CutoffGeoF s_geo[kWaves][kEmitGeoSlots];
   const int w = threadIdx.x / 64;
   const unsigned lane = __lane_id();
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -639,7 +765,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
       if (large) {
         s_org[w][lane] = (uint32_t)rc.x | ((uint32_t)rc.z << 16);
         s_wh[w][lane] = (uint32_t)cv.W | ((uint32_t)cv.H << 16);
-        if (slot < kEmitGeoSlots) s_geo[w][slot] = cutoff_geo(rec[rid]);
+        if (slot < kEmitGeoSlots) s_geo[w][slot] = cutoff_geo_f(rec[rid]);
       }
     }
   }
@@ -654,7 +780,10 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
   for (int o = 32; o > 0; o >>= 1) before += (uint32_t)__shfl_xor((int)before, o);
   const uint32_t lo_off = block_off[g / (kScanItems / 64)] + before;
   const uint32_t hi_end = lo_off + group_sums[g];
-  if (hi_end > K || hi_end < lo_off) return;   // never for a consistent scan; guards the writes
+  // the pair buffers hold st->n_eff pairs (0 when they are too small for this
+  // binning: then nothing is written)
+  const unsigned long long K = st->n_eff;
+  if (hi_end > K || hi_end < lo_off) return;
   uint32_t pos = lo_off;
   int carry = 0;
   for (uint32_t cb = 0; cb < C; cb += 64) {
@@ -677,9 +806,18 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
         } else {
           const uint32_t org = s_org[w][lo], wh = s_wh[w][lo];
           const int sl = s_slot[w][lo];
-          const CutoffGeo geo = sl >= 0 ? s_geo[w][sl] : cutoff_geo(rec[r]);
-          keep = tile_meets_cutoff(geo, (int)((org & 0xffffu) + tx), (int)((org >> 16) + ty), T,
-                                   (int)(wh & 0xffffu), (int)(wh >> 16));
+          const uint64_t ib = s_bits[w][lo];
+          if (ib & kRedoFlag) {
+            // outcomes stored by the exact pass
+            keep = ((redo_bits[(size_t)(ib & ~kRedoFlag) + li / 32u] >> (li & 31u)) & 1u) != 0u;
+          } else {
+            // the fp32 test decided every candidate of this entry in the count (else
+            // the exact pass would have stored its outcomes, or reported a full
+            // outcome array), and decides them the same way here
+            const CutoffGeoF geo = sl >= 0 ? s_geo[w][sl] : cutoff_geo_f(rec[r]);
+            keep = tile_cutoff_fast(geo, (int)((org & 0xffffu) + tx), (int)((org >> 16) + ty), T,
+                                    (int)(wh & 0xffffu), (int)(wh >> 16)) > 0;
+          }
         }
       }
     }
@@ -697,7 +835,9 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
 
 // Tile boundaries in the sorted tile ids: each thread takes 4 consecutive ids (one
 // 16-byte load) and the id before them.
-__global__ void k_ranges(const uint32_t* __restrict__ tile, size_t K, uint2* __restrict__ ranges, uint32_t n_tiles) {
+__global__ void k_ranges(const uint32_t* __restrict__ tile, size_t K_cap, const unsigned long long* __restrict__ n_dev,
+                         uint2* __restrict__ ranges, uint32_t n_tiles) {
+  const size_t K = item_count(K_cap, n_dev);
   const size_t i0 = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (i0 >= K) return;
   uint32_t t[4];
@@ -757,9 +897,10 @@ namespace {
 // scan's parts to the scatter.
 struct PassScan {
   size_t n;
+  const unsigned long long* n_dev;
   int n_blocks, cs, n_chunks;
   uint32_t *hist, *chunk_sum, *digit_base[2];
-  PassScan(size_t n_, SortScratch sc) : n(n_) {
+  PassScan(size_t n_, const unsigned long long* n_dev_, SortScratch sc) : n(n_), n_dev(n_dev_) {
     n_blocks = (int)((n + kSortTileItems - 1) / kSortTileItems);
     cs = chunk_blocks(n_blocks);
     n_chunks = (n_blocks + cs - 1) / cs;
@@ -769,7 +910,7 @@ struct PassScan {
     digit_base[1] = digit_base[0] + kRadix;
   }
   void run(const uint32_t* keys, int shift, int db, hipStream_t s) const {
-    hipLaunchKernelGGL(k_radix_hist, dim3(n_blocks), dim3(kThreads), 0, s, keys, n, shift, hist, n_blocks);
+    hipLaunchKernelGGL(k_radix_hist, dim3(n_blocks), dim3(kThreads), 0, s, keys, n, n_dev, shift, hist, n_blocks);
     hipLaunchKernelGGL(k_radix_chunk_sums, dim3(n_chunks), dim3(kRadix), 0, s, hist, n_blocks, cs, chunk_sum);
     hipLaunchKernelGGL(k_radix_chunk_scan, dim3(1), dim3(kChunkScanThreads), 0, s, chunk_sum, n_chunks,
                        digit_base[db]);
@@ -779,27 +920,28 @@ struct PassScan {
 }  // namespace
 
 hipError_t radix_sort_pairs(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, size_t n,
-                            int bits, int vals24, SortScratch scratch, int* result_in_b, hipStream_t s) {
+                            const unsigned long long* n_dev, int bits, int vals24, SortScratch scratch,
+                            int* result_in_b, hipStream_t s) {
   *result_in_b = 0;
   if (n == 0 || bits <= 0) return hipSuccess;
-  const PassScan ps(n, scratch);
+  const PassScan ps(n, n_dev, scratch);
   const dim3 grid((unsigned)(8 * ((ps.n_blocks + 7) / 8)));   // the scatter's XCD-ordered grid
   if (bits > 8 && bits <= 16 && vals24) {
     // two passes moving one packed word between them; the result lands in *_a
     ps.run(keys_a, 0, 0, s);
-    hipLaunchKernelGGL(k_radix_scatter<kScatterPack>, grid, dim3(kScatterThreads), 0, s, keys_a, vals_a, n, 0, ps.starts(0),
-                       nullptr, keys_b, nullptr);
+    hipLaunchKernelGGL(k_radix_scatter<kScatterPack>, grid, dim3(kScatterThreads), 0, s, keys_a, vals_a, n, n_dev, 0,
+                       ps.starts(0), nullptr, keys_b, nullptr);
     ps.run(keys_b, 24, 1, s);
-    hipLaunchKernelGGL(k_radix_scatter<kScatterUnpack>, grid, dim3(kScatterThreads), 0, s, keys_b, nullptr, n, 8, ps.starts(1),
-                       ps.digit_base[0], keys_a, vals_a);
+    hipLaunchKernelGGL(k_radix_scatter<kScatterUnpack>, grid, dim3(kScatterThreads), 0, s, keys_b, nullptr, n, n_dev, 8,
+                       ps.starts(1), ps.digit_base[0], keys_a, vals_a);
     return hipGetLastError();
   }
   uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
   int in_b = 0;
   for (int shift = 0; shift < bits; shift += 8) {
     ps.run(ki, shift, 0, s);
-    hipLaunchKernelGGL(k_radix_scatter<kScatterPlain>, grid, dim3(kScatterThreads), 0, s, ki, vi, n, shift, ps.starts(0),
-                       nullptr, ko, vo);
+    hipLaunchKernelGGL(k_radix_scatter<kScatterPlain>, grid, dim3(kScatterThreads), 0, s, ki, vi, n, n_dev, shift,
+                       ps.starts(0), nullptr, ko, vo);
     uint32_t* t;
     t = ki; ki = ko; ko = t;
     t = vi; vi = vo; vo = t;
@@ -813,16 +955,16 @@ hipError_t radix_sort_depth(const uint32_t* depth, const uint32_t* count, uint32
                             uint32_t* keys_b, uint32_t* vals_b, size_t n, SortScratch scratch, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (count && n > kPackMaxEntries) return hipErrorInvalidValue;
-  const PassScan ps(n, scratch);
+  const PassScan ps(n, nullptr, scratch);
   const dim3 grid((unsigned)(8 * ((ps.n_blocks + 7) / 8)));   // the scatter's XCD-ordered grid
   ps.run(depth, 0, 0, s);
-  hipLaunchKernelGGL(k_radix_scatter<kScatterIota>, grid, dim3(kScatterThreads), 0, s, depth, count, n, 0, ps.starts(0), nullptr,
-                     keys_b, vals_b);
+  hipLaunchKernelGGL(k_radix_scatter<kScatterIota>, grid, dim3(kScatterThreads), 0, s, depth, count, n, nullptr, 0,
+                     ps.starts(0), nullptr, keys_b, vals_b);
   uint32_t *ki = keys_b, *vi = vals_b, *ko = keys_a, *vo = vals_a;
   for (int shift = 8; shift < 32; shift += 8) {
     ps.run(ki, shift, 0, s);
-    hipLaunchKernelGGL(k_radix_scatter<kScatterPlain>, grid, dim3(kScatterThreads), 0, s, ki, vi, n, shift, ps.starts(0),
-                       nullptr, ko, vo);
+    hipLaunchKernelGGL(k_radix_scatter<kScatterPlain>, grid, dim3(kScatterThreads), 0, s, ki, vi, n, nullptr, shift,
+                       ps.starts(0), nullptr, ko, vo);
     uint32_t* t;
     t = ki; ki = ko; ko = t;
     t = vi; vi = vo; vo = t;
@@ -843,29 +985,53 @@ hipError_t launch_scan_touched(const uint32_t* order, int packed, const uint32_t
 
 hipError_t launch_emit_pairs(const uint32_t* order, int packed, const uint32_t* touched, const uint32_t* group_sums,
                              const uint32_t* block_off, const ushort4* rect, const Record* rec, size_t n_entries,
-                             int n, const ViewDev* views, size_t K, int cull, int tile, const EmitInfo* info,
-                             uint32_t* pair_tile, uint32_t* pair_rec, hipStream_t s) {
+                             int n, const ViewDev* views, const DevStatus* st, int cull, int tile,
+                             const EmitInfo* info, const uint32_t* redo_bits, uint32_t* pair_tile, uint32_t* pair_rec,
+                             hipStream_t s) {
   if (n_entries == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n_entries + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, order, packed, touched, group_sums, block_off, rect,
-                     rec, n_entries, n, views, K, cull, tile, info, pair_tile, pair_rec);
+                     rec, n_entries, n, views, st, cull, tile, info, redo_bits, pair_tile, pair_rec);
   return hipGetLastError();
 }
 
 hipError_t launch_count_kept(const uint32_t* touched, const ushort4* rect, const Record* rec, size_t n_entries, int n,
-                             const ViewDev* views, int tile, uint32_t* kept, EmitInfo* info, hipStream_t s) {
+                             const ViewDev* views, int tile, int exact_all, uint32_t* kept, EmitInfo* info,
+                             DevStatus* st, uint32_t* redo_list, hipStream_t s) {
   if (n_entries == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n_entries + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_count_kept, dim3(blocks), dim3(kThreads), 0, s, touched, rect, rec, n_entries, n, views, tile,
-                     kept, info);
+                     exact_all, kept, info, st, redo_list);
   return hipGetLastError();
 }
 
-hipError_t launch_ranges(const uint32_t* pair_tile, size_t K, uint2* ranges, int n_tiles, hipStream_t s) {
+hipError_t launch_count_redo(const uint32_t* touched, const ushort4* rect, const Record* rec, int n,
+                             const ViewDev* views, int tile, int exact_all, const float* P, int stride,
+                             uint32_t* kept, EmitInfo* info, DevStatus* st, const uint32_t* redo_list,
+                             uint32_t* redo_bits, size_t redo_cap, hipStream_t s) {
+  // a fixed grid walks the list, whose length only the device knows (a few
+  // thousandths of the entries at most in practice)
+  hipLaunchKernelGGL(k_count_redo, dim3(256), dim3(kThreads), 0, s, touched, rect, rec, n, views, tile, exact_all, P,
+                     stride, kept, info, st, redo_list, redo_bits, redo_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_status_reset(DevStatus* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(1), 0, s, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_pairs(DevStatus* st, DevStatus* mirror, size_t cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_pairs, dim3(1), dim3(1), 0, s, st, mirror, (unsigned long long)cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_ranges(const uint32_t* pair_tile, size_t K_cap, const unsigned long long* n_dev, uint2* ranges,
+                         int n_tiles, hipStream_t s) {
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, (size_t)n_tiles * 2, s);
-  if (e != hipSuccess || K == 0) return e;
-  const unsigned blocks = (unsigned)((K + 4 * 256 - 1) / (4 * 256));
-  hipLaunchKernelGGL(k_ranges, dim3(blocks), dim3(256), 0, s, pair_tile, K, ranges, (uint32_t)n_tiles);
+  if (e != hipSuccess || K_cap == 0) return e;
+  const unsigned blocks = (unsigned)((K_cap + 4 * 256 - 1) / (4 * 256));
+  hipLaunchKernelGGL(k_ranges, dim3(blocks), dim3(256), 0, s, pair_tile, K_cap, n_dev, ranges, (uint32_t)n_tiles);
   return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@ import torch
 
 from . import (gs_memory_bytes, gs_load_balance, gs_create, gs_destroy, gs_layout, gs_preprocess, gs_bin_sort, gs_render_fwd, gs_loss,
                gs_render_bwd, gs_adam_step, gs_render_bwd_adam, gs_buffer_size, gs_copy_buffer, gs_profile_enable,
+               gs_sync_status,
                gs_profile_read,
                KERNEL_NAMES, GS_BUF_RECORDS, GS_BUF_DEPTH, GS_BUF_TOUCHED, GS_BUF_TILE_RECT, GS_BUF_KEYS,
                GS_BUF_VALUES, GS_BUF_RANGES, GS_BUF_T_FINAL, GS_BUF_N_CONTRIB, GS_BUF_LAST, GS_BUF_GRAD2D,
@@ -89,9 +90,14 @@ class Rasterizer:
         self.stride = params.shape[1]
         gs_preprocess(self.ctx, params, n, self.stride, sh_degree, self.cams, self.tile, stream)
 
-    def bin_sort(self, stream=None) -> int:
-        self.K = gs_bin_sort(self.ctx, stream)
+    def bin_sort(self, stream=None, count: bool = True) -> Optional[int]:
+        """K when count is True (waits for the device); count False keeps K on the
+        device (check the step with sync_status)."""
+        self.K = gs_bin_sort(self.ctx, stream, count)
         return self.K
+
+    def sync_status(self, stream=None):
+        gs_sync_status(self.ctx, stream)
 
     def render_fwd(self, color: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         if color is None:

@@ -27,7 +27,7 @@ def ambiguous(r) -> np.ndarray:
 
 def run_gpu(scene, upstream=None, loss=False, cull=None, tile=16):
     """Forward (and optionally backward) of the HIP path; returns numpy outputs.
-    cull: None (library default), "rect" or "ellipse"; tile: 8, 16 or 32."""
+    cull: None (library default), "rect", "ellipse" or "exact"; tile: 8, 16 or 32."""
     from paper_2503_13086_amd.pipeline import Rasterizer, params_to_device
     from paper_2503_13086_amd import (GS_BUF_RECORDS, GS_BUF_DEPTH, GS_BUF_TOUCHED, GS_BUF_TILE_RECT,
                                       GS_BUF_KEYS, GS_BUF_VALUES, GS_BUF_RANGES, GS_BUF_T_FINAL,
@@ -36,7 +36,8 @@ def run_gpu(scene, upstream=None, loss=False, cull=None, tile=16):
     rz = Rasterizer(0)
     try:
         if cull is not None:
-            gs.gs_set_cull(rz.ctx, gs.GS_CULL_RECT if cull == "rect" else gs.GS_CULL_ELLIPSE)
+            gs.gs_set_cull(rz.ctx, {"rect": gs.GS_CULL_RECT, "ellipse": gs.GS_CULL_ELLIPSE,
+                                    "exact": gs.GS_CULL_ELLIPSE_EXACT}[cull])
         P = params_to_device(scene.params)
         rz.set_views(scene.cams, tile)
         rz.preprocess(P, scene.n, scene.sh_degree)
