@@ -244,23 +244,25 @@ def main():
     color = rz.new_image()
     dl = rz.new_image()
 
-    def one_step():
+    def one_step(count=False):
         rz.preprocess(params, n, D, sc.cams)
-        rz.bin_sort()
+        rz.bin_sort(count=count)     # count False: K stays on the device, no host wait
         rz.render_fwd(color)
         rz.loss(color, target, sc.w_l1, sc.w_dssim, loss, dl)
         rz.render_bwd_adam(dl, m, v, step, DEFAULT_LR, scales, group_mask=1)
 
-    for _ in range(args.warmup):
-        one_step()
+    for i in range(args.warmup):
+        one_step(count=i == 0)
     torch.cuda.synchronize()
+    rz.sync_status()
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    K = rz.K
+    rz.preprocess(params, n, D, sc.cams)
+    K = rz.bin_sort(count=True)
     rz.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -268,6 +270,7 @@ def main():
         one_step()
     torch.cuda.synchronize()
     t_step = (time.perf_counter() - t0) / args.steps
+    rz.sync_status()      # raises if a binning in the timed steps ran out of room
     prof = rz.profile_read()
     rz.profile(False)
     kern_ms = {k: (ms / cnt if cnt else 0.0) for k, (cnt, ms) in prof.items()}
@@ -290,7 +293,7 @@ def main():
         def plain_step():
             for vi, c in enumerate(sc.cams):
                 rz.preprocess(params, n, D, [c])
-                rz.bin_sort()
+                rz.bin_sort(count=False)
                 col = rz.render_fwd(color[: 3 * c["width"] * c["height"]])
                 rz.loss(col, target[3 * rz_off[vi]: 3 * rz_off[vi + 1]], sc.w_l1, sc.w_dssim, loss[:1],
                         dl[: 3 * c["width"] * c["height"]])
@@ -301,12 +304,14 @@ def main():
         for _ in range(2):
             plain_step()
         torch.cuda.synchronize()
+        rz.sync_status()
         t0 = time.perf_counter()
         reps = max(2, args.steps // 4)
         for _ in range(reps):
             plain_step()
         torch.cuda.synchronize()
         plain_ms = (time.perf_counter() - t0) / reps * 1e3
+        rz.sync_status()
 
     n_p = n_params(D)
     rz.set_views(sc.cams)

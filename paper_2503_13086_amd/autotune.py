@@ -17,6 +17,7 @@ from typing import Dict, Optional, Sequence, Tuple
 
 import torch
 
+from . import gs_reserve_pairs
 from .pipeline import Rasterizer
 
 CANDIDATES = (8, 16, 32)
@@ -67,13 +68,20 @@ class Autotuner:
                target: torch.Tensor, w_l1: float = 0.8, w_dssim: float = 0.2) -> int:
         """The fastest tile edge for this workload (timed once per signature)."""
         key = signature(n, sh_degree, cams)
-        if key not in self.table:
+        timed = key not in self.table
+        if timed:
             t = {tile: self.time_tile(rz, tile, params, n, sh_degree, cams, target, w_l1, w_dssim)
                  for tile in self.candidates}
             self.timings[key] = t
             self.table[key] = min(t, key=t.get)
         best = self.table[key]
         rz.set_views(cams, best)
+        if timed and len(self.candidates) > 1:
+            # the smallest edge lists the most pairs and left the pair buffers sized
+            # for it: size them for the chosen edge (with the library's 25% slack)
+            rz.preprocess(params, n, sh_degree)
+            k = rz.bin_sort(count=True)
+            gs_reserve_pairs(rz.ctx, max(1, k + k // 4 + 1024))
         return best
 
     def last_timings(self, n: int, sh_degree: int, cams: Sequence[dict]) -> Optional[Dict[int, float]]:

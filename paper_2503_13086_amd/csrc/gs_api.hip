@@ -420,6 +420,9 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
   GS_HIP(c, hipEventRecord(c->status_ev, s));
   c->status_ev_pending = true;
   const unsigned long long* n_eff = &dst->n_eff;
+  // grids for K when the host knows it, else for the capacity (the kernels read the
+  // count on the device either way, so a failed check sorts nothing)
+  const size_t k_grid = c->K_known ? (size_t)c->K : c->pair_cap;
   {
     Prof pr(c, GS_K_EMIT, s);
     GS_HIP(c, launch_emit_pairs(order, packed ? 1 : 0, per_entry, c->groupsums.as<uint32_t>(),
@@ -436,12 +439,12 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
     // record indices are below NV: up to 2^24 entries the two tile passes move one
     // packed word between them
     GS_HIP(c, radix_sort_pairs(c->pkey[0].as<uint32_t>(), c->pval[0].as<uint32_t>(), c->pkey[1].as<uint32_t>(),
-                               c->pval[1].as<uint32_t>(), c->pair_cap, n_eff, bits, packed ? 1 : 0, sc,
+                               c->pval[1].as<uint32_t>(), k_grid, n_eff, bits, packed ? 1 : 0, sc,
                                &c->pairs_in_b, s));
   }
   {
     Prof pr(c, GS_K_RANGES, s);
-    GS_HIP(c, launch_ranges(c->pkey[c->pairs_in_b].as<uint32_t>(), c->pair_cap, n_eff, c->ranges.as<uint2>(),
+    GS_HIP(c, launch_ranges(c->pkey[c->pairs_in_b].as<uint32_t>(), k_grid, n_eff, c->ranges.as<uint2>(),
                             c->n_tiles, s));
   }
   c->stage = kBinned;

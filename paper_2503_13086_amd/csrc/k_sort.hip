@@ -58,9 +58,12 @@ __device__ inline size_t item_count(size_t n, const unsigned long long* n_dev) {
 
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys, size_t n_cap,
                                                           const unsigned long long* __restrict__ n_dev, int shift,
-                                                          uint32_t* __restrict__ hist, int n_blocks) {
+                                                          uint32_t* __restrict__ hist) {
   __shared__ uint32_t hw[kWaves][kRadix];
-  const size_t n = item_count(n_cap, n_dev);   // blocks past it count nothing
+  const size_t n = item_count(n_cap, n_dev);
+  // rows past the item count's blocks are never read (the scan and the scatter
+  // size themselves from the same count)
+  if ((size_t)blockIdx.x * kSortTileItems >= n) return;
   const int w = threadIdx.x / 64;
   for (int i = 0; i < kWaves; ++i) hw[i][threadIdx.x] = 0;
   __syncthreads();
@@ -102,17 +105,42 @@ constexpr int kChunkScanThreads = 1024;                       // k_radix_chunk_s
 constexpr int kChunkParts = kChunkScanThreads / kRadix;
 
 // Blocks per chunk for n_blocks blocks: a multiple of kScanChunk, at least kScanChunk.
-inline int chunk_blocks(int n_blocks) {
+__host__ __device__ inline int chunk_blocks(int n_blocks) {
   int cs = (n_blocks + kMaxChunks - 1) / kMaxChunks;
   cs = (cs + kScanChunk - 1) / kScanChunk * kScanChunk;
   return cs < kScanChunk ? kScanChunk : cs;
 }
 
+// Shape of one pass's digit table for n items: blocks, blocks per chunk, chunks
+// (at most kMaxChunks, and at most ceil(blocks / kScanChunk)).  The kernels derive
+// it from the item count they read, so a grid sized for a capacity costs only its
+// empty workgroups.
+struct SortGeo {
+  int nb, cs, nch;
+};
+__host__ __device__ inline SortGeo sort_geo(size_t n) {
+  SortGeo g;
+  g.nb = (int)((n + kSortTileItems - 1) / kSortTileItems);
+  g.cs = chunk_blocks(g.nb);
+  g.nch = (g.nb + g.cs - 1) / g.cs;
+  return g;
+}
+
+// Chunk rows a table for up to nb_cap blocks may need.
+inline int max_chunks(int nb_cap) {
+  const int c = (nb_cap + kScanChunk - 1) / kScanChunk;
+  return c < kMaxChunks ? c : kMaxChunks;
+}
+
 // hist[b][d] <- digit d's count over the blocks of b's chunk before b;
 // chunk_sum[c][d] <- its count over the whole chunk c.
-__global__ __launch_bounds__(kRadix) void k_radix_chunk_sums(uint32_t* __restrict__ hist, int n_blocks, int cs,
+__global__ __launch_bounds__(kRadix) void k_radix_chunk_sums(uint32_t* __restrict__ hist, size_t n_cap,
+                                                              const unsigned long long* __restrict__ n_dev,
                                                               uint32_t* __restrict__ chunk_sum) {
-  const int b0 = blockIdx.x * cs, b1 = min(b0 + cs, n_blocks);
+  const SortGeo sg = sort_geo(item_count(n_cap, n_dev));
+  if ((int)blockIdx.x >= sg.nch) return;
+  const int cs = sg.cs;
+  const int b0 = blockIdx.x * cs, b1 = min(b0 + cs, sg.nb);
   uint32_t run = 0;
   for (int b = b0; b < b1; b += kScanChunk) {
     uint32_t x[kScanChunk];
@@ -133,10 +161,12 @@ __global__ __launch_bounds__(kRadix) void k_radix_chunk_sums(uint32_t* __restric
 // through LDS), then the exclusive scan of the digit totals over digits, stored in
 // digit_base.
 __global__ __launch_bounds__(kChunkScanThreads) void k_radix_chunk_scan(uint32_t* __restrict__ chunk_sum,
-                                                                         int n_chunks,
+                                                                         size_t n_cap,
+                                                                         const unsigned long long* __restrict__ n_dev,
                                                                          uint32_t* __restrict__ digit_base) {
   __shared__ uint32_t part[kChunkParts][kRadix];
   __shared__ uint32_t wsum[kRadix / 64];
+  const int n_chunks = sort_geo(item_count(n_cap, n_dev)).nch;
   const int d = threadIdx.x % kRadix, pi = threadIdx.x / kRadix;
   const int per = (n_chunks + kChunkParts - 1) / kChunkParts;
   const int c0 = pi * per, c1 = min(c0 + per, n_chunks);
@@ -194,7 +224,6 @@ struct DigitStarts {
   const uint32_t* in_chunk;     // [b][d]: over the earlier blocks of b's chunk
   const uint32_t* chunk_pre;    // [c][d]: over the earlier chunks
   const uint32_t* digit_base;   // [d]: items with a smaller digit
-  int cs;                       // blocks per chunk
 };
 
 // Stable scatter of one digit pass.  Items are ranked in workgroup order (wave w
@@ -265,7 +294,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_radix_scatter(const uint32_
   for (int i = tid; i < kScatterWaves * kRadix; i += kScatterThreads) (&wc[0][0])[i] = 0;
   if (digit_thread)
     goff[tid] = starts.in_chunk[(size_t)blk * kRadix + tid] +
-                starts.chunk_pre[(size_t)(blk / starts.cs) * kRadix + tid] + starts.digit_base[tid];
+                starts.chunk_pre[(size_t)(blk / sort_geo(n).cs) * kRadix + tid] + starts.digit_base[tid];
   const size_t blk0 = (size_t)blk * kSortTileItems;
   const size_t valid_items = n > blk0 ? (n - blk0 < (size_t)kSortTileItems ? n - blk0 : (size_t)kSortTileItems) : 0;
   if (MODE == kScatterUnpack) {
@@ -675,7 +704,9 @@ __global__ void k_check_pairs(DevStatus* __restrict__ st, DevStatus* __restrict_
     st->need_pairs = K;
     status_fail(st, GS_ERR_CAPACITY);
   } else {
-    st->n_eff = K;
+    // an earlier failure (the exact pass's outcome store too small) leaves counts
+    // the emission could not reproduce: then no pair is emitted either
+    st->n_eff = st->code == GS_OK ? K : 0ull;
   }
   mirror->n_pairs = K;
   mirror->n_eff = st->n_eff;
@@ -895,27 +926,29 @@ namespace {
 // Digit table of the pass at `shift` over keys and its scan, the digit starts into
 // digit_base[db] (two slots: a pass and the one before it); starts(db) hands the
 // scan's parts to the scatter.
+// n is the capacity the grids are sized for; with n_dev the kernels sort the count
+// found there (at most n) and size the table's scan from it.
 struct PassScan {
   size_t n;
   const unsigned long long* n_dev;
-  int n_blocks, cs, n_chunks;
+  int n_blocks, n_chunks;
   uint32_t *hist, *chunk_sum, *digit_base[2];
   PassScan(size_t n_, const unsigned long long* n_dev_, SortScratch sc) : n(n_), n_dev(n_dev_) {
-    n_blocks = (int)((n + kSortTileItems - 1) / kSortTileItems);
-    cs = chunk_blocks(n_blocks);
-    n_chunks = (n_blocks + cs - 1) / cs;
+    const SortGeo g = sort_geo(n);
+    n_blocks = g.nb;
+    n_chunks = n_dev ? max_chunks(n_blocks) : g.nch;   // grid for any count up to n
     hist = sc.hist;
     chunk_sum = hist + (size_t)kRadix * n_blocks;
-    digit_base[0] = chunk_sum + (size_t)kRadix * n_chunks;
+    digit_base[0] = chunk_sum + (size_t)kRadix * max_chunks(n_blocks);
     digit_base[1] = digit_base[0] + kRadix;
   }
   void run(const uint32_t* keys, int shift, int db, hipStream_t s) const {
-    hipLaunchKernelGGL(k_radix_hist, dim3(n_blocks), dim3(kThreads), 0, s, keys, n, n_dev, shift, hist, n_blocks);
-    hipLaunchKernelGGL(k_radix_chunk_sums, dim3(n_chunks), dim3(kRadix), 0, s, hist, n_blocks, cs, chunk_sum);
-    hipLaunchKernelGGL(k_radix_chunk_scan, dim3(1), dim3(kChunkScanThreads), 0, s, chunk_sum, n_chunks,
+    hipLaunchKernelGGL(k_radix_hist, dim3(n_blocks), dim3(kThreads), 0, s, keys, n, n_dev, shift, hist);
+    hipLaunchKernelGGL(k_radix_chunk_sums, dim3(n_chunks), dim3(kRadix), 0, s, hist, n, n_dev, chunk_sum);
+    hipLaunchKernelGGL(k_radix_chunk_scan, dim3(1), dim3(kChunkScanThreads), 0, s, chunk_sum, n, n_dev,
                        digit_base[db]);
   }
-  DigitStarts starts(int db) const { return DigitStarts{hist, chunk_sum, digit_base[db], cs}; }
+  DigitStarts starts(int db) const { return DigitStarts{hist, chunk_sum, digit_base[db]}; }
 };
 }  // namespace
 

@@ -137,3 +137,32 @@ def test_exact_outcome_store_overflow_is_reported_and_recovered():
                               b["ranges"])
     finally:
         rz.close()
+
+
+@pytest.mark.parametrize("cap", [None, 3, 12_000_000])
+def test_binning_into_large_capacity_matches(cap):
+    """Pair buffers much larger than K (a multiple of K, and 12M pairs: a digit
+    table of more than 2048 blocks, so the capacity's chunking differs from the
+    count's): binning without waiting sorts exactly K pairs, as a counted binning does."""
+    sc = _scene()
+    rz = Rasterizer(0)
+    try:
+        P = params_to_device(sc.params)
+        rz.preprocess(P, sc.n, sc.sh_degree, sc.cams)
+        K = rz.bin_sort(count=True)
+        ref_keys = rz.buffer(gs.GS_BUF_KEYS).cpu().numpy()
+        ref_ranges = rz.buffer(gs.GS_BUF_RANGES).cpu().numpy()
+        ref_color = rz.render_fwd().cpu().numpy()
+        if cap is not None:
+            gs.gs_reserve_pairs(rz.ctx, cap * K if cap < 100 else cap)
+        print(f"[status] K={K}, capacity {cap}", flush=True)
+        for _ in range(2):
+            rz.preprocess(P, sc.n, sc.sh_degree, sc.cams)
+            assert rz.bin_sort(count=False) is None
+            color = rz.render_fwd()
+            rz.sync_status()
+            assert np.array_equal(rz.buffer(gs.GS_BUF_KEYS).cpu().numpy(), ref_keys)
+            assert np.array_equal(rz.buffer(gs.GS_BUF_RANGES).cpu().numpy(), ref_ranges)
+            assert np.array_equal(color.cpu().numpy(), ref_color)
+    finally:
+        rz.close()
