@@ -3,11 +3,11 @@
 // Per view: w_l1 * mean|x - y| + w_dssim * (1 - mean SSIM(x, y)), SSIM per channel
 // from windowed means under a normalised 11x11 Gaussian window (sigma 1.5, zero
 // padding), C1 = 0.01^2, C2 = 0.03^2.  All views share one launch of 32x32-pixel
-// output tiles (256 threads); each workgroup stages the 42x42 halo of a channel
-// in LDS and applies the separable window in two register-blocked passes: a
-// thread filters 8 consecutive columns of a row (reading 18 staged values once),
-// then 4 consecutive rows of a column, one windowed map at a time (the LDS holds
-// the staged planes and one half-filtered map).
+// output tiles (256 threads); the separable window runs in two register-blocked
+// passes per map (a thread filters a run of consecutive columns of a row, then a
+// run of rows of a column), one map at a time through LDS.  E[x^2] and E[y^2]
+// enter SSIM only through their sum (in D2), so four maps are filtered: x, y,
+// x^2 + y^2 and xy.
 //
 // Backward: with N1 = 2 mx my + C1, N2 = 2 sxy + C2, D1 = mx^2 + my^2 + C1,
 // D2 = sxx + syy + C2 and S = N1 N2 / (D1 D2), the per-pixel partials of S with
@@ -15,9 +15,12 @@
 //   A = 2 my (N2 - N1) / (D1 D2) + 2 mx S (1/D2 - 1/D1),  B = -S / D2,
 //   Cc = 2 N1 / (D1 D2),
 // and dS_mean/dx = (window * A + 2 x (window * B) + y (window * Cc)) / N, with 1/D1
-// and 1/D2 taken once per pixel from the hardware reciprocal.  The first kernel
-// stores A, B, Cc; the second filters them the same way (the window is
-// symmetric) and adds the L1 term.  Loss sums are reduced per tile in FP64.
+// and 1/D2 taken once per pixel from the hardware reciprocal.
+//
+// k_ssim_fwd forms the statistics over each tile (a 42x42 halo staged) and stores
+// A, B, Cc (36 B per pixel); k_ssim_bwd filters them the same way (the window is
+// symmetric) and adds the L1 term.
+// Loss sums are reduced per tile in FP64.
 //
 // The load-balancing term of Eq. 9 (kernels at the end) works on the soft
 // per-pixel Gaussian count the forward writes.
@@ -198,7 +201,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                                                    const float* __restrict__ x, const float* __restrict__ y,
                                                    float* __restrict__ aux, Win win, double2* __restrict__ partials) {
   __shared__ float sin_[2][HALO * HS];
-  __shared__ float hbuf[1][HALO * LT];   // the five maps one after another: 20 KB of LDS
+  __shared__ float hbuf[1][HALO * LT];   // the four maps one after another: 20 KB of LDS
   __shared__ double sh[4];
   const int tile = xcd_tile(blockIdx.x, lt.off[V]);
   if (tile >= lt.off[V]) return;
@@ -212,21 +215,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     const float* src[2] = {x + base + ch * hw, y + base + ch * hw};
     stage_halo<2>(sin_, src, cv.W, cv.H, t.x0, t.y0);
     __syncthreads();
-    float m[5][VSEG];
+    float m[4][VSEG];
     window_map<2>(sin_, hbuf, win, col, r0, [](const float* v, float* f) { f[0] = v[0]; }, m[0]);
     window_map<2>(sin_, hbuf, win, col, r0, [](const float* v, float* f) { f[0] = v[1]; }, m[1]);
-    window_map<2>(sin_, hbuf, win, col, r0, [](const float* v, float* f) { f[0] = v[0] * v[0]; }, m[2]);
-    window_map<2>(sin_, hbuf, win, col, r0, [](const float* v, float* f) { f[0] = v[1] * v[1]; }, m[3]);
-    window_map<2>(sin_, hbuf, win, col, r0, [](const float* v, float* f) { f[0] = v[0] * v[1]; }, m[4]);
+    window_map<2>(sin_, hbuf, win, col, r0,
+                  [](const float* v, float* f) { f[0] = __fmaf_rn(v[0], v[0], v[1] * v[1]); }, m[2]);
+    window_map<2>(sin_, hbuf, win, col, r0, [](const float* v, float* f) { f[0] = v[0] * v[1]; }, m[3]);
     float* ac = aux + (size_t)cv.pix_off * 9 + (size_t)ch * 3 * hw;
 #pragma unroll
     for (int j = 0; j < VSEG; ++j) {
       const int px = t.x0 + col, py = t.y0 + r0 + j;
       if (px < cv.W && py < cv.H) {
         const float mx = m[0][j], my = m[1][j];
-        const float sxx = m[2][j] - mx * mx, syy = m[3][j] - my * my, sxy = m[4][j] - mx * my;
+        const float sxy = m[3][j] - mx * my;
         const float N1 = 2.0f * mx * my + kC1, N2 = 2.0f * sxy + kC2;
-        const float D1 = mx * mx + my * my + kC1, D2 = sxx + syy + kC2;
+        const float M2 = mx * mx + my * my;
+        const float D1 = M2 + kC1, D2 = (m[2][j] - M2) + kC2;
         // hardware reciprocals (1 ulp): D1, D2 >= C1 > 0
         const float r1 = __builtin_amdgcn_rcpf(D1), r2 = __builtin_amdgcn_rcpf(D2);
         const float rden = r1 * r2;

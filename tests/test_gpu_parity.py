@@ -138,7 +138,8 @@ def test_render_bwd_parity(name):
         assert rel <= 1e-3 and elem <= 1.0, (grp, rel, elem)
 
 
-@pytest.mark.parametrize("w_l1,w_dssim,size", [(1.0, 0.0, (37, 29)), (0.8, 0.2, (64, 48)), (0.0, 1.0, (23, 40))])
+@pytest.mark.parametrize("w_l1,w_dssim,size", [(1.0, 0.0, (37, 29)), (0.8, 0.2, (64, 48)), (0.0, 1.0, (23, 40)),
+                                              (0.8, 0.2, (101, 70))])
 def test_loss_parity(w_l1, w_dssim, size):
     """Loss value and dL/dimage on the same fp32 images for both sides (two views)."""
     from paper_2503_13086_amd.pipeline import Rasterizer, params_to_device
