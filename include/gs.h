@@ -178,6 +178,19 @@ gs_status gs_render_fwd(gs_ctx* ctx, float* color, gs_stream stream);
 gs_status gs_loss(gs_ctx* ctx, const float* color, const float* target, float w_l1, float w_dssim,
                   double* loss_out, float* dL_dcolor, gs_stream stream);
 
+/* gs_loss for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid allocation): the same
+ * computation, arguments and results, with the per-tile loss sums in a static
+ * device array of the library (1 MiB per GPU, held until the process ends) instead
+ * of context memory; it calls no allocating routine.  Limit: at most 65536 32x32
+ * loss tiles summed over the context's views (ceil(W/32) ceil(H/32) per view,
+ * about 67 Mpix); beyond it GS_ERR_CAPACITY and nothing is queued.  Every call on
+ * one GPU shares that array, from any context or stream: calls that overlap on a
+ * GPU race and must be ordered by the caller.  Nothing in it needs clearing (each
+ * call writes every tile's sums before reading them). */
+gs_status gs_loss_noalloc(gs_ctx* ctx, const float* color, const float* target, float w_l1, float w_dssim,
+                          double* loss_out, float* dL_dcolor, gs_stream stream);
+
 /* Eq. 9 load-balancing term: per view, w_load * std over the view's pixels of G_p,
  * the number of Gaussians associated with pixel p, read as the soft count
  * G_p = sum of the alphas p blended (written by gs_render_fwd; a count has no

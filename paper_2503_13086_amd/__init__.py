@@ -33,7 +33,7 @@ _STATUS = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_CAPACITY", -3: "GS_ERR_
 
 # Exported symbols (must match include/gs.h).
 EXPORTS = ["gs_abi_version", "gs_create", "gs_destroy", "gs_last_error", "gs_layout", "gs_preprocess", "gs_bin_sort",
-           "gs_render_fwd", "gs_loss", "gs_load_balance", "gs_render_bwd", "gs_adam_step", "gs_render_bwd_adam",
+           "gs_render_fwd", "gs_loss", "gs_loss_noalloc", "gs_load_balance", "gs_render_bwd", "gs_adam_step", "gs_render_bwd_adam",
            "gs_set_cull", "gs_buffer_size", "gs_sync_status", "gs_reserve_pairs",
            "gs_copy_buffer", "gs_profile_enable", "gs_profile_read", "gs_memory_bytes", "gs_sched_weights",
            "gs_sched_plan", "gs_sched_lr"]
@@ -81,6 +81,7 @@ def _load():
         "gs_reserve_pairs": (_I32, [_P, ctypes.c_int64, _P]),
         "gs_render_fwd": (_I32, [_P, _P, _P]),
         "gs_loss": (_I32, [_P, _P, _P, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
+        "gs_loss_noalloc": (_I32, [_P, _P, _P, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
         "gs_render_bwd": (_I32, [_P, _P, _P, _P, _I32, _P]),
         "gs_load_balance": (_I32, [_P, ctypes.c_float, _P, _P]),
         "gs_adam_step": (_I32, [_P, _P, _P, _P, _P, _P, _I32, _I32, _I32, ctypes.POINTER(ctypes.c_float),
@@ -211,6 +212,11 @@ def gs_render_fwd(ctx, color, stream=None) -> None:
 def gs_loss(ctx, color, target, w_l1: float, w_dssim: float, loss_out, dL_dcolor, stream=None) -> None:
     _check(ctx, _load().gs_loss(ctx, _ptr(color), _ptr(target), w_l1, w_dssim, _ptr(loss_out), _ptr(dL_dcolor),
                                 _stream(stream)), "gs_loss")
+
+
+def gs_loss_noalloc(ctx, color, target, w_l1: float, w_dssim: float, loss_out, dL_dcolor, stream=None) -> None:
+    _check(ctx, _load().gs_loss_noalloc(ctx, _ptr(color), _ptr(target), w_l1, w_dssim, _ptr(loss_out),
+                                        _ptr(dL_dcolor), _stream(stream)), "gs_loss_noalloc")
 
 
 def gs_load_balance(ctx, w_load: float, loss_out=None, stream=None) -> None:

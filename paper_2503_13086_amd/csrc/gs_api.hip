@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -21,6 +22,34 @@ struct DevBuf {
 };
 
 enum Stage { kNone = 0, kProjected = 1, kBinned = 2, kRendered = 3 };
+
+// Scratch of gs_loss_noalloc: the per-tile loss sums (two doubles per 32x32 loss
+// tile), 1 MiB that every GPU the library runs on holds until the process ends.
+// In host code this name is a host-side stand-in, not a device address: host code
+// uses the per-device address gs_create looks up (scratch_ptr).
+constexpr size_t kNoAllocLossTiles = 65536;
+static __device__ __align__(256) double scratch[2 * kNoAllocLossTiles];
+
+constexpr int kMaxScratchDevices = 256;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxScratchDevices] = {};
+
+// Looks up this device's copy of `scratch` once (the device must be current).
+bool scratch_setup(int device) {
+  if (device >= kMaxScratchDevices) return true;   // gs_loss_noalloc then reports unsupported
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (scratch_ptr[device]) return true;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return false;
+  scratch_ptr[device] = p;
+  return true;
+}
+
+void* scratch_for(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  return scratch_ptr[device];
+}
 
 }  // namespace
 
@@ -234,7 +263,8 @@ gs_status gs_create(gs_ctx** out, int32_t device) {
       hipEventCreateWithFlags(&c->views_ev, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->status_ev, hipEventDisableTiming) != hipSuccess ||
       hipMalloc(&c->status.p, sizeof(DevStatus)) != hipSuccess ||
-      hipMemset(c->status.p, 0, sizeof(DevStatus)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+      hipMemset(c->status.p, 0, sizeof(DevStatus)) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+      !scratch_setup(device)) {
     gs_destroy(c);
     return GS_ERR_HIP;
   }
@@ -527,7 +557,34 @@ gs_status gs_loss(gs_ctx* c, const float* color, const float* target, float w_l1
   if (w_dssim != 0.0f && (st = ensure(c, c->aux, (size_t)c->P * 9 * 4, s)) != GS_OK) return st;
   Prof pr(c, GS_K_LOSS, s);
   GS_HIP(c, launch_loss_dev(c->views.as<ViewDev>(), c->hviews.data(), c->V, color, target, w_l1, w_dssim,
-                            c->lossp.as<double>(), c->aux.as<float>(), loss_out, dL_dcolor, s));
+                            c->lossp.as<double>(), w_dssim != 0.0f ? c->aux.as<float>() : nullptr, loss_out,
+                            dL_dcolor, s));
+  return GS_OK;
+}
+
+gs_status gs_loss_noalloc(gs_ctx* c, const float* color, const float* target, float w_l1, float w_dssim,
+                          double* loss_out, float* dL_dcolor, gs_stream stream) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (c->stage < kProjected) return fail(c, GS_ERR_STATE, "gs_loss_noalloc needs the views of a preceding gs_preprocess");
+  if (!color || !target || !dL_dcolor || !aligned(color, 4) || !aligned(target, 4) || !aligned(dL_dcolor, 4))
+    return fail(c, GS_ERR_INVALID, "color, target and dL_dcolor must be non-NULL and aligned");
+  if (loss_out && !aligned(loss_out, 8)) return fail(c, GS_ERR_INVALID, "loss_out misaligned");
+  if (!std::isfinite(w_l1) || !std::isfinite(w_dssim)) return fail(c, GS_ERR_INVALID, "non-finite loss weight");
+  const size_t tiles = (size_t)loss_tiles(c->hviews.data(), c->V);
+  if (tiles > kNoAllocLossTiles) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "gs_loss_noalloc: the views hold %zu 32x32 loss tiles, more than its %zu",
+                  tiles, kNoAllocLossTiles);
+    return fail(c, GS_ERR_CAPACITY, buf);
+  }
+  void* sp = scratch_for(c->device);
+  if (!sp) return fail(c, GS_ERR_UNSUPPORTED, "gs_loss_noalloc: no scratch address for this device");
+  GS_HIP(c, hipSetDevice(c->device));
+  // every tile's sums are written before they are read: nothing to clear; the SSIM
+  // term runs as the fused kernel, which keeps its per-pixel terms in LDS
+  GS_HIP(c, launch_loss_dev(c->views.as<ViewDev>(), c->hviews.data(), c->V, color, target, w_l1, w_dssim,
+                            reinterpret_cast<double*>(sp), nullptr, loss_out, dL_dcolor, (hipStream_t)stream));
   return GS_OK;
 }
 

@@ -265,7 +265,8 @@ hipError_t launch_render_bwd(const ViewDev* views, int V, int n_tiles, const uin
                              const float* dL_dcolor, const float* dL_dG, float* grad2d, int tile, hipStream_t s);
 
 // Loss over all views in 32x32-pixel tiles: loss_tiles() tiles, partials 2 doubles
-// per tile, aux 9 floats per pixel (SSIM only).
+// per tile; aux 9 floats per pixel for the SSIM term, or NULL for the fused SSIM
+// kernel, which needs none.
 int loss_tiles(const ViewDev* hviews, int V);
 // Eq. 9 on the soft count asum [P]: per-view loss w std (loss_out, may be NULL)
 // and dL/dG [P]; partials: V x load_chunks doubles2, stats: V doubles2

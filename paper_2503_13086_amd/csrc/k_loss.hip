@@ -17,9 +17,18 @@
 // and dS_mean/dx = (window * A + 2 x (window * B) + y (window * Cc)) / N, with 1/D1
 // and 1/D2 taken once per pixel from the hardware reciprocal.
 //
-// k_ssim_fwd forms the statistics over each tile (a 42x42 halo staged) and stores
-// A, B, Cc (36 B per pixel); k_ssim_bwd filters them the same way (the window is
-// symmetric) and adds the L1 term.
+// Two forms of the SSIM term:
+// * gs_loss: k_ssim_fwd forms the statistics over each tile (a 42x42 halo staged)
+//   and stores A, B, Cc (36 B per pixel); k_ssim_bwd filters them the same way (the
+//   window is symmetric) and adds the L1 term.
+// * gs_loss_noalloc: k_ssim_fused does both per tile with nothing but the images,
+//   the gradient and the per-tile sums in HBM: it stages the 52x52 patch that
+//   reaches the tile through two windows, forms the statistics over the 42x42
+//   region whose SSIM terms reach the tile, turns them into A, B, Cc there in the
+//   LDS the patch occupied, and filters those over the tile.  About a third of the
+//   HBM traffic, 1.4x the filtering work (the 42x42 region is recomputed by
+//   neighbouring tiles); the kernel is bound by instruction issue, so on this chip
+//   it is the slower of the two (0.57 against 0.45 ms at 10 Mpix).
 // Loss sums are reduced per tile in FP64.
 //
 // The load-balancing term of Eq. 9 (kernels at the end) works on the soft
@@ -36,6 +45,9 @@ constexpr int HALO = LT + 2 * R;    // 42
 constexpr int HS = HALO;            // LDS row stride (unpadded: the backward then fits six workgroups per CU)
 constexpr int HSEG = 8;             // horizontal outputs per thread
 constexpr int VSEG = 4;             // vertical outputs per thread
+constexpr int IN = LT + 4 * R;      // 52: the fused kernel's patch (two windows around the tile)
+constexpr int FVSEG = 7;            // vertical outputs per thread of its 42-high forward maps
+constexpr int FTASKS = HALO * (HALO / FVSEG);   // 252 threads hold its forward statistics
 constexpr float kC1 = 0.01f * 0.01f;
 constexpr float kC2 = 0.03f * 0.03f;
 
@@ -300,6 +312,202 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
   }
 }
 
+// ---- fused SSIM (gs_loss_noalloc) ----
+
+// Horizontal pass over ROWS rows of one or two staged planes (row stride IS) into
+// an OW-wide map (row stride OW): out(r, c) = sum_k w[k] form(in0, in1)(r, c + k).
+// A thread filters SEG consecutive columns of one row; a row's tasks start at
+// min(s SEG, OW - SEG), so the last may repeat columns of the one before it, with
+// bit-identical values (same operations in the same order).
+template <int ROWS, int IS, int OW, int SEG, class F>
+__device__ inline void row_pass(const float* in0, const float* in1, float* out, const Win& win, F form) {
+  constexpr int NSEG = (OW + SEG - 1) / SEG;
+  static_assert(ROWS * NSEG <= 256, "one task per thread");
+  const int task = threadIdx.x;
+  if (task < ROWS * NSEG) {
+    const int r = task / NSEG, s = task % NSEG;
+    const int c0 = min(s * SEG, OW - SEG);
+    float acc[SEG];
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) acc[j] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < SEG + 2 * R; ++k) {
+      const int q = r * IS + c0 + k;
+      const float f = form(in0[q], in1 ? in1[q] : 0.0f);
+#pragma unroll
+      for (int j = 0; j < SEG; ++j) {
+        const int tap = k - j;
+        if (tap >= 0 && tap < TAPS) acc[j] = __fmaf_rn(win.w[tap], f, acc[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) out[r * OW + c0 + j] = acc[j];
+  }
+}
+
+// Vertical pass of an OW-wide half-filtered map for SEG consecutive rows of one
+// column (rows r0 .. r0 + SEG - 1 of the result; input rows r0 .. r0 + SEG + 9).
+template <int OW, int SEG>
+__device__ inline void col_pass(const float* hb, const Win& win, int col, int r0, bool active, float (&res)[SEG]) {
+#pragma unroll
+  for (int j = 0; j < SEG; ++j) res[j] = 0.0f;
+  if (!active) return;
+#pragma unroll
+  for (int k = 0; k < SEG + 2 * R; ++k) {
+    const float f = hb[(r0 + k) * OW + col];
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) {
+      const int tap = k - j;
+      if (tap >= 0 && tap < TAPS) res[j] = __fmaf_rn(win.w[tap], f, res[j]);
+    }
+  }
+}
+
+// The sums are formed where they are pinned (see window_map).
+template <int N>
+__device__ inline void pin(float (&res)[N]) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) asm volatile("" : "+v"(res[j]));
+}
+
+// Forward statistics: maps of the 52x52 patch over the 42x42 region (rows in runs
+// of FHSEG = 11: 208 row tasks; columns in runs of FVSEG = 7: 252 threads).
+// Backward: maps of the 42x42 A, B, Cc planes over the 32x32 tile (runs of 6: 252
+// row tasks; runs of VSEG = 4 rows: all 256 threads).
+constexpr int FHRUN = 11;
+constexpr int BHRUN = 6;
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_ssim_fused(const ViewDev* __restrict__ views, int V, LossTiles lt,
+                                               const float* __restrict__ x, const float* __restrict__ y, Win win,
+                                               float w_l1, float w_dssim, float* __restrict__ grad,
+                                               double2* __restrict__ partials) {
+  // the staged patch (two 52x52 planes), later the A, B, Cc planes of the 42x42
+  // region; two half-filtered maps (one is filled while the other is read, one
+  // barrier per map): 39 KB of LDS, four workgroups per CU
+  __shared__ float sp[2 * IN * IN];
+  __shared__ float hb[2][IN * HALO];
+  __shared__ double sh[4];
+  static_assert(3 * HALO * HS <= 2 * IN * IN, "A, B, Cc planes fit where the patch was");
+  static_assert(HALO * LT <= IN * HALO, "backward half-filtered maps fit");
+  const int tile = xcd_tile(blockIdx.x, lt.off[V]);
+  if (tile >= lt.off[V]) return;
+  const TileLoc t = loss_tile(views, lt, V, tile);
+  const ViewDev& cv = views[t.v];
+  const size_t hw = (size_t)cv.W * cv.H;
+  const size_t base = 3 * (size_t)cv.pix_off;
+  const float invN = 1.0f / (float)(3 * hw);
+  // forward statistics: region column fc, rows fr0 .. fr0 + 6 (threads < 252);
+  // gradient: tile column col, rows r0 .. r0 + 3
+  const int fc = threadIdx.x % HALO, fr0 = (threadIdx.x / HALO) * FVSEG;
+  const bool factive = (int)threadIdx.x < FTASKS;
+  const int col = threadIdx.x % LT, r0 = (threadIdx.x / LT) * VSEG;
+  const float* X = sp;
+  const float* Y = sp + IN * IN;
+  double sl1 = 0.0, sss = 0.0;
+  for (int ch = 0; ch < 3; ++ch) {
+    const float* xc = x + base + ch * hw;
+    const float* yc = y + base + ch * hw;
+    for (int i = threadIdx.x; i < IN * IN; i += blockDim.x) {
+      const int r = i / IN, c = i % IN;
+      const int gx = t.x0 - 2 * R + c, gy = t.y0 - 2 * R + r;
+      const bool in = gx >= 0 && gx < cv.W && gy >= 0 && gy < cv.H;
+      const size_t p = (size_t)gy * cv.W + gx;
+      sp[i] = in ? xc[p] : 0.0f;
+      sp[IN * IN + i] = in ? yc[p] : 0.0f;
+    }
+    __syncthreads();
+    float xs[VSEG], ys[VSEG];
+#pragma unroll
+    for (int j = 0; j < VSEG; ++j) {
+      xs[j] = X[(r0 + j + 2 * R) * IN + col + 2 * R];
+      ys[j] = Y[(r0 + j + 2 * R) * IN + col + 2 * R];
+    }
+    // windowed x, y, x^2 + y^2 (E[x^2] and E[y^2] enter S only through their sum,
+    // in D2) and xy; map q's vertical pass runs beside map q + 1's horizontal one
+    const auto fx = [](float a, float b) { return a; };
+    const auto fy = [](float a, float b) { return b; };
+    const auto fss = [](float a, float b) { return __fmaf_rn(a, a, b * b); };
+    const auto fxy = [](float a, float b) { return a * b; };
+    float m[4][FVSEG];
+    row_pass<IN, IN, HALO, FHRUN>(X, Y, hb[0], win, fx);
+    __syncthreads();
+    col_pass<HALO, FVSEG>(hb[0], win, fc, fr0, factive, m[0]);
+    pin(m[0]);
+    row_pass<IN, IN, HALO, FHRUN>(X, Y, hb[1], win, fy);
+    __syncthreads();
+    col_pass<HALO, FVSEG>(hb[1], win, fc, fr0, factive, m[1]);
+    pin(m[1]);
+    row_pass<IN, IN, HALO, FHRUN>(X, Y, hb[0], win, fss);
+    __syncthreads();
+    col_pass<HALO, FVSEG>(hb[0], win, fc, fr0, factive, m[2]);
+    pin(m[2]);
+    row_pass<IN, IN, HALO, FHRUN>(X, Y, hb[1], win, fxy);
+    __syncthreads();
+    col_pass<HALO, FVSEG>(hb[1], win, fc, fr0, factive, m[3]);
+    pin(m[3]);
+    // every thread is past its last read of the patch (the barrier before the last
+    // vertical pass): A, B, Cc go where it was
+    float* pa = sp;
+    if (factive) {
+#pragma unroll
+      for (int j = 0; j < FVSEG; ++j) {
+        const int gx = t.x0 - R + fc, gy = t.y0 - R + fr0 + j;
+        float A = 0.0f, B = 0.0f, Cc = 0.0f;
+        if (gx >= 0 && gx < cv.W && gy >= 0 && gy < cv.H) {
+          const float mx = m[0][j], my = m[1][j];
+          const float sxy = m[3][j] - mx * my;
+          const float N1 = 2.0f * mx * my + kC1, N2 = 2.0f * sxy + kC2;
+          const float M2 = mx * mx + my * my;
+          const float D1 = M2 + kC1, D2 = (m[2][j] - M2) + kC2;
+          // hardware reciprocals (1 ulp): D1, D2 >= C1 > 0
+          const float r1 = __builtin_amdgcn_rcpf(D1), r2 = __builtin_amdgcn_rcpf(D2);
+          const float rden = r1 * r2;
+          const float S = (N1 * N2) * rden;
+          A = 2.0f * my * (N2 - N1) * rden + 2.0f * mx * S * (r2 - r1);
+          B = -S * r2;
+          Cc = 2.0f * N1 * rden;
+          const int lx = fc - R, ly = fr0 + j - R;   // inside the tile: its SSIM term is counted here
+          if (lx >= 0 && lx < LT && ly >= 0 && ly < LT) sss += (double)S;
+        }
+        const int q = (fr0 + j) * HS + fc;
+        pa[q] = A;
+        pa[HALO * HS + q] = B;
+        pa[2 * HALO * HS + q] = Cc;
+      }
+    }
+    __syncthreads();
+    float g[3][VSEG];
+    const auto fid = [](float a, float b) { return a; };
+    row_pass<HALO, HS, LT, BHRUN>(pa, nullptr, hb[0], win, fid);
+    __syncthreads();
+    col_pass<LT, VSEG>(hb[0], win, col, r0, true, g[0]);
+    pin(g[0]);
+    row_pass<HALO, HS, LT, BHRUN>(pa + HALO * HS, nullptr, hb[1], win, fid);
+    __syncthreads();
+    col_pass<LT, VSEG>(hb[1], win, col, r0, true, g[1]);
+    pin(g[1]);
+    row_pass<HALO, HS, LT, BHRUN>(pa + 2 * HALO * HS, nullptr, hb[0], win, fid);
+    __syncthreads();
+    col_pass<LT, VSEG>(hb[0], win, col, r0, true, g[2]);
+    pin(g[2]);
+#pragma unroll
+    for (int j = 0; j < VSEG; ++j) {
+      const int px = t.x0 + col, py = t.y0 + r0 + j;
+      if (px < cv.W && py < cv.H) {
+        const size_t p = base + ch * hw + (size_t)py * cv.W + px;
+        const float xv = xs[j], yv = ys[j];
+        const float d = xv - yv;
+        sl1 += fabs((double)d);
+        const float l1 = w_l1 * invN * (float)((d > 0.0f) - (d < 0.0f));
+        grad[p] = l1 - w_dssim * invN * (g[0][j] + 2.0f * xv * g[1][j] + yv * g[2][j]);
+      }
+    }
+  }
+  const double t1 = block_sum_d(sl1, sh);
+  const double t2 = block_sum_d(sss, sh);
+  if (threadIdx.x == 0) partials[tile] = make_double2(t1, t2);
+}
+
 // One workgroup per view: the view's tile partials summed in FP64.
 __global__ __launch_bounds__(256) void k_loss_final(const ViewDev* __restrict__ views, LossTiles lt,
                                                      const double2* __restrict__ partials, float w_l1,
@@ -418,6 +626,7 @@ int loss_tiles(const ViewDev* hviews, int V) {
 hipError_t launch_loss_dev(const ViewDev* dviews, const ViewDev* hviews, int V, const float* color,
                            const float* target, float w_l1, float w_dssim, double* partials, float* aux,
                            double* loss_out, float* dL_dcolor, hipStream_t s) {
+  // aux NULL: the fused SSIM kernel (no per-pixel scratch)
   Win win;
   double g[TAPS], tot = 0.0;
   for (int k = 0; k < TAPS; ++k) {
@@ -438,6 +647,9 @@ hipError_t launch_loss_dev(const ViewDev* dviews, const ViewDev* hviews, int V, 
   const dim3 grid(kXcds * xcd_tile_chunk(t));   // >= t workgroups, see xcd_tile
   if (!ssim) {
     hipLaunchKernelGGL(k_l1, grid, dim3(256), 0, s, dviews, V, lt, color, target, w_l1, dL_dcolor, part);
+  } else if (!aux) {
+    hipLaunchKernelGGL(k_ssim_fused, grid, dim3(256), 0, s, dviews, V, lt, color, target, win, w_l1, w_dssim,
+                       dL_dcolor, part);
   } else {
     hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, s, dviews, V, lt, color, target, aux, win, part);
     hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, s, dviews, V, lt, color, target, aux, win, w_l1, w_dssim,
