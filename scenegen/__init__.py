@@ -226,6 +226,50 @@ def small_scene(seed: int, n: int, sh_degree: int, sizes, *, log_scale_mean=-2.6
     return Scene(P, n, sh_degree, cams, tg, w_l1, w_dssim, name=f"small_s{seed}_n{n}_d{sh_degree}")
 
 
+def opaque_scene(seed: int, n: int, sh_degree: int, sizes, *, frac=0.2, logit_range=(6.0, 9.0),
+                 opaque_log_scale=-1.6, **kw) -> Scene:
+    """small_scene with a fraction `frac` of nearly opaque Gaussians: their opacity
+    logits are drawn from U(logit_range), so o > 0.9975 and their alpha reaches the
+    0.99 cap within about a seventh of a standard deviation of their centre; their
+    log-scales are drawn around opaque_log_scale (several pixels across), so that
+    region holds pixel centres (a pixel behind two of them stops at the third)."""
+    sc = small_scene(seed, n, sh_degree, sizes, **kw)
+    rng = np.random.default_rng(seed + 7919)
+    pick = rng.choice(n, int(frac * n), replace=False)
+    sc.params[10, pick] = rng.uniform(logit_range[0], logit_range[1], size=len(pick))
+    sc.params[3:6, pick] = rng.normal(opaque_log_scale, 0.3, size=(3, len(pick)))
+    sc.name = f"opaque_s{seed}_n{n}_d{sh_degree}"
+    return sc
+
+
+def edge_scene(seed: int, n_inner: int, n_edge: int, sh_degree: int, sizes, *, edge_log_scale=-1.0,
+               depth_range=(2.5, 3.5), beyond=(1.35, 1.65), **kw) -> Scene:
+    """small_scene plus n_edge large Gaussians placed, for the first camera, just
+    outside 1.3x its half field of view in x or in y (the direction tangent is
+    `beyond` times the half field of view) at depths in depth_range, with log-scales
+    around edge_log_scale, so their footprints still reach into the image."""
+    sc = small_scene(seed, n_inner, sh_degree, sizes, **kw)
+    rng = np.random.default_rng(seed + 104729)
+    cam = sc.cams[0]
+    hx = 0.5 * cam["width"] / float(cam["fx"])
+    hy = 0.5 * cam["height"] / float(cam["fy"])
+    E = make_field(rng, n_edge, sh_degree, log_scale_mean=edge_log_scale, log_scale_std=0.25)
+    z = rng.uniform(depth_range[0], depth_range[1], n_edge)
+    side = rng.integers(0, 4, n_edge)                      # +x, -x, +y, -y
+    out = rng.uniform(beyond[0], beyond[1], n_edge)
+    sx = np.where(side < 2, out * hx * np.where(side == 0, 1.0, -1.0), rng.uniform(-hx, hx, n_edge))
+    sy = np.where(side >= 2, out * hy * np.where(side == 2, 1.0, -1.0), rng.uniform(-hy, hy, n_edge))
+    xc = np.stack([sx * z, sy * z, z])                      # camera coordinates
+    R = np.asarray(cam["R"], np.float64)
+    t = np.asarray(cam["t"], np.float64)
+    E[0:3] = R.T @ (xc - t[:, None])                        # world = R^T (x_cam - t)
+    E[10] = rng.normal(1.0, 1.0, n_edge)
+    sc.params = np.concatenate([sc.params[:, :n_inner], E], axis=1)
+    sc.n = n_inner + n_edge
+    sc.name = f"edge_s{seed}_n{n_inner}+{n_edge}_d{sh_degree}"
+    return sc
+
+
 def upstream_grads(seed: int, cams, scale=1e-3) -> List[np.ndarray]:
     """Seeded synthetic dL/dcolor images (fp32 [3, H, W] per view)."""
     rng = np.random.default_rng(seed)

@@ -1,11 +1,13 @@
-"""Parity at the benchmark's full size, in the launch configuration it times: 1M
-Gaussians, SH degree 3, nine views at 1600x1067, 1296x864 and 979x546 in one
-batched launch, the autotuned tile edge, cutoff culling.  The oracle checks what
-it can compute one by one: the projection of sampled Gaussians, sampled pixels
-(blended over the Gaussians whose pixel rect holds them, the only ones whose
-cutoff region can reach them), the complete lists of sampled tiles, the gradient
-of an upstream placed on the sampled pixels, the loss of full-size images and a
-dense Adam step over the whole field."""
+"""Parity at full size, in the launch configuration the benchmark times: the
+1M-Gaussian benchmark workload (SH degree 3, nine views at 1600x1067, 1296x864 and
+979x546 in one batched launch) and the 300k-Gaussian single-view workload
+(1296x864, SH degree 3), each at its autotuned tile edge with cutoff culling.  The
+oracle checks what it can compute one by one: the projection of sampled
+Gaussians, sampled pixels (blended over the Gaussians whose pixel rect holds them,
+the only ones whose cutoff region can reach them), the complete lists of sampled
+tiles, the gradient of an upstream placed on the sampled pixels (through the
+plain backward and through the fused backward + Adam call the benchmark times),
+the loss of full-size images and a dense Adam step over the whole field."""
 import numpy as np
 import pytest
 import torch
@@ -18,24 +20,30 @@ from tests import gpu_util as gu
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(400)]
 
-N_PIX = 40          # sampled pixels per view
+N_PIX = {"c2": 240, "c3": 40}   # sampled pixels per view
 N_GAUSS = 4000      # sampled Gaussians
 N_TILES = 24        # random tiles over all views, plus the centre tile of each view
+# Ambiguous sampled pixels (the oracle's decision margins at these seeded pixels,
+# the same on every run: 1 at C2, 0 at C3), with a quarter of slack, at least one.
+AMBIGUOUS_MAX = {"c2": 2, "c3": 1}
 
 
 def _say(msg):
-    print(f"[c3] {msg}", flush=True)
+    print(f"[full] {msg}", flush=True)
 
 
-@pytest.fixture(scope="module")
-def c3():
+@pytest.fixture(scope="module", params=["c2", "c3"])
+def c3(request):
     from paper_2503_13086_amd.pipeline import Rasterizer, params_to_device
     from paper_2503_13086_amd.autotune import Autotuner
     import paper_2503_13086_amd as gs
-    sc = scenegen.config3()
+    cfg = request.param
+    sc = scenegen.config3() if cfg == "c3" else scenegen.config2()
     V, n, D = len(sc.cams), sc.n, sc.sh_degree
+    N_PIX_ = N_PIX[cfg]
+    _say(f"workload {sc.name}")
     rng = np.random.default_rng(33)
-    pix = [(rng.integers(0, c["width"], N_PIX), rng.integers(0, c["height"], N_PIX)) for c in sc.cams]
+    pix = [(rng.integers(0, c["width"], N_PIX_), rng.integers(0, c["height"], N_PIX_)) for c in sc.cams]
     sample = np.sort(rng.choice(n, N_GAUSS, replace=False))
     rz = Rasterizer(0)
     dev = rz.device
@@ -49,7 +57,7 @@ def c3():
     torch.cuda.synchronize()
     _say(f"forward done, {K} pairs")
 
-    out = dict(sc=sc, tile=tile, pix=pix, sample=sample, K=K, rz=rz, P=P)
+    out = dict(cfg=cfg, sc=sc, tile=tile, pix=pix, sample=sample, K=K, rz=rz, P=P)
     idx = torch.as_tensor(sample, device=dev)
     rec = rz.buffer(gs.GS_BUF_RECORDS).view(V, n, 48)[:, idx].cpu().numpy()
     out["u"] = rec[:, :, 0:8].copy().view(np.float64)[..., 0]
@@ -115,7 +123,7 @@ def c3():
     # upstream on the sampled pixels, zero on the ambiguous ones (both sides)
     up = [np.zeros((3, c["height"], c["width"]), np.float32) for c in sc.cams]
     for v, (px, py) in enumerate(pix):
-        g = rng.normal(0, 1, size=(3, N_PIX)).astype(np.float32)
+        g = rng.normal(0, 1, size=(3, N_PIX_)).astype(np.float32)
         g[:, amb[v]] = 0.0
         up[v][:, py, px] = g
     grad = rz.render_bwd(rz.pack_images(up))
@@ -128,7 +136,7 @@ def c3():
     rz.close()
 
 
-def test_c3_preprocess_sampled_gaussians(c3):
+def test_full_preprocess_sampled_gaussians(c3):
     s = c3["sample"]
     for v, p in enumerate(c3["projs"]):
         vis = p["visible"][s]
@@ -145,10 +153,10 @@ def test_c3_preprocess_sampled_gaussians(c3):
         rgb = p["rgb"].numpy()[:, s][:, vis]
         got = np.stack([c3["r"][v][vis], c3["g"][v][vis], c3["bl"][v][vis]])
         assert np.abs(got - rgb).max() <= 1e-6 * max(1.0, np.abs(rgb).max())
-    assert sum(int(p["visible"][s].sum()) for p in c3["projs"]) >= N_GAUSS
+    assert sum(int(p["visible"][s].sum()) for p in c3["projs"]) >= 0.9 * N_GAUSS, "most sampled Gaussians are checked"
 
 
-def test_c3_sampled_pixels(c3):
+def test_full_sampled_pixels(c3):
     n_amb = 0
     for v, (r, a, g) in enumerate(zip(c3["refs"], c3["amb"], c3["px"])):
         ok = ~a
@@ -158,10 +166,10 @@ def test_c3_sampled_pixels(c3):
         assert np.array_equal(g["n"][ok], r["n_contrib"][ok]), v
         assert np.array_equal(g["last_g"][ok], r["last_g"][ok]), v
         assert (r["n_contrib"] > 0).mean() >= 0.5, "most sampled pixels blend something"
-    assert n_amb <= 2 + 0.02 * N_PIX * len(c3["refs"])
+    assert n_amb <= AMBIGUOUS_MAX[c3["cfg"]], n_amb
 
 
-def test_c3_sampled_tile_lists(c3):
+def test_full_sampled_tile_lists(c3):
     """Bit-exact: the Gaussians whose tile rect covers the tile and whose cutoff
     region meets its pixel-centre box, in (depth, index) order, with their keys
     and views."""
@@ -186,21 +194,30 @@ def test_c3_sampled_tile_lists(c3):
     assert busy >= len(sc.cams) // 2, "the centre tiles hold long lists"
 
 
-def test_c3_gradient_of_sampled_pixels(c3):
+def _ref_grad(c3):
+    """The oracle gradient of the crop for the sampled-pixel upstream (computed once)."""
+    if "ref_grad" not in c3:
+        sc = c3["sc"]
+        c3["ref_grad"] = oracle.param_grads(c3["Pc"], len(c3["crop"]), sc.sh_degree, sc.cams, c3["up"],
+                                            tile=c3["tile"])
+    return c3["ref_grad"]
+
+
+def test_full_gradient_of_sampled_pixels(c3):
     """The batched backward of the whole field, upstream on the sampled pixels:
     the crop against the oracle gradient; every other Gaussian gets exactly 0."""
     sc, crop, g = c3["sc"], c3["crop"], c3["grad"]
     outside = np.ones(sc.n, bool)
     outside[crop] = False
     assert not g[:, outside].any()
-    ref = oracle.param_grads(c3["Pc"], len(crop), sc.sh_degree, sc.cams, c3["up"], tile=c3["tile"])
+    ref = _ref_grad(c3)
     assert np.abs(ref).max(axis=0).astype(bool).sum() >= 1000
     errs = gu.grad_errors(g[:, crop], ref, np.ones(len(crop), bool), gu.param_groups(sc.sh_degree))
     for name, (rel, elem) in errs.items():
         assert rel <= 1e-3 and elem <= 1.0, (name, rel, elem)
 
 
-def test_c3_loss_full_size(c3):
+def test_full_loss_full_size(c3):
     """0.8 L1 + 0.2 D-SSIM of seeded full-size image pairs, all nine views in one
     launch: value and dL/dimage per view."""
     sc, rz = c3["sc"], c3["rz"]
@@ -216,7 +233,55 @@ def test_c3_loss_full_size(c3):
         assert np.abs(dl[v] - grad).max() <= 1e-4 * np.abs(grad).max(), v
 
 
-def test_c3_adam_full_field(c3):
+def _view_scales(sc):
+    from paper_2503_13086_amd.pipeline import DEFAULT_LR
+    iters = sc.iters if sc.iters is not None else np.zeros(len(sc.cams))
+    return [lr_current(float(it), 1.6e-4, 1.6e-6, 30000.0) / DEFAULT_LR[0] for it in iters]
+
+
+def test_full_fused_backward_adam(c3):
+    """gs_render_bwd_adam, the call the benchmark times, on the sampled-pixel
+    upstream: the gradient it writes against the oracle gradient (the crop; exactly
+    0 elsewhere), and the parameters, moments and steps it leaves against the
+    oracle's dense Adam step (per-view rates of Eq. 6-7) applied to that gradient.
+    It runs on a copy of the parameters (the same values the forward used)."""
+    import paper_2503_13086_amd as gs
+    from paper_2503_13086_amd.pipeline import DEFAULT_LR
+    sc, rz, crop = c3["sc"], c3["rz"], c3["crop"]
+    n = sc.n
+    rng = np.random.default_rng(14)
+    rows = sc.params.shape[0]
+    M = rng.normal(0, 1e-4, size=(rows, n)).astype(np.float32)
+    Vv = np.abs(rng.normal(0, 1e-8, size=(rows, n))).astype(np.float32)
+    step = rng.integers(0, 50, size=n).astype(np.uint32)
+    scale = _view_scales(sc)
+    dev = lambda a: torch.as_tensor(a).to(rz.device)
+    P2 = c3["P"].clone()
+    tM, tV, tS = dev(M), dev(Vv), dev(step.view(np.int32))
+    G = torch.zeros_like(P2)
+    gs.gs_render_bwd_adam(rz.ctx, P2, rz.pack_images(c3["up"]), G, tM, tV, tS, DEFAULT_LR, scale, 0b1)
+    torch.cuda.synchronize()
+    g = G[:, :n].cpu().numpy()
+    out = [t.cpu().numpy() for t in (P2, tM, tV)] + [tS.cpu().numpy().view(np.uint32)]
+    del P2, tM, tV, tS, G
+    outside = np.ones(n, bool)
+    outside[crop] = False
+    assert not g[:, outside].any()
+    errs = gu.grad_errors(g[:, crop], _ref_grad(c3), np.ones(len(crop), bool), gu.param_groups(sc.sh_degree))
+    for name, (rel, elem) in errs.items():
+        assert rel <= 1e-3 and elem <= 1.0, (name, rel, elem)
+    vis = np.stack([p["touched"] > 0 for p in c3["projs"]])
+    p1, m1, v1, s1 = oracle.adam_step(sc.params, g, M, Vv, step, DEFAULT_LR, view_scale=scale, visible=vis,
+                                      group_mask=0b1)
+    assert np.array_equal(out[3].astype(np.int64), s1)
+    assert np.abs(out[1] - m1).max() <= 1e-6 * np.abs(m1).max()
+    assert np.abs(out[2] - v1).max() <= 1e-6 * np.abs(v1).max()
+    p0 = sc.params.astype(np.float64)
+    dp_ref, dp = p1 - p0, out[0].astype(np.float64) - p0
+    assert np.all(np.abs(dp - dp_ref) <= 1e-4 * np.abs(dp_ref) + 2 * np.spacing(np.abs(sc.params)))
+
+
+def test_full_adam_full_field(c3):
     """Dense Adam over all 1M Gaussians with the per-view rates of Eq. 6-7 from
     the views' trained-iteration counters (runs last: it updates the field)."""
     from paper_2503_13086_amd.pipeline import DEFAULT_LR
@@ -228,7 +293,7 @@ def test_c3_adam_full_field(c3):
     M = rng.normal(0, 1e-3, size=(rows, n)).astype(np.float32)
     Vv = np.abs(rng.normal(0, 1e-6, size=(rows, n))).astype(np.float32)
     step = rng.integers(0, 50, size=n).astype(np.uint32)
-    scale = [lr_current(float(it), 1.6e-4, 1.6e-6, 30000.0) / DEFAULT_LR[0] for it in sc.iters]
+    scale = _view_scales(sc)
     dev = lambda a: torch.as_tensor(a).to(rz.device)
     tG, tM, tV, tS = dev(G), dev(M), dev(Vv), dev(step.view(np.int32))
     rz.adam_step(tG, tM, tV, tS, DEFAULT_LR, scale, group_mask=0b1)

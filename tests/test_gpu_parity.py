@@ -26,7 +26,19 @@ SCENES = {
                                                  log_scale_mean=-2.6),
     "sh2_dense": lambda: scenegen.small_scene(103, 3000, 2, [(96, 64)], log_scale_mean=-2.4, w_dssim=0.2,
                                               w_l1=0.8),
+    # 30% of the Gaussians nearly opaque: capped alphas, their zero derivative and
+    # pixels that stop right after them
+    "opaque_sh1": lambda: scenegen.opaque_scene(104, 1500, 1, [(80, 60), (48, 40)], log_scale_mean=-2.7,
+                                                frac=0.15, opaque_log_scale=-1.0),
+    # large Gaussians just outside 1.3x the half field of view that still reach
+    # into the image: the clamped projection Jacobian and its gradient
+    "edge_sh2": lambda: scenegen.edge_scene(105, 1200, 300, 2, [(96, 64), (70, 50)], log_scale_mean=-2.6),
 }
+
+# Ambiguous pixels per scene (the oracle's decision margins, so the same count on
+# every run): the bound is a quarter above the count measured on the oracle.
+AMBIGUOUS_MAX = {"ragged2v_sh3": 13, "c1_10k_sh0": 41, "ragged3v_sh1": 9, "sh2_dense": 27, "opaque_sh1": 13,
+                 "edge_sh2": 32}
 
 _cache = {}
 
@@ -124,7 +136,7 @@ def test_render_fwd_parity(name):
         last_g = np.where(Lg[v] > 0, g["values"][np.clip(pos, 0, max(len(g["values"]) - 1, 0))].astype(np.int64)
                           if len(g["values"]) else -1, -1)
         assert np.array_equal(last_g[ok], r["last_g"][ok])
-    assert n_amb <= max(2, 0.01 * n_pix), f"{n_amb} ambiguous pixels of {n_pix}"
+    assert n_amb <= AMBIGUOUS_MAX[name], f"{n_amb} ambiguous pixels of {n_pix}"
 
 
 @pytest.mark.parametrize("name", list(SCENES))
@@ -134,6 +146,42 @@ def test_render_bwd_parity(name):
     ref = oracle.param_grads(sc.params, sc.n, sc.sh_degree, sc.cams, up)
     keep = np.ones(sc.n, bool)
     errs = gu.grad_errors(g["grad"], ref, keep, gu.param_groups(sc.sh_degree))
+    for grp, (rel, elem) in errs.items():
+        assert rel <= 1e-3 and elem <= 1.0, (grp, rel, elem)
+
+
+def test_alpha_cap_reached_and_matched():
+    """The nearly opaque scene blends capped alphas: the oracle image with the cap
+    lifted differs at well over a hundred pixels, and the GPU image follows the
+    capped one there (its gradient, with the capped alphas' zero derivative, is
+    checked by test_render_bwd_parity)."""
+    sc, projs, g, _, renders = _get("opaque_sh1")
+    n_capped = 0
+    for v, p in enumerate(projs):
+        r, r_free = renders[v], composite.render_view(p, alpha_max=1.0 - 1e-12)
+        ok = ~gu.ambiguous(r)
+        capped = (np.abs(r["T_final"] - r_free["T_final"]) > 1e-9) & ok
+        n_capped += int(capped.sum())
+        err = np.abs(g["color"][v] - r["color"]).max(axis=0)[capped]
+        if capped.any():
+            assert err.max() <= 1e-4
+    assert n_capped >= 150, n_capped
+
+
+def test_jacobian_clamp_reached_and_matched():
+    """The edge scene's large Gaussians outside 1.3x the half field of view reach
+    the image: at least 200 visible ones in the first view have a clamped
+    projection Jacobian, and their gradients meet the per-group bar on their own."""
+    sc, projs, g, up, renders = _get("edge_sh2")
+    cam, p = sc.cams[0], projs[0]
+    u, w = p["u"].numpy(), p["w"].numpy()
+    limx = 1.3 * 0.5 * cam["width"] / float(cam["fx"])
+    limy = 1.3 * 0.5 * cam["height"] / float(cam["fy"])
+    clamped = p["visible"] & ((np.abs((u - float(cam["cx"])) / float(cam["fx"])) > limx) |
+                              (np.abs((w - float(cam["cy"])) / float(cam["fy"])) > limy))
+    assert clamped.sum() >= 200, clamped.sum()
+    ref = oracle.param_grads(sc.params, sc.n, sc.sh_degree, sc.cams, up)
+    errs = gu.grad_errors(g["grad"], ref, clamped, gu.param_groups(sc.sh_degree))
     for grp, (rel, elem) in errs.items():
         assert rel <= 1e-3 and elem <= 1.0, (grp, rel, elem)
 
