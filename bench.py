@@ -65,24 +65,64 @@ def algorithmic_bytes(n, n_p, V, K, P, tiles, ssim):
 
 
 # Flops per pixel-Gaussian evaluation (add, mul, compare, min, exp2, reciprocal = 1;
-# fma = 2).  Every list position up to a pixel's last blended Gaussian takes the
-# cutoff test: centre offset (2), base-2 exponent (3 mul + 2 fma = 7), two
-# comparisons (2) = 11.  A blended Gaussian adds, in the forward, exp2, opacity
-# product, clamp, 1 - alpha, transmittance product, stop test, weight and three
-# colour fmas = 13; in the backward, exp2, opacity product, clamp, 1 - alpha,
-# reciprocal, transmittance recovery, weight, the alpha derivative over three
-# channels (15), cap select, exponent derivative, six moment/opacity products,
-# three colour products, three suffix-colour fmas (6) and the nine sums over
-# pixels = 48.
+# fma = 2).  The method's work per pixel is E, the Gaussians that pass its cutoff
+# test before it stops (the blended ones and the one that stops it; counted by
+# gs_render_count, independent of the tile edge): each takes the cutoff test,
+# centre offset (2), base-2 exponent (3 mul + 2 fma = 7), two comparisons (2) = 11.
+# A blended Gaussian adds, in the forward, exp2, opacity product, clamp, 1 - alpha,
+# transmittance product, stop test, weight and three colour fmas = 13; in the
+# backward, exp2, opacity product, clamp, 1 - alpha, reciprocal, transmittance
+# recovery, weight, the alpha derivative over three channels (15), cap select,
+# exponent derivative, six moment/opacity products, three colour products, three
+# suffix-colour fmas (6) and the nine sums over pixels = 48.  List positions a
+# kernel walks without the Gaussian passing (up to each pixel's last blended
+# position) are reported beside it as "visits": work of the tiling, not of the method.
 TEST_FLOPS = 11
 FWD_BLEND_FLOPS = 13
 BWD_BLEND_FLOPS = 48
 
 
-def raster_flops(visits, blends):
+def raster_flops(evals, blends):
     """Algorithmic flops of one forward and one backward raster launch."""
-    return {"render_fwd": TEST_FLOPS * visits + FWD_BLEND_FLOPS * blends,
-            "render_bwd": TEST_FLOPS * visits + BWD_BLEND_FLOPS * blends}
+    return {"render_fwd": TEST_FLOPS * evals + FWD_BLEND_FLOPS * blends,
+            "render_bwd": TEST_FLOPS * evals + BWD_BLEND_FLOPS * blends}
+
+
+def probe_rates(dev):
+    """Achievable rates on this GPU from the library's probes: a streaming copy of
+    1 GiB (bytes read + written per second, best of 5) and fp32 FMA chains (flops
+    per second, best of 3), each timed with HIP events on the stream it runs on."""
+    import torch
+    from paper_2503_13086_amd import gs_probe_copy, gs_probe_fma
+    stream = torch.cuda.current_stream(dev)
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    nbytes = src.numel() * 4
+    best = float("inf")
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        gs_probe_copy(src, dst, nbytes, stream)
+        e1.record(stream)
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    assert torch.equal(src[:1024], dst[:1024]) and torch.equal(src[-1024:], dst[-1024:])
+    copy_gbs = 2 * nbytes / (best * 1e-3) / 1e9
+    del src, dst
+    blocks, iters = 256 * 32, 4096
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    best = float("inf")
+    flops = 0
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        flops = gs_probe_fma(out, blocks, iters, stream)
+        e1.record(stream)
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    assert bool(torch.isfinite(out).all())
+    return copy_gbs, flops / (best * 1e-3) / 1e12
 
 
 KERNEL_SOURCE = {"render_fwd": "k_raster.hip", "render_bwd": "k_raster.hip", "preprocess": "k_preprocess.hip",
@@ -108,12 +148,27 @@ def traffic_for(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(scene, budget_s=20.0):
-    """The FP64 oracle, as it is, on a bounded sample of the workload: forward and
-    backward of a few pixels of the first view (every Gaussian evaluated per pixel),
-    timed on the host's cores."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(scene, budget_s=15.0):
+    """The FP64 oracle, as it is, on the host's cores: (1) a bounded sample of the
+    benchmark workload, forward and backward of random pixels of its first view
+    (every visible Gaussian evaluated per pixel) plus one projection of the whole
+    field; (2) the whole 10k-Gaussian 128x128 workload, forward and backward of
+    every pixel (L1 loss gradient)."""
     import torch
     import oracle
+    import scenegen
     from oracle import composite
     from oracle.geometry import params_f64, project_view
     cam = scene.cams[0]
@@ -141,10 +196,24 @@ def cpu_baseline(scene, budget_s=20.0):
     grads = [leaves[k].grad for k in leaves if leaves[k].grad is not None]
     torch.autograd.backward(outs, grads)
     t_total = time.perf_counter() - t1 + t_proj
+    # the whole small workload
+    c1 = scenegen.config1()
+    t2 = time.perf_counter()
+    projs = oracle.project_views(c1.params, c1.n, c1.sh_degree, c1.cams)
+    img = composite.render_view(projs[0], margins=False)["color"]
+    up = [(np.sign(img - c1.targets[0]) / img.size).astype(np.float32)]
+    oracle.param_grads(c1.params, c1.n, c1.sh_degree, c1.cams, up)
+    t_c1 = time.perf_counter() - t2
+    px_c1 = c1.cams[0]["width"] * c1.cams[0]["height"]
     return {"value": n_pix / t_total / 1e6, "unit": "Mpix/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "cpu_model": _cpu_model(),
             "sample": f"{n_pix} random pixels of view 0 ({cam['width']}x{cam['height']}), FP64 forward + "
                       f"autograd backward over all {len(ids)} visible Gaussians, including one projection of "
-                      f"all {scene.n} Gaussians; {t_total:.1f} s"}
+                      f"all {scene.n} Gaussians; {t_total:.1f} s",
+            "small_workload_full": {"workload": c1.name, "pixels": px_c1, "seconds": round(t_c1, 2),
+                                    "mpix_s": px_c1 / t_c1 / 1e6,
+                                    "what": "FP64 projection, forward of every pixel and autograd backward of "
+                                            "the L1 loss gradient"}}
 
 
 def serving_leg(n_arrivals, time_scale, slots):
@@ -279,9 +348,12 @@ def main():
                      ["preprocess", "depth_sort", "scan", "emit", "tile_sort", "ranges", "render_fwd", "loss", "zero",
                       "render_bwd", "preprocess_bwd_adam"])
 
-    # per-pixel work the method needs: list positions up to each pixel's last blended
-    # Gaussian (each takes the cutoff test) and the Gaussians it blended
-    from paper_2503_13086_amd import GS_BUF_LAST, GS_BUF_N_CONTRIB, GS_BUF_RANGES
+    # per-pixel work of the method, from the last timed step's forward state: the
+    # Gaussians each pixel evaluated up to termination and those it blended; beside
+    # them the list positions the kernels walked (up to each pixel's last blend)
+    from paper_2503_13086_amd import GS_BUF_LAST, GS_BUF_N_CONTRIB, GS_BUF_RANGES, GS_BUF_EVALS, gs_render_count
+    gs_render_count(rz.ctx)
+    evals = int(rz.buffer(GS_BUF_EVALS).to(torch.int64).sum().item())
     visits = int(rz.buffer(GS_BUF_LAST).to(torch.int64).sum().item())
     blends = int(rz.buffer(GS_BUF_N_CONTRIB).to(torch.int64).sum().item())
     rg = rz.buffer(GS_BUF_RANGES).view(-1, 2).to(torch.int64)
@@ -320,13 +392,17 @@ def main():
     # dominant kernel and its roofline
     dom = max(["render_fwd", "render_bwd", "preprocess", "tile_sort", "depth_sort", "preprocess_bwd_adam", "loss",
                "emit"], key=lambda k: kern_ms[k] * kern_launches[k])
+    copy_gbs, fma_tflops = probe_rates(dev)
     if dom in ("render_bwd", "render_fwd"):
-        flops = raster_flops(visits, blends)[dom]
+        flops = raster_flops(evals, blends)[dom]
         achieved = flops / (kern_ms[dom] * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic_for(dom, args.workload), "kernel": dom,
                 "kernel_ms": kern_ms[dom], "algorithmic_flops": flops,
-                "peak_nonpacked": FP32_NONPACKED_PEAK_TFLOPS, "frac_nonpacked": achieved / FP32_NONPACKED_PEAK_TFLOPS}
+                "flop_model": f"{TEST_FLOPS} x evals + {BWD_BLEND_FLOPS if dom == 'render_bwd' else FWD_BLEND_FLOPS}"
+                              f" x blends",
+                "peak_nonpacked": FP32_NONPACKED_PEAK_TFLOPS, "frac_nonpacked": achieved / FP32_NONPACKED_PEAK_TFLOPS,
+                "measured_fma_tflops": round(fma_tflops, 2), "frac_of_measured_fma": achieved / fma_tflops}
     else:
         key = {"tile_sort": "tile_sort", "depth_sort": "tile_sort", "emit": "scan_emit"}.get(dom, dom)
         achieved = algo[key] / (kern_ms[dom] * 1e-3) / 1e9
@@ -334,19 +410,6 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom, args.workload), "kernel": dom,
                 "kernel_ms": kern_ms[dom]}
 
-    # achievable HBM bandwidth: a plain device copy of 1 GiB (read + write), best of 3
-    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-    dst = torch.empty_like(src)
-    best = float("inf")
-    for _ in range(3):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        dst.copy_(src)
-        e1.record()
-        e1.synchronize()
-        best = min(best, e0.elapsed_time(e1))
-    copy_gbs = 2 * src.numel() * 4 / (best * 1e-3) / 1e9
-    del src, dst
     fb_stages = ["preprocess", "scan_emit", "tile_sort", "ranges", "render_fwd", "loss", "render_bwd",
                  "preprocess_bwd_adam"]
     fb_gbs = sum(algo[k] for k in fb_stages) / (fwd_bwd_ms * 1e-3) / 1e9
@@ -378,8 +441,10 @@ def main():
         "fwd_bwd_algorithmic_gbs": round(fb_gbs, 1),
         "achievable_hbm_gbs": round(copy_gbs, 1),
         "fwd_bwd_frac_of_achievable_hbm": round(fb_gbs / copy_gbs, 4),
-        "visits": visits,
+        "evals": evals,
         "blends": blends,
+        "visits": visits,
+        "measured_fma_tflops": round(fma_tflops, 2),
         "roofline": roof,
     }
     if args.serve_arrivals > 0:

@@ -89,7 +89,9 @@ enum {
   GS_BUF_GRAD2D = 10,   /* float  [V*n][9]: dL/d(u, w, a, b, c, o, r, g, b) per (view, Gaussian) */
   GS_BUF_PAIR_VIEW = 11,/* uint32 [K]: view of each sorted pair */
   GS_BUF_ALPHA_SUM = 12,/* float  [P]: sum of the alphas each pixel blended (soft Gaussian count) */
-  GS_N_BUFS = 13
+  GS_BUF_EVALS = 13,    /* uint32 [P]: Gaussians each pixel evaluated up to its termination (after
+                           gs_render_count; size 0 before it) */
+  GS_N_BUFS = 14
 };
 
 /* Kernel ids for gs_profile_read. */
@@ -271,6 +273,25 @@ gs_status gs_copy_buffer(gs_ctx* ctx, int32_t which, void* dst, size_t bytes, gs
  * `kernel` (GS_K_*) since the last enable. */
 gs_status gs_profile_enable(gs_ctx* ctx, int32_t enable);
 gs_status gs_profile_read(gs_ctx* ctx, int32_t kernel, int64_t* launches, double* total_ms);
+
+/* Work count of the forward for rooflines (Sec. III Eq. 2): walks the lists of the
+ * last gs_bin_sort exactly as gs_render_fwd does and stores, per pixel, the number
+ * of Gaussians that pass its cutoff test before it stops (the blended ones plus,
+ * for a pixel that stopped, the one that would have taken its transmittance below
+ * 1e-4), readable as GS_BUF_EVALS.  This count depends on no tile edge.  The
+ * forward state (images, transmittances, counts) is left as it was. */
+gs_status gs_render_count(gs_ctx* ctx, gs_stream stream);
+
+/* Measurement probes (no context).  gs_probe_copy copies `bytes` (a multiple of
+ * 16; both pointers 16-byte aligned, device memory, not overlapping) with a plain
+ * streaming kernel: its rate (2 x bytes / time) is the achievable HBM bandwidth the
+ * HBM-bound stages are compared with.  gs_probe_fma runs `blocks` x 256 threads of
+ * eight independent fp32 FMA chains of `iters` steps each, built like the library's
+ * other kernels (packed fp32 off), and writes one float per thread to `out` (device,
+ * blocks x 256 floats); *flops (may be NULL) receives its flop count (2 per FMA).
+ * Both are stream-ordered; the caller times them. */
+gs_status gs_probe_copy(const void* src, void* dst, size_t bytes, gs_stream stream);
+gs_status gs_probe_fma(float* out, int32_t blocks, int32_t iters, int64_t* flops, gs_stream stream);
 
 /* Device memory (bytes) held by the context's own buffers right now. */
 gs_status gs_memory_bytes(const gs_ctx* ctx, size_t* bytes);

@@ -15,9 +15,11 @@ from .constants import ALPHA_MAX, T_MIN
 
 
 def render_pixel(proj, i: int, j: int):
-    """Returns (colour [3] with background, T_final, n_blended, last_g, alpha_sum):
-    alpha_sum is the sum of the alphas of the blended Gaussians (the soft
-    per-pixel Gaussian count of the load-balancing term, see loss.py)."""
+    """Returns (colour [3] with background, T_final, n_blended, last_g, alpha_sum,
+    n_eval): alpha_sum is the sum of the alphas of the blended Gaussians (the soft
+    per-pixel Gaussian count of the load-balancing term, see loss.py); n_eval counts
+    the Gaussians that pass the cutoff test before the walk ends, the one that
+    stops it included."""
     vis = [g for g in range(len(proj["visible"])) if proj["visible"][g]]
     vis.sort(key=lambda g: (int(proj["depth_bits"][g]), g))
     u, w = proj["u"].detach().numpy(), proj["w"].detach().numpy()
@@ -28,12 +30,14 @@ def render_pixel(proj, i: int, j: int):
     C = [0.0, 0.0, 0.0]
     nb, last = 0, -1
     asum = 0.0
+    ne = 0
     for g in vis:
         dx = float(u[g]) - (i + 0.5)
         dy = float(w[g]) - (j + 0.5)
         power = -0.5 * (float(a[g]) * dx * dx + float(c[g]) * dy * dy) - float(b[g]) * dx * dy
         if power > 0.0 or power < float(tau[g]):
             continue
+        ne += 1
         alpha = min(ALPHA_MAX, float(o[g]) * math.exp(power))
         Tn = T * (1.0 - alpha)
         if Tn < T_MIN:
@@ -45,7 +49,7 @@ def render_pixel(proj, i: int, j: int):
         last = g
         asum += alpha
     bg = proj["bg"]
-    return [C[ch] + T * bg[ch] for ch in range(3)], T, nb, last, asum
+    return [C[ch] + T * bg[ch] for ch in range(3)], T, nb, last, asum, ne
 
 
 def render_image(proj):
@@ -55,12 +59,14 @@ def render_image(proj):
     nc = np.zeros((H, W), np.int64)
     lg = np.zeros((H, W), np.int64)
     asum = np.zeros((H, W))
+    ne = np.zeros((H, W), np.int64)
     for j in range(H):
         for i in range(W):
-            cc, t, n, l, a = render_pixel(proj, i, j)
+            cc, t, n, l, a, e = render_pixel(proj, i, j)
+            ne[j, i] = e
             col[:, j, i] = cc
             Tf[j, i] = t
             nc[j, i] = n
             lg[j, i] = l
             asum[j, i] = a
-    return dict(color=col, T_final=Tf, n_contrib=nc, last_g=lg, alpha_sum=asum)
+    return dict(color=col, T_final=Tf, n_contrib=nc, last_g=lg, alpha_sum=asum, n_eval=ne)

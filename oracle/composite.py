@@ -99,6 +99,9 @@ def blend(q, px: np.ndarray, py: np.ndarray, *, cutoffs=True, alpha_max=ALPHA_MA
         kidx = torch.arange(nc)
         blended = ps & (kidx[None, :] < kstar[:, None])
         out["n_contrib"] = blended.sum(1).numpy().astype(np.int64)
+        # Gaussians that pass the cutoff test before the walk ends (the stopping one
+        # included): the pixel's work count
+        out["n_eval"] = (ps & (kidx[None, :] <= kstar[:, None])).sum(1).numpy().astype(np.int64)
         lastk = torch.where(blended.any(1), nc - 1 - _first_true(blended.flip(1)),
                             torch.full((n,), -1, dtype=torch.long))
         if nc:
@@ -164,7 +167,7 @@ def composite_pixels(proj, px, py, *, cutoffs=True, alpha_max=ALPHA_MAX, t_min=T
     n = len(px)
     chunk = max(1, min(1024, max_elems // max(1, len(ids))))
     keys = ["m_cut", "m_sign", "m_cap", "m_T"] if margins else []
-    acc = {k: [] for k in ["C", "T_final", "n_contrib", "last", "alpha_sum"] + keys}
+    acc = {k: [] for k in ["C", "T_final", "n_contrib", "n_eval", "last", "alpha_sum"] + keys}
     for s in range(0, n, chunk):
         r = blend(q, px[s:s + chunk], py[s:s + chunk], cutoffs=cutoffs, alpha_max=alpha_max,
                   t_min=t_min, margins=margins)

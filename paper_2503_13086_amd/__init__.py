@@ -22,7 +22,8 @@ GS_MAX_VIEWS = 64
 (GS_GROUP_MEAN, GS_GROUP_SCALE, GS_GROUP_ROT, GS_GROUP_OPACITY, GS_GROUP_SH_DC, GS_GROUP_SH_REST) = range(6)
 GS_N_GROUPS = 6
 (GS_BUF_RECORDS, GS_BUF_DEPTH, GS_BUF_TOUCHED, GS_BUF_TILE_RECT, GS_BUF_KEYS, GS_BUF_VALUES, GS_BUF_RANGES,
- GS_BUF_T_FINAL, GS_BUF_N_CONTRIB, GS_BUF_LAST, GS_BUF_GRAD2D, GS_BUF_PAIR_VIEW, GS_BUF_ALPHA_SUM) = range(13)
+ GS_BUF_T_FINAL, GS_BUF_N_CONTRIB, GS_BUF_LAST, GS_BUF_GRAD2D, GS_BUF_PAIR_VIEW, GS_BUF_ALPHA_SUM,
+ GS_BUF_EVALS) = range(14)
 (GS_K_PREPROCESS, GS_K_DEPTH_SORT, GS_K_SCAN, GS_K_EMIT, GS_K_TILE_SORT, GS_K_RANGES, GS_K_RENDER_FWD, GS_K_LOSS,
  GS_K_RENDER_BWD, GS_K_PREPROCESS_BWD, GS_K_ADAM, GS_K_ZERO, GS_K_LOAD, GS_K_BWD_ADAM) = range(14)
 KERNEL_NAMES = ["preprocess", "depth_sort", "scan", "emit", "tile_sort", "ranges", "render_fwd", "loss",
@@ -35,7 +36,8 @@ _STATUS = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_CAPACITY", -3: "GS_ERR_
 EXPORTS = ["gs_abi_version", "gs_create", "gs_destroy", "gs_last_error", "gs_layout", "gs_preprocess", "gs_bin_sort",
            "gs_render_fwd", "gs_loss", "gs_loss_noalloc", "gs_load_balance", "gs_render_bwd", "gs_adam_step", "gs_render_bwd_adam",
            "gs_set_cull", "gs_buffer_size", "gs_sync_status", "gs_reserve_pairs",
-           "gs_copy_buffer", "gs_profile_enable", "gs_profile_read", "gs_memory_bytes", "gs_sched_weights",
+           "gs_copy_buffer", "gs_profile_enable", "gs_profile_read", "gs_memory_bytes", "gs_render_count",
+           "gs_probe_copy", "gs_probe_fma", "gs_sched_weights",
            "gs_sched_plan", "gs_sched_lr"]
 GS_CULL_RECT, GS_CULL_ELLIPSE, GS_CULL_ELLIPSE_EXACT = 0, 1, 2
 
@@ -96,6 +98,9 @@ def _load():
         "gs_profile_enable": (_I32, [_P, _I32]),
         "gs_profile_read": (_I32, [_P, _I32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
         "gs_memory_bytes": (_I32, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+        "gs_render_count": (_I32, [_P, _P]),
+        "gs_probe_copy": (_I32, [_P, _P, ctypes.c_size_t, _P]),
+        "gs_probe_fma": (_I32, [_P, _I32, _I32, ctypes.POINTER(ctypes.c_int64), _P]),
         "gs_sched_weights": (_I32, [_D, _I32, _I32, _D, _IP]),
         "gs_sched_plan": (_I32, [_D, _I32, _I32, _I32, _D, _IP, _IP]),
         "gs_sched_lr": (_I32, [_LP, _D, _I32, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D, _D]),
@@ -286,6 +291,24 @@ def gs_memory_bytes(ctx) -> int:
     b = ctypes.c_size_t(0)
     _check(ctx, _load().gs_memory_bytes(ctx, ctypes.byref(b)), "gs_memory_bytes")
     return b.value
+
+
+def gs_render_count(ctx, stream=None) -> None:
+    """Per-pixel count of the Gaussians evaluated up to termination (GS_BUF_EVALS)."""
+    _check(ctx, _load().gs_render_count(ctx, _stream(stream)), "gs_render_count")
+
+
+def gs_probe_copy(src, dst, nbytes: int, stream=None) -> None:
+    """Streaming copy probe of nbytes (multiple of 16) from src to dst (device tensors)."""
+    _check(None, _load().gs_probe_copy(_ptr(src), _ptr(dst), int(nbytes), _stream(stream)), "gs_probe_copy")
+
+
+def gs_probe_fma(out, blocks: int, iters: int, stream=None) -> int:
+    """fp32 FMA-rate probe writing blocks x 256 floats to out; returns its flop count."""
+    f = ctypes.c_int64(0)
+    _check(None, _load().gs_probe_fma(_ptr(out), int(blocks), int(iters), ctypes.byref(f), _stream(stream)),
+           "gs_probe_fma")
+    return f.value
 
 
 def _f64_array(x, n=None):

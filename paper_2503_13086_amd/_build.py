@@ -20,7 +20,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["gs_api.hip", "k_preprocess.hip", "k_sort.hip", "k_raster.hip", "k_loss.hip", "k_adam.hip",
-           "gs_sched.hip"]
+           "k_probe.hip", "gs_sched.hip"]
 
 # Packed fp32 instructions are disabled for every HIP translation unit.
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

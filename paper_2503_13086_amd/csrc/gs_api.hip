@@ -74,7 +74,8 @@ struct gs_ctx {
   DevBuf views, rec, depth, touched, rect;
   DevBuf dkey[2], dval[2], groupsums, blocksums, total, hist;
   DevBuf pkey[2], pval[2], ranges;
-  DevBuf tfinal, ncontrib, last, grad2d, lossp, aux;
+  DevBuf tfinal, ncontrib, last, grad2d, lossp, aux, evals;
+  bool evals_ok = false;           // evals holds gs_render_count's counts for the current binning
   DevBuf asum, dG, loadp, loadst, kept, emitinfo, redo_list, redo_bits, status;
   DevStatus* h_status = nullptr;   // host mirror of the device status, written by the binning's last check
   DevStatus* d_mirror = nullptr;   // its device-side address
@@ -127,7 +128,7 @@ std::vector<DevBuf*> all_bufs(gs_ctx* c) {
   return {&c->views, &c->rec, &c->depth, &c->touched, &c->rect, &c->dkey[0], &c->dkey[1], &c->dval[0],
           &c->dval[1], &c->groupsums, &c->blocksums, &c->total, &c->hist, &c->pkey[0],
           &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->tfinal, &c->ncontrib, &c->last,
-          &c->grad2d, &c->lossp, &c->aux, &c->asum, &c->dG, &c->loadp, &c->loadst, &c->kept, &c->emitinfo,
+          &c->grad2d, &c->lossp, &c->aux, &c->evals, &c->asum, &c->dG, &c->loadp, &c->loadst, &c->kept, &c->emitinfo,
           &c->redo_list, &c->redo_bits, &c->status};
 }
 
@@ -349,6 +350,7 @@ gs_status gs_preprocess(gs_ctx* c, const float* params, int32_t n, int32_t strid
   c->n = n; c->stride = stride; c->D = sh_degree; c->V = n_views; c->params = params;
   c->hviews = hv; c->n_tiles = n_tiles; c->tile = tile; c->P = P; c->K = 0;
   c->stage = kProjected;
+  c->evals_ok = false;
   return GS_OK;
 }
 
@@ -478,6 +480,7 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
                             c->n_tiles, s));
   }
   c->stage = kBinned;
+  c->evals_ok = false;
   if (n_pairs_out) *n_pairs_out = (int64_t)c->K;
   return GS_OK;
 }
@@ -539,6 +542,32 @@ gs_status gs_render_fwd(gs_ctx* c, float* color, gs_stream stream) {
   c->stage = kRendered;
   c->load_pending = false;
   return GS_OK;
+}
+
+gs_status gs_render_count(gs_ctx* c, gs_stream stream) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (c->stage < kBinned) return fail(c, GS_ERR_STATE, "gs_render_count needs a preceding gs_bin_sort");
+  hipStream_t s = (hipStream_t)stream;
+  GS_HIP(c, hipSetDevice(c->device));
+  gs_status st;
+  if ((st = ensure(c, c->evals, (size_t)c->P * 4, s)) != GS_OK) return st;
+  GS_HIP(c, launch_render_count(c->views.as<ViewDev>(), c->V, c->n_tiles, c->ranges.as<uint2>(),
+                                c->pval[c->pairs_in_b].as<uint32_t>(), c->rec.as<Record>(),
+                                (uint32_t)((size_t)c->V * c->n), c->evals.as<uint32_t>(), c->tile, s));
+  c->evals_ok = true;
+  return GS_OK;
+}
+
+gs_status gs_probe_copy(const void* src, void* dst, size_t bytes, gs_stream stream) {
+  if (!src || !dst || bytes % 16 != 0 || !aligned(src, 16) || !aligned(dst, 16)) return GS_ERR_INVALID;
+  return launch_probe_copy(src, dst, bytes, (hipStream_t)stream) == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+gs_status gs_probe_fma(float* out, int32_t blocks, int32_t iters, int64_t* flops, gs_stream stream) {
+  if (!out || blocks < 1 || iters < 1 || !aligned(out, 4)) return GS_ERR_INVALID;
+  if (flops) *flops = probe_fma_flops(blocks, iters);
+  return launch_probe_fma(out, blocks, iters, (hipStream_t)stream) == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 
 gs_status gs_loss(gs_ctx* c, const float* color, const float* target, float w_l1, float w_dssim, double* loss_out,
@@ -754,6 +783,7 @@ gs_status gs_buffer_size(const gs_ctx* c, int32_t which, size_t* bytes) {
     case GS_BUF_KEYS: b = c->stage >= kBinned ? c->K * 8 : 0; break;
     case GS_BUF_VALUES: case GS_BUF_PAIR_VIEW: b = c->stage >= kBinned ? c->K * 4 : 0; break;
     case GS_BUF_RANGES: b = c->stage >= kBinned ? (size_t)c->n_tiles * 8 : 0; break;
+    case GS_BUF_EVALS: b = (c->stage >= kBinned && c->evals_ok) ? (size_t)c->P * 4 : 0; break;
     case GS_BUF_T_FINAL: case GS_BUF_N_CONTRIB: case GS_BUF_LAST: case GS_BUF_ALPHA_SUM:
       b = c->stage >= kRendered ? (size_t)c->P * 4 : 0;
       break;
@@ -784,6 +814,7 @@ gs_status gs_copy_buffer(gs_ctx* c, int32_t which, void* dst, size_t bytes, gs_s
     case GS_BUF_N_CONTRIB: src = c->ncontrib.p; break;
     case GS_BUF_LAST: src = c->last.p; break;
     case GS_BUF_ALPHA_SUM: src = c->asum.p; break;
+    case GS_BUF_EVALS: src = c->evals.p; break;
     case GS_BUF_GRAD2D: src = c->grad2d.p; break;
     case GS_BUF_KEYS:
       GS_HIP(c, launch_compose_keys(c->pkey[c->pairs_in_b].as<uint32_t>(), c->pval[c->pairs_in_b].as<uint32_t>(),

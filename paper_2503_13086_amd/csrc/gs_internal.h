@@ -260,6 +260,14 @@ hipError_t launch_compose_keys(const uint32_t* pair_tile, const uint32_t* pair_r
 hipError_t launch_render_fwd(const ViewDev* views, int V, int n_tiles, const uint2* ranges, const uint32_t* pair_rec,
                              const Record* rec, uint32_t n_rec, float* color, float* t_final, uint32_t* n_contrib,
                              uint32_t* last, float* asum, int tile, hipStream_t s);
+// The forward walk counting per pixel the Gaussians evaluated up to termination.
+hipError_t launch_render_count(const ViewDev* views, int V, int n_tiles, const uint2* ranges, const uint32_t* pair_rec,
+                               const Record* rec, uint32_t n_rec, uint32_t* evals, int tile, hipStream_t s);
+// Probes: a streaming 16-byte-vector copy of `bytes` (a multiple of 16) and
+// `blocks` x 256 threads of eight fp32 FMA chains of `iters` steps.
+hipError_t launch_probe_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+hipError_t launch_probe_fma(float* out, int blocks, int iters, hipStream_t s);
+int64_t probe_fma_flops(int blocks, int iters);
 hipError_t launch_render_bwd(const ViewDev* views, int V, int n_tiles, const uint2* ranges, const uint32_t* pair_rec,
                              const Record* rec, uint32_t n_rec, const float* t_final, const uint32_t* last,
                              const float* dL_dcolor, const float* dL_dG, float* grad2d, int tile, hipStream_t s);

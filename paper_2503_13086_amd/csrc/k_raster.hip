@@ -174,14 +174,18 @@ __device__ inline void block_masks(const float4* s0, const float4* s1, int m, fl
   }
 }
 
-template <int T>
+// COUNT: the same walk, writing only the number of Gaussians each pixel evaluated up
+// to its termination (those that pass its cutoff test: the blended ones and, if it
+// stopped, the one that stopped it) into evals; the forward state is left alone.
+template <int T, bool COUNT = false>
 __global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict__ views, int V, int n_tiles_total,
                                                     const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ pair_rec,
                                                     const Record* __restrict__ rec, uint32_t n_rec,
                                                     float* __restrict__ color,
                                                     float* __restrict__ t_final, uint32_t* __restrict__ n_contrib,
-                                                    uint32_t* __restrict__ last, float* __restrict__ asum) {
+                                                    uint32_t* __restrict__ last, float* __restrict__ asum,
+                                                    uint32_t* __restrict__ evals = nullptr) {
   constexpr int NT = T * T, NM = NT / 64;
   __shared__ float4 s0[NT], s1[NT], s2[NT];
   const int tile = xcd_raster_tile((int)blockIdx.x);
@@ -248,6 +252,13 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict_
       }
     }
     if (__syncthreads_and(pmax < 0.0f)) break;
+  }
+  if (COUNT) {
+    if (tg.inside) {
+      const ViewDev& cv = views[tg.v];
+      evals[(size_t)cv.pix_off + (size_t)tg.py * cv.W + tg.px] = cnt + (pmax < 0.0f ? 1u : 0u);
+    }
+    return;
   }
   if (tg.inside) {
     const ViewDev& cv = views[tg.v];
@@ -570,6 +581,28 @@ hipError_t launch_render_fwd(const ViewDev* views, int V, int n_tiles, const uin
     case 32:
       hipLaunchKernelGGL(k_render_fwd<32>, grid, dim3(1024), 0, s, views, V, n_tiles, ranges, pair_rec, rec, n_rec, color,
                          t_final, n_contrib, last, asum);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_render_count(const ViewDev* views, int V, int n_tiles, const uint2* ranges, const uint32_t* pair_rec,
+                               const Record* rec, uint32_t n_rec, uint32_t* evals, int tile, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((n_tiles + 8 * kXcdRun - 1) / (8 * kXcdRun) * (8 * kXcdRun)));
+  switch (tile) {
+    case 8:
+      hipLaunchKernelGGL((k_render_fwd<8, true>), grid, dim3(64), 0, s, views, V, n_tiles, ranges, pair_rec, rec, n_rec,
+                         nullptr, nullptr, nullptr, nullptr, nullptr, evals);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_render_fwd<16, true>), grid, dim3(256), 0, s, views, V, n_tiles, ranges, pair_rec, rec,
+                         n_rec, nullptr, nullptr, nullptr, nullptr, nullptr, evals);
+      break;
+    case 32:
+      hipLaunchKernelGGL((k_render_fwd<32, true>), grid, dim3(1024), 0, s, views, V, n_tiles, ranges, pair_rec, rec,
+                         n_rec, nullptr, nullptr, nullptr, nullptr, nullptr, evals);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -62,6 +62,11 @@ def run_gpu(scene, upstream=None, loss=False, cull=None, tile=16):
         out["T_final"] = rz.buffer(GS_BUF_T_FINAL).cpu().numpy()
         out["n_contrib"] = rz.buffer(GS_BUF_N_CONTRIB).cpu().numpy()
         out["last"] = rz.buffer(GS_BUF_LAST).cpu().numpy()
+        # the work count of the same walk; it must leave the forward state alone
+        gs.gs_render_count(rz.ctx)
+        out["evals"] = rz.buffer(gs.GS_BUF_EVALS).cpu().numpy()
+        out["count_kept_state"] = (np.array_equal(rz.buffer(GS_BUF_T_FINAL).cpu().numpy(), out["T_final"]) and
+                                   np.array_equal(rz.buffer(GS_BUF_LAST).cpu().numpy(), out["last"]))
         assert out["T_final"].size == P_
         if loss:
             tgt = rz.pack_images(scene.targets)

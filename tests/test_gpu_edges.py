@@ -267,3 +267,24 @@ def test_views_reused_or_changed_between_calls():
             assert torch.equal(rz.render_fwd(), ref[name]), name
     finally:
         rz.close()
+
+
+@pytest.mark.gpu
+def test_measurement_probes():
+    """The copy probe copies (every byte, including a ragged last workgroup) and the
+    FMA probe's chains stay finite, with the flop count its launch shape implies;
+    misaligned or odd sizes are refused."""
+    import paper_2503_13086_amd as gs
+    n = (1 << 20) + 36                     # not a multiple of a workgroup's 256 vectors
+    src = torch.arange(n, dtype=torch.float32, device="cuda")
+    dst = torch.zeros_like(src)
+    gs.gs_probe_copy(src, dst, n * 4)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    with pytest.raises(gs.GsError):
+        gs.gs_probe_copy(src, dst, n * 4 - 4)
+    out = torch.zeros(64 * 256, dtype=torch.float32, device="cuda")
+    flops = gs.gs_probe_fma(out, 64, 100)
+    torch.cuda.synchronize()
+    assert flops == 64 * 256 * 100 * 8 * 2
+    assert bool(torch.isfinite(out).all()) and float(out.abs().min()) > 0.0

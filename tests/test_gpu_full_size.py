@@ -74,7 +74,9 @@ def c3(request):
     values_t = rz.buffer(gs.GS_BUF_VALUES)
     keys_t = rz.buffer(gs.GS_BUF_KEYS)
     views_t = rz.buffer(gs.GS_BUF_PAIR_VIEW)
-    Tf, Nc, La = (rz.buffer(b) for b in (gs.GS_BUF_T_FINAL, gs.GS_BUF_N_CONTRIB, gs.GS_BUF_LAST))
+    gs.gs_render_count(rz.ctx)
+    Tf, Nc, La, Ev = (rz.buffer(b) for b in (gs.GS_BUF_T_FINAL, gs.GS_BUF_N_CONTRIB, gs.GS_BUF_LAST,
+                                             gs.GS_BUF_EVALS))
     tiles_x, tiles_y, toff = oracle.tile_layout(sc.cams, tile)
     imgs = rz.image_views(color)
     out["px"] = []
@@ -87,6 +89,7 @@ def c3(request):
         last_g = torch.where(last > 0, values_t[pos.clamp(min=0)].long(), torch.full_like(last, -1))
         out["px"].append(dict(color=imgs[v][:, torch.as_tensor(py, device=dev), torch.as_tensor(px, device=dev)]
                               .cpu().numpy(), T=Tf[flat].cpu().numpy(), n=Nc[flat].cpu().numpy().astype(np.int64),
+                              e=Ev[flat].cpu().numpy().astype(np.int64),
                               last_g=last_g.cpu().numpy()))
 
     # complete lists of sampled tiles
@@ -99,7 +102,7 @@ def c3(request):
         a, b = rg[t]
         out["tiles"][t] = (keys_t[a:b].cpu().numpy().view(np.uint64), values_t[a:b].cpu().numpy().astype(np.int64),
                            views_t[a:b].cpu().numpy().astype(np.int64))
-    del keys_t, values_t, views_t, Tf, Nc, La, rec
+    del keys_t, values_t, views_t, Tf, Nc, La, Ev, rec
     _say("GPU outputs gathered")
 
     # oracle: projection of the whole field, the crop that can reach the sampled
@@ -164,6 +167,7 @@ def test_full_sampled_pixels(c3):
         assert np.abs(g["color"] - r["color"])[:, ok].max() <= 1e-4, v
         assert np.abs(g["T"] - r["T_final"])[ok].max() <= 1e-4, v
         assert np.array_equal(g["n"][ok], r["n_contrib"][ok]), v
+        assert np.array_equal(g["e"][ok], r["n_eval"][ok]), v
         assert np.array_equal(g["last_g"][ok], r["last_g"][ok]), v
         assert (r["n_contrib"] > 0).mean() >= 0.5, "most sampled pixels blend something"
     assert n_amb <= AMBIGUOUS_MAX[c3["cfg"]], n_amb

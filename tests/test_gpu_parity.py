@@ -115,6 +115,8 @@ def test_render_fwd_parity(name):
     sc, projs, g, _, renders = _get(name)
     Tg = gu.split_pixels(sc, g["T_final"])
     Ng = gu.split_pixels(sc, g["n_contrib"])
+    Eg = gu.split_pixels(sc, g["evals"])
+    assert g["count_kept_state"], "gs_render_count changed the forward state"
     Lg = gu.split_pixels(sc, g["last"])
     tiles_x, tiles_y, toff = oracle.tile_layout(sc.cams, 16)
     n_amb = n_pix = 0
@@ -128,6 +130,7 @@ def test_render_fwd_parity(name):
         assert err[ok].max() <= 1e-4, f"view {v}: max image error {err[ok].max()}"
         assert np.abs(Tg[v] - r["T_final"])[ok].max() <= 1e-4
         assert np.array_equal(Ng[v][ok].astype(np.int64), r["n_contrib"][ok])
+        assert np.array_equal(Eg[v][ok].astype(np.int64), r["n_eval"][ok])
         # identity of the last blended Gaussian, from its list position
         H, W = Tg[v].shape
         jj, ii = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")

@@ -175,6 +175,7 @@ def test_vectorised_equals_scalar_brute_force(seed, deg, size):
     assert np.abs(rv["color"] - rb["color"]).max() < 1e-14
     assert np.abs(rv["T_final"] - rb["T_final"]).max() < 1e-15
     assert (rv["n_contrib"] == rb["n_contrib"]).all()
+    assert (rv["n_eval"] == rb["n_eval"]).all()
     assert (rv["last_g"] == rb["last_g"]).all()
     assert np.abs(rv["alpha_sum"] - rb["alpha_sum"]).max() < 1e-13
     assert rv["n_contrib"].max() >= 4
@@ -197,6 +198,7 @@ def test_soft_count_stops_with_the_walk():
     r = composite.render_view(pr)
     assert (1 - ALPHA_MAX) ** 2 < T_MIN
     assert r["n_contrib"][8, 8] == 1
+    assert r["n_eval"][8, 8] == 2          # the blended one and the one that stops the walk
     assert abs(r["alpha_sum"][8, 8] - ALPHA_MAX) < 1e-15
     rb = brute.render_image(pr)
     assert np.abs(r["alpha_sum"] - rb["alpha_sum"]).max() < 1e-13
