@@ -232,12 +232,14 @@ def serving_leg(n_arrivals, time_scale, slots):
     print(f"[bench] serving stream {st.name}: {n_arrivals} arrivals, prepared in {time.perf_counter() - t:.1f}s",
           file=sys.stderr, flush=True)
     out = {"workload": st.name, "arrivals": n_arrivals, "iterations_per_arrival": 200,
-           "time_scale": time_scale, "mean_interarrival_s": 2.0 * time_scale,
+           "time_scale": time_scale, "stream_mean_interarrival_s": 2.0, "mean_interarrival_s": 2.0 * time_scale,
            "initial_gaussians": int(st.initial.shape[1]),
            "loss": "Eq. 10: 0.47 L1 + 0.12 D-SSIM + 0.41 load balance (Eq. 9)", "lr": "Eq. 6-8, T_a = 200"}
+    from paper_2503_13086_amd.autotune import Autotuner
     for name, s in (("plain_loop", 1), ("continuous_batching", slots)):
         fld = Field(st.initial, st.sh_degree, capacity=st.initial.shape[1])
-        eng = Engine(fld, max_slots=s, t_i=200, seed=5, w_l1=0.47, w_dssim=0.12, w_load=0.41)
+        tuner = Autotuner(coarse=True)
+        eng = Engine(fld, max_slots=s, t_i=200, seed=5, w_l1=0.47, w_dssim=0.12, w_load=0.41, autotuner=tuner)
         t = time.perf_counter()
         done = [0]
 
@@ -250,6 +252,7 @@ def serving_leg(n_arrivals, time_scale, slots):
         stats = eng.run(st.arrivals, targets, time_scale=time_scale, on_job_done=progress)
         eng.close()
         out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in stats.summary().items()}
+        out[name]["tiles_chosen"] = {f"n<=2^{k[0]}": t for k, t in sorted(tuner.table.items())}
         print(f"[bench] serving {name}: {json.dumps(out[name])} ({time.perf_counter() - t:.1f}s)", file=sys.stderr,
               flush=True)
         del fld, eng
@@ -265,7 +268,7 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain-loop", action="store_true")
-    ap.add_argument("--serve-arrivals", type=int, default=60,
+    ap.add_argument("--serve-arrivals", type=int, default=200,
                     help="arrivals of the serving stream (0 skips the serving leg)")
     ap.add_argument("--serve-time-scale", type=float, default=0.1,
                     help="arrival times (Poisson, mean gap 2 s) are multiplied by this factor")

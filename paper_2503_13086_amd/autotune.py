@@ -23,16 +23,24 @@ from .pipeline import Rasterizer
 CANDIDATES = (8, 16, 32)
 
 
-def signature(n: int, sh_degree: int, cams: Sequence[dict]) -> Tuple:
-    sizes = tuple(sorted((int(c["width"]), int(c["height"])) for c in cams))
+def signature(n: int, sh_degree: int, cams: Sequence[dict], coarse: bool = False) -> Tuple:
+    """Workload key: field size rounded up to a power of two, SH degree and (unless
+    coarse) the multiset of view sizes."""
+    sizes = () if coarse else tuple(sorted((int(c["width"]), int(c["height"])) for c in cams))
     return (int(math.ceil(math.log2(max(n, 1)))), int(sh_degree), sizes)
 
 
 class Autotuner:
-    def __init__(self, candidates: Sequence[int] = CANDIDATES, warmup: int = 1, reps: int = 3):
+    """coarse: key on field size and SH degree only, timing the first step shape met
+    in each bucket (for loops whose batches change from step to step, where timing
+    every shape would cost more than it saves)."""
+
+    def __init__(self, candidates: Sequence[int] = CANDIDATES, warmup: int = 1, reps: int = 3,
+                 coarse: bool = False):
         self.candidates = tuple(candidates)
         self.warmup = warmup
         self.reps = reps
+        self.coarse = coarse
         self.table: Dict[Tuple, int] = {}
         self.timings: Dict[Tuple, Dict[int, float]] = {}
 
@@ -67,7 +75,7 @@ class Autotuner:
     def choose(self, rz: Rasterizer, params: torch.Tensor, n: int, sh_degree: int, cams: Sequence[dict],
                target: torch.Tensor, w_l1: float = 0.8, w_dssim: float = 0.2) -> int:
         """The fastest tile edge for this workload (timed once per signature)."""
-        key = signature(n, sh_degree, cams)
+        key = signature(n, sh_degree, cams, self.coarse)
         timed = key not in self.table
         if timed:
             t = {tile: self.time_tile(rz, tile, params, n, sh_degree, cams, target, w_l1, w_dssim)
@@ -85,4 +93,4 @@ class Autotuner:
         return best
 
     def last_timings(self, n: int, sh_degree: int, cams: Sequence[dict]) -> Optional[Dict[int, float]]:
-        return self.timings.get(signature(n, sh_degree, cams))
+        return self.timings.get(signature(n, sh_degree, cams, self.coarse))

@@ -148,7 +148,7 @@ class Engine:
     def __init__(self, fld: Field, *, max_slots: int = 8, hbm_budget: Optional[int] = None, t_i: int = 200,
                  n_m: int = 10, eta0: float = 1.6e-4, etaf: float = 1.6e-6, t_a: float = 200.0, w_l1: float = 0.8,
                  w_dssim: float = 0.2, w_load: float = 0.0, lr_group: Sequence[float] = DEFAULT_LR,
-                 group_mask: int = 1, seed: int = 0, rasterizer=None):
+                 group_mask: int = 1, seed: int = 0, rasterizer=None, autotuner=None):
         if not 1 <= max_slots <= 64:
             raise ValueError("max_slots must be in 1..64 (views per batched launch)")
         self.field = fld
@@ -161,6 +161,9 @@ class Engine:
         self.group_mask = group_mask
         self.rng = np.random.default_rng(seed)
         self.rz = rasterizer if rasterizer is not None else Rasterizer(fld.device.index or 0)
+        # tile edge per step shape (autotune.Autotuner: timed once per field-size bucket,
+        # SH degree and multiset of view sizes), or the rasterizer's edge when None
+        self.autotuner = autotuner
         self.cams: List[dict] = []
         self.targets: List[torch.Tensor] = []
         self.M = np.zeros((0, 0), np.float64)
@@ -251,6 +254,8 @@ class Engine:
             self._dl = torch.empty(P3, dtype=torch.float32, device=fld.device)
         color, dl = self._img[:P3], self._dl[:P3]
         target = torch.cat([self.targets[v] for v in views]) if len(views) > 1 else self.targets[views[0]]
+        if self.autotuner is not None:
+            self.autotuner.choose(rz, fld.params, fld.n, fld.sh_degree, cams, target, self.w_l1, self.w_dssim)
         rz.preprocess(fld.params, fld.n, fld.sh_degree)
         K = rz.bin_sort()
         rz.render_fwd(color)
