@@ -531,6 +531,8 @@ __device__ inline uint32_t wave_incl_scan(uint32_t x) {
 // ballots by the run's first lane.  Each entry also gets a 16-byte EmitInfo: its
 // rect and, when it has at most 64 candidates, the outcome of every test (bit i
 // for the rect's i-th tile, row-major), which is all emission then has to fetch.
+constexpr uint32_t kRedoMark = 1u << 31;
+
 __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restrict__ touched,
                                                           const ushort4* __restrict__ rect,
                                                           const Record* __restrict__ rec, size_t n_entries, int n,
@@ -546,7 +548,6 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
   __shared__ uint64_t s_bits[kWaves][64];
   __shared__ int s_own[kWaves][64];
   __shared__ CutoffGeoF s_geo[kWaves][64];    // fp32 clear-case geometry
-  __shared__ uint32_t s_redo[kWaves][64];     // the entry has a candidate the fp32 test cannot decide
   const int w = threadIdx.x / 64;
   const unsigned lane = __lane_id();
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -557,7 +558,6 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
   if (lane == 0) s_cp[w][0] = 0u;
   s_k[w][lane] = 0u;
   s_bits[w][lane] = 0ull;
-  s_redo[w][lane] = 0u;
   if (cand) {
     rc = rect[e];
     const ViewDev& cv = views[e / (size_t)n];
@@ -575,7 +575,7 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
     const int owner = round_owner(incl - cand, cand, cb, s_own[w], carry);
     carry = __builtin_amdgcn_readlane(owner, 63);
     int lo = 0;
-    bool pass = false, first = false;
+    bool pass = false, first = false, undecided = false;
     if (valid) {
       lo = owner;
       const uint32_t li = q - s_cp[w][lo];
@@ -587,27 +587,30 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
       const int W = (int)(wh & 0xffffu), H = (int)(wh >> 16);
       const int fast = exact_all ? -1 : tile_cutoff_fast(s_geo[w][lo], gx, gy, T, W, H);
       pass = fast > 0;
-      if (fast < 0) s_redo[w][lo] = 1u;   // decided by the exact pass
+      undecided = fast < 0;   // decided by the exact pass
     }
     const uint64_t fmask = __ballot(first);
     const uint64_t pmask = __ballot(pass);
+    const uint64_t umask = __ballot(undecided);
     if (first) {
       const uint64_t above = lane == 63 ? 0ull : (fmask & (~0ull << (lane + 1)));
       const unsigned next = above ? (unsigned)__builtin_ctzll(above) : 64u;
       const uint64_t run = (next == 64u ? ~0ull : ((1ull << next) - 1ull)) & (~0ull << lane);
-      s_k[w][lo] += (uint32_t)__popcll(pmask & run);
+      // the top bit flags an entry with an undecided candidate (counts stay below 2^31)
+      s_k[w][lo] = (s_k[w][lo] + (uint32_t)__popcll(pmask & run)) | ((umask & run) ? kRedoMark : 0u);
       if (s_cp[w][lo + 1] - s_cp[w][lo] <= 64u)   // the run's outcomes at their rect positions
         s_bits[w][lo] |= ((pmask & run) >> lane) << (q - s_cp[w][lo]);
     }
     __builtin_amdgcn_wave_barrier();
   }
   if (e < n_entries) {
-    kept[e] = s_k[w][lane];
+    const uint32_t k = s_k[w][lane];
+    kept[e] = k & ~kRedoMark;
     EmitInfo in;
     in.rect = rc;
     in.bits = s_bits[w][lane];
     info[e] = in;
-    if (s_redo[w][lane]) redo_list[atomicAdd(&st->redo_count, 1ull)] = (uint32_t)e;
+    if (k & kRedoMark) redo_list[atomicAdd(&st->redo_count, 1ull)] = (uint32_t)e;
   }
 }
 
@@ -1044,7 +1047,7 @@ hipError_t launch_count_redo(const uint32_t* touched, const ushort4* rect, const
                              uint32_t* redo_bits, size_t redo_cap, hipStream_t s) {
   // a fixed grid walks the list, whose length only the device knows (a few
   // thousandths of the entries at most in practice)
-  hipLaunchKernelGGL(k_count_redo, dim3(256), dim3(kThreads), 0, s, touched, rect, rec, n, views, tile, exact_all, P,
+  hipLaunchKernelGGL(k_count_redo, dim3(2048), dim3(kThreads), 0, s, touched, rect, rec, n, views, tile, exact_all, P,
                      stride, kept, info, st, redo_list, redo_bits, redo_cap);
   return hipGetLastError();
 }
