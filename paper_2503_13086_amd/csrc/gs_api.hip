@@ -110,8 +110,19 @@ gs_status hip_fail(gs_ctx* c, const char* what, hipError_t e) {
     if (e_ != hipSuccess) return hip_fail(c, #expr, e_); \
   } while (0)
 
+// True while `s` is being captured into a HIP graph.  Under capture nothing may be
+// allocated, waited for or copied from pageable state: the calls then require the
+// buffers a previous uncaptured step sized and report GS_ERR_STATE otherwise.
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive;
+}
+
 gs_status ensure(gs_ctx* c, DevBuf& b, size_t bytes, hipStream_t s) {
   if (bytes <= b.cap && b.p) return GS_OK;
+  if (capturing(s))
+    return fail(c, GS_ERR_STATE, "a context buffer would grow during stream capture: run one uncaptured step "
+                                 "with the same sizes first");
   if (b.p) {
     GS_HIP(c, hipStreamSynchronize(s));
     GS_HIP(c, hipFree(b.p));
@@ -147,7 +158,7 @@ struct Prof {
   hipStream_t s;
   hipEvent_t a = nullptr;
   Prof(gs_ctx* c_, int id_, hipStream_t s_) : c(c_), id(id_), s(s_) {
-    if (c->prof && (a = next_event(c))) (void)hipEventRecord(a, s);
+    if (c->prof && !capturing(s) && (a = next_event(c))) (void)hipEventRecord(a, s);
   }
   ~Prof() {
     if (!c->prof || !a) return;
@@ -333,6 +344,9 @@ gs_status gs_preprocess(gs_ctx* c, const float* params, int32_t n, int32_t strid
   const bool same_views = c->views_valid && (int32_t)c->hviews.size() == n_views &&
                           std::memcmp(c->hviews.data(), hv.data(), sizeof(ViewDev) * n_views) == 0;
   if (!same_views) {
+    if (capturing(s))
+      return fail(c, GS_ERR_STATE, "the views differ from the last gs_preprocess: run one uncaptured step with "
+                                   "these views before capturing");
     c->views_valid = false;
     if (c->views_ev_pending) GS_HIP(c, hipEventSynchronize(c->views_ev));
     std::memcpy(c->h_views, hv.data(), sizeof(ViewDev) * n_views);
@@ -362,9 +376,13 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
   GS_HIP(c, hipSetDevice(c->device));
   const size_t NV = (size_t)c->V * c->n;
   gs_status st;
+  const bool cap = capturing(s);
+  if (cap && (n_pairs_out != nullptr || c->pair_cap == 0))
+    return fail(c, GS_ERR_STATE, "gs_bin_sort cannot wait for K during stream capture (pass n_pairs_out = NULL "
+                                 "after an uncaptured binning)");
   // what an earlier binning found too small, if the stream has passed its check
   // (read without waiting; gs_sync_status reads it after waiting)
-  if (c->status_ev_pending && hipEventQuery(c->status_ev) == hipSuccess) {
+  if (!cap && c->status_ev_pending && hipEventQuery(c->status_ev) == hipSuccess) {
     absorb_status(c);
     c->status_ev_pending = false;
   }
@@ -449,8 +467,12 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
   }
   if ((st = ensure(c, c->ranges, (size_t)c->n_tiles * 8, s)) != GS_OK) return st;
   GS_HIP(c, launch_check_pairs(dst, c->d_mirror, c->pair_cap, s));
-  GS_HIP(c, hipEventRecord(c->status_ev, s));
-  c->status_ev_pending = true;
+  if (!cap) {
+    GS_HIP(c, hipEventRecord(c->status_ev, s));
+    c->status_ev_pending = true;
+  } else {
+    c->status_ev_pending = false;   // gs_sync_status waits for the stream before reading the mirror
+  }
   const unsigned long long* n_eff = &dst->n_eff;
   // grids for K when the host knows it, else for the capacity (the kernels read the
   // count on the device either way, so a failed check sorts nothing)
