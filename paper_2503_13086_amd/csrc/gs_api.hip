@@ -76,6 +76,7 @@ struct gs_ctx {
   DevBuf pkey[2], pval[2], ranges;
   DevBuf tfinal, ncontrib, last, grad2d, lossp, aux, evals;
   bool evals_ok = false;           // evals holds gs_render_count's counts for the current binning
+  bool status_fresh = false;       // the status was cleared by the last gs_preprocess and not used since
   DevBuf asum, dG, loadp, loadst, kept, emitinfo, redo_list, redo_bits, status;
   DevStatus* h_status = nullptr;   // host mirror of the device status, written by the binning's last check
   DevStatus* d_mirror = nullptr;   // its device-side address
@@ -359,8 +360,10 @@ gs_status gs_preprocess(gs_ctx* c, const float* params, int32_t n, int32_t strid
   {
     Prof pr(c, GS_K_PREPROCESS, s);
     GS_HIP(c, launch_preprocess(params, n, stride, sh_degree, c->views.as<ViewDev>(), n_views, c->rec.as<Record>(),
-                                c->depth.as<uint32_t>(), c->touched.as<uint32_t>(), c->rect.as<ushort4>(), s));
+                                c->depth.as<uint32_t>(), c->touched.as<uint32_t>(), c->rect.as<ushort4>(),
+                                c->status.as<DevStatus>(), s));
   }
+  c->status_fresh = true;   // the projection cleared the binning status
   c->n = n; c->stride = stride; c->D = sh_degree; c->V = n_views; c->params = params;
   c->hviews = hv; c->n_tiles = n_tiles; c->tile = tile; c->P = P; c->K = 0;
   c->stage = kProjected;
@@ -394,7 +397,8 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
   if ((st = ensure(c, c->blocksums, scan_block_words(NV) * 4, s)) != GS_OK) return st;
   if ((st = ensure(c, c->hist, sort_hist_words(NV > c->pair_cap ? NV : c->pair_cap) * 4, s)) != GS_OK) return st;
   DevStatus* dst = c->status.as<DevStatus>();
-  GS_HIP(c, launch_status_reset(dst, s));
+  if (!c->status_fresh) GS_HIP(c, launch_status_reset(dst, s));
+  c->status_fresh = false;
   const bool cull = c->cull != GS_CULL_RECT;
   const int exact_all = c->cull == GS_CULL_ELLIPSE_EXACT ? 1 : 0;
   // pairs per entry: the rect's tiles, or with culling the tiles whose pixel-centre
@@ -415,7 +419,7 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
     GS_HIP(c, launch_count_kept(c->touched.as<uint32_t>(), c->rect.as<ushort4>(), c->rec.as<Record>(), NV, c->n,
                                 c->views.as<ViewDev>(), c->tile, exact_all, c->kept.as<uint32_t>(),
                                 c->emitinfo.as<EmitInfo>(), dst, c->redo_list.as<uint32_t>(), s));
-    GS_HIP(c, launch_count_redo(c->touched.as<uint32_t>(), c->rect.as<ushort4>(), c->rec.as<Record>(), c->n,
+    GS_HIP(c, launch_count_redo(c->touched.as<uint32_t>(), c->rect.as<ushort4>(), c->rec.as<Record>(), NV, c->n,
                                 c->views.as<ViewDev>(), c->tile, exact_all, c->params, c->stride,
                                 c->kept.as<uint32_t>(), c->emitinfo.as<EmitInfo>(), dst, c->redo_list.as<uint32_t>(),
                                 c->redo_bits.as<uint32_t>(), c->redo_cap, s));
@@ -433,16 +437,37 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
     c->depth_in_b = 0;
   }
   const uint32_t* order = c->dval[c->depth_in_b].as<uint32_t>();
-  {
-    Prof pr(c, GS_K_SCAN, s);
-    GS_HIP(c, launch_scan_touched(order, packed ? 1 : 0, per_entry, NV, c->groupsums.as<uint32_t>(),
-                                  c->blocksums.as<uint32_t>(), &dst->n_pairs, s));
-  }
   // The pair buffers are sized from K itself when the caller asks for K, on a
   // context's first binning, and after a binning that found them too small;
-  // otherwise K stays on the device and the kernels below read it there.
+  // otherwise K stays on the device and the kernels below read it there.  Without
+  // a wait the capacity is fixed before the scan, which checks K against it.
   const bool wait = n_pairs_out != nullptr || c->pair_cap == 0;
-  size_t want = 0;
+  auto grow_pairs = [&](size_t want) -> gs_status {
+    gs_status g;
+    for (int i = 0; i < 2; ++i) {
+      if ((g = ensure(c, c->pkey[i], want * 4 + 4, s)) != GS_OK) return g;
+      if ((g = ensure(c, c->pval[i], want * 4 + 4, s)) != GS_OK) return g;
+    }
+    size_t held = c->pkey[0].cap;
+    for (DevBuf* b : {&c->pkey[1], &c->pval[0], &c->pval[1]}) held = b->cap < held ? b->cap : held;
+    c->pair_cap = held / 4 - 1;
+    c->pair_want = 0;
+    return ensure(c, c->hist, sort_hist_words(NV > c->pair_cap ? NV : c->pair_cap) * 4, s);
+  };
+  if (!wait && c->pair_want > c->pair_cap && (st = grow_pairs(c->pair_want)) != GS_OK) return st;
+  if ((st = ensure(c, c->ranges, (size_t)c->n_tiles * 8, s)) != GS_OK) return st;
+  {
+    Prof pr(c, GS_K_SCAN, s);
+    // with a wait the buffers grow to K before anything reads them: no cap here
+    GS_HIP(c, launch_scan_touched(order, packed ? 1 : 0, per_entry, NV, c->groupsums.as<uint32_t>(),
+                                  c->blocksums.as<uint32_t>(), dst, c->d_mirror, wait ? ~0ull : c->pair_cap, s));
+  }
+  if (!cap) {
+    GS_HIP(c, hipEventRecord(c->status_ev, s));
+    c->status_ev_pending = true;
+  } else {
+    c->status_ev_pending = false;   // gs_sync_status waits for the stream before reading the mirror
+  }
   c->K_known = false;
   if (wait) {
     GS_HIP(c, hipMemcpyAsync(c->h_total, &dst->n_pairs, 8, hipMemcpyDeviceToHost, s));
@@ -451,27 +476,8 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
     if (K >= (1ull << 32)) return fail(c, GS_ERR_CAPACITY, "more than 2^32 - 1 (tile, Gaussian) pairs");
     c->K = K;
     c->K_known = true;
-    want = (size_t)K;
-  }
-  if (c->pair_want > want) want = c->pair_want;
-  if (want > c->pair_cap || c->pair_cap == 0) {
-    for (int i = 0; i < 2; ++i) {
-      if ((st = ensure(c, c->pkey[i], want * 4 + 4, s)) != GS_OK) return st;
-      if ((st = ensure(c, c->pval[i], want * 4 + 4, s)) != GS_OK) return st;
-    }
-    size_t cap = c->pkey[0].cap;
-    for (DevBuf* b : {&c->pkey[1], &c->pval[0], &c->pval[1]}) cap = b->cap < cap ? b->cap : cap;
-    c->pair_cap = cap / 4 - 1;
-    c->pair_want = 0;
-    if ((st = ensure(c, c->hist, sort_hist_words(NV > c->pair_cap ? NV : c->pair_cap) * 4, s)) != GS_OK) return st;
-  }
-  if ((st = ensure(c, c->ranges, (size_t)c->n_tiles * 8, s)) != GS_OK) return st;
-  GS_HIP(c, launch_check_pairs(dst, c->d_mirror, c->pair_cap, s));
-  if (!cap) {
-    GS_HIP(c, hipEventRecord(c->status_ev, s));
-    c->status_ev_pending = true;
-  } else {
-    c->status_ev_pending = false;   // gs_sync_status waits for the stream before reading the mirror
+    size_t want = (size_t)K > c->pair_want ? (size_t)K : c->pair_want;
+    if ((want > c->pair_cap || c->pair_cap == 0) && (st = grow_pairs(want)) != GS_OK) return st;
   }
   const unsigned long long* n_eff = &dst->n_eff;
   // grids for K when the host knows it, else for the capacity (the kernels read the

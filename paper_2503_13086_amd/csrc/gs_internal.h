@@ -163,13 +163,24 @@ struct DevStatus {
 // pass stored: this flag | the first of its words in the outcome array.
 constexpr uint64_t kRedoFlag = 1ull << 63;
 
+__device__ inline void status_clear(DevStatus* st) {
+  st->code = GS_OK;
+  st->pad = 0u;
+  st->n_pairs = 0ull;
+  st->n_eff = 0ull;
+  st->need_pairs = 0ull;
+  st->redo_count = 0ull;
+  st->redo_words = 0ull;
+  st->need_redo = 0ull;
+}
+
 __device__ inline void status_fail(DevStatus* st, int32_t code) {
   atomicCAS(&st->code, (int32_t)GS_OK, code);
 }
 
 // ---- launchers (each file defines its own) ----
 hipError_t launch_preprocess(const float* P, int n, int stride, int D, const ViewDev* views, int V,
-                             Record* rec, uint32_t* depth, uint32_t* touched, ushort4* rect,
+                             Record* rec, uint32_t* depth, uint32_t* touched, ushort4* rect, DevStatus* st,
                              hipStream_t s);
 hipError_t launch_preprocess_bwd(const float* P, int n, int stride, int D, const ViewDev* views, int V,
                                  const uint32_t* touched, const float* grad2d, float* grad, int accumulate,
@@ -204,12 +215,16 @@ constexpr uint32_t kPackRidMask = 0x00ffffffu;
 
 // Scan of the depth-ordered counts touched[order[e]]: group_sums[g] = sum over the
 // 64 entries [64 g, 64 g + 64) (scan_group_words(n) words), block_sums[b] = the
-// exclusive prefix at entry 4096 b (scan_block_words(n) words), *total = the sum
+// exclusive prefix at entry 4096 b (scan_block_words(n) words); the total K goes to
+// st->n_pairs and is checked against the pair capacity: n_eff = K if K <= cap, K <
+// 2^32 and no earlier failure, else 0 (GS_ERR_CAPACITY with need_pairs = K when K
+// does not fit); then the status is copied to `mirror` (host-visible memory).
 // (packed != 0: order entries come from radix_sort_depth with counts)
 size_t scan_block_words(size_t n);
 inline size_t scan_group_words(size_t n) { return (n + 63) / 64; }
 hipError_t launch_scan_touched(const uint32_t* order, int packed, const uint32_t* touched, size_t n,
-                               uint32_t* group_sums, uint32_t* block_sums, unsigned long long* total, hipStream_t s);
+                               uint32_t* group_sums, uint32_t* block_sums, DevStatus* st, DevStatus* mirror,
+                               unsigned long long cap, hipStream_t s);
 // kept[e] = tiles of entry e's rect whose pixel-centre box meets its cutoff region
 // (entries in index order; rect tile count in touched)
 // What emission fetches per culled entry: its tile rect and, for rects of at most
@@ -229,15 +244,13 @@ struct alignas(16) EmitInfo {
 hipError_t launch_count_kept(const uint32_t* touched, const ushort4* rect, const Record* rec, size_t n_entries, int n,
                              const ViewDev* views, int tile, int exact_all, uint32_t* kept, EmitInfo* info,
                              DevStatus* st, uint32_t* redo_list, hipStream_t s);
-hipError_t launch_count_redo(const uint32_t* touched, const ushort4* rect, const Record* rec, int n,
+hipError_t launch_count_redo(const uint32_t* touched, const ushort4* rect, const Record* rec, size_t n_entries, int n,
                              const ViewDev* views, int tile, int exact_all, const float* P, int stride,
                              uint32_t* kept, EmitInfo* info, DevStatus* st, const uint32_t* redo_list,
                              uint32_t* redo_bits, size_t redo_cap, hipStream_t s);
+// Clears the status (the projection also clears it, so a binning right after a
+// gs_preprocess needs no reset launch).
 hipError_t launch_status_reset(DevStatus* st, hipStream_t s);
-// K against the pair capacity: n_eff = K if K <= cap and K < 2^32, else 0 and
-// GS_ERR_CAPACITY with need_pairs = K; then the status is copied to `mirror`
-// (host-visible memory).
-hipError_t launch_check_pairs(DevStatus* st, DevStatus* mirror, size_t cap, hipStream_t s);
 // pairs of the depth-ordered entries order[0..n_entries): touched, group_sums and
 // block_sums as scanned by launch_scan_touched; cull != 0 keeps only the rect tiles
 // that meet the cutoff region (touched must then be the kept counts); writes only

@@ -113,10 +113,13 @@ __device__ inline void camera_dir_f(const float m[3], const ViewDev& V, float di
 }
 
 template <int D>
+// st (may be NULL): the binning status, cleared here for the binning that follows.
 __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ P, int n, int stride,
                                                      const ViewDev* __restrict__ views, int V,
                                                      Record* __restrict__ rec, uint32_t* __restrict__ depth,
-                                                     uint32_t* __restrict__ touched, ushort4* __restrict__ rect) {
+                                                     uint32_t* __restrict__ touched, ushort4* __restrict__ rect,
+                                                     DevStatus* __restrict__ st) {
+  if (st && blockIdx.x == 0 && threadIdx.x == 0) status_clear(st);
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   Gauss G;
@@ -429,13 +432,13 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, size_t coun
 }  // namespace
 
 hipError_t launch_preprocess(const float* P, int n, int stride, int D, const ViewDev* views, int V, Record* rec,
-                             uint32_t* depth, uint32_t* touched, ushort4* rect, hipStream_t s) {
+                             uint32_t* depth, uint32_t* touched, ushort4* rect, DevStatus* st, hipStream_t s) {
   const int blocks = (n + 255) / 256;
   switch (D) {
-    case 0: hipLaunchKernelGGL(k_preprocess<0>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, rec, depth, touched, rect); break;
-    case 1: hipLaunchKernelGGL(k_preprocess<1>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, rec, depth, touched, rect); break;
-    case 2: hipLaunchKernelGGL(k_preprocess<2>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, rec, depth, touched, rect); break;
-    default: hipLaunchKernelGGL(k_preprocess<3>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, rec, depth, touched, rect); break;
+    case 0: hipLaunchKernelGGL(k_preprocess<0>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, rec, depth, touched, rect, st); break;
+    case 1: hipLaunchKernelGGL(k_preprocess<1>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, rec, depth, touched, rect, st); break;
+    case 2: hipLaunchKernelGGL(k_preprocess<2>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, rec, depth, touched, rect, st); break;
+    default: hipLaunchKernelGGL(k_preprocess<3>, dim3(blocks), dim3(256), 0, s, P, n, stride, views, V, rec, depth, touched, rect, st); break;
   }
   return hipGetLastError();
 }

@@ -447,8 +447,36 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t* __rest
 }
 
 // single workgroup: exclusive scan of block sums in 64-bit, total to *total
+// Besides the scan: the binning's capacity check on the total K (thread 0, once
+// every block sum is in), which also copies the status into the host-visible
+// mirror; the host reads it once the stream has passed this point (see
+// check_pairs).
+__device__ inline void check_pairs(DevStatus* __restrict__ st, DevStatus* __restrict__ mirror,
+                                   unsigned long long K, unsigned long long cap) {
+  st->n_pairs = K;
+  if (K > cap || K >= (1ull << 32)) {
+    st->n_eff = 0ull;
+    st->need_pairs = K;
+    status_fail(st, GS_ERR_CAPACITY);
+  } else {
+    // an earlier failure (the exact pass's outcome store too small) leaves counts
+    // the emission could not reproduce: then no pair is emitted either
+    st->n_eff = st->code == GS_OK ? K : 0ull;
+  }
+  mirror->n_pairs = K;
+  mirror->n_eff = st->n_eff;
+  mirror->need_pairs = st->need_pairs;
+  mirror->redo_count = st->redo_count;
+  mirror->redo_words = st->redo_words;
+  mirror->need_redo = st->need_redo;
+  mirror->pad = 0u;
+  __threadfence_system();
+  mirror->code = st->code;
+}
+
 __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t* __restrict__ block_sums, int nb,
-                                                       unsigned long long* __restrict__ total) {
+                                                       DevStatus* __restrict__ st, DevStatus* __restrict__ mirror,
+                                                       unsigned long long cap) {
   __shared__ unsigned long long wsum[16];
   __shared__ unsigned long long carry;
   if (threadIdx.x == 0) carry = 0;
@@ -471,7 +499,7 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t* __restrict__ blo
     if (threadIdx.x == 1023) carry = c + wpre + incl;
     __syncthreads();
   }
-  if (threadIdx.x == 0) *total = carry;
+  if (threadIdx.x == 0) check_pairs(st, mirror, carry, cap);
 }
 
 // Inclusive max over lanes 0..l (DPP: shifts within rows of 16 lanes, then the
@@ -686,41 +714,8 @@ __global__ __launch_bounds__(kThreads) void k_count_redo(const uint32_t* __restr
   }
 }
 
-__global__ void k_status_reset(DevStatus* __restrict__ st) {
-  st->code = GS_OK;
-  st->pad = 0u;
-  st->n_pairs = 0ull;
-  st->n_eff = 0ull;
-  st->need_pairs = 0ull;
-  st->redo_count = 0ull;
-  st->redo_words = 0ull;
-  st->need_redo = 0ull;
-}
+__global__ void k_status_reset(DevStatus* __restrict__ st) { status_clear(st); }
 
-// The binning's last status word: checks K against the pair capacity and copies
-// the whole status into the host-visible mirror, which the host reads once the
-// stream has passed this point (without waiting for it).
-__global__ void k_check_pairs(DevStatus* __restrict__ st, DevStatus* __restrict__ mirror, unsigned long long cap) {
-  const unsigned long long K = st->n_pairs;
-  if (K > cap || K >= (1ull << 32)) {
-    st->n_eff = 0ull;
-    st->need_pairs = K;
-    status_fail(st, GS_ERR_CAPACITY);
-  } else {
-    // an earlier failure (the exact pass's outcome store too small) leaves counts
-    // the emission could not reproduce: then no pair is emitted either
-    st->n_eff = st->code == GS_OK ? K : 0ull;
-  }
-  mirror->n_pairs = K;
-  mirror->n_eff = st->n_eff;
-  mirror->need_pairs = st->need_pairs;
-  mirror->redo_count = st->redo_count;
-  mirror->redo_words = st->redo_words;
-  mirror->need_redo = st->need_redo;
-  mirror->pad = 0u;
-  __threadfence_system();
-  mirror->code = st->code;
-}
 
 // Pair emission, one wave per 64 consecutive depth-ordered entries.  The wave's
 // pairs occupy one contiguous output range.  Its candidates (rect tiles of its
@@ -1011,11 +1006,12 @@ hipError_t radix_sort_depth(const uint32_t* depth, const uint32_t* count, uint32
 size_t scan_block_words(size_t n) { return (n + kScanItems - 1) / kScanItems + 1; }
 
 hipError_t launch_scan_touched(const uint32_t* order, int packed, const uint32_t* touched, size_t n,
-                               uint32_t* group_sums, uint32_t* block_sums, unsigned long long* total, hipStream_t s) {
+                               uint32_t* group_sums, uint32_t* block_sums, DevStatus* st, DevStatus* mirror,
+                               unsigned long long cap, hipStream_t s) {
   const int nb = (int)((n + kScanItems - 1) / kScanItems);
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, s, order, touched, n, packed, group_sums,
                      block_sums);
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, block_sums, nb, total);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, block_sums, nb, st, mirror, cap);
   return hipGetLastError();
 }
 
@@ -1041,13 +1037,22 @@ hipError_t launch_count_kept(const uint32_t* touched, const ushort4* rect, const
   return hipGetLastError();
 }
 
-hipError_t launch_count_redo(const uint32_t* touched, const ushort4* rect, const Record* rec, int n,
+// Workgroups of the exact pass: one wave per 2048 entries, 16 to 2048 workgroups
+// (the listed entries are a few thousandths of the candidates; the grid-stride
+// loop covers any number).
+inline unsigned redo_blocks(size_t n_entries) {
+  const size_t b = (n_entries + 2048 * kWaves - 1) / (2048 * kWaves);
+  return (unsigned)(b < 16 ? 16 : (b > 2048 ? 2048 : b));
+}
+
+hipError_t launch_count_redo(const uint32_t* touched, const ushort4* rect, const Record* rec, size_t n_entries, int n,
                              const ViewDev* views, int tile, int exact_all, const float* P, int stride,
                              uint32_t* kept, EmitInfo* info, DevStatus* st, const uint32_t* redo_list,
                              uint32_t* redo_bits, size_t redo_cap, hipStream_t s) {
   // a fixed grid walks the list, whose length only the device knows (a few
   // thousandths of the entries at most in practice)
-  hipLaunchKernelGGL(k_count_redo, dim3(2048), dim3(kThreads), 0, s, touched, rect, rec, n, views, tile, exact_all, P,
+  hipLaunchKernelGGL(k_count_redo, dim3(redo_blocks(n_entries)), dim3(kThreads), 0, s, touched, rect, rec, n, views,
+                     tile, exact_all, P,
                      stride, kept, info, st, redo_list, redo_bits, redo_cap);
   return hipGetLastError();
 }
@@ -1057,10 +1062,6 @@ hipError_t launch_status_reset(DevStatus* st, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_check_pairs(DevStatus* st, DevStatus* mirror, size_t cap, hipStream_t s) {
-  hipLaunchKernelGGL(k_check_pairs, dim3(1), dim3(1), 0, s, st, mirror, (unsigned long long)cap);
-  return hipGetLastError();
-}
 
 hipError_t launch_ranges(const uint32_t* pair_tile, size_t K_cap, const unsigned long long* n_dev, uint2* ranges,
                          int n_tiles, hipStream_t s) {
