@@ -78,6 +78,7 @@ struct gs_ctx {
   bool evals_ok = false;           // evals holds gs_render_count's counts for the current binning
   bool status_fresh = false;       // the status was cleared by the last gs_preprocess and not used since
   DevBuf asum, dG, loadp, loadst, kept, emitinfo, redo_list, redo_bits, status;
+  DevBuf split_ents, split_items;  // large entries handed to the binning's chunk passes
   DevStatus* h_status = nullptr;   // host mirror of the device status, written by the binning's last check
   DevStatus* d_mirror = nullptr;   // its device-side address
   bool load_pending = false;   // dG holds a load-balancing gradient for the current forward
@@ -141,7 +142,7 @@ std::vector<DevBuf*> all_bufs(gs_ctx* c) {
           &c->dval[1], &c->groupsums, &c->blocksums, &c->total, &c->hist, &c->pkey[0],
           &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->tfinal, &c->ncontrib, &c->last,
           &c->grad2d, &c->lossp, &c->aux, &c->evals, &c->asum, &c->dG, &c->loadp, &c->loadst, &c->kept, &c->emitinfo,
-          &c->redo_list, &c->redo_bits, &c->status};
+          &c->redo_list, &c->redo_bits, &c->status, &c->split_ents, &c->split_items};
 }
 
 hipEvent_t next_event(gs_ctx* c) {
@@ -275,13 +276,13 @@ gs_status gs_create(gs_ctx** out, int32_t device) {
       hipHostGetDevicePointer((void**)&c->d_mirror, c->h_status, 0) != hipSuccess ||
       hipEventCreateWithFlags(&c->views_ev, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->status_ev, hipEventDisableTiming) != hipSuccess ||
-      hipMalloc(&c->status.p, sizeof(DevStatus)) != hipSuccess ||
-      hipMemset(c->status.p, 0, sizeof(DevStatus)) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+      hipMalloc(&c->status.p, kStatusAllocBytes) != hipSuccess ||
+      hipMemset(c->status.p, 0, kStatusAllocBytes) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
       !scratch_setup(device)) {
     gs_destroy(c);
     return GS_ERR_HIP;
   }
-  c->status.cap = sizeof(DevStatus);
+  c->status.cap = kStatusAllocBytes;
   std::memset(c->h_status, 0, sizeof(DevStatus));
   *out = c;
   return GS_OK;
@@ -405,6 +406,9 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
   // box meets the cutoff region (counted in index order, coalesced; the candidates
   // the fp32 test cannot decide go to the exact pass)
   const uint32_t* per_entry = c->touched.as<uint32_t>();
+  if ((st = ensure(c, c->split_items, kSplitLists * split_item_cap(NV) * sizeof(uint2), s)) != GS_OK) return st;
+  if ((st = ensure(c, c->split_ents, kSplitLists * split_entry_cap(NV) * sizeof(SplitEntry), s)) != GS_OK)
+    return st;
   if (cull) {
     Prof pr(c, GS_K_SCAN, s);
     if ((st = ensure(c, c->kept, NV * 4, s)) != GS_OK) return st;
@@ -418,8 +422,9 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
     }
     GS_HIP(c, launch_count_kept(c->touched.as<uint32_t>(), c->rect.as<ushort4>(), c->rec.as<Record>(), NV, c->n,
                                 c->views.as<ViewDev>(), c->tile, exact_all, c->kept.as<uint32_t>(),
-                                c->emitinfo.as<EmitInfo>(), dst, c->redo_list.as<uint32_t>(), s));
-    GS_HIP(c, launch_count_redo(c->touched.as<uint32_t>(), c->rect.as<ushort4>(), c->rec.as<Record>(), NV, c->n,
+                                c->emitinfo.as<EmitInfo>(), dst, c->redo_list.as<uint32_t>(),
+                                c->split_items.as<uint2>(), s));
+    GS_HIP(c, launch_count_redo(c->touched.as<uint32_t>(), c->rect.as<ushort4>(), c->rec.as<Record>(), c->n,
                                 c->views.as<ViewDev>(), c->tile, exact_all, c->params, c->stride,
                                 c->kept.as<uint32_t>(), c->emitinfo.as<EmitInfo>(), dst, c->redo_list.as<uint32_t>(),
                                 c->redo_bits.as<uint32_t>(), c->redo_cap, s));
@@ -489,8 +494,9 @@ gs_status gs_bin_sort(gs_ctx* c, int64_t* n_pairs_out, gs_stream stream) {
                                 c->blocksums.as<uint32_t>(), c->rect.as<ushort4>(), c->rec.as<Record>(), NV, c->n,
                                 c->views.as<ViewDev>(), dst, cull ? 1 : 0, c->tile,
                                 cull ? c->emitinfo.as<EmitInfo>() : nullptr,
-                                cull ? c->redo_bits.as<uint32_t>() : nullptr, c->pkey[0].as<uint32_t>(),
-                                c->pval[0].as<uint32_t>(), s));
+                                cull ? c->redo_bits.as<uint32_t>() : nullptr, c->split_ents.as<SplitEntry>(),
+                                c->split_items.as<uint2>(), c->pkey[0].as<uint32_t>(), c->pval[0].as<uint32_t>(),
+                                s));
   }
   {
     Prof pr(c, GS_K_TILE_SORT, s);

@@ -234,6 +234,46 @@ struct alignas(16) EmitInfo {
   ushort4 rect;
   uint64_t bits;
 };
+// Work split for entries with large rects (near the camera, where the depth order
+// puts them side by side).  A wave whose 64 entries have more than kSplitWave
+// candidates in all hands its largest entries (those above the threshold that
+// leaves it at most kSplitWave candidates, or all of more than 64) to a chunk pass
+// instead of walking their rects itself: one item (entry, first candidate) per
+// kChunk candidates, so a large rect is spread over many waves.  Items go to one
+// of kSplitLists lists (by wave index), each with its own counter on its own
+// 128-byte line, so heavy waves do not queue on one address; slot k of list l is
+// items[l * cap + k] (x = entry, or the SplitEntry slot for the emission; y =
+// first candidate; x = ~0 for a slot a full list left unused).  A full list
+// leaves the entry with its wave.
+constexpr uint32_t kSplitWave = 2048u;
+constexpr uint32_t kChunk = 512u;
+constexpr int kSplitLists = 64;
+constexpr int kSplitCtrStride = 16;   // counters 16 x 8 bytes apart
+// The counters sit after the status word in the same allocation: three sets of
+// kSplitLists (the count's items, the emission's entries and its items).
+constexpr size_t kStatusBytes = 256;
+static_assert(sizeof(DevStatus) <= kStatusBytes, "status word");
+constexpr size_t kStatusAllocBytes = kStatusBytes + 3 * kSplitLists * kSplitCtrStride * 8;
+enum SplitSet { kSplitCountItems = 0, kSplitEmitEnts = 1, kSplitEmitItems = 2 };
+__device__ inline unsigned long long* split_ctr(DevStatus* st, int set, int list) {
+  return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(st) + kStatusBytes) +
+         (size_t)(set * kSplitLists + list) * kSplitCtrStride;
+}
+// Clears the counters (the calling workgroup's threads share the stores).
+__device__ inline void split_clear(DevStatus* st) {
+  for (int i = (int)threadIdx.x; i < 3 * kSplitLists; i += (int)blockDim.x)
+    *split_ctr(st, i / kSplitLists, i % kSplitLists) = 0ull;
+}
+// An entry whose pairs the emission's chunk pass writes: its output range starts
+// at `base`; `ctr` counts the pairs written so far (chunks take their slots in the
+// range with atomics: within one entry's range the order does not matter, since
+// its pairs go to distinct tiles and the tile sort is stable).
+struct alignas(16) SplitEntry {
+  uint32_t rid, base, ctr, pad;
+};
+// slots per list (in all about one item per 16 entries and one split entry per 64)
+inline size_t split_item_cap(size_t n_entries) { return n_entries / (16 * kSplitLists) + 256; }
+inline size_t split_entry_cap(size_t n_entries) { return n_entries / (64 * kSplitLists) + 64; }
 // Entries where the fp32 test leaves some candidate undecided are counted without
 // those candidates and listed in redo_list (count in st->redo_count); the exact
 // pass launch_count_redo then recomputes their FP64 conic and cutoff from the
@@ -241,10 +281,12 @@ struct alignas(16) EmitInfo {
 // candidates: kRedoFlag | offset of their outcome bits in redo_bits, which holds
 // redo_cap words; beyond that st reports GS_ERR_CAPACITY).
 // exact_all != 0: no candidate is decided by the fp32 test (every test in FP64).
+// Entries split into chunk items (items: kSplitLists * split_item_cap(n_entries)
+// slots) are counted by a chunk pass in the same call.
 hipError_t launch_count_kept(const uint32_t* touched, const ushort4* rect, const Record* rec, size_t n_entries, int n,
                              const ViewDev* views, int tile, int exact_all, uint32_t* kept, EmitInfo* info,
-                             DevStatus* st, uint32_t* redo_list, hipStream_t s);
-hipError_t launch_count_redo(const uint32_t* touched, const ushort4* rect, const Record* rec, size_t n_entries, int n,
+                             DevStatus* st, uint32_t* redo_list, uint2* items, hipStream_t s);
+hipError_t launch_count_redo(const uint32_t* touched, const ushort4* rect, const Record* rec, int n,
                              const ViewDev* views, int tile, int exact_all, const float* P, int stride,
                              uint32_t* kept, EmitInfo* info, DevStatus* st, const uint32_t* redo_list,
                              uint32_t* redo_bits, size_t redo_cap, hipStream_t s);
@@ -254,12 +296,14 @@ hipError_t launch_status_reset(DevStatus* st, hipStream_t s);
 // pairs of the depth-ordered entries order[0..n_entries): touched, group_sums and
 // block_sums as scanned by launch_scan_touched; cull != 0 keeps only the rect tiles
 // that meet the cutoff region (touched must then be the kept counts); writes only
-// below st->n_eff pairs
+// below st->n_eff pairs.  Entries split into chunk items (ents: kSplitLists *
+// split_entry_cap(n_entries) slots, items: kSplitLists * split_item_cap(n_entries))
+// are emitted by a chunk pass in the same call.
 hipError_t launch_emit_pairs(const uint32_t* order, int packed, const uint32_t* touched, const uint32_t* group_sums,
                              const uint32_t* block_off, const ushort4* rect, const Record* rec, size_t n_entries,
-                             int n, const ViewDev* views, const DevStatus* st, int cull, int tile,
-                             const EmitInfo* info, const uint32_t* redo_bits, uint32_t* pair_tile, uint32_t* pair_rec,
-                             hipStream_t s);
+                             int n, const ViewDev* views, DevStatus* st, int cull, int tile,
+                             const EmitInfo* info, const uint32_t* redo_bits, SplitEntry* ents, uint2* items,
+                             uint32_t* pair_tile, uint32_t* pair_rec, hipStream_t s);
 // ranges of the first min(*n_dev, K_cap) sorted pairs (all K_cap without n_dev)
 hipError_t launch_ranges(const uint32_t* pair_tile, size_t K_cap, const unsigned long long* n_dev, uint2* ranges,
                          int n_tiles, hipStream_t s);

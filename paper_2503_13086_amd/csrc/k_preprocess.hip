@@ -113,13 +113,17 @@ __device__ inline void camera_dir_f(const float m[3], const ViewDev& V, float di
 }
 
 template <int D>
-// st (may be NULL): the binning status, cleared here for the binning that follows.
+// st (may be NULL): the binning status and the split counters after it, cleared
+// here for the binning that follows.
 __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ P, int n, int stride,
                                                      const ViewDev* __restrict__ views, int V,
                                                      Record* __restrict__ rec, uint32_t* __restrict__ depth,
                                                      uint32_t* __restrict__ touched, ushort4* __restrict__ rect,
                                                      DevStatus* __restrict__ st) {
-  if (st && blockIdx.x == 0 && threadIdx.x == 0) status_clear(st);
+  if (st && blockIdx.x == 0) {
+    if (threadIdx.x == 0) status_clear(st);
+    split_clear(st);
+  }
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   Gauss G;

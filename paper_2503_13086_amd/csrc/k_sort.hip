@@ -553,6 +553,26 @@ __device__ inline uint32_t wave_incl_scan(uint32_t x) {
   return x;
 }
 
+// Wave-wide counter update: lane 0 adds `total` to *ctr; every lane gets the old
+// value (0 and no update when total is 0).
+__device__ inline unsigned long long wave_take(unsigned long long* ctr, uint32_t total) {
+  unsigned long long o = 0ull;
+  if (total != 0u && __lane_id() == 0u) o = atomicAdd(ctr, (unsigned long long)total);
+  return (unsigned long long)__shfl((long long)o, 0);
+}
+
+// The split rule of a heavy wave (more than kSplitWave candidates): the largest
+// threshold t (64 doubled up to 8192) that leaves at most kSplitWave candidates
+// to the entries of at most t; the entries above it go to the chunk pass.  (64 if
+// none does: entries of at most 64 candidates always stay with their wave.)
+__device__ inline uint32_t split_threshold(uint32_t cand) {
+  for (uint32_t t = 8192u; t > 64u; t >>= 1) {
+    const uint32_t rem = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(cand <= t ? cand : 0u), 63);
+    if (rem <= kSplitWave) return t;
+  }
+  return 64u;
+}
+
 // Kept pairs per entry (index order, coalesced reads): the tiles of the entry's
 // rect whose pixel-centre box meets its cutoff region.  The wave's candidates are
 // spread over its lanes; runs of one entry within 64 candidates are counted with
@@ -567,7 +587,8 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
                                                           const ViewDev* __restrict__ views, int T, int exact_all,
                                                           uint32_t* __restrict__ kept,
                                                           EmitInfo* __restrict__ info, DevStatus* __restrict__ st,
-                                                          uint32_t* __restrict__ redo_list) {
+                                                          uint32_t* __restrict__ redo_list,
+                                                          uint2* __restrict__ items, size_t icap) {
   __shared__ uint32_t s_cp[kWaves][65];
   __shared__ uint32_t s_nx[kWaves][64];
   __shared__ uint32_t s_org[kWaves][64];    // rect origin (tx0 | ty0 << 16)
@@ -579,15 +600,38 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
   const int w = threadIdx.x / 64;
   const unsigned lane = __lane_id();
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t cand = e < n_entries ? touched[e] : 0u;
-  ushort4 rc = make_ushort4(0, 0, 0, 0);
-  const uint32_t incl = wave_incl_scan(cand);
+  const uint32_t touched_e = e < n_entries ? touched[e] : 0u;
+  uint32_t cand = touched_e;
+  uint32_t incl = wave_incl_scan(cand);
+  // a heavy wave hands its large entries to k_count_chunks (their kept[e] is
+  // written as 0 below; the chunks add to it)
+  if (!exact_all && (uint32_t)__builtin_amdgcn_readlane((int)incl, 63) > kSplitWave) {
+    const uint32_t t = split_threshold(cand);   // (a wave-wide step: every lane takes it)
+    // the wave's items are taken with one counter update
+    const uint32_t nch = cand > t ? (cand + kChunk - 1u) / kChunk : 0u;
+    const uint32_t nincl = wave_incl_scan(nch);
+    const int list = (int)((blockIdx.x * kWaves + w) % kSplitLists);
+    const unsigned long long i0 =
+        wave_take(split_ctr(st, kSplitCountItems, list), (uint32_t)__builtin_amdgcn_readlane((int)nincl, 63)) +
+        (nincl - nch);
+    bool split = false;
+    if (nch) {
+      uint2* li = items + (size_t)list * icap;
+      split = i0 + nch <= icap;
+      for (uint32_t c = 0; c < nch && i0 + c < icap; ++c)
+        li[i0 + c] = split ? make_uint2((uint32_t)e, c * kChunk) : make_uint2(~0u, 0u);
+    }
+    if (__ballot(split)) {
+      cand = split ? 0u : cand;
+      incl = wave_incl_scan(cand);
+    }
+  }
+  const ushort4 rc = touched_e ? rect[e] : make_ushort4(0, 0, 0, 0);
   s_cp[w][lane + 1] = incl;
   if (lane == 0) s_cp[w][0] = 0u;
   s_k[w][lane] = 0u;
   s_bits[w][lane] = 0ull;
   if (cand) {
-    rc = rect[e];
     const ViewDev& cv = views[e / (size_t)n];
     s_nx[w][lane] = (uint32_t)(rc.y - rc.x + 1);
     s_org[w][lane] = (uint32_t)rc.x | ((uint32_t)rc.z << 16);
@@ -639,6 +683,54 @@ __global__ __launch_bounds__(kThreads) void k_count_kept(const uint32_t* __restr
     in.bits = s_bits[w][lane];
     info[e] = in;
     if (k & kRedoMark) redo_list[atomicAdd(&st->redo_count, 1ull)] = (uint32_t)e;
+  }
+}
+
+// Kept counts of the entries k_count_kept split into chunk items, one wave per
+// item (kChunk candidates): the fp32 test as in k_count_kept, the item's passes
+// added to kept[e]; an undecided candidate marks kept[e] (top bit) and the first
+// chunk to mark it lists the entry for the exact pass, which rewrites its count.
+__global__ __launch_bounds__(kThreads) void k_count_chunks(const ushort4* __restrict__ rect,
+                                                            const Record* __restrict__ rec, int n,
+                                                            const ViewDev* __restrict__ views, int T,
+                                                            uint32_t* __restrict__ kept, DevStatus* __restrict__ st,
+                                                            uint32_t* __restrict__ redo_list,
+                                                            const uint2* __restrict__ items, size_t icap) {
+  const unsigned lane = __lane_id();
+  // the waves are dealt out over the lists: wave v walks list v % kSplitLists
+  const size_t v = (size_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const int list = (int)(v % kSplitLists);
+  const unsigned long long listed = *split_ctr(st, kSplitCountItems, list);
+  const size_t cnt = listed < icap ? (size_t)listed : icap;
+  const size_t step = (size_t)gridDim.x * (blockDim.x / 64) / kSplitLists;
+  const uint2* li = items + (size_t)list * icap;
+  for (size_t i = v / kSplitLists; i < cnt; i += step) {
+    const uint2 it = li[i];
+    if (it.x == ~0u) continue;
+    const uint32_t e = it.x;
+    const ushort4 rc = rect[e];
+    const ViewDev& cv = views[e / (uint32_t)n];
+    const CutoffGeoF geo = cutoff_geo_f(rec[e]);
+    const uint32_t nx = (uint32_t)(rc.y - rc.x + 1), C = nx * (uint32_t)(rc.w - rc.z + 1);
+    const uint32_t c1 = it.y + kChunk < C ? it.y + kChunk : C;
+    uint32_t k = 0;
+    bool undecided = false;
+    for (uint32_t cb = it.y; cb < c1; cb += 64u) {
+      const uint32_t li = cb + lane;
+      int f = 0;
+      if (li < c1) {
+        uint32_t tx, ty;
+        rect_cell(li, nx, tx, ty);
+        f = tile_cutoff_fast(geo, (int)(rc.x + tx), (int)(rc.z + ty), T, cv.W, cv.H);
+      }
+      k += (uint32_t)__popcll(__ballot(f > 0));
+      undecided |= __ballot(f < 0) != 0ull;
+    }
+    if (lane == 0) {
+      if (k) atomicAdd(&kept[e], k);
+      if (undecided && !(atomicOr(&kept[e], kRedoMark) & kRedoMark))
+        redo_list[atomicAdd(&st->redo_count, 1ull)] = e;
+    }
   }
 }
 
@@ -714,7 +806,10 @@ __global__ __launch_bounds__(kThreads) void k_count_redo(const uint32_t* __restr
   }
 }
 
-__global__ void k_status_reset(DevStatus* __restrict__ st) { status_clear(st); }
+__global__ void k_status_reset(DevStatus* __restrict__ st) {
+  if (threadIdx.x == 0) status_clear(st);
+  split_clear(st);
+}
 
 
 // Pair emission, one wave per 64 consecutive depth-ordered entries.  The wave's
@@ -725,22 +820,27 @@ __global__ void k_status_reset(DevStatus* __restrict__ st) { status_clear(st); }
 // candidates, the same test repeated for larger ones, so the kept counts and
 // offsets agree), and kept candidates are written in order at running positions
 // taken from a ballot: writes are coalesced and large rects are shared by the wave.
-// With culling the entry's rect comes from its EmitInfo (one 16-byte fetch).
+// With culling the entry's rect comes from its EmitInfo (one 16-byte fetch).  A
+// heavy wave (more than kSplitWave candidates) hands its largest entries, with
+// their output ranges, to k_emit_chunks and writes the others around those ranges.
 constexpr int kEmitGeoSlots = 8;   // per wave: LDS for the geometry of its large entries
 
-__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ order, int packed,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_emit(const uint32_t* __restrict__ order, int packed,
                                                     const uint32_t* __restrict__ touched,
                                                     const uint32_t* __restrict__ group_sums,
                                                     const uint32_t* __restrict__ block_off,
                                                     const ushort4* __restrict__ rect,
                                                     const Record* __restrict__ rec, size_t n_entries, int n,
                                                     const ViewDev* __restrict__ views,
-                                                    const DevStatus* __restrict__ st, int cull, int T,
+                                                    DevStatus* __restrict__ st, int cull, int T,
                                                     const EmitInfo* __restrict__ info,
                                                     const uint32_t* __restrict__ redo_bits,
+                                                    SplitEntry* __restrict__ ents, size_t ecap,
+                                                    uint2* __restrict__ items, size_t icap,
                                                     uint32_t* __restrict__ pair_tile,
                                                     uint32_t* __restrict__ pair_rec) {
   __shared__ uint32_t s_cp[kWaves][65];
+  __shared__ uint32_t s_dpre[kWaves][64];   // pairs of the wave's split entries before each entry
   __shared__ uint32_t s_rid[kWaves][64];
   __shared__ uint32_t s_base[kWaves][64];   // global tile id of the rect's first tile
   __shared__ uint32_t s_nx[kWaves][64];     // rect width in tiles
@@ -773,7 +873,65 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
       cand = (uint32_t)(rc.y - rc.x + 1) * (uint32_t)(rc.w - rc.z + 1);
     }
   }
-  const uint32_t incl = wave_incl_scan(cand);
+  uint32_t incl = wave_incl_scan(cand);
+  const uint32_t C_all = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+  if (C_all == 0u) return;
+  // output range of the wave (group g of 64 entries, valid since it has
+  // candidates): the start of its scan block plus the sums of the block's earlier
+  // groups, then its own sum
+  const size_t g = ((size_t)blockIdx.x * blockDim.x + (size_t)w * 64) / 64;
+  const size_t gb = g & ~(size_t)(kScanItems / 64 - 1);
+  uint32_t before = gb + lane < g ? group_sums[gb + lane] : 0u;
+  for (int o = 32; o > 0; o >>= 1) before += (uint32_t)__shfl_xor((int)before, o);
+  const uint32_t lo_off = block_off[g / (kScanItems / 64)] + before;
+  const uint32_t hi_end = lo_off + group_sums[g];
+  // the pair buffers hold st->n_eff pairs (0 when they are too small for this
+  // binning: then nothing is written)
+  const unsigned long long K = st->n_eff;
+  if (hi_end > K || hi_end < lo_off) return;
+  bool any_split = false;
+  uint32_t dpre = 0;
+  if (C_all > kSplitWave) {
+    // exact pair counts of the entries (the packed count saturates) place the
+    // split entries' ranges
+    const uint32_t ck = cand ? (packed && cnt == kPackSat ? touched[rid] : cnt) : 0u;
+    const uint32_t cincl = wave_incl_scan(ck);
+    const uint32_t t = split_threshold(cand);   // (a wave-wide step: every lane takes it)
+    // the wave's entries and items are taken with one update of each counter
+    const uint32_t nch = cand > t ? (cand + kChunk - 1u) / kChunk : 0u;
+    const uint64_t want = __ballot(nch != 0u);
+    const uint32_t nincl = wave_incl_scan(nch);
+    const int list = (int)(g % kSplitLists);
+    const unsigned long long j = wave_take(split_ctr(st, kSplitEmitEnts, list), (uint32_t)__popcll(want)) +
+                                 (uint32_t)__popcll(want & lanemask_lt());
+    const unsigned long long i0 =
+        wave_take(split_ctr(st, kSplitEmitItems, list), (uint32_t)__builtin_amdgcn_readlane((int)nincl, 63)) +
+        (nincl - nch);
+    bool split = false;
+    if (nch) {
+      split = j < ecap && i0 + nch <= icap;
+      const uint32_t slot = (uint32_t)((size_t)list * ecap + (size_t)j);
+      if (split) {
+        SplitEntry se;
+        se.rid = rid;
+        se.base = lo_off + cincl - ck;
+        se.ctr = 0u;
+        se.pad = 0u;
+        ents[slot] = se;
+      }
+      uint2* li = items + (size_t)list * icap;
+      for (uint32_t c = 0; c < nch && i0 + c < icap; ++c)
+        li[i0 + c] = split ? make_uint2(slot, c * kChunk) : make_uint2(~0u, 0u);
+    }
+    if (__ballot(split)) {
+      any_split = true;
+      const uint32_t sk = split ? ck : 0u;
+      dpre = wave_incl_scan(sk) - sk;
+      cand = split ? 0u : cand;
+      incl = wave_incl_scan(cand);
+    }
+  }
+  s_dpre[w][lane] = dpre;
   s_cp[w][lane + 1] = incl;
   if (lane == 0) s_cp[w][0] = 0u;
   s_rid[w][lane] = rid;
@@ -801,19 +959,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
   __builtin_amdgcn_wave_barrier();
   const uint32_t C = s_cp[w][64];
   if (C == 0u) return;
-  // output range of the wave (group g of 64 entries, valid since C > 0): the start
-  // of its scan block plus the sums of the block's earlier groups, then its own sum
-  const size_t g = ((size_t)blockIdx.x * blockDim.x + (size_t)w * 64) / 64;
-  const size_t gb = g & ~(size_t)(kScanItems / 64 - 1);
-  uint32_t before = gb + lane < g ? group_sums[gb + lane] : 0u;
-  for (int o = 32; o > 0; o >>= 1) before += (uint32_t)__shfl_xor((int)before, o);
-  const uint32_t lo_off = block_off[g / (kScanItems / 64)] + before;
-  const uint32_t hi_end = lo_off + group_sums[g];
-  // the pair buffers hold st->n_eff pairs (0 when they are too small for this
-  // binning: then nothing is written)
-  const unsigned long long K = st->n_eff;
-  if (hi_end > K || hi_end < lo_off) return;
-  uint32_t pos = lo_off;
+  uint32_t pos = lo_off;   // the next pair of the entries the wave writes itself
   int carry = 0;
   for (uint32_t cb = 0; cb < C; cb += 64) {
     const uint32_t q = cb + lane;
@@ -852,13 +998,96 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t* __restrict__ 
     }
     const uint64_t kmask = __ballot(keep);
     if (keep) {
-      const uint32_t dst = pos + (uint32_t)__popcll(kmask & lanemask_lt());
+      const uint32_t dst = pos + (any_split ? s_dpre[w][owner] : 0u) + (uint32_t)__popcll(kmask & lanemask_lt());
       if (dst < hi_end) {
         pair_tile[dst] = tile;
         pair_rec[dst] = r;
       }
     }
     pos += (uint32_t)__popcll(kmask);
+  }
+}
+
+// Pairs of the entries k_emit split into chunk items, one wave per item (kChunk
+// candidates): the same test as k_emit's for entries of more than 64 candidates;
+// the item takes its slots in the entry's range with one counter update, then
+// writes its kept pairs there in candidate order.
+__global__ __launch_bounds__(kThreads) void k_emit_chunks(SplitEntry* __restrict__ ents,
+                                                           const uint2* __restrict__ items, size_t icap,
+                                                           DevStatus* __restrict__ st,
+                                                           const ushort4* __restrict__ rect,
+                                                           const Record* __restrict__ rec, int n,
+                                                           const ViewDev* __restrict__ views, int cull, int T,
+                                                           const EmitInfo* __restrict__ info,
+                                                           const uint32_t* __restrict__ redo_bits,
+                                                           uint32_t* __restrict__ pair_tile,
+                                                           uint32_t* __restrict__ pair_rec) {
+  constexpr int R = (int)(kChunk / 64u);
+  const unsigned lane = __lane_id();
+  const size_t v = (size_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const int list = (int)(v % kSplitLists);
+  const unsigned long long listed = *split_ctr(st, kSplitEmitItems, list);
+  const size_t cnt = listed < icap ? (size_t)listed : icap;
+  const unsigned long long K = st->n_eff;
+  const size_t step = (size_t)gridDim.x * (blockDim.x / 64) / kSplitLists;
+  const uint2* li = items + (size_t)list * icap;
+  for (size_t i = v / kSplitLists; i < cnt; i += step) {
+    const uint2 it = li[i];
+    if (it.x == ~0u) continue;
+    SplitEntry* se = ents + it.x;
+    const uint32_t rid = se->rid, base = se->base;
+    ushort4 rc;
+    uint64_t ib = 0ull;
+    if (cull) {
+      const EmitInfo in = info[rid];
+      rc = in.rect;
+      ib = in.bits;
+    } else {
+      rc = rect[rid];
+    }
+    const ViewDev& cv = views[rid / (uint32_t)n];
+    const bool stored = (ib & kRedoFlag) != 0ull;
+    CutoffGeoF geo{};
+    if (cull && !stored) geo = cutoff_geo_f(rec[rid]);
+    const uint32_t nx = (uint32_t)(rc.y - rc.x + 1), C = nx * (uint32_t)(rc.w - rc.z + 1);
+    const uint32_t c1 = it.y + kChunk < C ? it.y + kChunk : C;
+    const uint32_t tile0 = (uint32_t)cv.tile_off + (uint32_t)rc.z * (uint32_t)cv.tiles_x + rc.x;
+    uint64_t m[R];
+    uint32_t tl[R];
+    uint32_t total = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t li = it.y + (uint32_t)r * 64u + lane;
+      bool keep = false;
+      tl[r] = 0;
+      if (li < c1) {
+        uint32_t tx, ty;
+        rect_cell(li, nx, tx, ty);
+        tl[r] = tile0 + ty * (uint32_t)cv.tiles_x + tx;
+        keep = true;
+        if (cull) {
+          keep = stored ? ((redo_bits[(size_t)(ib & ~kRedoFlag) + li / 32u] >> (li & 31u)) & 1u) != 0u
+                        : tile_cutoff_fast(geo, (int)(rc.x + tx), (int)(rc.z + ty), T, cv.W, cv.H) > 0;
+        }
+      }
+      m[r] = __ballot(keep);
+      total += (uint32_t)__popcll(m[r]);
+    }
+    if (total == 0u) continue;
+    uint32_t s0 = 0;
+    if (lane == 0) s0 = atomicAdd(&se->ctr, total);
+    size_t dst0 = (size_t)base + (uint32_t)__shfl((int)s0, 0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if ((m[r] >> lane) & 1ull) {
+        const size_t dst = dst0 + (uint32_t)__popcll(m[r] & lanemask_lt());
+        if (dst < K) {
+          pair_tile[dst] = tl[r];
+          pair_rec[dst] = rid;
+        }
+      }
+      dst0 += (uint32_t)__popcll(m[r]);
+    }
   }
 }
 
@@ -1015,50 +1244,59 @@ hipError_t launch_scan_touched(const uint32_t* order, int packed, const uint32_t
   return hipGetLastError();
 }
 
+// Workgroups of the chunk passes: enough waves for every item of a heavy scene to
+// have its own (their number is known on the device only; workgroups with no item
+// exit at once and cost next to nothing).
+constexpr unsigned kChunkBlocks = 4096;
+static_assert(kChunkBlocks * kWaves % kSplitLists == 0, "every list gets the same number of waves");
+
 hipError_t launch_emit_pairs(const uint32_t* order, int packed, const uint32_t* touched, const uint32_t* group_sums,
                              const uint32_t* block_off, const ushort4* rect, const Record* rec, size_t n_entries,
-                             int n, const ViewDev* views, const DevStatus* st, int cull, int tile,
-                             const EmitInfo* info, const uint32_t* redo_bits, uint32_t* pair_tile, uint32_t* pair_rec,
-                             hipStream_t s) {
+                             int n, const ViewDev* views, DevStatus* st, int cull, int tile,
+                             const EmitInfo* info, const uint32_t* redo_bits, SplitEntry* ents, uint2* items,
+                             uint32_t* pair_tile, uint32_t* pair_rec, hipStream_t s) {
   if (n_entries == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n_entries + kThreads - 1) / kThreads);
+  const size_t ecap = split_entry_cap(n_entries), icap = split_item_cap(n_entries);
   hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, order, packed, touched, group_sums, block_off, rect,
-                     rec, n_entries, n, views, st, cull, tile, info, redo_bits, pair_tile, pair_rec);
+                     rec, n_entries, n, views, st, cull, tile, info, redo_bits, ents, ecap, items, icap, pair_tile,
+                     pair_rec);
+  hipLaunchKernelGGL(k_emit_chunks, dim3(kChunkBlocks), dim3(kThreads), 0, s, ents, items, icap, st, rect,
+                     rec, n, views, cull, tile, info, redo_bits, pair_tile, pair_rec);
   return hipGetLastError();
 }
 
 hipError_t launch_count_kept(const uint32_t* touched, const ushort4* rect, const Record* rec, size_t n_entries, int n,
                              const ViewDev* views, int tile, int exact_all, uint32_t* kept, EmitInfo* info,
-                             DevStatus* st, uint32_t* redo_list, hipStream_t s) {
+                             DevStatus* st, uint32_t* redo_list, uint2* items, hipStream_t s) {
   if (n_entries == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n_entries + kThreads - 1) / kThreads);
+  const size_t icap = split_item_cap(n_entries);
   hipLaunchKernelGGL(k_count_kept, dim3(blocks), dim3(kThreads), 0, s, touched, rect, rec, n_entries, n, views, tile,
-                     exact_all, kept, info, st, redo_list);
+                     exact_all, kept, info, st, redo_list, items, icap);
+  if (!exact_all)
+    hipLaunchKernelGGL(k_count_chunks, dim3(kChunkBlocks), dim3(kThreads), 0, s, rect, rec, n, views,
+                       tile, kept, st, redo_list, items, icap);
   return hipGetLastError();
 }
 
-// Workgroups of the exact pass: one wave per 2048 entries, 16 to 2048 workgroups
-// (the listed entries are a few thousandths of the candidates; the grid-stride
-// loop covers any number).
-inline unsigned redo_blocks(size_t n_entries) {
-  const size_t b = (n_entries + 2048 * kWaves - 1) / (2048 * kWaves);
-  return (unsigned)(b < 16 ? 16 : (b > 2048 ? 2048 : b));
-}
+// Workgroups of the exact pass: its list is known on the device only (a few
+// thousandths of the entries in practice; the grid-stride loop covers any number),
+// and workgroups with nothing to do exit at once.
+constexpr unsigned kRedoBlocks = 2048;
 
-hipError_t launch_count_redo(const uint32_t* touched, const ushort4* rect, const Record* rec, size_t n_entries, int n,
+hipError_t launch_count_redo(const uint32_t* touched, const ushort4* rect, const Record* rec, int n,
                              const ViewDev* views, int tile, int exact_all, const float* P, int stride,
                              uint32_t* kept, EmitInfo* info, DevStatus* st, const uint32_t* redo_list,
                              uint32_t* redo_bits, size_t redo_cap, hipStream_t s) {
-  // a fixed grid walks the list, whose length only the device knows (a few
-  // thousandths of the entries at most in practice)
-  hipLaunchKernelGGL(k_count_redo, dim3(redo_blocks(n_entries)), dim3(kThreads), 0, s, touched, rect, rec, n, views,
+  hipLaunchKernelGGL(k_count_redo, dim3(kRedoBlocks), dim3(kThreads), 0, s, touched, rect, rec, n, views,
                      tile, exact_all, P,
                      stride, kept, info, st, redo_list, redo_bits, redo_cap);
   return hipGetLastError();
 }
 
 hipError_t launch_status_reset(DevStatus* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(1), 0, s, st);
+  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(256), 0, s, st);
   return hipGetLastError();
 }
 

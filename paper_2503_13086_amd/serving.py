@@ -207,14 +207,15 @@ class Engine:
         return job
 
     def _view_bytes(self, n: int, pixels: int) -> int:
-        """Context and image memory of one view of a step: 141 B per Gaussian
+        """Context and image memory of one view of a step: 142 B per Gaussian
         (record, depth, tiles touched, rect, sort keys and values, scan, kept
-        counts and emission info, 2D gradient, histograms), 16 B per pair (tile ids and record ids, ping-pong),
-        the buffers' 25 % over-allocation and small fixed buffers; 100 B per pixel
-        (per-pixel forward state, soft count and its gradient, SSIM statistics,
-        image and dL/dimage)."""
+        counts and emission info, 2D gradient, histograms, split-work lists), 16 B
+        per pair (tile ids and record ids, ping-pong), the buffers' 25 %
+        over-allocation and 320 KiB of fixed buffers (status and split counters,
+        the split lists' floors, small scratch); 100 B per pixel (per-pixel forward
+        state, soft count and its gradient, SSIM statistics, image and dL/dimage)."""
         pairs = self.pairs_per_view if self.pairs_per_view is not None else 16 * n
-        ctx = int((141 * n + 16 * pairs) * 5 // 4) + 65536
+        ctx = int((142 * n + 16 * pairs) * 5 // 4) + 327680
         return ctx + 100 * pixels
 
     def _resident_bytes(self, n_total: int, extra_targets: int) -> int:

@@ -40,10 +40,22 @@ def run_gpu(scene, upstream=None, loss=False, cull=None, tile=16):
                                     "exact": gs.GS_CULL_ELLIPSE_EXACT}[cull])
         P = params_to_device(scene.params)
         rz.set_views(scene.cams, tile)
-        rz.preprocess(P, scene.n, scene.sh_degree)
-        K = rz.bin_sort()
+        # a binning that runs out of room (pairs or the exact pass's outcome store)
+        # reports it and grows; the next one fits
+        retried = False
+        for attempt in range(2):
+            rz.preprocess(P, scene.n, scene.sh_degree)
+            K = rz.bin_sort()
+            try:
+                rz.sync_status()
+                break
+            except gs.GsError as e:
+                if attempt or e.status != gs.GS_ERR_CAPACITY:
+                    raise
+                retried = True
         color = rz.render_fwd()
-        out = dict(K=K, n_tiles=rz.tile_off[-1], color=[x.cpu().numpy() for x in rz.image_views(color)])
+        out = dict(K=K, n_tiles=rz.tile_off[-1], color=[x.cpu().numpy() for x in rz.image_views(color)],
+                   retried=retried)
         V, n = len(scene.cams), scene.n
         rec = rz.buffer(GS_BUF_RECORDS).cpu().numpy().view(np.uint8).reshape(V, n, 48)
         out["u"] = rec[:, :, 0:8].copy().view(np.float64)[..., 0]
