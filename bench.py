@@ -216,7 +216,7 @@ def cpu_baseline(scene, budget_s=15.0):
                                             "the L1 loss gradient"}}
 
 
-def serving_leg(n_arrivals, time_scale, slots):
+def serving_leg(n_arrivals, time_scale, slots, autotune=True):
     """The on-the-fly stream served twice on fresh fields: the plain loop (one job
     at a time, one view per step) and continuous batching (up to `slots` jobs per
     step).  Targets and new Gaussians are resident on the device before timing."""
@@ -238,7 +238,7 @@ def serving_leg(n_arrivals, time_scale, slots):
     from paper_2503_13086_amd.autotune import Autotuner
     for name, s in (("plain_loop", 1), ("continuous_batching", slots)):
         fld = Field(st.initial, st.sh_degree, capacity=st.initial.shape[1])
-        tuner = Autotuner(coarse=True)
+        tuner = Autotuner(coarse=True) if autotune else None
         eng = Engine(fld, max_slots=s, t_i=200, seed=5, w_l1=0.47, w_dssim=0.12, w_load=0.41, autotuner=tuner)
         t = time.perf_counter()
         done = [0]
@@ -252,7 +252,8 @@ def serving_leg(n_arrivals, time_scale, slots):
         stats = eng.run(st.arrivals, targets, time_scale=time_scale, on_job_done=progress)
         eng.close()
         out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in stats.summary().items()}
-        out[name]["tiles_chosen"] = {f"n<=2^{k[0]}": t for k, t in sorted(tuner.table.items())}
+        out[name]["tiles_chosen"] = ({f"n<=2^{k[0]}": t for k, t in sorted(tuner.table.items())} if tuner
+                                     else "16 (fixed)")
         print(f"[bench] serving {name}: {json.dumps(out[name])} ({time.perf_counter() - t:.1f}s)", file=sys.stderr,
               flush=True)
         del fld, eng
@@ -273,6 +274,10 @@ def main():
     ap.add_argument("--serve-time-scale", type=float, default=0.1,
                     help="arrival times (Poisson, mean gap 2 s) are multiplied by this factor")
     ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-autotune", action="store_true",
+                    help="let the serving engine autotune the tile edge per field-size bucket")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run the serving leg alone (no training-step figures; prints {\"serving\": ...})")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager calls only (by default the step is also captured into a HIP graph and "
                          "replayed, and the replay rate is the reported value)")
@@ -284,6 +289,10 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU split of this path "
               "is a design note, not a measured configuration.", file=sys.stderr)
         sys.exit(2)
+    if args.serve_only:
+        print(json.dumps({"serving": serving_leg(max(args.serve_arrivals, 1), args.serve_time_scale,
+                                                 args.serve_slots, autotune=args.serve_autotune)}), flush=True)
+        return
 
     import torch
     from paper_2503_13086_amd.pipeline import Rasterizer, params_to_device, DEFAULT_LR, n_params
@@ -478,7 +487,8 @@ def main():
     }
     if args.serve_arrivals > 0:
         rz.close()
-        line["serving"] = serving_leg(args.serve_arrivals, args.serve_time_scale, args.serve_slots)
+        line["serving"] = serving_leg(args.serve_arrivals, args.serve_time_scale, args.serve_slots,
+                                      autotune=args.serve_autotune)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(sc)
