@@ -236,9 +236,11 @@ gs_status gs_adam_step(gs_ctx* ctx, float* params, const float* grad, float* m, 
  * dL_dcolor, grad, 0) followed by gs_adam_step(ctx, params, grad, m, v, step, n,
  * stride, sh_degree, ...) with the n, stride and sh_degree of the last
  * gs_preprocess, but the parameter gradient of each Gaussian is applied as soon as
- * it is formed instead of going through memory.  (The backward's 2D gradients are
- * summed with floating-point atomics across tiles, whose order is not fixed, so
- * repeated backward passes, fused or not, agree to rounding, not bit for bit.)  grad: device, parameter
+ * it is formed instead of going through memory.  (In the default GS_BWD_ATOMIC
+ * order the backward's 2D gradients are summed with floating-point atomics across
+ * tiles, whose order is not fixed, so repeated backward passes, fused or not,
+ * agree to rounding, not bit for bit; GS_BWD_ORDERED makes them bit for bit, see
+ * gs_set_backward_order.)  grad: device, parameter
  * layout, receives the gradient when not NULL (may be NULL).  params is updated
  * in place; it must be the array the last gs_preprocess read.  Other arguments and
  * errors as for gs_render_bwd and gs_adam_step (n_views > 0 with view_lr_scale
@@ -260,6 +262,22 @@ gs_status gs_render_bwd_adam(gs_ctx* ctx, float* params, const float* dL_dcolor,
  * Takes effect at the next gs_bin_sort. */
 enum { GS_CULL_RECT = 0, GS_CULL_ELLIPSE = 1, GS_CULL_ELLIPSE_EXACT = 2 };
 gs_status gs_set_cull(gs_ctx* ctx, int32_t mode);
+
+/* Summation order of the per-Gaussian 2D gradients in gs_render_bwd and
+ * gs_render_bwd_adam (the splat-level accumulation of Sec. IV-E).
+ * GS_BWD_ATOMIC (the default): each (tile, Gaussian) partial sum is added with a
+ * floating-point atomic, in whatever order the tiles finish.  GS_BWD_ORDERED:
+ * each partial is written to its own slot (the partials themselves are formed in
+ * a fixed order: per-wave reductions, then the waves in order), the pairs are
+ * sorted by Gaussian (stably, so tile order is kept) and each Gaussian's partials
+ * are summed in tile order: the gradients, and the parameters an Adam step makes
+ * of them, are the same bits on every run and on every device load, which makes
+ * it the reference for checking the atomic path for races (the two differ by
+ * rounding only).  Costs 36 B per pair of extra memory, a sort of the pairs and a
+ * gather (several times the atomic backward's time).  Returns GS_ERR_INVALID for
+ * an unknown mode; takes effect at the next backward. */
+enum { GS_BWD_ATOMIC = 0, GS_BWD_ORDERED = 1 };
+gs_status gs_set_backward_order(gs_ctx* ctx, int32_t mode);
 
 /* Size in bytes of a context buffer (GS_BUF_*) for the current state. */
 gs_status gs_buffer_size(const gs_ctx* ctx, int32_t which, size_t* bytes);

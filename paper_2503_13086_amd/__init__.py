@@ -35,11 +35,12 @@ _STATUS = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_CAPACITY", -3: "GS_ERR_
 # Exported symbols (must match include/gs.h).
 EXPORTS = ["gs_abi_version", "gs_create", "gs_destroy", "gs_last_error", "gs_layout", "gs_preprocess", "gs_bin_sort",
            "gs_render_fwd", "gs_loss", "gs_loss_noalloc", "gs_load_balance", "gs_render_bwd", "gs_adam_step", "gs_render_bwd_adam",
-           "gs_set_cull", "gs_buffer_size", "gs_sync_status", "gs_reserve_pairs",
+           "gs_set_cull", "gs_set_backward_order", "gs_buffer_size", "gs_sync_status", "gs_reserve_pairs",
            "gs_copy_buffer", "gs_profile_enable", "gs_profile_read", "gs_memory_bytes", "gs_render_count",
            "gs_probe_copy", "gs_probe_fma", "gs_sched_weights",
            "gs_sched_plan", "gs_sched_lr"]
 GS_CULL_RECT, GS_CULL_ELLIPSE, GS_CULL_ELLIPSE_EXACT = 0, 1, 2
+GS_BWD_ATOMIC, GS_BWD_ORDERED = 0, 1
 
 
 class GsError(RuntimeError):
@@ -93,6 +94,7 @@ def _load():
                                       ctypes.POINTER(ctypes.c_float), _I32, ctypes.c_uint32, ctypes.c_float,
                                       ctypes.c_float, ctypes.c_float, _P]),
         "gs_set_cull": (_I32, [_P, _I32]),
+        "gs_set_backward_order": (_I32, [_P, _I32]),
         "gs_buffer_size": (_I32, [_P, _I32, ctypes.POINTER(ctypes.c_size_t)]),
         "gs_copy_buffer": (_I32, [_P, _I32, _P, ctypes.c_size_t, _P]),
         "gs_profile_enable": (_I32, [_P, _I32]),
@@ -264,6 +266,10 @@ def gs_render_bwd_adam(ctx, params, dL_dcolor, grad, m, v, step, lr_group: Seque
 
 def gs_set_cull(ctx, mode: int) -> None:
     _check(ctx, _load().gs_set_cull(ctx, mode), "gs_set_cull")
+
+
+def gs_set_backward_order(ctx, mode: int) -> None:
+    _check(ctx, _load().gs_set_backward_order(ctx, mode), "gs_set_backward_order")
 
 
 def gs_buffer_size(ctx, which: int) -> int:

@@ -79,6 +79,8 @@ struct gs_ctx {
   bool status_fresh = false;       // the status was cleared by the last gs_preprocess and not used since
   DevBuf asum, dG, loadp, loadst, kept, emitinfo, redo_list, redo_bits, status;
   DevBuf split_ents, split_items;  // large entries handed to the binning's chunk passes
+  int bwd_order = GS_BWD_ATOMIC;
+  DevBuf part, okey[2], oval[2], eranges;   // the ordered backward's partials, entry sort and ranges
   DevStatus* h_status = nullptr;   // host mirror of the device status, written by the binning's last check
   DevStatus* d_mirror = nullptr;   // its device-side address
   bool load_pending = false;   // dG holds a load-balancing gradient for the current forward
@@ -142,7 +144,8 @@ std::vector<DevBuf*> all_bufs(gs_ctx* c) {
           &c->dval[1], &c->groupsums, &c->blocksums, &c->total, &c->hist, &c->pkey[0],
           &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->tfinal, &c->ncontrib, &c->last,
           &c->grad2d, &c->lossp, &c->aux, &c->evals, &c->asum, &c->dG, &c->loadp, &c->loadst, &c->kept, &c->emitinfo,
-          &c->redo_list, &c->redo_bits, &c->status, &c->split_ents, &c->split_items};
+          &c->redo_list, &c->redo_bits, &c->status, &c->split_ents, &c->split_items, &c->part, &c->okey[0],
+          &c->okey[1], &c->oval[0], &c->oval[1], &c->eranges};
 }
 
 hipEvent_t next_event(gs_ctx* c) {
@@ -673,6 +676,54 @@ gs_status gs_load_balance(gs_ctx* c, float w_load, double* loss_out, gs_stream s
   return GS_OK;
 }
 
+namespace {
+
+// The raster backward into grad2d (per-entry 2D gradients), in the context's
+// summation order.
+gs_status raster_backward(gs_ctx* c, const float* dL_dcolor, hipStream_t s) {
+  const size_t NV = (size_t)c->V * c->n;
+  gs_status st;
+  if ((st = ensure(c, c->grad2d, NV * kGrad2D * 4, s)) != GS_OK) return st;
+  const float* dG = c->load_pending ? c->dG.as<float>() : nullptr;
+  if (c->bwd_order == GS_BWD_ORDERED) {
+    // one partial per pair position (the pair buffers hold pair_cap >= K pairs);
+    // grids for K when the host knows it, else for the capacity
+    const size_t cap = c->pair_cap > 0 ? c->pair_cap : 1;
+    const size_t k_grid = c->K_known ? (size_t)c->K : c->pair_cap;
+    if ((st = ensure(c, c->part, cap * kGrad2D * 4, s)) != GS_OK) return st;
+    for (int i = 0; i < 2; ++i) {
+      if ((st = ensure(c, c->okey[i], cap * 4, s)) != GS_OK) return st;
+      if ((st = ensure(c, c->oval[i], cap * 4, s)) != GS_OK) return st;
+    }
+    if ((st = ensure(c, c->eranges, NV * 8, s)) != GS_OK) return st;
+    Prof pr(c, GS_K_RENDER_BWD, s);
+    GS_HIP(c, launch_render_bwd(c->views.as<ViewDev>(), c->V, c->n_tiles, c->ranges.as<uint2>(),
+                                c->pval[c->pairs_in_b].as<uint32_t>(), c->rec.as<Record>(), (uint32_t)NV,
+                                c->tfinal.as<float>(), c->last.as<uint32_t>(), dL_dcolor, dG, c->part.as<float>(),
+                                c->tile, 1, s));
+    SortScratch sc{c->hist.as<uint32_t>()};
+    GS_HIP(c, launch_ordered_sum(c->pval[c->pairs_in_b].as<uint32_t>(), k_grid, &c->status.as<DevStatus>()->n_eff,
+                                 NV, c->part.as<float>(), c->okey[0].as<uint32_t>(), c->oval[0].as<uint32_t>(),
+                                 c->okey[1].as<uint32_t>(), c->oval[1].as<uint32_t>(), c->eranges.as<uint2>(), sc,
+                                 c->grad2d.as<float>(), s));
+    return GS_OK;
+  }
+  {
+    Prof pr(c, GS_K_ZERO, s);
+    GS_HIP(c, launch_fill_u32(c->grad2d.as<uint32_t>(), 0u, NV * kGrad2D, s));
+  }
+  {
+    Prof pr(c, GS_K_RENDER_BWD, s);
+    GS_HIP(c, launch_render_bwd(c->views.as<ViewDev>(), c->V, c->n_tiles, c->ranges.as<uint2>(),
+                                c->pval[c->pairs_in_b].as<uint32_t>(), c->rec.as<Record>(), (uint32_t)NV,
+                                c->tfinal.as<float>(), c->last.as<uint32_t>(), dL_dcolor, dG, c->grad2d.as<float>(),
+                                c->tile, 0, s));
+  }
+  return GS_OK;
+}
+
+}  // namespace
+
 gs_status gs_render_bwd(gs_ctx* c, const float* params, const float* dL_dcolor, float* grad, int32_t accumulate,
                         gs_stream stream) {
   if (!c) return GS_ERR_INVALID;
@@ -682,20 +733,8 @@ gs_status gs_render_bwd(gs_ctx* c, const float* params, const float* dL_dcolor, 
     return fail(c, GS_ERR_INVALID, "params, dL_dcolor and grad must be non-NULL and aligned");
   hipStream_t s = (hipStream_t)stream;
   GS_HIP(c, hipSetDevice(c->device));
-  const size_t NV = (size_t)c->V * c->n;
   gs_status st;
-  if ((st = ensure(c, c->grad2d, NV * kGrad2D * 4, s)) != GS_OK) return st;
-  {
-    Prof pr(c, GS_K_ZERO, s);
-    GS_HIP(c, launch_fill_u32(c->grad2d.as<uint32_t>(), 0u, NV * kGrad2D, s));
-  }
-  {
-    Prof pr(c, GS_K_RENDER_BWD, s);
-    GS_HIP(c, launch_render_bwd(c->views.as<ViewDev>(), c->V, c->n_tiles, c->ranges.as<uint2>(),
-                                c->pval[c->pairs_in_b].as<uint32_t>(), c->rec.as<Record>(), (uint32_t)NV,
-                                c->tfinal.as<float>(), c->last.as<uint32_t>(), dL_dcolor,
-                                c->load_pending ? c->dG.as<float>() : nullptr, c->grad2d.as<float>(), c->tile, s));
-  }
+  if ((st = raster_backward(c, dL_dcolor, s)) != GS_OK) return st;
   {
     Prof pr(c, GS_K_PREPROCESS_BWD, s);
     GS_HIP(c, launch_preprocess_bwd(params, c->n, c->stride, c->D, c->views.as<ViewDev>(), c->V,
@@ -770,19 +809,7 @@ gs_status gs_render_bwd_adam(gs_ctx* c, float* params, const float* dL_dcolor, f
     return st;
   hipStream_t s = (hipStream_t)stream;
   GS_HIP(c, hipSetDevice(c->device));
-  const size_t NV = (size_t)c->V * c->n;
-  if ((st = ensure(c, c->grad2d, NV * kGrad2D * 4, s)) != GS_OK) return st;
-  {
-    Prof pr(c, GS_K_ZERO, s);
-    GS_HIP(c, launch_fill_u32(c->grad2d.as<uint32_t>(), 0u, NV * kGrad2D, s));
-  }
-  {
-    Prof pr(c, GS_K_RENDER_BWD, s);
-    GS_HIP(c, launch_render_bwd(c->views.as<ViewDev>(), c->V, c->n_tiles, c->ranges.as<uint2>(),
-                                c->pval[c->pairs_in_b].as<uint32_t>(), c->rec.as<Record>(), (uint32_t)NV,
-                                c->tfinal.as<float>(), c->last.as<uint32_t>(), dL_dcolor,
-                                c->load_pending ? c->dG.as<float>() : nullptr, c->grad2d.as<float>(), c->tile, s));
-  }
+  if ((st = raster_backward(c, dL_dcolor, s)) != GS_OK) return st;
   {
     Prof pr(c, GS_K_BWD_ADAM, s);
     GS_HIP(c, launch_preprocess_bwd_adam(params, c->n, c->stride, c->D, c->views.as<ViewDev>(), c->V,
@@ -799,6 +826,14 @@ gs_status gs_set_cull(gs_ctx* c, int32_t mode) {
     return fail(c, GS_ERR_INVALID, "unknown cull mode");
   c->cull = mode;
   if (c->stage > kProjected) c->stage = kProjected;   // pair lists must be rebuilt
+  return GS_OK;
+}
+
+gs_status gs_set_backward_order(gs_ctx* c, int32_t mode) {
+  if (!c) return GS_ERR_INVALID;
+  c->err.clear();
+  if (mode != GS_BWD_ATOMIC && mode != GS_BWD_ORDERED) return fail(c, GS_ERR_INVALID, "unknown backward order");
+  c->bwd_order = mode;
   return GS_OK;
 }
 

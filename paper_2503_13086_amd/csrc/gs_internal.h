@@ -325,9 +325,24 @@ hipError_t launch_render_count(const ViewDev* views, int V, int n_tiles, const u
 hipError_t launch_probe_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_probe_fma(float* out, int blocks, int iters, hipStream_t s);
 int64_t probe_fma_flops(int blocks, int iters);
+// ordered == 0: per-tile partial sums added into grad2d[V*n][kGrad2D] with global
+// atomics (grad2d zeroed first).  ordered != 0: the partial of the pair at sorted
+// position i goes to grad2d[i * kGrad2D ...] (a [K][kGrad2D] buffer: every position of
+// every tile list written, the same bits on every run); launch_ordered_sum then
+// forms the per-entry sums.
 hipError_t launch_render_bwd(const ViewDev* views, int V, int n_tiles, const uint2* ranges, const uint32_t* pair_rec,
                              const Record* rec, uint32_t n_rec, const float* t_final, const uint32_t* last,
-                             const float* dL_dcolor, const float* dL_dG, float* grad2d, int tile, hipStream_t s);
+                             const float* dL_dcolor, const float* dL_dG, float* grad2d, int tile, int ordered,
+                             hipStream_t s);
+// grad2d[e] = the sum, in ascending pair position (tile order), of the partials
+// part[i] of the pairs i whose entry pair_rec[i] is e, for e < n_entries (zero for
+// an entry with no pair): the pairs' entries are sorted stably (keys/vals a and b:
+// K_cap words each, scratch sized for K_cap items), then delimited per entry
+// (eranges: n_entries uint2).  K = min(*n_dev, K_cap) pairs.
+hipError_t launch_ordered_sum(const uint32_t* pair_rec, size_t K_cap, const unsigned long long* n_dev,
+                              size_t n_entries, const float* part, uint32_t* keys_a, uint32_t* vals_a,
+                              uint32_t* keys_b, uint32_t* vals_b, uint2* eranges, SortScratch scratch,
+                              float* grad2d, hipStream_t s);
 
 // Loss over all views in 32x32-pixel tiles: loss_tiles() tiles, partials 2 doubles
 // per tile; aux 9 floats per pixel for the SSIM term, or NULL for the fused SSIM

@@ -388,7 +388,13 @@ __device__ inline int reduce18_slot(unsigned lane) {
   return -1;
 }
 
-template <int T>
+// ORDERED: instead of adding each (tile, Gaussian) partial sum into grad2d with a
+// global atomic, write it to out[pair position * kGrad2D + component] (every
+// position of the tile's list, zeros included), each wave reducing into its own
+// LDS rows and the waves' rows summed in wave order, so that every partial is the
+// same bits on every run; the per-Gaussian sums are then taken in tile order by
+// launch_ordered_sum.
+template <int T, bool ORDERED = false>
 __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict__ views, int V, int n_tiles_total,
                                                     const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ pair_rec,
@@ -399,10 +405,12 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
                                                     const float* __restrict__ dL_dG, float* __restrict__ grad2d) {
   // records are staged NB at a time, half the tile's threads (at least 64): 11 KB of
   // LDS at T = 16, so registers rather than LDS set the occupancy (8 waves per SIMD)
-  constexpr int NT = T * T, NB = NT >= 128 ? NT / 2 : NT, NM = NB / 64, NW = NT / 64;
+  // (the ordered mode keeps one accumulator per wave: 64 records per batch)
+  constexpr int NT = T * T, NB = ORDERED ? 64 : (NT >= 128 ? NT / 2 : NT), NM = NB / 64, NW = NT / 64;
   __shared__ float4 s0[NB], s1[NB], s2[NB];
   __shared__ uint32_t srid[NB];
-  __shared__ float acc[NB][kGrad2D];
+  constexpr int NACC = ORDERED ? NW : 1;
+  __shared__ float acc[NACC][NB][kGrad2D];
   __shared__ uint32_t smax[NW];
   const int tile = xcd_raster_tile((int)blockIdx.x);
   if (tile >= n_tiles_total) return;
@@ -440,12 +448,11 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
   // 32-bit LDS byte addresses of this lane's columns in acc[0] for the two
   // reductions (plain integer arithmetic in the loop: the compiler would otherwise
   // form the address in 64 bits)
-  const uint32_t acc0 = (uint32_t)(uintptr_t)(LdsFloat*)&acc[0][0];
+  const uint32_t acc0 = (uint32_t)(uintptr_t)(LdsFloat*)&acc[ORDERED ? threadIdx.x / 64 : 0][0][0];
   const uint32_t col9 = acc0 + 4u * (uint32_t)(slot < 0 ? 0 : slot);
   const uint32_t col18 = acc0 + 4u * (uint32_t)(slot18 < 0 ? 0 : slot18 % kGrad2D);
   if (__lane_id() == 0) smax[threadIdx.x / 64] = mx;
-  if ((int)threadIdx.x < NB)
-    for (int k = 0; k < kGrad2D; ++k) acc[threadIdx.x][k] = 0.0f;
+  for (int i = threadIdx.x; i < NACC * NB * kGrad2D; i += NT) (&acc[0][0][0])[i] = 0.0f;
   __syncthreads();
   int jmax = 0;
   for (int w = 0; w < NW; ++w) jmax = max(jmax, (int)smax[w]);
@@ -533,7 +540,11 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
     }
     __syncthreads();
     if ((int)threadIdx.x < m) {
-      float* a = acc[threadIdx.x];
+      float* a = acc[0][threadIdx.x];
+      if (ORDERED) {
+        for (int w = 1; w < NACC; ++w)
+          for (int k = 0; k < kGrad2D; ++k) a[k] += acc[w][threadIdx.x][k];
+      }
       // moments -> partials: with exponent p = -(a dx^2 + 2 b dx dy + c dy^2)/2 and the
       // staged coefficients A, B, C = (-a/2, -b, -c/2) log2(e):
       // dp/du = ln2 (2A dx + B dy), dp/dw = ln2 (B dx + 2C dy),
@@ -550,15 +561,28 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
     // one global atomic per (tile, Gaussian, component); consecutive lanes take
     // consecutive components, so a wavefront's atomics fall on a few cache lines
     // (element offsets in 64 bits: n_rec * 9 may pass 2^32 bytes)
-    float* af = &acc[0][0];
-    for (int i = threadIdx.x; i < m * kGrad2D; i += NT) {
-      const int j = i / kGrad2D;
-      const uint32_t rid = srid[j];
-      const float x = af[i];
-      if (x != 0.0f && rid < n_rec)
-        unsafeAtomicAdd(grad2d + ((size_t)rid * kGrad2D + (size_t)(i - kGrad2D * j)), x);
-      af[i] = 0.0f;
+    float* af = &acc[0][0][0];
+    if (ORDERED) {
+      float* po = grad2d + ((size_t)rg.x + (size_t)beg) * kGrad2D;
+      for (int i = threadIdx.x; i < m * kGrad2D; i += NT) po[i] = srid[i / kGrad2D] < n_rec ? af[i] : 0.0f;
+      __syncthreads();
+      for (int i = threadIdx.x; i < NACC * NB * kGrad2D; i += NT) af[i] = 0.0f;
+    } else {
+      for (int i = threadIdx.x; i < m * kGrad2D; i += NT) {
+        const int j = i / kGrad2D;
+        const uint32_t rid = srid[j];
+        const float x = af[i];
+        if (x != 0.0f && rid < n_rec)
+          unsafeAtomicAdd(grad2d + ((size_t)rid * kGrad2D + (size_t)(i - kGrad2D * j)), x);
+        af[i] = 0.0f;
+      }
     }
+  }
+  if (ORDERED) {
+    // list positions no pixel of the tile reached: zero partials
+    const size_t len = rg.y > rg.x ? (size_t)(rg.y - rg.x) : 0;
+    float* po = grad2d + (size_t)rg.x * kGrad2D;
+    for (size_t i = (size_t)jmax * kGrad2D + threadIdx.x; i < len * kGrad2D; i += NT) po[i] = 0.0f;
   }
 }
 
@@ -611,24 +635,20 @@ hipError_t launch_render_count(const ViewDev* views, int V, int n_tiles, const u
 
 hipError_t launch_render_bwd(const ViewDev* views, int V, int n_tiles, const uint2* ranges, const uint32_t* pair_rec,
                              const Record* rec, uint32_t n_rec, const float* t_final, const uint32_t* last,
-                             const float* dL_dcolor, const float* dL_dG, float* grad2d, int tile, hipStream_t s) {
+                             const float* dL_dcolor, const float* dL_dG, float* grad2d, int tile, int ordered,
+                             hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   const dim3 grid((unsigned)((n_tiles + 8 * kXcdRun - 1) / (8 * kXcdRun) * (8 * kXcdRun)));
+#define GS_BWD(TT, OO)                                                                                            \
+  hipLaunchKernelGGL((k_render_bwd<TT, OO>), grid, dim3(TT * TT), 0, s, views, V, n_tiles, ranges, pair_rec, rec, \
+                     n_rec, t_final, last, dL_dcolor, dL_dG, grad2d)
   switch (tile) {
-    case 8:
-      hipLaunchKernelGGL(k_render_bwd<8>, grid, dim3(64), 0, s, views, V, n_tiles, ranges, pair_rec, rec, n_rec, t_final, last,
-                         dL_dcolor, dL_dG, grad2d);
-      break;
-    case 16:
-      hipLaunchKernelGGL(k_render_bwd<16>, grid, dim3(256), 0, s, views, V, n_tiles, ranges, pair_rec, rec, n_rec, t_final,
-                         last, dL_dcolor, dL_dG, grad2d);
-      break;
-    case 32:
-      hipLaunchKernelGGL(k_render_bwd<32>, grid, dim3(1024), 0, s, views, V, n_tiles, ranges, pair_rec, rec, n_rec, t_final,
-                         last, dL_dcolor, dL_dG, grad2d);
-      break;
+    case 8: if (ordered) GS_BWD(8, true); else GS_BWD(8, false); break;
+    case 16: if (ordered) GS_BWD(16, true); else GS_BWD(16, false); break;
+    case 32: if (ordered) GS_BWD(32, true); else GS_BWD(32, false); break;
     default: return hipErrorInvalidValue;
   }
+#undef GS_BWD
   return hipGetLastError();
 }
 

@@ -1310,6 +1310,62 @@ hipError_t launch_ranges(const uint32_t* pair_tile, size_t K_cap, const unsigned
   return hipGetLastError();
 }
 
+// ---- ordered backward: per-Gaussian sums of the per-tile partials in tile order ----
+
+// keys[i] = entry of sorted pair i, vals[i] = i (the first min(*n_dev, K_cap) pairs)
+__global__ void k_entry_keys(const uint32_t* __restrict__ pair_rec, size_t K_cap,
+                             const unsigned long long* __restrict__ n_dev, uint32_t* __restrict__ keys,
+                             uint32_t* __restrict__ vals) {
+  const size_t K = item_count(K_cap, n_dev);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (size_t)gridDim.x * blockDim.x) {
+    keys[i] = pair_rec[i];
+    vals[i] = (uint32_t)i;
+  }
+}
+
+// grad2d[e] = sum over the pair positions of entry e (ascending, i.e. in tile order)
+// of the partials written by the ordered backward; zero for an entry with no pair.
+__global__ void k_ordered_sum(const uint2* __restrict__ eranges, const uint32_t* __restrict__ pos,
+                              const float* __restrict__ part, float* __restrict__ grad2d, size_t n_entries) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_entries) return;
+  const uint2 r = eranges[e];
+  float acc[kGrad2D];
+#pragma unroll
+  for (int c = 0; c < kGrad2D; ++c) acc[c] = 0.0f;
+  for (uint32_t k = r.x; k < r.y; ++k) {
+    const float* p = part + (size_t)pos[k] * kGrad2D;
+#pragma unroll
+    for (int c = 0; c < kGrad2D; ++c) acc[c] += p[c];
+  }
+#pragma unroll
+  for (int c = 0; c < kGrad2D; ++c) grad2d[e * kGrad2D + c] = acc[c];
+}
+
+hipError_t launch_ordered_sum(const uint32_t* pair_rec, size_t K_cap, const unsigned long long* n_dev,
+                              size_t n_entries, const float* part, uint32_t* keys_a, uint32_t* vals_a,
+                              uint32_t* keys_b, uint32_t* vals_b, uint2* eranges, SortScratch scratch,
+                              float* grad2d, hipStream_t s) {
+  if (n_entries == 0) return hipSuccess;
+  hipError_t e;
+  int in_b = 0;
+  if (K_cap > 0) {
+    hipLaunchKernelGGL(k_entry_keys, dim3(grid_for(K_cap, 256, 65536)), dim3(256), 0, s, pair_rec, K_cap, n_dev,
+                       keys_a, vals_a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int bits = 1;
+    while (bits < 32 && ((size_t)1 << bits) < n_entries) ++bits;
+    // stable: each entry's positions stay ascending
+    if ((e = radix_sort_pairs(keys_a, vals_a, keys_b, vals_b, K_cap, n_dev, bits, 0, scratch, &in_b, s)) !=
+        hipSuccess)
+      return e;
+  }
+  if ((e = launch_ranges(in_b ? keys_b : keys_a, K_cap, n_dev, eranges, (int)n_entries, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ordered_sum, dim3((unsigned)((n_entries + 255) / 256)), dim3(256), 0, s, eranges,
+                     in_b ? vals_b : vals_a, part, grad2d, n_entries);
+  return hipGetLastError();
+}
+
 hipError_t launch_compose_keys(const uint32_t* pair_tile, const uint32_t* pair_rec, const uint32_t* depth, size_t K,
                                int n, size_t n_rec, unsigned long long* keys, uint32_t* values, uint32_t* views,
                                int mode, hipStream_t s) {

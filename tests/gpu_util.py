@@ -25,9 +25,10 @@ def ambiguous(r) -> np.ndarray:
             (r["m_T"] < MARGIN_T))
 
 
-def run_gpu(scene, upstream=None, loss=False, cull=None, tile=16):
+def run_gpu(scene, upstream=None, loss=False, cull=None, tile=16, bwd=None):
     """Forward (and optionally backward) of the HIP path; returns numpy outputs.
-    cull: None (library default), "rect", "ellipse" or "exact"; tile: 8, 16 or 32."""
+    cull: None (library default), "rect", "ellipse" or "exact"; tile: 8, 16 or 32;
+    bwd: None (library default), "atomic" or "ordered" (the backward's summation order)."""
     from paper_2503_13086_amd.pipeline import Rasterizer, params_to_device
     from paper_2503_13086_amd import (GS_BUF_RECORDS, GS_BUF_DEPTH, GS_BUF_TOUCHED, GS_BUF_TILE_RECT,
                                       GS_BUF_KEYS, GS_BUF_VALUES, GS_BUF_RANGES, GS_BUF_T_FINAL,
@@ -38,6 +39,8 @@ def run_gpu(scene, upstream=None, loss=False, cull=None, tile=16):
         if cull is not None:
             gs.gs_set_cull(rz.ctx, {"rect": gs.GS_CULL_RECT, "ellipse": gs.GS_CULL_ELLIPSE,
                                     "exact": gs.GS_CULL_ELLIPSE_EXACT}[cull])
+        if bwd is not None:
+            gs.gs_set_backward_order(rz.ctx, {"atomic": gs.GS_BWD_ATOMIC, "ordered": gs.GS_BWD_ORDERED}[bwd])
         P = params_to_device(scene.params)
         rz.set_views(scene.cams, tile)
         # a binning that runs out of room (pairs or the exact pass's outcome store)
@@ -92,6 +95,7 @@ def run_gpu(scene, upstream=None, loss=False, cull=None, tile=16):
         if upstream is not None or loss:
             grad = rz.render_bwd(upstream_t)
             out["grad"] = grad[:, :scene.n].cpu().numpy()
+            out["grad2d"] = rz.buffer(gs.GS_BUF_GRAD2D).cpu().numpy().copy()
         torch.cuda.synchronize()
         return out
     finally:
