@@ -25,9 +25,19 @@ A step renders and differentiates each of its views exactly as a step with that
 view alone would on the same field: images and losses are the same bit for bit
 and the gradient is the sum of the single-view gradients (up to the order of fp32
 atomic additions).
+
+Checkpoint and resume: Engine.save(path) writes the field (parameters, Adam
+moments, step counters, capacity), the registered images (cameras, targets,
+overlap matrix, trained-iteration counts), the jobs with their plans and
+progress, the planning generator's state and the clock to one safetensors file;
+Engine.load(path) rebuilds the engine, and run() on the same arrival stream
+continues where the saved one stopped (arrivals already registered are skipped,
+unfinished jobs resume).  With the ordered backward and a plain loop the resumed
+run ends with the same bits as an uninterrupted one.
 """
 from __future__ import annotations
 
+import json
 import time
 from collections import deque
 from dataclasses import dataclass, field as dc_field
@@ -174,6 +184,66 @@ class Engine:
         self._load = torch.zeros(64, dtype=torch.float64, device=fld.device)
         self.stats = ServeStats()
         self.jobs: List[Job] = []
+        self.elapsed = 0.0          # seconds of run() so far (arrival times are measured on this clock)
+        self._hyper = dict(max_slots=max_slots, hbm_budget=hbm_budget, t_i=t_i, n_m=n_m, eta0=eta0, etaf=etaf,
+                           t_a=t_a, w_l1=w_l1, w_dssim=w_dssim, w_load=w_load, lr_group=list(self.lr_group),
+                           group_mask=group_mask)
+
+    # ---- checkpoint / resume ----
+    def save(self, path: str) -> None:
+        """Write the engine's state to `path` (safetensors; the scalar state as JSON
+        metadata).  Call between run() calls (no step in flight)."""
+        from safetensors.torch import save_file
+        self._sync()
+        fld = self.field
+        n = fld.n
+        t = {"field.params": fld.params[:, :n], "field.m": fld.m[:, :n], "field.v": fld.v[:, :n],
+             "field.step": fld.step[:n], "engine.M": torch.as_tensor(self.M)}
+        for i, tg in enumerate(self.targets):
+            t[f"engine.target.{i}"] = tg
+        t = {k: v.detach().to("cpu").contiguous() for k, v in t.items()}
+        jobs = [dict(image=j.image, plan=j.plan, arrival=j.arrival, admitted=j.admitted, done=j.done, next=j.next,
+                     local_share=None if j.local_share is None else np.asarray(j.local_share).tolist())
+                for j in self.jobs]
+        cams = [{k: np.asarray(v).tolist() for k, v in c.items()} for c in self.cams]
+        meta = dict(format=1, sh_degree=fld.sh_degree, n=n, cap=fld.cap, growths=fld.growths, hyper=self._hyper,
+                    cams=cams, trained=[int(x) for x in self.trained], jobs=jobs, elapsed=self.elapsed,
+                    pairs_per_view=self.pairs_per_view, rng=self.rng.bit_generator.state,
+                    stats=dict(self.stats.__dict__))
+        save_file(t, path, metadata={"engine": json.dumps(meta)})
+
+    @classmethod
+    def load(cls, path: str, device=0, rasterizer=None, autotuner=None) -> "Engine":
+        """An engine in the state Engine.save wrote (the field on `device`)."""
+        from safetensors import safe_open
+        from safetensors.torch import load_file
+        with safe_open(path, framework="pt") as f:
+            meta = json.loads(f.metadata()["engine"])
+        if meta.get("format") != 1:
+            raise ValueError(f"{path}: unknown checkpoint format {meta.get('format')}")
+        t = load_file(path)
+        fld = Field(t["field.params"].numpy(), meta["sh_degree"], device=device, capacity=meta["cap"])
+        fld.m[:, :fld.n].copy_(t["field.m"])
+        fld.v[:, :fld.n].copy_(t["field.v"])
+        fld.step[:fld.n].copy_(t["field.step"])
+        fld.growths = meta["growths"]
+        h = dict(meta["hyper"])
+        eng = cls(fld, rasterizer=rasterizer, autotuner=autotuner, **h)
+        eng.M = t["engine.M"].numpy().astype(np.float64)
+        eng.cams = [{k: (np.asarray(v, np.float32) if isinstance(v, list) else np.float32(v) if isinstance(v, float)
+                         else v) for k, v in c.items()} for c in meta["cams"]]
+        eng.targets = [t[f"engine.target.{i}"].to(fld.device) for i in range(len(eng.cams))]
+        eng.trained = [int(x) for x in meta["trained"]]
+        eng.jobs = [Job(image=j["image"], plan=[int(x) for x in j["plan"]], arrival=j["arrival"],
+                        admitted=j["admitted"], done=j["done"], next=j["next"],
+                        local_share=None if j["local_share"] is None else np.asarray(j["local_share"]))
+                    for j in meta["jobs"]]
+        eng.elapsed = meta["elapsed"]
+        eng.pairs_per_view = meta["pairs_per_view"]
+        eng.rng.bit_generator.state = meta["rng"]
+        for k, v in meta["stats"].items():
+            setattr(eng.stats, k, v)
+        return eng
 
     def close(self):
         self.rz.close()
@@ -289,18 +359,24 @@ class Engine:
 
     # ---- the loop ----
     def run(self, arrivals, targets: Sequence[torch.Tensor], time_scale: float = 1.0,
-            on_job_done=None) -> ServeStats:
+            on_job_done=None, max_steps: Optional[int] = None) -> ServeStats:
         """Serve a stream.  arrivals: objects with .time (s), .cam, .overlap (with
         the earlier images), .block (new Gaussians); targets: the images as device
         tensors, in arrival order.  Arrival times are multiplied by time_scale and
-        measured from the start of the call; a job's latency runs from its arrival
-        to the end of the step that completes its last iteration.  on_job_done(job)
-        is called as each job completes."""
-        pending = deque(range(len(arrivals)))
-        active: List[Job] = []
+        measured on the engine's clock (from the start of its first run); a job's
+        latency runs from its arrival to the end of the step that completes its
+        last iteration.  on_job_done(job) is called as each job completes.  Arrivals
+        the engine has already registered are skipped and its unfinished jobs
+        continue (a loaded checkpoint resumes).  max_steps: return after this many
+        engine steps of this call (then save() and a later run() carry on)."""
+        pending = deque(range(len(self.cams), len(arrivals)))
+        active: List[Job] = [j for j in self.jobs if not j.finished]
         st = self.stats
-        t0 = time.perf_counter()
+        t0 = time.perf_counter() - self.elapsed
+        steps0 = st.steps
         while pending or active:
+            if max_steps is not None and st.steps - steps0 >= max_steps:
+                break
             now = time.perf_counter() - t0
             while pending and len(active) < self.max_slots:
                 a = arrivals[pending[0]]
@@ -329,7 +405,8 @@ class Engine:
                     if on_job_done is not None:
                         on_job_done(j)
         self._sync()
-        st.makespan = time.perf_counter() - t0
+        self.elapsed = time.perf_counter() - t0
+        st.makespan = self.elapsed
         st.field_growths = self.field.growths
         st.final_n = self.field.n
         return st

@@ -122,3 +122,42 @@ def test_admission_respects_hbm_budget():
     assert len(stats.latencies) == 5
     assert 1 <= stats.max_batch <= 2
     assert stats.peak_bytes <= eng.budget
+
+
+def test_checkpoint_resume_ends_with_the_same_bits(tmp_path):
+    """Plain loop with the ordered backward (gradients the same bits on every run):
+    a run stopped after 18 steps with a job in flight, saved, loaded into a fresh
+    engine and resumed ends with the same parameters, moments, step counters and
+    per-image training counts, bit for bit, as an uninterrupted run."""
+    import paper_2503_13086_amd as gs
+    from paper_2503_13086_amd.serving import Engine
+    st = _stream(3)
+    tg = _targets(st)
+    kw = dict(max_slots=1, t_i=12, seed=2, w_l1=0.47, w_dssim=0.12, w_load=0.41)
+    ref = _engine(st, **kw)
+    try:
+        gs.gs_set_backward_order(ref.rz.ctx, gs.GS_BWD_ORDERED)
+        ref.run(st.arrivals, tg, time_scale=0.0)
+        want = {k: getattr(ref.field, k)[..., : ref.field.n].cpu().numpy().copy() for k in ("params", "m", "v", "step")}
+        want_trained = list(ref.trained)
+    finally:
+        ref.close()
+    eng = _engine(st, **kw)
+    path = str(tmp_path / "serve.safetensors")
+    try:
+        gs.gs_set_backward_order(eng.rz.ctx, gs.GS_BWD_ORDERED)
+        eng.run(st.arrivals, tg, time_scale=0.0, max_steps=18)
+        assert any(not j.finished for j in eng.jobs) and len(eng.cams) < 3
+        eng.save(path)
+    finally:
+        eng.close()
+    back = Engine.load(path)
+    try:
+        gs.gs_set_backward_order(back.rz.ctx, gs.GS_BWD_ORDERED)
+        back.run(st.arrivals, tg, time_scale=0.0)
+        assert back.trained == want_trained
+        for k, v in want.items():
+            got = getattr(back.field, k)[..., : back.field.n].cpu().numpy()
+            assert got.shape == v.shape and np.array_equal(got.view(np.uint32), v.view(np.uint32)), k
+    finally:
+        back.close()
