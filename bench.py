@@ -46,9 +46,11 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def algorithmic_bytes(n, n_p, V, K, P, tiles, ssim):
+def algorithmic_bytes(n, n_p, V, K, P, tiles, ssim, K_eff=0):
     """Compulsory HBM bytes per stage: each input read once, each output written
-    once; K = the (tile, Gaussian) pairs that belong to a tile's list."""
+    once; K = the (tile, Gaussian) pairs that belong to a tile's list, K_eff = those
+    some pixel of the tile blends (the backward adds their 9 partial gradients into
+    the Gaussian's sums: 36 B each)."""
     return {
         "preprocess": 4 * n_p * n + 64 * V * n,
         "scan_emit": 8 * V * n + 12 * K,
@@ -56,7 +58,7 @@ def algorithmic_bytes(n, n_p, V, K, P, tiles, ssim):
         "ranges": 8 * K + 8 * tiles,
         "render_fwd": 52 * K + 20 * P,
         "loss": (72 if ssim else 36) * P,
-        "render_bwd": 52 * K + 24 * P,
+        "render_bwd": 52 * K + 24 * P + 36 * K_eff,
         "preprocess_bwd": 36 * V * n + 8 * n_p * n,
         "adam": 28 * n_p * n + 8 * n,
         # grad2d and visibility per (view, Gaussian); params, m, v read and written; step
@@ -386,9 +388,11 @@ def main():
     # per-pixel work of the method, from the last timed step's forward state: the
     # Gaussians each pixel evaluated up to termination and those it blended; beside
     # them the list positions the kernels walked (up to each pixel's last blend)
-    from paper_2503_13086_amd import GS_BUF_LAST, GS_BUF_N_CONTRIB, GS_BUF_RANGES, GS_BUF_EVALS, gs_render_count
+    from paper_2503_13086_amd import (GS_BUF_LAST, GS_BUF_N_CONTRIB, GS_BUF_RANGES, GS_BUF_EVALS, GS_BUF_PAIRS_EFF,
+                                      gs_render_count)
     gs_render_count(rz.ctx)
     evals = int(rz.buffer(GS_BUF_EVALS).to(torch.int64).sum().item())
+    k_eff = int(rz.buffer(GS_BUF_PAIRS_EFF).to(torch.int64).sum().item())
     visits = int(rz.buffer(GS_BUF_LAST).to(torch.int64).sum().item())
     blends = int(rz.buffer(GS_BUF_N_CONTRIB).to(torch.int64).sum().item())
     rg = rz.buffer(GS_BUF_RANGES).view(-1, 2).to(torch.int64)
@@ -423,7 +427,7 @@ def main():
     n_p = n_params(D)
     rz.set_views(sc.cams)
     n_tiles = rz.tile_off[-1]
-    algo = algorithmic_bytes(n, n_p, V, K_valid, P, n_tiles, sc.w_dssim != 0)
+    algo = algorithmic_bytes(n, n_p, V, K_valid, P, n_tiles, sc.w_dssim != 0, k_eff)
     # dominant kernel and its roofline
     dom = max(["render_fwd", "render_bwd", "preprocess", "tile_sort", "depth_sort", "preprocess_bwd_adam", "loss",
                "emit"], key=lambda k: kern_ms[k] * kern_launches[k])
@@ -480,6 +484,7 @@ def main():
         "achievable_hbm_gbs": round(copy_gbs, 1),
         "fwd_bwd_frac_of_achievable_hbm": round(fb_gbs / copy_gbs, 4),
         "evals": evals,
+        "pairs_blended": k_eff,
         "blends": blends,
         "visits": visits,
         "measured_fma_tflops": round(fma_tflops, 2),

@@ -91,7 +91,9 @@ enum {
   GS_BUF_ALPHA_SUM = 12,/* float  [P]: sum of the alphas each pixel blended (soft Gaussian count) */
   GS_BUF_EVALS = 13,    /* uint32 [P]: Gaussians each pixel evaluated up to its termination (after
                            gs_render_count; size 0 before it) */
-  GS_N_BUFS = 14
+  GS_BUF_PAIRS_EFF = 14,/* uint32 [tiles]: entries of each tile's list that at least one of the
+                           tile's pixels blended (after gs_render_count; size 0 before it) */
+  GS_N_BUFS = 15
 };
 
 /* Kernel ids for gs_profile_read. */
@@ -296,8 +298,11 @@ gs_status gs_profile_read(gs_ctx* ctx, int32_t kernel, int64_t* launches, double
  * last gs_bin_sort exactly as gs_render_fwd does and stores, per pixel, the number
  * of Gaussians that pass its cutoff test before it stops (the blended ones plus,
  * for a pixel that stopped, the one that would have taken its transmittance below
- * 1e-4), readable as GS_BUF_EVALS.  This count depends on no tile edge.  The
- * forward state (images, transmittances, counts) is left as it was. */
+ * 1e-4), readable as GS_BUF_EVALS.  This count depends on no tile edge.  It
+ * also stores, per tile, how many entries of its list at least one of its pixels
+ * blended (GS_BUF_PAIRS_EFF: the (tile, Gaussian) pairs whose partial gradient the
+ * backward adds with atomics).  The forward state (images, transmittances,
+ * counts) is left as it was. */
 gs_status gs_render_count(gs_ctx* ctx, gs_stream stream);
 
 /* Measurement probes (no context).  gs_probe_copy copies `bytes` (a multiple of

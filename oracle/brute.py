@@ -70,3 +70,28 @@ def render_image(proj):
             lg[j, i] = l
             asum[j, i] = a
     return dict(color=col, T_final=Tf, n_contrib=nc, last_g=lg, alpha_sum=asum, n_eval=ne)
+
+
+def blended_ids(proj, i: int, j: int):
+    """The Gaussians pixel (i, j) blends, in blending order (same walk as
+    render_pixel)."""
+    vis = [g for g in range(len(proj["visible"])) if proj["visible"][g]]
+    vis.sort(key=lambda g: (int(proj["depth_bits"][g]), g))
+    u, w = proj["u"].detach().numpy(), proj["w"].detach().numpy()
+    a, b, c = proj["a"].detach().numpy(), proj["b"].detach().numpy(), proj["c"].detach().numpy()
+    o, tau = proj["o"].detach().numpy(), proj["tau"].detach().numpy()
+    T = 1.0
+    ids = []
+    for g in vis:
+        dx = float(u[g]) - (i + 0.5)
+        dy = float(w[g]) - (j + 0.5)
+        power = -0.5 * (float(a[g]) * dx * dx + float(c[g]) * dy * dy) - float(b[g]) * dx * dy
+        if power > 0.0 or power < float(tau[g]):
+            continue
+        alpha = min(ALPHA_MAX, float(o[g]) * math.exp(power))
+        Tn = T * (1.0 - alpha)
+        if Tn < T_MIN:
+            break
+        T = Tn
+        ids.append(g)
+    return ids

@@ -71,7 +71,8 @@ def blend(q, px: np.ndarray, py: np.ndarray, *, cutoffs=True, alpha_max=ALPHA_MA
     Returns dict with C [3, n] (differentiable through grad_q when given), T_final
     [n], n_contrib [n], last (position in the ordered list of the last blended
     Gaussian, -1 if none), alpha_sum [n] (sum of the blended alphas, differentiable
-    like C) and, if margins, m_cut / m_sign / m_cap / m_T [n]."""
+    like C), blended_any (positions in the ordered list of the Gaussians that at
+    least one of the pixels blends) and, if margins, m_cut / m_sign / m_cap / m_T [n]."""
     n = len(px)
     G = q["u"].shape[0]
     pxc = torch.as_tensor(np.asarray(px, np.float64) + 0.5)
@@ -99,6 +100,7 @@ def blend(q, px: np.ndarray, py: np.ndarray, *, cutoffs=True, alpha_max=ALPHA_MA
         kidx = torch.arange(nc)
         blended = ps & (kidx[None, :] < kstar[:, None])
         out["n_contrib"] = blended.sum(1).numpy().astype(np.int64)
+        out["blended_any"] = cols[blended.any(0)].numpy() if nc else np.zeros(0, np.int64)
         # Gaussians that pass the cutoff test before the walk ends (the stopping one
         # included): the pixel's work count
         out["n_eval"] = (ps & (kidx[None, :] <= kstar[:, None])).sum(1).numpy().astype(np.int64)
@@ -198,3 +200,22 @@ def render_view(proj, **kw):
 
 def render_views(projs, **kw):
     return [render_view(p, **kw) for p in projs]
+
+
+def tile_blended_counts(proj, tile: int = 16) -> np.ndarray:
+    """[tiles_y, tiles_x] for the view: per tile, the number of Gaussians that at
+    least one pixel of the tile blends (O9's cutoff, cap and stop rules).  These
+    are the (tile, Gaussian) pairs whose per-tile partial gradients the backward
+    adds into each Gaussian's sum (the splat-level accumulation of Sec. IV-E)."""
+    ids = ordered_visible(proj)
+    q = select(proj, ids)
+    W, H = proj["width"], proj["height"]
+    tx_n, ty_n = -(-W // tile), -(-H // tile)
+    out = np.zeros((ty_n, tx_n), np.int64)
+    for ty in range(ty_n):
+        for tx in range(tx_n):
+            jj, ii = np.meshgrid(np.arange(ty * tile, min((ty + 1) * tile, H)),
+                                 np.arange(tx * tile, min((tx + 1) * tile, W)), indexing="ij")
+            r = blend(q, ii.ravel(), jj.ravel(), margins=False)
+            out[ty, tx] = len(r["blended_any"])
+    return out

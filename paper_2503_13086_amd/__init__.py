@@ -23,7 +23,7 @@ GS_MAX_VIEWS = 64
 GS_N_GROUPS = 6
 (GS_BUF_RECORDS, GS_BUF_DEPTH, GS_BUF_TOUCHED, GS_BUF_TILE_RECT, GS_BUF_KEYS, GS_BUF_VALUES, GS_BUF_RANGES,
  GS_BUF_T_FINAL, GS_BUF_N_CONTRIB, GS_BUF_LAST, GS_BUF_GRAD2D, GS_BUF_PAIR_VIEW, GS_BUF_ALPHA_SUM,
- GS_BUF_EVALS) = range(14)
+ GS_BUF_EVALS, GS_BUF_PAIRS_EFF) = range(15)
 (GS_K_PREPROCESS, GS_K_DEPTH_SORT, GS_K_SCAN, GS_K_EMIT, GS_K_TILE_SORT, GS_K_RANGES, GS_K_RENDER_FWD, GS_K_LOSS,
  GS_K_RENDER_BWD, GS_K_PREPROCESS_BWD, GS_K_ADAM, GS_K_ZERO, GS_K_LOAD, GS_K_BWD_ADAM) = range(14)
 KERNEL_NAMES = ["preprocess", "depth_sort", "scan", "emit", "tile_sort", "ranges", "render_fwd", "loss",

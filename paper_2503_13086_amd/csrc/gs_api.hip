@@ -74,7 +74,7 @@ struct gs_ctx {
   DevBuf views, rec, depth, touched, rect;
   DevBuf dkey[2], dval[2], groupsums, blocksums, total, hist;
   DevBuf pkey[2], pval[2], ranges;
-  DevBuf tfinal, ncontrib, last, grad2d, lossp, aux, evals;
+  DevBuf tfinal, ncontrib, last, grad2d, lossp, aux, evals, pairs_eff;
   bool evals_ok = false;           // evals holds gs_render_count's counts for the current binning
   bool status_fresh = false;       // the status was cleared by the last gs_preprocess and not used since
   DevBuf asum, dG, loadp, loadst, kept, emitinfo, redo_list, redo_bits, status;
@@ -143,7 +143,7 @@ std::vector<DevBuf*> all_bufs(gs_ctx* c) {
   return {&c->views, &c->rec, &c->depth, &c->touched, &c->rect, &c->dkey[0], &c->dkey[1], &c->dval[0],
           &c->dval[1], &c->groupsums, &c->blocksums, &c->total, &c->hist, &c->pkey[0],
           &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->tfinal, &c->ncontrib, &c->last,
-          &c->grad2d, &c->lossp, &c->aux, &c->evals, &c->asum, &c->dG, &c->loadp, &c->loadst, &c->kept, &c->emitinfo,
+          &c->grad2d, &c->lossp, &c->aux, &c->evals, &c->pairs_eff, &c->asum, &c->dG, &c->loadp, &c->loadst, &c->kept, &c->emitinfo,
           &c->redo_list, &c->redo_bits, &c->status, &c->split_ents, &c->split_items, &c->part, &c->okey[0],
           &c->okey[1], &c->oval[0], &c->oval[1], &c->eranges};
 }
@@ -589,9 +589,11 @@ gs_status gs_render_count(gs_ctx* c, gs_stream stream) {
   GS_HIP(c, hipSetDevice(c->device));
   gs_status st;
   if ((st = ensure(c, c->evals, (size_t)c->P * 4, s)) != GS_OK) return st;
+  if ((st = ensure(c, c->pairs_eff, (size_t)c->n_tiles * 4, s)) != GS_OK) return st;
   GS_HIP(c, launch_render_count(c->views.as<ViewDev>(), c->V, c->n_tiles, c->ranges.as<uint2>(),
                                 c->pval[c->pairs_in_b].as<uint32_t>(), c->rec.as<Record>(),
-                                (uint32_t)((size_t)c->V * c->n), c->evals.as<uint32_t>(), c->tile, s));
+                                (uint32_t)((size_t)c->V * c->n), c->evals.as<uint32_t>(),
+                                c->pairs_eff.as<uint32_t>(), c->tile, s));
   c->evals_ok = true;
   return GS_OK;
 }
@@ -853,6 +855,7 @@ gs_status gs_buffer_size(const gs_ctx* c, int32_t which, size_t* bytes) {
     case GS_BUF_VALUES: case GS_BUF_PAIR_VIEW: b = c->stage >= kBinned ? c->K * 4 : 0; break;
     case GS_BUF_RANGES: b = c->stage >= kBinned ? (size_t)c->n_tiles * 8 : 0; break;
     case GS_BUF_EVALS: b = (c->stage >= kBinned && c->evals_ok) ? (size_t)c->P * 4 : 0; break;
+    case GS_BUF_PAIRS_EFF: b = (c->stage >= kBinned && c->evals_ok) ? (size_t)c->n_tiles * 4 : 0; break;
     case GS_BUF_T_FINAL: case GS_BUF_N_CONTRIB: case GS_BUF_LAST: case GS_BUF_ALPHA_SUM:
       b = c->stage >= kRendered ? (size_t)c->P * 4 : 0;
       break;
@@ -884,6 +887,7 @@ gs_status gs_copy_buffer(gs_ctx* c, int32_t which, void* dst, size_t bytes, gs_s
     case GS_BUF_LAST: src = c->last.p; break;
     case GS_BUF_ALPHA_SUM: src = c->asum.p; break;
     case GS_BUF_EVALS: src = c->evals.p; break;
+    case GS_BUF_PAIRS_EFF: src = c->pairs_eff.p; break;
     case GS_BUF_GRAD2D: src = c->grad2d.p; break;
     case GS_BUF_KEYS:
       GS_HIP(c, launch_compose_keys(c->pkey[c->pairs_in_b].as<uint32_t>(), c->pval[c->pairs_in_b].as<uint32_t>(),

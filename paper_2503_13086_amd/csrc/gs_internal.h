@@ -317,9 +317,11 @@ hipError_t launch_compose_keys(const uint32_t* pair_tile, const uint32_t* pair_r
 hipError_t launch_render_fwd(const ViewDev* views, int V, int n_tiles, const uint2* ranges, const uint32_t* pair_rec,
                              const Record* rec, uint32_t n_rec, float* color, float* t_final, uint32_t* n_contrib,
                              uint32_t* last, float* asum, int tile, hipStream_t s);
-// The forward walk counting per pixel the Gaussians evaluated up to termination.
+// The forward walk counting per pixel the Gaussians evaluated up to termination
+// (evals [P]) and per tile the list entries some pixel blended (pairs_eff [tiles]).
 hipError_t launch_render_count(const ViewDev* views, int V, int n_tiles, const uint2* ranges, const uint32_t* pair_rec,
-                               const Record* rec, uint32_t n_rec, uint32_t* evals, int tile, hipStream_t s);
+                               const Record* rec, uint32_t n_rec, uint32_t* evals, uint32_t* pairs_eff, int tile,
+                               hipStream_t s);
 // Probes: a streaming 16-byte-vector copy of `bytes` (a multiple of 16) and
 // `blocks` x 256 threads of eight fp32 FMA chains of `iters` steps.
 hipError_t launch_probe_copy(const void* src, void* dst, size_t bytes, hipStream_t s);

@@ -176,7 +176,9 @@ __device__ inline void block_masks(const float4* s0, const float4* s1, int m, fl
 
 // COUNT: the same walk, writing only the number of Gaussians each pixel evaluated up
 // to its termination (those that pass its cutoff test: the blended ones and, if it
-// stopped, the one that stopped it) into evals; the forward state is left alone.
+// stopped, the one that stopped it) into evals, and the number of the tile's list
+// entries that at least one of its pixels blended into pairs_eff[tile]; the forward
+// state is left alone.
 template <int T, bool COUNT = false>
 __global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict__ views, int V, int n_tiles_total,
                                                     const uint2* __restrict__ ranges,
@@ -185,9 +187,12 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict_
                                                     float* __restrict__ color,
                                                     float* __restrict__ t_final, uint32_t* __restrict__ n_contrib,
                                                     uint32_t* __restrict__ last, float* __restrict__ asum,
-                                                    uint32_t* __restrict__ evals = nullptr) {
+                                                    uint32_t* __restrict__ evals = nullptr,
+                                                    uint32_t* __restrict__ pairs_eff = nullptr) {
   constexpr int NT = T * T, NM = NT / 64;
   __shared__ float4 s0[NT], s1[NT], s2[NT];
+  __shared__ uint32_t s_eff[COUNT ? NT / 32 : 1];   // batch entries some pixel blended (COUNT)
+  uint32_t n_eff = 0;
   const int tile = xcd_raster_tile((int)blockIdx.x);
   if (tile >= n_tiles_total) return;
   const TileGeom tg = tile_geom<T>(views, V, tile);
@@ -203,6 +208,7 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict_
   for (uint32_t base = rg.x; base < rg.y; base += NT) {
     const uint32_t m = min((uint32_t)NT, rg.y - base);
     __syncthreads();
+    if (COUNT && threadIdx.x < NT / 32) s_eff[threadIdx.x] = 0u;
     if (threadIdx.x < m) {
       const uint32_t rid = pair_rec[base + threadIdx.x];
       if (rid < n_rec) {
@@ -244,12 +250,18 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict_
             A += ab;
             cnt += blend ? 1u : 0u;
             lastp = blend ? pos0 + j : lastp;
+            if (COUNT && wave_mask(blend) != 0ull && __lane_id() == 0u) atomicOr(&s_eff[j >> 5], 1u << (j & 31u));
             // leave the batch once every pixel of this wavefront has stopped
             mk = wave_mask(pmax == 0.0f) == 0ull ? 0ull : mk;
           }
         }
         live = wave_mask(pmax == 0.0f) != 0ull;
       }
+    }
+    if (COUNT) {
+      __syncthreads();
+      if (threadIdx.x == 0)
+        for (int w = 0; w < NT / 32; ++w) n_eff += (uint32_t)__popc(s_eff[w]);
     }
     if (__syncthreads_and(pmax < 0.0f)) break;
   }
@@ -258,6 +270,7 @@ __global__ __launch_bounds__(T * T) void k_render_fwd(const ViewDev* __restrict_
       const ViewDev& cv = views[tg.v];
       evals[(size_t)cv.pix_off + (size_t)tg.py * cv.W + tg.px] = cnt + (pmax < 0.0f ? 1u : 0u);
     }
+    if (threadIdx.x == 0) pairs_eff[tile] = n_eff;
     return;
   }
   if (tg.inside) {
@@ -612,21 +625,22 @@ hipError_t launch_render_fwd(const ViewDev* views, int V, int n_tiles, const uin
 }
 
 hipError_t launch_render_count(const ViewDev* views, int V, int n_tiles, const uint2* ranges, const uint32_t* pair_rec,
-                               const Record* rec, uint32_t n_rec, uint32_t* evals, int tile, hipStream_t s) {
+                               const Record* rec, uint32_t n_rec, uint32_t* evals, uint32_t* pairs_eff, int tile,
+                               hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   const dim3 grid((unsigned)((n_tiles + 8 * kXcdRun - 1) / (8 * kXcdRun) * (8 * kXcdRun)));
   switch (tile) {
     case 8:
       hipLaunchKernelGGL((k_render_fwd<8, true>), grid, dim3(64), 0, s, views, V, n_tiles, ranges, pair_rec, rec, n_rec,
-                         nullptr, nullptr, nullptr, nullptr, nullptr, evals);
+                         nullptr, nullptr, nullptr, nullptr, nullptr, evals, pairs_eff);
       break;
     case 16:
       hipLaunchKernelGGL((k_render_fwd<16, true>), grid, dim3(256), 0, s, views, V, n_tiles, ranges, pair_rec, rec,
-                         n_rec, nullptr, nullptr, nullptr, nullptr, nullptr, evals);
+                         n_rec, nullptr, nullptr, nullptr, nullptr, nullptr, evals, pairs_eff);
       break;
     case 32:
       hipLaunchKernelGGL((k_render_fwd<32, true>), grid, dim3(1024), 0, s, views, V, n_tiles, ranges, pair_rec, rec,
-                         n_rec, nullptr, nullptr, nullptr, nullptr, nullptr, evals);
+                         n_rec, nullptr, nullptr, nullptr, nullptr, nullptr, evals, pairs_eff);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -17,13 +17,13 @@ from . import (gs_memory_bytes, gs_load_balance, gs_create, gs_destroy, gs_layou
                gs_profile_read,
                KERNEL_NAMES, GS_BUF_RECORDS, GS_BUF_DEPTH, GS_BUF_TOUCHED, GS_BUF_TILE_RECT, GS_BUF_KEYS,
                GS_BUF_VALUES, GS_BUF_RANGES, GS_BUF_T_FINAL, GS_BUF_N_CONTRIB, GS_BUF_LAST, GS_BUF_GRAD2D,
-               GS_BUF_PAIR_VIEW, GS_BUF_ALPHA_SUM, GS_BUF_EVALS)
+               GS_BUF_PAIR_VIEW, GS_BUF_ALPHA_SUM, GS_BUF_EVALS, GS_BUF_PAIRS_EFF)
 
 _BUF_DTYPES = {GS_BUF_RECORDS: torch.uint8, GS_BUF_DEPTH: torch.int32, GS_BUF_TOUCHED: torch.int32,
                GS_BUF_TILE_RECT: torch.int16, GS_BUF_KEYS: torch.int64, GS_BUF_VALUES: torch.int32,
                GS_BUF_RANGES: torch.int32, GS_BUF_T_FINAL: torch.float32, GS_BUF_N_CONTRIB: torch.int32,
                GS_BUF_LAST: torch.int32, GS_BUF_GRAD2D: torch.float32, GS_BUF_PAIR_VIEW: torch.int32,
-               GS_BUF_ALPHA_SUM: torch.float32, GS_BUF_EVALS: torch.int32}
+               GS_BUF_ALPHA_SUM: torch.float32, GS_BUF_EVALS: torch.int32, GS_BUF_PAIRS_EFF: torch.int32}
 
 # 3DGS-lineage per-group learning rates (position is the per-view Eq. 6-8 rate's eta^0):
 # mean, log-scale, rotation, opacity, SH DC, SH rest

@@ -80,6 +80,7 @@ def run_gpu(scene, upstream=None, loss=False, cull=None, tile=16, bwd=None):
         # the work count of the same walk; it must leave the forward state alone
         gs.gs_render_count(rz.ctx)
         out["evals"] = rz.buffer(gs.GS_BUF_EVALS).cpu().numpy()
+        out["pairs_eff"] = rz.buffer(gs.GS_BUF_PAIRS_EFF).cpu().numpy().view(np.uint32).astype(np.int64)
         out["count_kept_state"] = (np.array_equal(rz.buffer(GS_BUF_T_FINAL).cpu().numpy(), out["T_final"]) and
                                    np.array_equal(rz.buffer(GS_BUF_LAST).cpu().numpy(), out["last"]))
         assert out["T_final"].size == P_

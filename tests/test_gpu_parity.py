@@ -143,6 +143,29 @@ def test_render_fwd_parity(name):
 
 
 @pytest.mark.parametrize("name", list(SCENES))
+def test_blended_pairs_per_tile(name):
+    """gs_render_count's per-tile count of list entries some pixel blended (the
+    pairs the backward sums) equals the oracle's on every tile whose pixels are
+    all unambiguous; the tiles holding an ambiguous pixel may differ."""
+    sc, projs, g, _, renders = _get(name)
+    tiles_x, tiles_y, toff = oracle.tile_layout(sc.cams, 16)
+    n_bad = n_amb_tiles = 0
+    for v, p in enumerate(projs):
+        ref = composite.tile_blended_counts(p, 16)
+        got = g["pairs_eff"][toff[v]:toff[v + 1]].reshape(tiles_y[v], tiles_x[v])
+        amb = gu.ambiguous(renders[v])
+        H, W = amb.shape
+        pad = np.zeros((tiles_y[v] * 16, tiles_x[v] * 16), bool)
+        pad[:H, :W] = amb
+        amb_tile = pad.reshape(tiles_y[v], 16, tiles_x[v], 16).any(axis=(1, 3))
+        assert np.array_equal(got[~amb_tile], ref[~amb_tile]), f"view {v}"
+        n_bad += int((got[amb_tile] != ref[amb_tile]).sum())
+        n_amb_tiles += int(amb_tile.sum())
+    assert n_bad <= n_amb_tiles
+    assert g["pairs_eff"].sum() > 0
+
+
+@pytest.mark.parametrize("name", list(SCENES))
 def test_render_bwd_parity(name):
     sc, projs, g, up, renders = _get(name)
     # the upstream of ambiguous pixels is zero on both sides

@@ -181,6 +181,27 @@ def test_vectorised_equals_scalar_brute_force(seed, deg, size):
     assert rv["n_contrib"].max() >= 4
 
 
+@pytest.mark.parametrize("seed,deg,size,tile", [(31, 0, (32, 32), 16), (32, 3, (29, 23), 8), (33, 1, (17, 40), 16)])
+def test_tile_blended_counts_equal_brute_force_union(seed, deg, size, tile):
+    """Per tile, the Gaussians some pixel blends: the vectorised count equals the
+    size of the union of the scalar walk's blended lists over the tile's pixels,
+    and every blended (pixel, Gaussian) belongs to exactly one tile's count."""
+    sc = scenegen.small_scene(seed, 64, deg, [size], log_scale_mean=-2.2)
+    pr = geometry.project_view(geometry.params_f64(sc.params, sc.n), sc.cams[0], deg)
+    got = composite.tile_blended_counts(pr, tile)
+    W, H = size
+    want = np.zeros_like(got)
+    for ty in range(got.shape[0]):
+        for tx in range(got.shape[1]):
+            u = set()
+            for j in range(ty * tile, min((ty + 1) * tile, H)):
+                for i in range(tx * tile, min((tx + 1) * tile, W)):
+                    u.update(brute.blended_ids(pr, i, j))
+            want[ty, tx] = len(u)
+    assert np.array_equal(got, want)
+    assert got.sum() > got.size        # tiles share Gaussians: several per tile on average
+
+
 
 def test_soft_count_stops_with_the_walk():
     """Four opaque Gaussians stacked on the axis: at the centre pixel the first
