@@ -258,6 +258,50 @@ gs_status resolve_pairs(const gs_ctx* cc) {
   return absorb_status(c);
 }
 
+// The raster backward into grad2d (per-entry 2D gradients), in the context's
+// summation order.
+gs_status raster_backward(gs_ctx* c, const float* dL_dcolor, hipStream_t s) {
+  const size_t NV = (size_t)c->V * c->n;
+  gs_status st;
+  if ((st = ensure(c, c->grad2d, NV * kGrad2D * 4, s)) != GS_OK) return st;
+  const float* dG = c->load_pending ? c->dG.as<float>() : nullptr;
+  if (c->bwd_order == GS_BWD_ORDERED) {
+    // one partial per pair position (the pair buffers hold pair_cap >= K pairs);
+    // grids for K when the host knows it, else for the capacity
+    const size_t cap = c->pair_cap > 0 ? c->pair_cap : 1;
+    const size_t k_grid = c->K_known ? (size_t)c->K : c->pair_cap;
+    if ((st = ensure(c, c->part, cap * kGrad2D * 4, s)) != GS_OK) return st;
+    for (int i = 0; i < 2; ++i) {
+      if ((st = ensure(c, c->okey[i], cap * 4, s)) != GS_OK) return st;
+      if ((st = ensure(c, c->oval[i], cap * 4, s)) != GS_OK) return st;
+    }
+    if ((st = ensure(c, c->eranges, NV * 8, s)) != GS_OK) return st;
+    Prof pr(c, GS_K_RENDER_BWD, s);
+    GS_HIP(c, launch_render_bwd(c->views.as<ViewDev>(), c->V, c->n_tiles, c->ranges.as<uint2>(),
+                                c->pval[c->pairs_in_b].as<uint32_t>(), c->rec.as<Record>(), (uint32_t)NV,
+                                c->tfinal.as<float>(), c->last.as<uint32_t>(), dL_dcolor, dG, c->part.as<float>(),
+                                c->tile, 1, s));
+    SortScratch sc{c->hist.as<uint32_t>()};
+    GS_HIP(c, launch_ordered_sum(c->pval[c->pairs_in_b].as<uint32_t>(), k_grid, &c->status.as<DevStatus>()->n_eff,
+                                 NV, c->part.as<float>(), c->okey[0].as<uint32_t>(), c->oval[0].as<uint32_t>(),
+                                 c->okey[1].as<uint32_t>(), c->oval[1].as<uint32_t>(), c->eranges.as<uint2>(), sc,
+                                 c->grad2d.as<float>(), s));
+    return GS_OK;
+  }
+  {
+    Prof pr(c, GS_K_ZERO, s);
+    GS_HIP(c, launch_fill_u32(c->grad2d.as<uint32_t>(), 0u, NV * kGrad2D, s));
+  }
+  {
+    Prof pr(c, GS_K_RENDER_BWD, s);
+    GS_HIP(c, launch_render_bwd(c->views.as<ViewDev>(), c->V, c->n_tiles, c->ranges.as<uint2>(),
+                                c->pval[c->pairs_in_b].as<uint32_t>(), c->rec.as<Record>(), (uint32_t)NV,
+                                c->tfinal.as<float>(), c->last.as<uint32_t>(), dL_dcolor, dG, c->grad2d.as<float>(),
+                                c->tile, 0, s));
+  }
+  return GS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -677,54 +721,6 @@ gs_status gs_load_balance(gs_ctx* c, float w_load, double* loss_out, gs_stream s
   c->load_pending = w_load != 0.0f;
   return GS_OK;
 }
-
-namespace {
-
-// The raster backward into grad2d (per-entry 2D gradients), in the context's
-// summation order.
-gs_status raster_backward(gs_ctx* c, const float* dL_dcolor, hipStream_t s) {
-  const size_t NV = (size_t)c->V * c->n;
-  gs_status st;
-  if ((st = ensure(c, c->grad2d, NV * kGrad2D * 4, s)) != GS_OK) return st;
-  const float* dG = c->load_pending ? c->dG.as<float>() : nullptr;
-  if (c->bwd_order == GS_BWD_ORDERED) {
-    // one partial per pair position (the pair buffers hold pair_cap >= K pairs);
-    // grids for K when the host knows it, else for the capacity
-    const size_t cap = c->pair_cap > 0 ? c->pair_cap : 1;
-    const size_t k_grid = c->K_known ? (size_t)c->K : c->pair_cap;
-    if ((st = ensure(c, c->part, cap * kGrad2D * 4, s)) != GS_OK) return st;
-    for (int i = 0; i < 2; ++i) {
-      if ((st = ensure(c, c->okey[i], cap * 4, s)) != GS_OK) return st;
-      if ((st = ensure(c, c->oval[i], cap * 4, s)) != GS_OK) return st;
-    }
-    if ((st = ensure(c, c->eranges, NV * 8, s)) != GS_OK) return st;
-    Prof pr(c, GS_K_RENDER_BWD, s);
-    GS_HIP(c, launch_render_bwd(c->views.as<ViewDev>(), c->V, c->n_tiles, c->ranges.as<uint2>(),
-                                c->pval[c->pairs_in_b].as<uint32_t>(), c->rec.as<Record>(), (uint32_t)NV,
-                                c->tfinal.as<float>(), c->last.as<uint32_t>(), dL_dcolor, dG, c->part.as<float>(),
-                                c->tile, 1, s));
-    SortScratch sc{c->hist.as<uint32_t>()};
-    GS_HIP(c, launch_ordered_sum(c->pval[c->pairs_in_b].as<uint32_t>(), k_grid, &c->status.as<DevStatus>()->n_eff,
-                                 NV, c->part.as<float>(), c->okey[0].as<uint32_t>(), c->oval[0].as<uint32_t>(),
-                                 c->okey[1].as<uint32_t>(), c->oval[1].as<uint32_t>(), c->eranges.as<uint2>(), sc,
-                                 c->grad2d.as<float>(), s));
-    return GS_OK;
-  }
-  {
-    Prof pr(c, GS_K_ZERO, s);
-    GS_HIP(c, launch_fill_u32(c->grad2d.as<uint32_t>(), 0u, NV * kGrad2D, s));
-  }
-  {
-    Prof pr(c, GS_K_RENDER_BWD, s);
-    GS_HIP(c, launch_render_bwd(c->views.as<ViewDev>(), c->V, c->n_tiles, c->ranges.as<uint2>(),
-                                c->pval[c->pairs_in_b].as<uint32_t>(), c->rec.as<Record>(), (uint32_t)NV,
-                                c->tfinal.as<float>(), c->last.as<uint32_t>(), dL_dcolor, dG, c->grad2d.as<float>(),
-                                c->tile, 0, s));
-  }
-  return GS_OK;
-}
-
-}  // namespace
 
 gs_status gs_render_bwd(gs_ctx* c, const float* params, const float* dL_dcolor, float* grad, int32_t accumulate,
                         gs_stream stream) {
