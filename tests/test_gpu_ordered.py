@@ -103,3 +103,32 @@ def test_ordered_fused_adam_is_the_same_bits_every_run():
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
     assert not np.array_equal(outs[0][0], start) and int(outs[0][3].max()) == 5
+
+
+def test_ordered_backward_with_the_load_balancing_term():
+    """The Eq. 9 gradient (added to every blended alpha's derivative) goes through
+    the ordered backward as through the atomic one: the two agree to rounding and
+    the ordered one is the same bits on a second run."""
+    sc = _scene()
+    outs = {}
+    for mode, runs in ((gs.GS_BWD_ATOMIC, 1), (gs.GS_BWD_ORDERED, 2)):
+        for r in range(runs):
+            rz = Rasterizer(0)
+            try:
+                gs.gs_set_backward_order(rz.ctx, mode)
+                P = params_to_device(sc.params)
+                rz.preprocess(P, sc.n, sc.sh_degree, sc.cams)
+                rz.bin_sort()
+                color = rz.render_fwd()
+                _, dl = rz.loss(color, rz.pack_images(sc.targets), 0.47, 0.12)
+                rz.load_balance(0.41)
+                grad = rz.render_bwd(dl)
+                torch.cuda.synchronize()
+                outs[(mode, r)] = grad[:, : sc.n].cpu().numpy().copy()
+            finally:
+                rz.close()
+    a, o1, o2 = outs[(gs.GS_BWD_ATOMIC, 0)], outs[(gs.GS_BWD_ORDERED, 0)], outs[(gs.GS_BWD_ORDERED, 1)]
+    assert np.array_equal(o1.view(np.uint32), o2.view(np.uint32))
+    for grp, rows in gu.param_groups(sc.sh_degree).items():
+        assert np.linalg.norm(a[rows] - o1[rows]) <= 1e-5 * (np.linalg.norm(a[rows]) + 1e-30), grp
+    assert np.abs(a).max() > 0
