@@ -8,7 +8,7 @@ newest pose of a seeded random-walk camera path plus its 8 neighbours by frustum
 overlap) at 3x 1600x1067, 3x 1296x864, 3x 979x546, loss 0.8 L1 + 0.2 D-SSIM,
 per-view learning rates from Eq. 6-7.  Prints one JSON line (rank 0).
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--workload c3|c2|c1] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--workload c3|c2|c1|c4] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -43,6 +43,8 @@ def make_workload(name):
         return scenegen.config2()
     if name == "c1":
         return scenegen.config1()
+    if name == "c4":
+        return scenegen.config4()
     raise SystemExit(f"unknown workload {name}")
 
 
