@@ -132,3 +132,13 @@ def test_ordered_backward_with_the_load_balancing_term():
     for grp, rows in gu.param_groups(sc.sh_degree).items():
         assert np.linalg.norm(a[rows] - o1[rows]) <= 1e-5 * (np.linalg.norm(a[rows]) + 1e-30), grp
     assert np.abs(a).max() > 0
+
+
+def test_unknown_backward_order_is_refused():
+    rz = Rasterizer(0)
+    try:
+        with pytest.raises(gs.GsError) as ei:
+            gs.gs_set_backward_order(rz.ctx, 7)
+        assert ei.value.status == gs.GS_ERR_INVALID
+    finally:
+        rz.close()
