@@ -534,7 +534,7 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
         p[2] = p[0] * dx;
         p[3] = p[0] * dy;
         p[4] = p[1] * dy;
-        p[5] = dLda * G;
+        p[5] = dpow;                            // dL/dopacity = (sum of dpow) / o, formed per tile
         p[6] = g0 * wgt;
         p[7] = g1 * wgt;
         p[8] = g2 * wgt;
@@ -569,6 +569,10 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
       a[2] = -0.5f * m3;
       a[3] = -m4;
       a[4] = -0.5f * m5;
+      // dL/dopacity: the exponent derivative summed over the tile's pixels is
+      // sum dL/dalpha o G, so dividing by o gives sum dL/dalpha G
+      const float o = s2[threadIdx.x].x;
+      a[5] = o > 0.0f ? a[5] / o : 0.0f;
     }
     __syncthreads();
     // one global atomic per (tile, Gaussian, component); consecutive lanes take
