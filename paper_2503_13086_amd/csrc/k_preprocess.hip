@@ -196,6 +196,18 @@ __device__ inline void gauss_geom_f(const float* __restrict__ P, int stride, int
     for (int l = 0; l < 3; ++l) G.Sig[k][l] = M[k][0] * M[l][0] + M[k][1] * M[l][1] + M[k][2] * M[l][2];
 }
 
+// The nine 2D gradients of one (view, Gaussian) entry, zeros for an entry the view
+// does not touch (one branch for the whole row).
+__device__ inline void load_grad2d(const float* __restrict__ src, uint32_t touched, float (&out)[kGrad2D]) {
+  if (touched != 0u) {
+#pragma unroll
+    for (int k = 0; k < kGrad2D; ++k) out[k] = src[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < kGrad2D; ++k) out[k] = 0.0f;
+  }
+}
+
 // With adam != 0 the gradient is applied at once (params updated in place, `out`
 // written only when not NULL); otherwise it goes to `out` (or is added to it).
 // One kernel serves both so that the gradient is the same machine arithmetic
@@ -213,6 +225,12 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(float* P, int n, int str
   if (g >= n) return;
   if (adam && st && st->code != GS_OK) return;   // the binning of this step failed: leave the state
   constexpr int K = (D + 1) * (D + 1);
+  // the loads of the view loop run ahead of it: the touched flag of view v + 2 and
+  // the 2D gradient of view v + 1 are in flight while view v is processed (at two
+  // waves per SIMD nothing else would cover their latency)
+  uint32_t t_next = V > 0 ? touched[g] : 0u;                  // view v + 1
+  uint32_t t_after = V > 1 ? touched[(size_t)n + g] : 0u;     // view v + 2
+  const uint32_t step_old = adam ? step[g] : 0u;
   GaussF G;
   gauss_geom_f(P, stride, g, G);
 
@@ -227,11 +245,31 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(float* P, int n, int str
     f[i] = P[(size_t)(11 + i) * stride + g];
   }
 
+  // the per-view learning-rate factor of the fused step (the mean of the scales of
+  // the views that see the Gaussian, else of all), summed in view order as
+  // adam_view_factor does, from the flags the loop reads anyway
+  const bool fold_factor = adam && a.n_views == V;
+  float fs = 0.0f, fall = 0.0f;
+  int fc = 0;
+  float g2n[kGrad2D];
+  load_grad2d(grad2d + (size_t)g * kGrad2D, t_next, g2n);
   for (int v = 0; v < V; ++v) {
-    const size_t idx = (size_t)v * n + g;
-    if (touched[idx] == 0u) continue;
+    const uint32_t t_cur = t_next;
+    float g2[kGrad2D];
+#pragma unroll
+    for (int k = 0; k < kGrad2D; ++k) g2[k] = g2n[k];
+    t_next = t_after;
+    if (v + 1 < V) load_grad2d(grad2d + ((size_t)(v + 1) * n + g) * kGrad2D, t_next, g2n);
+    t_after = v + 2 < V ? touched[(size_t)(v + 2) * n + g] : 0u;
+    if (fold_factor) {
+      fall += a.scale[v];
+      if (t_cur != 0u) {
+        fs += a.scale[v];
+        ++fc;
+      }
+    }
+    if (t_cur == 0u) continue;
     const ViewDev& cv = views[v];
-    const float* g2 = grad2d + idx * kGrad2D;
     const float gu = g2[0], gw = g2[1], ga = g2[2], gb = g2[3], gc = g2[4];
     go += g2[5];
     const float grgb[3] = {g2[6], g2[7], g2[8]};
@@ -378,26 +416,45 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(float* P, int n, int str
   for (int k = 0; k < 4; ++k) outv[6 + k] = (gq[k] - H.q[k] * qd) / H.qn;
   outv[10] = (double)go * H.o * (1.0 - H.o);
   if (adam) {
-    const uint32_t k = step[g] + 1u;
+    const uint32_t k = step_old + 1u;
     step[g] = k;
     float bc1, bc2;
     adam_bias(a, k, bc1, bc2);
-    const float factor = adam_view_factor(a, touched, n, g);
+    const float factor = fold_factor ? (fc > 0 ? fs / (float)fc : fall / (float)a.n_views)
+                                     : adam_view_factor(a, touched, n, g);
     constexpr int ROWS = 11 + 3 * K, B = 8;
     float grv[ROWS];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) grv[r] = r < 11 ? (float)outv[r] : gf[r - 11];
-    // rows in groups of B: all loads of a group issued before its stores
+    // rows in groups of B, the loads of the next group issued before this group's
+    // arithmetic and stores (rows of one thread never alias: each group's loads
+    // precede its own stores, and no group reads another's rows)
+    float np[B], nm[B], nv[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      if (j < ROWS) {
+        const size_t i = (size_t)j * stride + g;
+        np[j] = P[i];
+        nm[j] = M[i];
+        nv[j] = Vv[i];
+      }
+    }
 #pragma unroll
     for (int r0 = 0; r0 < ROWS; r0 += B) {
       float pp[B], mm[B], vv[B];
 #pragma unroll
       for (int j = 0; j < B; ++j) {
-        if (r0 + j < ROWS) {
-          const size_t i = (size_t)(r0 + j) * stride + g;
-          pp[j] = P[i];
-          mm[j] = M[i];
-          vv[j] = Vv[i];
+        pp[j] = np[j];
+        mm[j] = nm[j];
+        vv[j] = nv[j];
+      }
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        if (r0 + B + j < ROWS) {
+          const size_t i = (size_t)(r0 + B + j) * stride + g;
+          np[j] = P[i];
+          nm[j] = M[i];
+          nv[j] = Vv[i];
         }
       }
 #pragma unroll
