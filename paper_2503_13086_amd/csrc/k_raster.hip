@@ -320,6 +320,23 @@ __device__ inline float fold_dpp(float a, float b, bool hi) {
   return own + dpp<CTRL>(give);
 }
 
+// fold_dpp for a selector that is a DPP bank bit (bit 3: banks 2 and 3 of each row;
+// bit 2: banks 1 and 3), without the two selects: every lane forms a plus its
+// partner's a, then the lanes of the selected banks overwrite that with b plus the
+// partner's b (a DPP add that writes those banks only; the nop gives the two wait
+// states a DPP read of a VGPR just written by the VALU needs).  The same sums in
+// the same order as fold_dpp.
+__device__ inline float fold_ror8_bit3(float a, float b) {
+  float t = a + dpp<0x128>(a);
+  asm("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 row_ror:8 row_mask:0xf bank_mask:0xc bound_ctrl:1" : "+v"(t) : "v"(b));
+  return t;
+}
+__device__ inline float fold_mirror_bit2(float a, float b) {
+  float t = a + dpp<0x141>(a);
+  asm("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 row_half_mirror row_mask:0xf bank_mask:0xa bound_ctrl:1" : "+v"(t) : "v"(b));
+  return t;
+}
+
 // Reduce-scatter of nine per-lane values over the wave, added into an LDS row.
 // Each level halves the registers by pairing lanes whose selector bit differs
 // (across wave halves, across row pairs, across half-rows, across the halves of
@@ -334,14 +351,14 @@ __device__ inline float fold_dpp(float a, float b, bool hi) {
 // both ninth values at lane bit 1 set), which costs 45 instructions instead of 56.
 typedef __attribute__((address_space(3))) float LdsFloat;
 
-__device__ inline float reduce8_part(const float (&v)[kGrad2D], bool bit3) {
+__device__ inline float reduce8_part(const float (&v)[kGrad2D]) {
   const float b0 = fold32(v[0], v[1]);
   const float b1 = fold32(v[2], v[3]);
   const float b2 = fold32(v[4], v[5]);
   const float b3 = fold32(v[6], v[7]);
   const float c0 = fold16(b0, b1);
   const float c1 = fold16(b2, b3);
-  return fold_dpp<0x128>(c0, c1, bit3);
+  return fold_ror8_bit3(c0, c1);
 }
 
 __device__ inline void lds_add(uint32_t addr, float x) {
@@ -350,10 +367,10 @@ __device__ inline void lds_add(uint32_t addr, float x) {
 
 // d = reduce8_part of the record's first eight values, v8 its ninth; lanes with
 // `add` add their total at addr (row and column included).
-__device__ inline void reduce9_tail(float d, float v8, uint32_t addr, bool add, bool bit2) {
+__device__ inline void reduce9_tail(float d, float v8, uint32_t addr, bool add) {
   const float c2 = fold16(fold32(v8, 0.0f), 0.0f);
   const float d1 = c2 + dpp<0x128>(c2);
-  float e = fold_dpp<0x141>(d, d1, bit2);
+  float e = fold_mirror_bit2(d, d1);
   e += dpp<0x4E>(e);
   e += dpp<0xB1>(e);
   if (add) lds_add(addr, e);
@@ -362,10 +379,10 @@ __device__ inline void reduce9_tail(float d, float v8, uint32_t addr, bool add, 
 // Records a and b (parts da, db, ninth values a8, b8) reduced together; lanes that
 // hold a total of a add it at addr_a, those holding one of b at addr_b.
 __device__ inline void reduce18_tail(float da, float a8, float db, float b8, uint32_t addr_a, uint32_t addr_b,
-                                     bool add_a, bool add_b, bool bit2, bool bit1) {
+                                     bool add_a, bool add_b, bool bit1) {
   const float m2 = fold16(fold32(a8, b8), 0.0f);
   const float m3 = m2 + dpp<0x128>(m2);
-  const float e0 = fold_dpp<0x141>(da, db, bit2);
+  const float e0 = fold_mirror_bit2(da, db);
   const float e1 = m3 + dpp<0x141>(m3);
   float f = fold_dpp<0x4E>(e0, e1, bit1);
   f += dpp<0xB1>(f);
@@ -456,7 +473,7 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
   const int wave_last = (int)mx;           // this wave never needs list positions >= wave_last
   const unsigned lane = __lane_id();
   const int slot = reduce9_slot(lane), slot18 = reduce18_slot(lane);
-  const bool bit3 = (lane & 8u) != 0u, bit2 = (lane & 4u) != 0u, bit1 = (lane & 2u) != 0u;
+  const bool bit1 = (lane & 2u) != 0u;
   const bool add9 = slot >= 0, add_a = slot18 >= 0 && slot18 < kGrad2D, add_b = slot18 >= kGrad2D;
   // 32-bit LDS byte addresses of this lane's columns in acc[0] for the two
   // reductions (plain integer arithmetic in the loop: the compiler would otherwise
@@ -505,6 +522,9 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
         const float dx = a0.x - fx, dy = a0.y - fy;
         const float p2 = gauss_power2(a0.z, a0.w, a1.x, dx, dy);
         const bool on = (uint32_t)j < lrel && p2 <= 0.0f && p2 >= a1.y;
+        // (a2 is fetched with a0 and a1, before the branch: one address, and the blend
+        // below waits for nothing more)
+        asm volatile("" ::"v"(a2.x), "v"(a2.y), "v"(a2.z), "v"(a2.w));
         if (wave_mask(on) == 0ull) continue;    // no pixel of this wave blended it
         // straight-line update; lanes that did not blend this Gaussian keep their state
         // and contribute zeros
@@ -538,18 +558,17 @@ __global__ __launch_bounds__(T * T) void k_render_bwd(const ViewDev* __restrict_
         p[6] = g0 * wgt;
         p[7] = g1 * wgt;
         p[8] = g2 * wgt;
-        const float d = reduce8_part(p, bit3);
+        const float d = reduce8_part(p);
         if (ja < 0) {
           da = d;
           a8 = p[8];
           ja = j;
         } else {
-          reduce18_tail(da, a8, d, p[8], col18 + acc_row_offset(ja), col18 + acc_row_offset(j), add_a, add_b, bit2,
-                        bit1);
+          reduce18_tail(da, a8, d, p[8], col18 + acc_row_offset(ja), col18 + acc_row_offset(j), add_a, add_b, bit1);
           ja = -1;
         }
       }
-      if (ja >= 0) reduce9_tail(da, a8, col9 + acc_row_offset(ja), add9, bit2);
+      if (ja >= 0) reduce9_tail(da, a8, col9 + acc_row_offset(ja), add9);
     }
     __syncthreads();
     if ((int)threadIdx.x < m) {
