@@ -26,6 +26,19 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kItems = kSortTileItems / kThreads;   // items per thread (16)
 constexpr int kRadix = 256;
 
+// Wave-inclusive prefix of x over lanes (DPP: shifts within rows of 16 lanes, then
+// the last lane of a row broadcast into the rows after it; 0, the identity, is the
+// value of lanes with no source, so each step is one DPP add).  Whole wavefronts only.
+__device__ inline uint32_t wave_incl_scan(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);   // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);   // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);   // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);   // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
+  return x;
+}
+
 __device__ inline uint64_t lanemask_lt() {
   const unsigned lane = __lane_id();
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -198,20 +211,12 @@ __global__ __launch_bounds__(kChunkScanThreads) void k_radix_chunk_scan(uint32_t
     }
   }
   if (pi == 0) {   // the first kRadix threads: exclusive scan of the digit totals
-    uint32_t incl = tot;
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t y = __shfl_up(incl, off);
-      if ((int)__lane_id() >= off) incl += y;
-    }
+    const uint32_t incl = wave_incl_scan(tot);
     if (__lane_id() == 63) wsum[d / 64] = incl;
   }
   __syncthreads();
   if (pi == 0) {
-    uint32_t incl = tot;
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t y = __shfl_up(incl, off);
-      if ((int)__lane_id() >= off) incl += y;
-    }
+    const uint32_t incl = wave_incl_scan(tot);
     uint32_t wpre = 0;
     for (int w = 0; w < d / 64; ++w) wpre += wsum[w];
     digit_base[d] = wpre + incl - tot;
@@ -353,11 +358,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_radix_scatter(const uint32_
       wc[w][tid] = tot;
       tot += c;
     }
-    incl = tot;
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t y = __shfl_up(incl, off);
-      if ((int)__lane_id() >= off) incl += y;
-    }
+    incl = wave_incl_scan(tot);
     if (__lane_id() == 63) wsum[wave] = incl;
   }
   __syncthreads();
@@ -546,17 +547,6 @@ __device__ inline void rect_cell(uint32_t local, uint32_t nx, uint32_t& tx, uint
   tx = local - ty * nx;
 }
 
-// Wave-inclusive prefix of x over lanes, in the same DPP steps as wave_incl_max
-// (0, the identity, for lanes with no source: each step one DPP add).
-__device__ inline uint32_t wave_incl_scan(uint32_t x) {
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);   // row_shr:1
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);   // row_shr:2
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);   // row_shr:4
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);   // row_shr:8
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
-  return x;
-}
 
 // Wave-wide counter update: lane 0 adds `total` to *ctr; every lane gets the old
 // value (0 and no update when total is 0).
