@@ -323,17 +323,18 @@ __device__ inline float fold_dpp(float a, float b, bool hi) {
 // fold_dpp for a selector that is a DPP bank bit (bit 3: banks 2 and 3 of each row;
 // bit 2: banks 1 and 3), without the two selects: every lane forms a plus its
 // partner's a, then the lanes of the selected banks overwrite that with b plus the
-// partner's b (a DPP add that writes those banks only; the nop gives the two wait
-// states a DPP read of a VGPR just written by the VALU needs).  The same sums in
-// the same order as fold_dpp.
+// partner's b (a DPP add that writes those banks only).  A DPP read of a VGPR that
+// the VALU wrote in the last two cycles needs two wait states, and the compiler
+// does not see inside the asm: the nops before and after cover the asm's own read
+// and any DPP read of its result.  The same sums in the same order as fold_dpp.
 __device__ inline float fold_ror8_bit3(float a, float b) {
   float t = a + dpp<0x128>(a);
-  asm("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 row_ror:8 row_mask:0xf bank_mask:0xc bound_ctrl:1" : "+v"(t) : "v"(b));
+  asm("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 row_ror:8 row_mask:0xf bank_mask:0xc bound_ctrl:1\n\ts_nop 1" : "+v"(t) : "v"(b));
   return t;
 }
 __device__ inline float fold_mirror_bit2(float a, float b) {
   float t = a + dpp<0x141>(a);
-  asm("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 row_half_mirror row_mask:0xf bank_mask:0xa bound_ctrl:1" : "+v"(t) : "v"(b));
+  asm("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 row_half_mirror row_mask:0xf bank_mask:0xa bound_ctrl:1\n\ts_nop 1" : "+v"(t) : "v"(b));
   return t;
 }
 
