@@ -303,6 +303,14 @@ __device__ inline float fold16(float a, float b) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
+// x plus lane l ^ 16's x (the partner row within each half of the wave), through the
+// LDS crossbar (ds_swizzle, no memory access) rather than a VALU swap: the ninth
+// values need only the rows that the even rows end up with.
+__device__ inline float add_row_pair(float x) {
+  // bit mode: and_mask 0x1f, or_mask 0, xor_mask 0x10
+  return x + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x401F));
+}
+
 // Lane l receives v from the lane the DPP control names (row_ror:8 = 0x128: lane
 // l ^ 8 of its row; row_half_mirror = 0x141: lane 7 - l of its half-row;
 // quad_perm [2,3,0,1] = 0x4E and [1,0,3,2] = 0xB1: lanes l ^ 2 and l ^ 1).
@@ -369,7 +377,7 @@ __device__ inline void lds_add(uint32_t addr, float x) {
 // d = reduce8_part of the record's first eight values, v8 its ninth; lanes with
 // `add` add their total at addr (row and column included).
 __device__ inline void reduce9_tail(float d, float v8, uint32_t addr, bool add) {
-  const float c2 = fold16(fold32(v8, 0.0f), 0.0f);
+  const float c2 = add_row_pair(fold32(v8, 0.0f));
   const float d1 = c2 + dpp<0x128>(c2);
   float e = fold_mirror_bit2(d, d1);
   e += dpp<0x4E>(e);
@@ -381,7 +389,7 @@ __device__ inline void reduce9_tail(float d, float v8, uint32_t addr, bool add) 
 // hold a total of a add it at addr_a, those holding one of b at addr_b.
 __device__ inline void reduce18_tail(float da, float a8, float db, float b8, uint32_t addr_a, uint32_t addr_b,
                                      bool add_a, bool add_b, bool bit1) {
-  const float m2 = fold16(fold32(a8, b8), 0.0f);
+  const float m2 = add_row_pair(fold32(a8, b8));
   const float m3 = m2 + dpp<0x128>(m2);
   const float e0 = fold_mirror_bit2(da, db);
   const float e1 = m3 + dpp<0x141>(m3);
