@@ -241,6 +241,22 @@ def test_tile_rect_brute_force(tile):
                              for ty in range(pr["ty0"][g], pr["ty1"][g] + 1)}
 
 
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_tile_layout_brute_force(tile):
+    # ragged views: the tiles of a view are the distinct (x // tile, y // tile) of
+    # its pixels, numbered row by row after the tiles of the views before it
+    sizes = [(100, 37), (64, 64), (17, 129), (1, 1), (33, 8)]
+    cams = [{"width": w, "height": h} for w, h in sizes]
+    tx, ty, off = geometry.tile_layout(cams, tile)
+    assert off[0] == 0 and len(off) == len(sizes) + 1
+    for v, (w, h) in enumerate(sizes):
+        cols = {x // tile for x in range(w)}
+        rows = {y // tile for y in range(h)}
+        assert (tx[v], ty[v]) == (len(cols), len(rows))
+        ids = {off[v] + (y // tile) * tx[v] + x // tile for y in range(h) for x in range(w)}
+        assert ids == set(range(off[v], off[v + 1]))
+
+
 def test_binning_sorted_and_ranges():
     sc = scenegen.small_scene(12, 120, 1, [(40, 29), (33, 50)], log_scale_mean=-2.4)
     projs = geometry.project_views(sc.params, sc.n, 1, sc.cams, 16)

@@ -198,6 +198,24 @@ def test_adam_view_factor_and_first_step_closed_form():
     assert np.allclose(p1[3:6], -2.0, rtol=1e-12) and np.allclose(p1[14], -6.0, rtol=1e-12)
 
 
+def test_adam_group_rates_follow_the_parameter_layout():
+    # Every row's first step with a constant gradient moves it by its group's rate
+    # (update = lr / (1 + eps)); the groups follow the parameter layout: mean rows
+    # 0-2, log-scale 3-5, quaternion 6-9, opacity 10, SH coefficient 0 (the DC
+    # term, three channels) 11-13, the other SH coefficients after them.
+    lr = [1.0, 2.0, 3.0, 4.0, 5.0, 6.0]
+    for deg in range(4):
+        rows = 11 + 3 * (deg + 1) ** 2
+        want = np.empty(rows)
+        want[0:3], want[3:6], want[6:10], want[10] = lr[0], lr[1], lr[2], lr[3]
+        for k in range((deg + 1) ** 2):
+            want[11 + 3 * k: 14 + 3 * k] = lr[4] if k == 0 else lr[5]
+        n = 3
+        p1, _, _, _ = adam.adam_step(np.zeros((rows, n)), np.ones((rows, n)), np.zeros((rows, n)),
+                                     np.zeros((rows, n)), np.zeros(n, np.int64), lr)
+        assert np.allclose(-p1, want[:, None], rtol=1e-12), deg
+
+
 def test_schedule_eq6_to_eq8():
     e0, ef, ta = 1.6e-4, 1.6e-6, 200
     assert schedule.lr_current(0, e0, ef, ta) == pytest.approx(e0, rel=1e-15)

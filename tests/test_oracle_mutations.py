@@ -140,6 +140,23 @@ MUTATIONS = [
      [(TM.test_stop_margin_flags_every_stop_flip, ())]),
     ("composite", 'out["m_T"] = torch.where(upto_c, m_T, inf)', 'out["m_T"] = torch.where(blended, m_T, inf)',
      [(TM.test_stop_margin_flags_every_stop_flip, ())]),
+    ("geometry", "o = 1.0 / (1.0 + torch.exp(-P[10]))", "o = 1.0 / (1.0 + torch.exp(P[10]))",
+     [(TG.test_opacity_is_logistic, ())]),
+    ("geometry", "s = [torch.exp(P[3 + i]) for i in range(3)]", "s = [torch.exp(0.5 * P[3 + i]) for i in range(3)]",
+     [(TG.test_isotropic_on_axis_closed_form, ())]),
+    ("geometry", "M = [[R[k][j] * s[j] for j in range(3)] for k in range(3)]",
+     "M = [[R[j][k] * s[j] for j in range(3)] for k in range(3)]", [(TG.test_covariance_eigen_and_matrix_route, ())]),
+    ("geometry", 'tiles_y = [(c["height"] + tile - 1) // tile for c in cams]',
+     'tiles_y = [c["height"] // tile for c in cams]', [(TG.test_tile_layout_brute_force, (16,))]),
+    ("sh", "acc = acc * z + cf", "acc = acc * z - cf", [(TR.test_sh_matches_scipy_real_form, ())]),
+    ("adam", "g[11:14] = GROUP_SH_DC", "g[11:13] = GROUP_SH_DC", [(TL.test_adam_group_rates_follow_the_parameter_layout, ())]),
+    ("adam", "g[6:10] = GROUP_ROT", "g[6:10] = GROUP_SCALE", [(TL.test_adam_group_rates_follow_the_parameter_layout, ())]),
+    ("schedule", "return (lr_c[j] + sum(M[i, j] * lr_c[i] for i in nb)) / (len(nb) + 1)",
+     "return (lr_c[j] + sum(lr_c[i] for i in nb)) / (len(nb) + 1)", [(TL.test_schedule_eq6_to_eq8, ())]),
+    ("schedule", "raw = {i: (1.0 - math.exp(-weights[i])) for i in top}", "raw = {i: weights[i] for i in top}",
+     [(TL.test_schedule_eq3_to_eq5, ())]),
+    ("schedule", "for i in sorted(top, key=lambda i: (-(share[i] - base[i]), i))[:rem]:",
+     "for i in sorted(top, key=lambda i: ((share[i] - base[i]), i))[:rem]:", [(TL.test_schedule_iteration_plan, ())]),
 ]
 
 
