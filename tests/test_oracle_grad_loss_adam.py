@@ -46,6 +46,9 @@ def test_ssim_textbook_and_constant_images():
     ref = ((2 * mx * my + c1) * (2 * cxy + c2)) / ((mx ** 2 + my ** 2 + c1) * (vx + vy + c2))
     got = loss.ssim_map(torch.as_tensor(x), torch.as_tensor(y)).numpy()
     assert np.abs(got - ref).max() < 1e-12
+    # the loss of one view: w_l1 mean |x - y| + w_dssim (1 - mean SSIM), means over channels and pixels
+    val = loss.image_loss(torch.as_tensor(x), torch.as_tensor(y), 0.3, 0.7).item()
+    assert val == pytest.approx(0.3 * np.abs(x - y).mean() + 0.7 * (1.0 - ref.mean()), rel=1e-12)
     a, b = 0.2, 0.7
     m = loss.ssim_map(torch.full((1, 20, 20), a, dtype=torch.float64), torch.full((1, 20, 20), b, dtype=torch.float64))
     assert abs(m[0, 10, 10].item() - (2 * a * b + c1) / (a * a + b * b + c1)) < 1e-12

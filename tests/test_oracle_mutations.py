@@ -157,6 +157,13 @@ MUTATIONS = [
      [(TL.test_schedule_eq3_to_eq5, ())]),
     ("schedule", "for i in sorted(top, key=lambda i: (-(share[i] - base[i]), i))[:rem]:",
      "for i in sorted(top, key=lambda i: ((share[i] - base[i]), i))[:rem]:", [(TL.test_schedule_iteration_plan, ())]),
+    ("loss", "val = val + w_dssim * (1.0 - ssim_map(x, y).mean())",
+     "val = val + w_dssim * (1.0 - ssim_map(x, y).mean()) * 0.5", [(TL.test_ssim_textbook_and_constant_images, ())]),
+    ("adam", "s = (vs[:, None] * vis).sum(0)", "s = (vs[:, None]).sum(0)",
+     [(TL.test_adam_view_factor_and_first_step_closed_form, ())]),
+    ("adam", "if (group_mask >> groups[r]) & 1:", "if True:", [(TL.test_adam_view_factor_and_first_step_closed_form, ())]),
+    ("composite", 'order = np.lexsort((vis, proj["depth_bits"][vis]))',
+     'order = np.lexsort((-vis, proj["depth_bits"][vis]))', [(TR.test_two_gaussians_depth_order, ())]),
 ]
 
 

@@ -97,13 +97,15 @@ def test_two_gaussians_depth_order():
     c0 = 0.5 / math.sqrt(math.pi)
     P[11:14, 0] = (np.array([1.0, 0.0, 0.0]) - 0.5) / c0
     P[11:14, 1] = (np.array([0.0, 0.0, 1.0]) - 0.5) / c0
-    for z0, z1 in [(2.0, 3.0), (3.0, 2.0)]:
+    # (equal depths: the lower index is in front)
+    for z0, z1 in [(2.0, 3.0), (3.0, 2.0), (2.5, 2.5)]:
         Q = P.copy()
         Q[2] = [z0, z1]
         Q[0] = [0.01 * z0, -0.02 * z1]
         pr = geometry.project_view(geometry.params_f64(Q, 2), cam, 0)
         r = composite.render_view(pr)
-        first, second = (0, 1) if z0 < z1 else (1, 0)
+        first, second = (0, 1) if z0 <= z1 else (1, 0)
+        assert (z0 != z1) or pr["depth_bits"][0] == pr["depth_bits"][1]
         for (j, i) in [(16, 16), (15, 17), (18, 14)]:
             al = []
             for g in range(2):
