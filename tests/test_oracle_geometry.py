@@ -331,6 +331,36 @@ def test_box_min_matches_dense_sampling():
 
 
 @pytest.mark.parametrize("tile", [16, 8])
+def test_ellipse_culling_box_is_the_hull_of_pixel_centres(tile):
+    """A pair is kept exactly when the cutoff ellipse meets the rectangle spanned by
+    the centres of the tile's pixels that lie inside the image (the box found here by
+    listing those pixels; its minimum of the quadratic form by box_min_q, pinned by
+    dense sampling).  Ragged image sides make the last row and column of tiles
+    partial."""
+    W, H = 90, 70
+    sc = scenegen.small_scene(15, 400, 0, [(W, H)], log_scale_mean=-1.8, half_extent=1.6, depth=2.5)
+    p = geometry.project_views(sc.params, sc.n, 0, sc.cams, tile)[0]
+    full = binning.bin_pairs([p], sc.cams, tile, cull="rect")
+    kept = binning.bin_pairs([p], sc.cams, tile, cull="ellipse")
+    tiles_x = (W + tile - 1) // tile
+    kset = set(zip((kept["keys"] >> np.uint64(32)).astype(np.int64).tolist(), kept["values"].tolist()))
+    u, w = p["u"].numpy(), p["w"].numpy()
+    a, b, c, tau = (p[k].numpy() for k in ("a", "b", "c", "tau"))
+    want = set()
+    for key, g in zip(full["keys"], full["values"]):
+        t, g = int(key >> np.uint64(32)), int(g)
+        tx, ty = t % tiles_x, t // tiles_x
+        xs = [x + 0.5 for x in range(tx * tile, (tx + 1) * tile) if x < W]
+        ys = [y + 0.5 for y in range(ty * tile, (ty + 1) * tile) if y < H]
+        q = binning.box_min_q(np.array([a[g]]), np.array([b[g]]), np.array([c[g]]), np.array([min(xs) - u[g]]),
+                              np.array([max(xs) - u[g]]), np.array([min(ys) - w[g]]), np.array([max(ys) - w[g]]))
+        if q[0] <= -2.0 * tau[g]:
+            want.add((t, g))
+    assert kset == want
+    assert len(want) < len(full["keys"])
+
+
+@pytest.mark.parametrize("tile", [16, 8])
 def test_ellipse_culling_keeps_every_contributing_tile(tile):
     """Every (Gaussian, tile) pair with a pixel centre that passes the cutoff is
     kept; the culled pairs hold none; culling removes a real share of the rect."""

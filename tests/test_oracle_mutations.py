@@ -164,6 +164,11 @@ MUTATIONS = [
     ("adam", "if (group_mask >> groups[r]) & 1:", "if True:", [(TL.test_adam_view_factor_and_first_step_closed_form, ())]),
     ("composite", 'order = np.lexsort((vis, proj["depth_bits"][vis]))',
      'order = np.lexsort((-vis, proj["depth_bits"][vis]))', [(TR.test_two_gaussians_depth_order, ())]),
+    ("binning", "x1 = np.minimum(tx * tile + (tile - 0.5), W - 0.5)", "x1 = tx * tile + (tile - 0.5)",
+     [(TG.test_ellipse_culling_box_is_the_hull_of_pixel_centres, (16,))]),
+    ("binning", "y0 = ty * tile + 0.5", "y0 = ty * tile", [(TG.test_ellipse_culling_box_is_the_hull_of_pixel_centres, (16,))]),
+    ("binning", 'ty = p["ty0"][rep] + local // nx', 'ty = p["ty0"][rep] + local % nx',
+     [(TG.test_binning_sorted_and_ranges, ())]),
 ]
 
 
