@@ -169,6 +169,22 @@ MUTATIONS = [
     ("binning", "y0 = ty * tile + 0.5", "y0 = ty * tile", [(TG.test_ellipse_culling_box_is_the_hull_of_pixel_centres, (16,))]),
     ("binning", 'ty = p["ty0"][rep] + local // nx', 'ty = p["ty0"][rep] + local % nx',
      [(TG.test_binning_sorted_and_ranges, ())]),
+    ("geometry", "lam = 0.5 * (S00 + S11) + torch.sqrt(", "lam = 0.5 * (S00 + S11) - torch.sqrt(",
+     [(TG.test_conic_and_extent, ())]),
+    ("geometry", "tau = torch.clamp(-torch.log(ALPHA_MIN_INV * o), min=CUTOFF_FLOOR)", "tau = -torch.log(ALPHA_MIN_INV * o)",
+     [(TG.test_cutoff_exponent, ())]),
+    ("geometry", "i1 = np.nan_to_num(np.clip(xhi, -1, W - 1), nan=-1).astype(np.int64)",
+     "i1 = np.nan_to_num(np.clip(xhi, -1, W), nan=-1).astype(np.int64)", [(TG.test_tile_rect_brute_force, (16,))]),
+    ("geometry", "tx0, tx1, ty0, ty1 = i0 // tile, i1 // tile, j0 // tile, j1 // tile",
+     "tx0, tx1, ty0, ty1 = i0 // tile, i1 // tile + 1, j0 // tile, j1 // tile",
+     [(TG.test_ellipse_culling_box_is_the_hull_of_pixel_centres, (16,))]),
+    ("geometry", "depth_bits = tz.detach().to(torch.float32).numpy().view(np.uint32).copy()",
+     "depth_bits = tz.detach().to(torch.float64).numpy().view(np.uint64).astype(np.uint32)",
+     [(TR.test_two_gaussians_depth_order, ())]),
+    ("geometry", "rgb = torch.clamp(raw, min=0.0)", "rgb = raw", [(TG.test_view_dependent_colour_independent_route, ())]),
+    ("geometry", "acc = SH_OFFSET + 0.0 * mx", "acc = 0.0 * mx", [(TR.test_sh_degree0_colour, ())]),
+    ("geometry", "dx_, dy_, dz_ = mx - oc[0], my - oc[1], mz - oc[2]", "dx_, dy_, dz_ = mx, my, mz",
+     [(TG.test_view_dependent_colour_independent_route, ())]),
 ]
 
 
