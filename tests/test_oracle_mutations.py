@@ -185,6 +185,14 @@ MUTATIONS = [
     ("geometry", "acc = SH_OFFSET + 0.0 * mx", "acc = 0.0 * mx", [(TR.test_sh_degree0_colour, ())]),
     ("geometry", "dx_, dy_, dz_ = mx - oc[0], my - oc[1], mz - oc[2]", "dx_, dy_, dz_ = mx, my, mz",
      [(TG.test_view_dependent_colour_independent_route, ())]),
+    ("composite", "pxc = torch.as_tensor(np.asarray(px, np.float64) + 0.5)",
+     "pxc = torch.as_tensor(np.asarray(px, np.float64))", [(TR.test_cutoffs_off_is_eq2, ())]),
+    ("composite", "stop = ps & (T_incl < t_min)", "stop = ps & (T_incl <= 0.5 * t_min)", [(TR.test_blending_invariants, ())]),
+    ("composite", 'out["n_eval"] = (ps & (kidx[None, :] <= kstar[:, None])).sum(1)',
+     'out["n_eval"] = (ps & (kidx[None, :] < kstar[:, None])).sum(1)', [(TR.test_soft_count_stops_with_the_walk, ())]),
+    ("composite", "lastk = torch.where(blended.any(1), nc - 1 - _first_true(blended.flip(1)),",
+     "lastk = torch.where(blended.any(1), nc - 2 - _first_true(blended.flip(1)),",
+     [(TR.test_vectorised_equals_scalar_brute_force, (31, 0, (32, 32)))]),
 ]
 
 
