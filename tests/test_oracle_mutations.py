@@ -193,6 +193,11 @@ MUTATIONS = [
     ("composite", "lastk = torch.where(blended.any(1), nc - 1 - _first_true(blended.flip(1)),",
      "lastk = torch.where(blended.any(1), nc - 2 - _first_true(blended.flip(1)),",
      [(TR.test_vectorised_equals_scalar_brute_force, (31, 0, (32, 32)))]),
+    ("grad", "up = torch.as_tensor(g[:, py[s:s + chunk], px[s:s + chunk]])",
+     "up = torch.as_tensor(g[::-1, py[s:s + chunk], px[s:s + chunk]].copy())",
+     [(TL.test_param_grads_colour_closed_form, ())]),
+    ("grad", "active = np.any(g != 0, axis=0)", "active = np.all(g != 0, axis=0) & False",
+     [(TL.test_param_grads_colour_closed_form, ())]),
 ]
 
 
