@@ -198,6 +198,11 @@ MUTATIONS = [
      [(TL.test_param_grads_colour_closed_form, ())]),
     ("grad", "active = np.any(g != 0, axis=0)", "active = np.all(g != 0, axis=0) & False",
      [(TL.test_param_grads_colour_closed_form, ())]),
+    ("adam", "upd = (m_new / bc1[None, :]) / (np.sqrt(v_new / bc2[None, :]) + e)",
+     "upd = (m_new / bc1[None, :]) / np.sqrt(v_new / bc2[None, :] + e)", [(TL.test_adam_matches_torch_fp64, ())]),
+    ("adam", "m_new = b1 * m + (1.0 - b1) * g", "m_new = b1 * m + g", [(TL.test_adam_matches_torch_fp64, ())]),
+    ("loss", "val = w_l1 * (x - y).abs().mean()", "val = w_l1 * (x - y).abs().sum()",
+     [(TL.test_ssim_identity_and_l1_value, ())]),
 ]
 
 
