@@ -67,3 +67,14 @@ def test_traffic_is_dropped_once_the_source_changes(tmp_path, monkeypatch):
     with open(csrc / src_name, "a") as f:
         f.write("\n// edited\n")
     assert bench.traffic_for("render_bwd", "c3") is None
+
+
+def test_cpu_baseline_leg_reports_its_sample():
+    # the oracle leg of the bench on the small 10k-Gaussian workload, with a short budget
+    import scenegen
+    cb = bench.cpu_baseline(scenegen.config1(), budget_s=0.3)
+    assert cb["kind"] == "oracle" and cb["unit"] == "Mpix/s"
+    assert cb["value"] > 0 and cb["cores"] >= 1
+    assert "random pixels of view 0" in cb["sample"]
+    full = cb["small_workload_full"]
+    assert full["pixels"] == 128 * 128 and full["seconds"] > 0 and full["mpix_s"] > 0
